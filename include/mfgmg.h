@@ -1,0 +1,236 @@
+/*
+ * mfgmg.h -- matrix-free geometric multigrid for the variable-viscosity Stokes
+ * problem on adaptive hexahedral meshes of the unit cube, on AMD MI355X (gfx950).
+ *
+ * Method: Clevenger & Heister, "Comparison between algebraic and matrix-free
+ * geometric multigrid for a Stokes problem on adaptive meshes with variable
+ * viscosity" (arXiv 1907.06696).
+ *   - problem: -div(2 mu eps(u)) + grad p = f, div u = 0, u = 0 on the boundary
+ *     (Sec. 2, eq. stokes), Taylor-Hood Q2-Q1 (Sec. 2.1, eq. weak_form);
+ *   - block system [A B^T; B 0] (Sec. 2.1, eq. stokes_linear_system);
+ *   - FGMRES right-preconditioned by P = [A B^T; 0 -S] (Sec. 2.2,
+ *     eq. stokes_precond), A^{-1} ~ one matrix-free GMG V-cycle with a degree-4
+ *     Chebyshev smoother (Sec. 2.2.1), S^{-1} ~ CG on the mu^{-1}-weighted
+ *     pressure mass matrix (Sec. 2.2.2);
+ *   - cellwise viscosity by harmonic averaging over the quadrature points,
+ *     children averaged onto parents (Sec. 2.3).
+ *
+ * Conventions used by every call:
+ *   - Every function returns an int status: MFGMG_OK (0) or a negative
+ *     MFGMG_ERR_* code; mfgmg_last_error() gives a message.  No exception
+ *     crosses the interface.
+ *   - Levels are numbered 1..L: level 1 is the 2x2x2-cell coarse mesh, level L
+ *     the leaf (active) mesh; level l is the leaf mesh with every finer cell
+ *     replaced by its level-l ancestor (global coarsening).
+ *   - Velocity vectors of a level hold 3 values per Q2 node, node-major:
+ *     entry 3*node + component.  Every node is stored, constrained ones
+ *     included.  Pressure vectors hold one value per leaf Q1 node.
+ *   - Nodes are identified across layouts by a canonical key: with U = L + 1,
+ *     integer coordinates (X, Y, Z) in units of 2^-U, key = X + (S+1)(Y + (S+1)Z),
+ *     S = 2^U.
+ *   - Constrained dofs (Dirichlet boundary, hanging nodes) have identity rows:
+ *     (A x)_i = x_i.  Hanging values are interpolated from their masters
+ *     (Lagrange basis on {0, 1/2, 1} / {0, 1}) when a solution is returned.
+ *   - Pointers named *_dev are device pointers (e.g. torch CUDA tensors on the
+ *     current device); *_host are host pointers.  The caller owns them; device
+ *     arrays must stay alive until the work on `stream` has completed.
+ *     `stream` is a hipStream_t (NULL = default stream).  Calls marked async
+ *     only enqueue work on that stream.
+ *   - One context per host thread; a context is bound to the device that is
+ *     current when mfgmg_set_viscosity is first called.
+ */
+#ifndef MFGMG_H
+#define MFGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MFGMG_OK = 0,
+  MFGMG_ERR_INVALID = -1, /* bad argument: null pointer, size, level, flag */
+  MFGMG_ERR_STATE = -2,   /* call out of order (e.g. vmult before set_viscosity) */
+  MFGMG_ERR_NOMEM = -3,   /* host or device allocation failed */
+  MFGMG_ERR_HIP = -4,     /* a HIP runtime call failed */
+  MFGMG_ERR_NOCONV = -5,  /* solver did not reach the tolerance, or NaN/Inf */
+  MFGMG_ERR_MESH = -6     /* mesh cannot be built (too deep, bad cell) */
+};
+
+typedef enum { MFGMG_FP32 = 0, MFGMG_FP64 = 1 } mfgmg_prec;
+
+#define MFGMG_MAX_LEVELS 14
+
+typedef struct mfgmg_ctx mfgmg_ctx; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t n_levels;      /* L */
+  int32_t unit_exponent; /* U = L + 1 */
+  /* arrays indexed by level (entry 0 unused) */
+  int64_t n_cells[MFGMG_MAX_LEVELS + 1];
+  int64_t n_nodes[MFGMG_MAX_LEVELS + 1];    /* Q2 nodes */
+  int64_t n_u[MFGMG_MAX_LEVELS + 1];        /* 3 * n_nodes */
+  int64_t n_free[MFGMG_MAX_LEVELS + 1];     /* free velocity dofs */
+  int64_t n_hanging[MFGMG_MAX_LEVELS + 1];  /* hanging Q2 nodes */
+  int32_t uniform[MFGMG_MAX_LEVELS + 1];    /* 1: all 8^l cells of level l */
+  int64_t n_p;                              /* leaf Q1 nodes */
+  int64_t n_p_hanging;                      /* hanging leaf Q1 nodes */
+} mfgmg_info_t;
+
+/* ---------------------------------------------------------------- mesh setup
+ * The mesh is the unit cube as an octree (abstract; Sec. 3.2 domain).  Host
+ * only; these calls touch no GPU. */
+
+/* Unit cube refined uniformly to 2^base_level cells per edge
+ * (1 <= base_level <= MFGMG_MAX_LEVELS - 2).  *out receives a new context. */
+int mfgmg_create(int32_t base_level, mfgmg_ctx** out);
+
+/* Refine the listed active cells `levels_up` times (each becomes 8^levels_up
+ * cells), then restore 2:1 balance across faces, edges and vertices by
+ * refining further cells.  cells_host: [n][4] int32 (level, i, j, k) of active
+ * cells.  Errors: ERR_INVALID if a listed cell is not active, ERR_STATE after
+ * mfgmg_finalize_mesh. */
+int mfgmg_refine(mfgmg_ctx* ctx, const int32_t* cells_host, int64_t n, int32_t levels_up);
+
+/* Build the level meshes 1..L, Q2/Q1 node numbering, Dirichlet and hanging
+ * constraints, and the level transfers.  Host only. */
+int mfgmg_finalize_mesh(mfgmg_ctx* ctx);
+
+int mfgmg_info(const mfgmg_ctx* ctx, mfgmg_info_t* out);
+
+/* Cells of a level: [n_cells[level]][4] int32 (level, i, j, k). */
+int mfgmg_cells(const mfgmg_ctx* ctx, int32_t level, int32_t* cells_host);
+
+/* Canonical keys of the nodes of a level, in the library's storage order.
+ * field 0: Q2 velocity nodes of `level` ([n_nodes[level]]);
+ * field 1: Q1 pressure nodes of the leaf ([n_p]; level must be L). */
+int mfgmg_support_points(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_t* keys_host);
+
+/* Node kinds of a level: 0 free, 1 Dirichlet, 2 hanging.  field as above. */
+int mfgmg_node_types(const mfgmg_ctx* ctx, int32_t level, int32_t field, uint8_t* types_host);
+
+/* Hanging-node constraints of a level as CSR over the hanging nodes, in the
+ * order of increasing node index: node_host[nh], ptr_host[nh+1],
+ * master_host[nnz], weight_host[nnz] (masters on the boundary are omitted:
+ * they carry zero).  Call with all arrays NULL to get *nh and *nnz only. */
+int mfgmg_constraints(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_t* nh, int64_t* nnz,
+                      int64_t* node_host, int64_t* ptr_host, int64_t* master_host, double* weight_host);
+
+/* Node-level prolongation from level-1 to level (2 <= level <= L) as CSR
+ * over fine nodes: ptr_host[n_nodes[level]+1], col_host[nnz] (coarse nodes),
+ * weight_host[nnz].  The velocity prolongation applies it to each component.
+ * Rows of constrained fine nodes are empty.  NULL arrays: *nnz only. */
+int mfgmg_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* ptr_host, int64_t* col_host,
+                   double* weight_host);
+
+/* Physical coordinates of the 3x3x3 Gauss points of the leaf cells,
+ * [n_cells[L]][27][3] (points x-fastest), for evaluating the viscosity and
+ * body force the caller wants to solve with. */
+int mfgmg_leaf_quadrature_points(const mfgmg_ctx* ctx, double* xyz_host);
+
+/* --------------------------------------------------------------- device data */
+
+/* Viscosity at the leaf Gauss points, mu_qp_host [n_cells[L]][27] (> 0).
+ * On the GPU: harmonic mean per leaf cell, arithmetic child mean on every
+ * coarser level (Sec. 2.3); inverse diagonals of every level operator;
+ * Chebyshev eigenvalue estimates; coarse factorisation.  Allocates the
+ * library's device memory on first use.  Synchronises `stream`.
+ * Errors: ERR_INVALID for non-positive or non-finite values. */
+int mfgmg_set_viscosity(mfgmg_ctx* ctx, const double* mu_qp_host, void* stream);
+
+/* Cell viscosities of a level after averaging: [n_cells[level]] (host copy). */
+int mfgmg_cell_viscosity(const mfgmg_ctx* ctx, int32_t level, double* mu_host);
+
+/* Chebyshev upper bound lambda = 1.2 * estimated max eig of D^{-1} A of a level. */
+int mfgmg_smoother_lambda(const mfgmg_ctx* ctx, int32_t level, double* lambda_out);
+
+/* Inverse diagonal of the level operator (1 on constrained dofs), device,
+ * [n_u[level]] in the given precision.  Async. */
+int mfgmg_inverse_diagonal(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, void* dst_dev, void* stream);
+
+/* dst = A_level src: the matrix-free Q2 strain-rate operator of Sec. 2.1
+ * (A_ij = int 2 mu eps(phi_i):eps(phi_j)) by sum factorisation at the 3x3x3
+ * Gauss points of each cell, hanging nodes resolved in the gather and
+ * condensed in the scatter, identity on constrained dofs.  src_dev, dst_dev:
+ * [n_u[level]] of type float (FP32) or double (FP64); must not alias.  Async. */
+int mfgmg_vmult(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src_dev, void* dst_dev,
+                void* stream);
+
+/* x = V(b): one V(1,1)-cycle on the leaf level (Sec. 2.2.1) with degree-4
+ * Chebyshev smoothing (Saad, Alg. 12.1) preconditioned by the (scaled)
+ * inverse diagonal, global-coarsening transfers, exact coarse solve.
+ * rhs_dev, x_dev: [n_u[L]] in `prec`; x is overwritten.  Async. */
+int mfgmg_vcycle(mfgmg_ctx* ctx, mfgmg_prec prec, const void* rhs_dev, void* x_dev, void* stream);
+
+/* Level transfers (velocity, `prec`):  fine = P_level coarse (overwrite) and
+ * coarse = P_level^T fine.  Async. */
+int mfgmg_prolongate(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* coarse_dev, void* fine_dev,
+                     void* stream);
+int mfgmg_restrict(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* fine_dev, void* coarse_dev,
+                   void* stream);
+
+/* Chebyshev smoothing on a level: `degree`-4 polynomial applied to
+ * A x = b starting from x (x_is_zero: ignore x's content).  Async. */
+int mfgmg_smooth(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* b_dev, void* x_dev,
+                 int32_t x_is_zero, void* stream);
+
+/* Exact coarse solve on level 1 (375 entries): x = A_1^{-1} b.  Async. */
+int mfgmg_coarse_solve(mfgmg_ctx* ctx, mfgmg_prec prec, const void* b_dev, void* x_dev, void* stream);
+
+/* ------------------------------------------------------------ Stokes solve */
+
+/* Right-hand side b_u = C^T F, F_(a,c) = int phi_a f_c, from the body force at
+ * the leaf Gauss points f_qp_host [n_cells[L]][27][3]; constrained entries 0.
+ * rhs_u_dev: double [n_u[L]].  Synchronises `stream`. */
+int mfgmg_assemble_rhs(mfgmg_ctx* ctx, const double* f_qp_host, double* rhs_u_dev, void* stream);
+
+/* Leaf operators in FP64 (Sec. 2.1, 2.2.2), async:
+ *   div:  p_out = B u      (B_ij = -int psi_i div phi_j), [n_p] <- [n_u[L]]
+ *   grad: u_out = B^T p                                  , [n_u[L]] <- [n_p]
+ *   mass: p_out = M_p p    ([M_p]_ij = int mu^-1 psi_i psi_j, identity on
+ *                           hanging pressure nodes). */
+int mfgmg_apply_div(mfgmg_ctx* ctx, const double* u_dev, double* p_out_dev, void* stream);
+int mfgmg_apply_grad(mfgmg_ctx* ctx, const double* p_dev, double* u_out_dev, void* stream);
+int mfgmg_apply_pmass(mfgmg_ctx* ctx, const double* p_dev, double* p_out_dev, void* stream);
+
+typedef struct {
+  double rtol;            /* stop when ||b - K x||_2 <= rtol ||b||_2 (1e-8) */
+  int32_t restart;        /* FGMRES restart length (50) */
+  int32_t max_iter;       /* total outer iterations (1000) */
+  int32_t vcycle_prec;    /* MFGMG_FP32 or MFGMG_FP64 */
+  double schur_rtol;      /* inner pressure-mass CG tolerance (1e-6) */
+  int32_t schur_max_iter; /* (200) */
+  int32_t use_scaling;    /* 1: use the installed smoother scaling */
+} mfgmg_solve_opts;
+
+typedef struct {
+  int32_t iterations;    /* outer FGMRES iterations */
+  int32_t vcycles;
+  int64_t inner_cg_iterations;
+  double rel_residual;   /* ||b - K x|| / ||b||, recomputed in FP64 at the end */
+  double seconds;        /* wall time of the solve */
+  int32_t converged;
+} mfgmg_solve_stats;
+
+/* Fill opts with the defaults above. */
+int mfgmg_default_opts(mfgmg_solve_opts* opts);
+
+/* Solve the block system with FGMRES (x0 = 0) and the block-triangular
+ * preconditioner z_p = -S^{-1} r_p, z_u = V(r_u - B^T z_p).  Outputs have
+ * hanging values interpolated and the pressure shifted to zero mean.
+ * rhs_p_dev may be NULL (zero).  Synchronises `stream`.  Returns
+ * ERR_NOCONV (stats and outputs filled) if rtol is not reached. */
+int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u_dev, const double* rhs_p_dev, double* u_dev,
+                       double* p_dev, const mfgmg_solve_opts* opts, mfgmg_solve_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* mfgmg_last_error(const mfgmg_ctx* ctx); /* ctx may be NULL */
+void mfgmg_destroy(mfgmg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFGMG_H */

@@ -1,0 +1,1132 @@
+// C-ABI entry points and host drivers (V-cycle, eigenvalue estimate, FGMRES).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mfgmg.h"
+#include "mesh.h"
+#include "ops.h"
+
+using namespace mfgmg;
+
+namespace {
+
+// ------------------------------------------------------------ element data
+// Reference element on the unit cube (mu = 1), 3x3x3 Gauss quadrature:
+//   K[(a,c),(b,d)] = int delta_cd grad phi_a . grad phi_b + d_d phi_a d_c phi_b
+//   B[i,(b,d)]     = -int psi_i d_d phi_b,     M[i,j] = int psi_i psi_j
+struct Element {
+  double K[81 * 81];
+  double B[8 * 81];
+  double M[64];
+  Element() {
+    const double g = 0.5 * std::sqrt(3.0 / 5.0);
+    const double xi[3] = {0.5 - g, 0.5, 0.5 + g};
+    const double w1[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    std::memset(K, 0, sizeof K);
+    std::memset(B, 0, sizeof B);
+    std::memset(M, 0, sizeof M);
+    double v[3][3], dv[3][3];   // [point][basis]
+    for (int q = 0; q < 3; ++q) q2_basis_1d(xi[q], v[q]), q2_deriv_1d(xi[q], dv[q]);
+    for (int qz = 0; qz < 3; ++qz)
+      for (int qy = 0; qy < 3; ++qy)
+        for (int qx = 0; qx < 3; ++qx) {
+          const double w = w1[qx] * w1[qy] * w1[qz];
+          double phi[27], gr[27][3], psi[8];
+          for (int a = 0; a < 27; ++a) {
+            const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+            phi[a] = v[qx][i] * v[qy][j] * v[qz][k];
+            gr[a][0] = dv[qx][i] * v[qy][j] * v[qz][k];
+            gr[a][1] = v[qx][i] * dv[qy][j] * v[qz][k];
+            gr[a][2] = v[qx][i] * v[qy][j] * dv[qz][k];
+          }
+          for (int p = 0; p < 8; ++p) {
+            const double tx = (p & 1) ? xi[qx] : 1 - xi[qx], ty = (p & 2) ? xi[qy] : 1 - xi[qy],
+                         tz = (p & 4) ? xi[qz] : 1 - xi[qz];
+            psi[p] = tx * ty * tz;
+          }
+          for (int a = 0; a < 27; ++a)
+            for (int b = 0; b < 27; ++b) {
+              const double lap = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
+              for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d)
+                  K[(3 * a + c) * 81 + 3 * b + d] += w * ((c == d ? lap : 0.0) + gr[a][d] * gr[b][c]);
+            }
+          for (int p = 0; p < 8; ++p) {
+            for (int b = 0; b < 27; ++b)
+              for (int d = 0; d < 3; ++d) B[p * 81 + 3 * b + d] -= w * psi[p] * gr[b][d];
+            for (int r = 0; r < 8; ++r) M[p * 8 + r] += w * psi[p] * psi[r];
+          }
+        }
+  }
+};
+
+const Element& element() {
+  static const Element e;
+  return e;
+}
+
+// ------------------------------------------------------------ SplitMix64
+// Steele, Lea & Flood (2014): state += 0x9E3779B97F4A7C15, then the mixing
+// function; counter-based use: value(c) = mix(c + seed * 0xD1B54A32D192ED03 + gamma)
+double splitmix_pm1(uint64_t seed, uint64_t counter) {
+  uint64_t z = counter + seed * 0xD1B54A32D192ED03ULL + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix by Sturm bisection
+double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
+  const int n = int(d.size());
+  double lo = d[0], hi = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {   // number of eigenvalues < x
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(mid) >= n) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Cholesky factorisation and inverse of a dense SPD matrix (row major)
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> Lm(size_t(n) * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[size_t(j) * n + j];
+    for (int k = 0; k < j; ++k) s -= Lm[size_t(j) * n + k] * Lm[size_t(j) * n + k];
+    if (!(s > 0)) return false;
+    Lm[size_t(j) * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[size_t(i) * n + j];
+      for (int k = 0; k < j; ++k) t -= Lm[size_t(i) * n + k] * Lm[size_t(j) * n + k];
+      Lm[size_t(i) * n + j] = t / Lm[size_t(j) * n + j];
+    }
+  }
+  // columns of the inverse: solve L L^T x = e_c
+  std::vector<double> inv(size_t(n) * n), y(static_cast<size_t>(n));
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= Lm[size_t(i) * n + k] * y[size_t(k)];
+      y[size_t(i)] = t / Lm[size_t(i) * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[size_t(i)];
+      for (int k = i + 1; k < n; ++k) t -= Lm[size_t(k) * n + i] * inv[size_t(k) * n + c];
+      inv[size_t(i) * n + c] = t / Lm[size_t(i) * n + i];
+    }
+  }
+  A.swap(inv);
+  return true;
+}
+
+struct LevelDev {
+  DevLevel v;
+  double* mu_d = nullptr;
+  float* mu_f = nullptr;
+  double* minv_d = nullptr;
+  float* minv_f = nullptr;
+  const int64_t* P_ptr = nullptr;
+  const int32_t* P_col = nullptr;
+  const float* P_w = nullptr;
+  const int64_t* R_ptr = nullptr;
+  const int32_t* R_col = nullptr;
+  const float* R_w = nullptr;
+  const int32_t* mu_src = nullptr;
+  double lambda = 0.0;
+  void* work[2][5] = {{nullptr}};   // [prec][b, x, r, d, t]
+  float* scale_f = nullptr;         // optional smoother scaling s (FP32 copy)
+  double* scale_d = nullptr;
+};
+
+}  // namespace
+
+struct mfgmg_ctx {
+  std::unique_ptr<Mesh> mesh;
+  std::string err;
+  bool dev_ready = false;
+  bool mu_ready = false;
+  int device = -1;
+  std::vector<void*> allocs;
+  std::vector<LevelDev> lv;
+  DevPressure pres;
+  double* khat_d = nullptr;
+  double* Ainv_d = nullptr;
+  float* Ainv_f = nullptr;
+  int32_t* coarse_free = nullptr;
+  int ncfree = 0;
+  double* red_part = nullptr;   // reduction partials
+  double* red_res = nullptr;    // device results (up to 128)
+  double* host_res = nullptr;   // pinned host copy
+  double* pmass_minv = nullptr; // Jacobi preconditioner of M_p
+  double* pmean_w = nullptr;    // int psi_j (constrained) for the zero-mean pressure
+  double pmean_total = 0.0;
+  std::vector<double> mu_host_leaf;
+  bool has_scaling = false;
+
+  int set(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  template <typename T>
+  T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& h) {
+    T* p = dalloc<T>(h.size());
+    if (p && !h.empty()) (void)hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    return p;
+  }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return ctx->set(MFGMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int upload_mesh(mfgmg_ctx* ctx) {
+  if (ctx->dev_ready) return MFGMG_OK;
+  HIPCHK(hipGetDevice(&ctx->device));
+  const Mesh& m = *ctx->mesh;
+  const int L = m.L();
+  ctx->lv.assign(size_t(L + 1), LevelDev{});
+  const Element& E = element();
+  double kd[81];
+  for (int i = 0; i < 81; ++i) kd[i] = E.K[i * 81 + i];
+  set_element_constants(kd, E.B, E.M);
+  ctx->khat_d = ctx->upload(std::vector<double>(E.K, E.K + 81 * 81));
+  for (int ell = 1; ell <= L; ++ell) {
+    const Level& h = m.level(ell);
+    LevelDev& d = ctx->lv[size_t(ell)];
+    DevLevel& v = d.v;
+    v.ell = ell;
+    v.ncell = h.ncell;
+    v.nnode = h.nnode;
+    v.uniform = h.uniform;
+    v.n_edge = h.n_edge;
+    // constrained and hanging node lists
+    std::vector<int64_t> cons;
+    for (int64_t i = 0; i < h.nnode; ++i)
+      if (h.ntype[size_t(i)] != NODE_FREE) cons.push_back(i);
+    v.cons_nodes = ctx->upload(cons);
+    v.n_cons = int64_t(cons.size());
+    if (!h.uniform) {
+      std::vector<int32_t> slots(static_cast<size_t>(27 * h.ncell));
+      std::vector<int8_t> clev(static_cast<size_t>(h.ncell));
+      std::vector<int32_t> reg, hang;
+      for (int64_t c = 0; c < h.ncell; ++c) {
+        bool hh = false;
+        for (int a = 0; a < 27; ++a) {
+          const int32_t n = h.cell_nodes[size_t(27 * c + a)];
+          int32_t s = n;
+          if (h.ntype[size_t(n)] == NODE_DIRICHLET) s = -1;
+          else if (h.ntype[size_t(n)] == NODE_HANGING) s = -(2 + h.hang_index[size_t(n)]), hh = true;
+          slots[size_t(27 * c + a)] = s;
+        }
+        clev[size_t(c)] = int8_t(h.clev[size_t(c)]);
+        (hh ? hang : reg).push_back(int32_t(c));
+      }
+      v.slots = ctx->upload(slots);
+      v.clev = ctx->upload(clev);
+      v.ntype = ctx->upload(h.ntype);
+      v.reg_cells = ctx->upload(reg);
+      v.n_reg_cells = int64_t(reg.size());
+      v.hang_cells = ctx->upload(hang);
+      v.n_hang_cells = int64_t(hang.size());
+      v.hptr = ctx->upload(h.hang.ptr);
+      v.hmaster = ctx->upload(h.hang.master);
+      v.hw_d = ctx->upload(h.hang.weight);
+      std::vector<float> wf(h.hang.weight.begin(), h.hang.weight.end());
+      v.hw_f = ctx->upload(wf);
+      v.hnode = ctx->upload(h.hang.node);
+      v.nhang = int64_t(h.hang.count());
+    }
+    if (ell >= 2) {
+      d.P_ptr = ctx->upload(h.P_ptr);
+      d.P_col = ctx->upload(h.P_col);
+      d.P_w = ctx->upload(std::vector<float>(h.P_w.begin(), h.P_w.end()));
+      d.R_ptr = ctx->upload(h.R_ptr);
+      d.R_col = ctx->upload(h.R_col);
+      d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
+    }
+    if (ell < L) d.mu_src = ctx->upload(h.mu_src);
+    d.mu_d = ctx->dalloc<double>(size_t(h.ncell));
+    d.mu_f = ctx->dalloc<float>(size_t(h.ncell));
+    v.mu_d = d.mu_d;
+    v.mu_f = d.mu_f;
+    d.minv_d = ctx->dalloc<double>(size_t(3 * h.nnode));
+    d.minv_f = ctx->dalloc<float>(size_t(3 * h.nnode));
+    for (int p = 0; p < 2; ++p)
+      for (int k = 0; k < 5; ++k) {
+        if (ell == L && k < 2) continue;   // top-level b, x come from the caller
+        d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
+                              : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
+      }
+  }
+  // pressure on the leaf
+  const Level& lf = m.leaf();
+  {
+    std::vector<int32_t> ps(static_cast<size_t>(8 * lf.ncell));
+    for (int64_t c = 0; c < lf.ncell; ++c)
+      for (int i = 0; i < 8; ++i) {
+        const int32_t n = lf.cell_pnodes[size_t(8 * c + i)];
+        ps[size_t(8 * c + i)] = lf.ptype[size_t(n)] == NODE_HANGING ? -(2 + lf.phang_index[size_t(n)]) : n;
+      }
+    ctx->pres.np = lf.npnode;
+    ctx->pres.pslots = ctx->upload(ps);
+    ctx->pres.hptr = ctx->upload(lf.phang.ptr);
+    ctx->pres.hmaster = ctx->upload(lf.phang.master);
+    ctx->pres.hw = ctx->upload(lf.phang.weight);
+    ctx->pres.hang_nodes = ctx->upload(lf.phang.node);
+    ctx->pres.nh = int64_t(lf.phang.count());
+  }
+  // coarse level: free dofs of level 1
+  {
+    const Level& c1 = m.level(1);
+    std::vector<int32_t> fd;
+    for (int64_t i = 0; i < c1.nnode; ++i)
+      if (c1.ntype[size_t(i)] == NODE_FREE)
+        for (int c = 0; c < 3; ++c) fd.push_back(int32_t(3 * i + c));
+    ctx->ncfree = int(fd.size());
+    ctx->coarse_free = ctx->upload(fd);
+    ctx->Ainv_d = ctx->dalloc<double>(size_t(ctx->ncfree) * ctx->ncfree);
+    ctx->Ainv_f = ctx->dalloc<float>(size_t(ctx->ncfree) * ctx->ncfree);
+  }
+  ctx->red_part = ctx->dalloc<double>(256 * 256);
+  ctx->red_res = ctx->dalloc<double>(512);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctx->host_res), 512 * sizeof(double), hipHostMallocDefault));
+  ctx->pmass_minv = ctx->dalloc<double>(size_t(lf.npnode));
+  ctx->pmean_w = ctx->dalloc<double>(size_t(lf.npnode));
+  for (void* p : ctx->allocs)
+    if (!p) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+  HIPCHK(hipDeviceSynchronize());
+  ctx->dev_ready = true;
+  return MFGMG_OK;
+}
+
+double dot_sync(mfgmg_ctx* ctx, int64_t n, const double* a, const double* b, hipStream_t s) {
+  // result slot 511: slots [0, 511) hold batched Gram-Schmidt coefficients
+  launch_dot(n, a, b, ctx->red_part, ctx->red_res + 511, s);
+  (void)hipMemcpyAsync(ctx->host_res + 511, ctx->red_res + 511, sizeof(double), hipMemcpyDeviceToHost, s);
+  (void)hipStreamSynchronize(s);
+  return ctx->host_res[511];
+}
+
+template <typename T>
+constexpr int prec_index() {
+  return std::is_same<T, float>::value ? 0 : 1;
+}
+
+template <typename T>
+const T* minv_of(const LevelDev& d);
+template <>
+const float* minv_of<float>(const LevelDev& d) {
+  return d.minv_f;
+}
+template <>
+const double* minv_of<double>(const LevelDev& d) {
+  return d.minv_d;
+}
+
+// Chebyshev smoothing (Saad, Alg. 12.1) on [lambda/15, lambda], M^{-1} = minv
+template <typename T>
+void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t s) {
+  LevelDev& d = ctx->lv[size_t(ell)];
+  const int64_t n = 3 * d.v.nnode;
+  T* r = static_cast<T*>(d.work[prec_index<T>()][2]);
+  T* dd = static_cast<T*>(d.work[prec_index<T>()][3]);
+  T* t = static_cast<T*>(d.work[prec_index<T>()][4]);
+  const T* minv = minv_of<T>(d);
+  const double lam = d.lambda, lo = lam / 15.0;
+  const double theta = 0.5 * (lam + lo), delta = 0.5 * (lam - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (x_zero) {
+    launch_cheb_init0<T>(n, b, minv, r, dd, x, 1.0 / theta, s);
+  } else {
+    launch_vmult<T>(d.v, x, t, s);
+    launch_cheb_init<T>(n, b, t, minv, r, dd, x, 1.0 / theta, s);
+  }
+  for (int k = 1; k < 4; ++k) {
+    launch_vmult<T>(d.v, dd, t, s);
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    launch_cheb_step<T>(n, t, minv, r, dd, x, rho_new * rho, 2.0 * rho_new / delta, s);
+    rho = rho_new;
+  }
+}
+
+template <typename T>
+const T* ainv_of(mfgmg_ctx* ctx);
+template <>
+const float* ainv_of<float>(mfgmg_ctx* ctx) {
+  return ctx->Ainv_f;
+}
+template <>
+const double* ainv_of<double>(mfgmg_ctx* ctx) {
+  return ctx->Ainv_d;
+}
+
+template <typename T>
+void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
+  if (ell == 1) {
+    launch_coarse<T>(ainv_of<T>(ctx), ctx->coarse_free, ctx->ncfree, int(3 * ctx->lv[1].v.nnode), b, x, s);
+    return;
+  }
+  LevelDev& d = ctx->lv[size_t(ell)];
+  LevelDev& c = ctx->lv[size_t(ell - 1)];
+  const int pi = prec_index<T>();
+  T* t = static_cast<T*>(d.work[pi][4]);
+  T* bc = static_cast<T*>(c.work[pi][0]);
+  T* xc = static_cast<T*>(c.work[pi][1]);
+  smooth<T>(ctx, ell, b, x, true, s);
+  launch_vmult<T>(d.v, x, t, s);
+  launch_restrict<T>(c.v.nnode, d.R_ptr, d.R_col, d.R_w, b, t, bc, s);
+  vcycle<T>(ctx, ell - 1, bc, xc, s);
+  launch_prolong<T>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, xc, x, true, s);
+  smooth<T>(ctx, ell, b, x, false, s);
+}
+
+// lambda_max of M^{-1} A by 12 steps of preconditioned CG-Lanczos (FP64)
+int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
+  LevelDev& d = ctx->lv[size_t(ell)];
+  const Level& h = ctx->mesh->level(ell);
+  const int64_t n = 3 * h.nnode;
+  std::vector<double> r0(static_cast<size_t>(n));
+  for (int64_t i = 0; i < h.nnode; ++i)
+    for (int c = 0; c < 3; ++c)
+      r0[size_t(3 * i + c)] = h.ntype[size_t(i)] == NODE_FREE
+                                  ? splitmix_pm1(12345, uint64_t(3 * h.key[size_t(i)] + c))
+                                  : 0.0;
+  double* r = static_cast<double*>(d.work[1][2]);
+  double* z = static_cast<double*>(d.work[1][3]);
+  double* q = static_cast<double*>(d.work[1][4]);
+  double* p = ctx->dalloc<double>(size_t(n));
+  if (!p) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+  HIPCHK(hipMemcpyAsync(r, r0.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_mul(n, d.minv_d, r, z, s);
+  HIPCHK(hipMemcpyAsync(p, z, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double rz = dot_sync(ctx, n, r, z, s);
+  const double rz0 = rz;
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < 12; ++it) {
+    launch_vmult<double>(d.v, p, q, s);
+    const double pq = dot_sync(ctx, n, p, q, s);
+    if (!(pq > 0)) break;
+    const double alpha = rz / pq;
+    alphas.push_back(alpha);
+    launch_axpby(n, -alpha, q, 1.0, r, s);
+    launch_mul(n, d.minv_d, r, z, s);
+    const double rz_new = dot_sync(ctx, n, r, z, s);
+    const double beta = rz_new / rz;
+    if (rz_new <= 1e-30 * rz0) break;
+    betas.push_back(beta);
+    launch_axpby(n, 1.0, z, beta, p, s);
+    rz = rz_new;
+  }
+  const int k = int(alphas.size());
+  if (k == 0) return ctx->set(MFGMG_ERR_NOCONV, "eigenvalue estimate failed");
+  std::vector<double> dg(static_cast<size_t>(k)), e(size_t(std::max(k - 1, 0)));
+  for (int i = 0; i < k; ++i) {
+    dg[size_t(i)] = 1.0 / alphas[size_t(i)] + (i > 0 ? betas[size_t(i - 1)] / alphas[size_t(i - 1)] : 0.0);
+    if (i + 1 < k) e[size_t(i)] = std::sqrt(betas[size_t(i)]) / alphas[size_t(i)];
+  }
+  d.lambda = 1.2 * tridiag_max_eig(dg, e);
+  HIPCHK(hipStreamSynchronize(s));
+  // the scratch vector p is released with the context; mark it reusable
+  return MFGMG_OK;
+}
+
+int factor_coarse(mfgmg_ctx* ctx, hipStream_t s) {
+  const Level& c1 = ctx->mesh->level(1);
+  std::vector<double> mu(static_cast<size_t>(c1.ncell));
+  HIPCHK(hipMemcpyAsync(mu.data(), ctx->lv[1].mu_d, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const Element& E = element();
+  const int64_t n = 3 * c1.nnode;
+  std::vector<double> A(size_t(n * n), 0.0);
+  for (int64_t c = 0; c < c1.ncell; ++c) {
+    const double sc = mu[size_t(c)] * std::ldexp(1.0, -c1.clev[size_t(c)]);
+    for (int a = 0; a < 27; ++a)
+      for (int b = 0; b < 27; ++b)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            const int64_t ra = 3 * c1.cell_nodes[size_t(27 * c + a)] + i;
+            const int64_t cb = 3 * c1.cell_nodes[size_t(27 * c + b)] + j;
+            A[size_t(ra * n + cb)] += sc * E.K[(3 * a + i) * 81 + 3 * b + j];
+          }
+  }
+  std::vector<int32_t> fd;
+  for (int64_t i = 0; i < c1.nnode; ++i)
+    if (c1.ntype[size_t(i)] == NODE_FREE)
+      for (int c = 0; c < 3; ++c) fd.push_back(int32_t(3 * i + c));
+  const int nf = int(fd.size());
+  std::vector<double> Af(size_t(nf) * nf);
+  for (int i = 0; i < nf; ++i)
+    for (int j = 0; j < nf; ++j) Af[size_t(i) * nf + j] = A[size_t(fd[size_t(i)]) * n + fd[size_t(j)]];
+  if (!spd_inverse(Af, nf)) return ctx->set(MFGMG_ERR_NOCONV, "coarse matrix is not positive definite");
+  std::vector<float> Aff(Af.begin(), Af.end());
+  HIPCHK(hipMemcpyAsync(ctx->Ainv_d, Af.data(), Af.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->Ainv_f, Aff.data(), Aff.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MFGMG_OK;
+}
+
+// Jacobi preconditioner of M_p and the zero-mean weights (host, from leaf mu)
+int pressure_setup(mfgmg_ctx* ctx, hipStream_t s) {
+  const Level& lf = ctx->mesh->leaf();
+  const Element& E = element();
+  std::vector<double> mu(static_cast<size_t>(lf.ncell));
+  HIPCHK(hipMemcpyAsync(mu.data(), ctx->lv[size_t(ctx->mesh->L())].mu_d, mu.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> dg(size_t(lf.npnode), 0.0), mw(size_t(lf.npnode), 0.0);
+  for (int64_t c = 0; c < lf.ncell; ++c) {
+    const double h = std::ldexp(1.0, -lf.clev[size_t(c)]);
+    const double sm = h * h * h / mu[size_t(c)], sv = h * h * h;
+    // expansion of each local Q1 node into free masters
+    int ml[8][4];
+    double wl[8][4];
+    int nl[8];
+    for (int i = 0; i < 8; ++i) {
+      const int32_t n = lf.cell_pnodes[size_t(8 * c + i)];
+      if (lf.ptype[size_t(n)] == NODE_HANGING) {
+        const int32_t hh = lf.phang_index[size_t(n)];
+        nl[i] = 0;
+        for (int64_t q = lf.phang.ptr[size_t(hh)]; q < lf.phang.ptr[size_t(hh) + 1]; ++q)
+          ml[i][nl[i]] = lf.phang.master[size_t(q)], wl[i][nl[i]] = lf.phang.weight[size_t(q)], ++nl[i];
+      } else {
+        ml[i][0] = n, wl[i][0] = 1.0, nl[i] = 1;
+      }
+    }
+    for (int i = 0; i < 8; ++i) {
+      double rs = 0.0;
+      for (int j = 0; j < 8; ++j) rs += E.M[i * 8 + j];
+      for (int a = 0; a < nl[i]; ++a) {
+        mw[size_t(ml[i][a])] += sv * wl[i][a] * rs;
+        // diagonal: pairs (i, j) sharing the master
+        for (int j = 0; j < 8; ++j)
+          for (int b = 0; b < nl[j]; ++b)
+            if (ml[j][b] == ml[i][a]) dg[size_t(ml[i][a])] += sm * wl[i][a] * wl[j][b] * E.M[i * 8 + j];
+      }
+    }
+  }
+  double tot = 0.0;
+  for (int64_t i = 0; i < lf.npnode; ++i) {
+    if (lf.ptype[size_t(i)] == NODE_HANGING) dg[size_t(i)] = 1.0, mw[size_t(i)] = 0.0;
+    dg[size_t(i)] = 1.0 / dg[size_t(i)];
+    tot += mw[size_t(i)];
+  }
+  ctx->pmean_total = tot;
+  HIPCHK(hipMemcpyAsync(ctx->pmass_minv, dg.data(), dg.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->pmean_w, mw.data(), mw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MFGMG_OK;
+}
+
+int check_level(const mfgmg_ctx* ctx, int32_t level) {
+  if (!ctx || !ctx->mesh || !ctx->mesh->finalized()) return MFGMG_ERR_STATE;
+  if (level < 1 || level > ctx->mesh->L()) return MFGMG_ERR_INVALID;
+  return MFGMG_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int mfgmg_create(int32_t base_level, mfgmg_ctx** out) {
+  if (!out) return MFGMG_ERR_INVALID;
+  *out = nullptr;
+  if (base_level < 1 || base_level > MFGMG_MAX_LEVELS - 2) {
+    g_last_error = "base_level out of range";
+    return MFGMG_ERR_INVALID;
+  }
+  try {
+    auto* c = new mfgmg_ctx;
+    c->mesh = std::make_unique<Mesh>(base_level);
+    *out = c;
+  } catch (...) {
+    g_last_error = "out of host memory";
+    return MFGMG_ERR_NOMEM;
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_refine(mfgmg_ctx* ctx, const int32_t* cells, int64_t n, int32_t levels_up) {
+  if (!ctx || (!cells && n > 0) || n < 0) return MFGMG_ERR_INVALID;
+  if (ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "mesh already finalized");
+  try {
+    const std::string e = ctx->mesh->refine(cells, n, levels_up);
+    if (!e.empty()) return ctx->set(MFGMG_ERR_INVALID, e);
+  } catch (...) {
+    return ctx->set(MFGMG_ERR_NOMEM, "out of host memory");
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_finalize_mesh(mfgmg_ctx* ctx) {
+  if (!ctx) return MFGMG_ERR_INVALID;
+  try {
+    const std::string e = ctx->mesh->finalize();
+    if (!e.empty()) return ctx->set(MFGMG_ERR_MESH, e);
+  } catch (...) {
+    return ctx->set(MFGMG_ERR_NOMEM, "out of host memory");
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_info(const mfgmg_ctx* ctx, mfgmg_info_t* out) {
+  if (!ctx || !out) return MFGMG_ERR_INVALID;
+  if (!ctx->mesh->finalized()) return MFGMG_ERR_STATE;
+  std::memset(out, 0, sizeof(*out));
+  const Mesh& m = *ctx->mesh;
+  out->n_levels = m.L();
+  out->unit_exponent = m.U();
+  for (int l = 1; l <= m.L(); ++l) {
+    const Level& h = m.level(l);
+    out->n_cells[l] = h.ncell;
+    out->n_nodes[l] = h.nnode;
+    out->n_u[l] = 3 * h.nnode;
+    out->n_free[l] = 3 * h.nfree_nodes;
+    out->n_hanging[l] = int64_t(h.hang.count());
+    out->uniform[l] = h.uniform ? 1 : 0;
+  }
+  out->n_p = m.leaf().npnode;
+  out->n_p_hanging = int64_t(m.leaf().phang.count());
+  return MFGMG_OK;
+}
+
+int mfgmg_cells(const mfgmg_ctx* ctx, int32_t level, int32_t* cells) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!cells) return MFGMG_ERR_INVALID;
+  const Level& h = ctx->mesh->level(level);
+  for (int64_t c = 0; c < h.ncell; ++c) {
+    cells[4 * c] = h.clev[size_t(c)];
+    cells[4 * c + 1] = h.cijk[size_t(3 * c)];
+    cells[4 * c + 2] = h.cijk[size_t(3 * c + 1)];
+    cells[4 * c + 3] = h.cijk[size_t(3 * c + 2)];
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_support_points(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_t* keys) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!keys || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
+  const Level& h = ctx->mesh->level(level);
+  const auto& src = field == 0 ? h.key : h.pkey;
+  std::memcpy(keys, src.data(), src.size() * sizeof(int64_t));
+  return MFGMG_OK;
+}
+
+int mfgmg_node_types(const mfgmg_ctx* ctx, int32_t level, int32_t field, uint8_t* types) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!types || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
+  const Level& h = ctx->mesh->level(level);
+  const auto& src = field == 0 ? h.ntype : h.ptype;
+  std::memcpy(types, src.data(), src.size());
+  return MFGMG_OK;
+}
+
+int mfgmg_constraints(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_t* nh, int64_t* nnz, int64_t* node,
+                      int64_t* ptr, int64_t* master, double* weight) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!nh || !nnz || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
+  const Level& h = ctx->mesh->level(level);
+  const Constraints& cs = field == 0 ? h.hang : h.phang;
+  *nh = int64_t(cs.count());
+  *nnz = int64_t(cs.master.size());
+  if (node && ptr && master && weight) {
+    for (size_t i = 0; i < cs.count(); ++i) node[i] = cs.node[i];
+    for (size_t i = 0; i <= cs.count(); ++i) ptr[i] = cs.ptr[i];
+    for (size_t i = 0; i < cs.master.size(); ++i) master[i] = cs.master[i], weight[i] = cs.weight[i];
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* ptr, int64_t* col, double* w) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (level < 2 || !nnz) return MFGMG_ERR_INVALID;
+  const Level& h = ctx->mesh->level(level);
+  *nnz = int64_t(h.P_col.size());
+  if (ptr && col && w) {
+    for (size_t i = 0; i < h.P_ptr.size(); ++i) ptr[i] = h.P_ptr[i];
+    for (size_t i = 0; i < h.P_col.size(); ++i) col[i] = h.P_col[i], w[i] = h.P_w[i];
+  }
+  return MFGMG_OK;
+}
+
+int mfgmg_leaf_quadrature_points(const mfgmg_ctx* ctx, double* xyz) {
+  if (!ctx || !xyz) return MFGMG_ERR_INVALID;
+  if (!ctx->mesh->finalized()) return MFGMG_ERR_STATE;
+  ctx->mesh->leaf_quadrature_points(xyz);
+  return MFGMG_OK;
+}
+
+int mfgmg_set_viscosity(mfgmg_ctx* ctx, const double* mu_qp, void* stream) {
+  if (!ctx || !mu_qp) return MFGMG_ERR_INVALID;
+  if (!ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "finalize the mesh first");
+  const Mesh& m = *ctx->mesh;
+  const int L = m.L();
+  const int64_t nl = m.leaf().ncell;
+  for (int64_t i = 0; i < 27 * nl; ++i)
+    if (!(mu_qp[i] > 0) || !std::isfinite(mu_qp[i]))
+      return ctx->set(MFGMG_ERR_INVALID, "viscosity must be positive and finite");
+  int st = upload_mesh(ctx);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* mq = nullptr;
+  HIPCHK(hipMalloc(&mq, size_t(27 * nl) * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(mq, mu_qp, size_t(27 * nl) * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_harmonic_mu(nl, mq, ctx->lv[size_t(L)].mu_d, s);
+  for (int ell = L - 1; ell >= 1; --ell)
+    launch_restrict_mu(ctx->lv[size_t(ell)].v.ncell, ctx->lv[size_t(ell)].mu_src, ctx->lv[size_t(ell + 1)].mu_d,
+                       ctx->lv[size_t(ell)].mu_d, s);
+  double* dtmp = nullptr;
+  HIPCHK(hipMalloc(&dtmp, size_t(3 * m.leaf().nnode) * sizeof(double) + 64));
+  for (int ell = 1; ell <= L; ++ell) {
+    LevelDev& d = ctx->lv[size_t(ell)];
+    launch_to_float(d.v.ncell, d.mu_d, d.mu_f, s);
+    const int64_t n = 3 * d.v.nnode;
+    launch_fill(n, 0.0, dtmp, s);
+    launch_diag(d.v, ctx->khat_d, dtmp, s);
+    launch_invert_diag(d.v, dtmp, d.minv_d, d.minv_f, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFree(dtmp));
+  HIPCHK(hipFree(mq));
+  for (int ell = 2; ell <= L; ++ell) {
+    st = estimate_lambda(ctx, ell, s);
+    if (st) return st;
+  }
+  st = factor_coarse(ctx, s);
+  if (st) return st;
+  st = pressure_setup(ctx, s);
+  if (st) return st;
+  ctx->mu_ready = true;
+  return MFGMG_OK;
+}
+
+int mfgmg_cell_viscosity(const mfgmg_ctx* ctx, int32_t level, double* mu) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!mu) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return MFGMG_ERR_STATE;
+  const LevelDev& d = ctx->lv[size_t(level)];
+  if (hipMemcpy(mu, d.mu_d, size_t(d.v.ncell) * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return MFGMG_ERR_HIP;
+  return MFGMG_OK;
+}
+
+int mfgmg_smoother_lambda(const mfgmg_ctx* ctx, int32_t level, double* out) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!out) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return MFGMG_ERR_STATE;
+  *out = ctx->lv[size_t(level)].lambda;
+  return MFGMG_OK;
+}
+
+int mfgmg_inverse_diagonal(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, void* dst, void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!dst) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  const LevelDev& d = ctx->lv[size_t(level)];
+  const size_t n = size_t(3 * d.v.nnode);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (prec == MFGMG_FP64)
+    HIPCHK(hipMemcpyAsync(dst, d.minv_d, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    HIPCHK(hipMemcpyAsync(dst, d.minv_f, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return MFGMG_OK;
+}
+
+int mfgmg_vmult(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src, void* dst, void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!src || !dst || src == dst || (prec != MFGMG_FP32 && prec != MFGMG_FP64)) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLevel& v = ctx->lv[size_t(level)].v;
+  if (prec == MFGMG_FP64)
+    launch_vmult<double>(v, static_cast<const double*>(src), static_cast<double*>(dst), s);
+  else
+    launch_vmult<float>(v, static_cast<const float*>(src), static_cast<float*>(dst), s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_vcycle(mfgmg_ctx* ctx, mfgmg_prec prec, const void* rhs, void* x, void* stream) {
+  if (!ctx || !rhs || !x || rhs == x) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int L = ctx->mesh->L();
+  if (prec == MFGMG_FP64)
+    vcycle<double>(ctx, L, static_cast<const double*>(rhs), static_cast<double*>(x), s);
+  else if (prec == MFGMG_FP32)
+    vcycle<float>(ctx, L, static_cast<const float*>(rhs), static_cast<float*>(x), s);
+  else
+    return MFGMG_ERR_INVALID;
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_prolongate(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* coarse, void* fine, void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (level < 2 || !coarse || !fine) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LevelDev& d = ctx->lv[size_t(level)];
+  if (prec == MFGMG_FP64)
+    launch_prolong<double>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, static_cast<const double*>(coarse),
+                           static_cast<double*>(fine), false, s);
+  else
+    launch_prolong<float>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, static_cast<const float*>(coarse),
+                          static_cast<float*>(fine), false, s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_restrict(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* fine, void* coarse, void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (level < 2 || !coarse || !fine) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const LevelDev& d = ctx->lv[size_t(level)];
+  const int64_t nc = ctx->lv[size_t(level - 1)].v.nnode;
+  if (prec == MFGMG_FP64)
+    launch_restrict<double>(nc, d.R_ptr, d.R_col, d.R_w, static_cast<const double*>(fine), nullptr,
+                            static_cast<double*>(coarse), s);
+  else
+    launch_restrict<float>(nc, d.R_ptr, d.R_col, d.R_w, static_cast<const float*>(fine), nullptr,
+                           static_cast<float*>(coarse), s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_smooth(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* b, void* x, int32_t x_is_zero,
+                 void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (level < 2 || !b || !x || b == x) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (prec == MFGMG_FP64)
+    smooth<double>(ctx, level, static_cast<const double*>(b), static_cast<double*>(x), x_is_zero != 0, s);
+  else
+    smooth<float>(ctx, level, static_cast<const float*>(b), static_cast<float*>(x), x_is_zero != 0, s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_coarse_solve(mfgmg_ctx* ctx, mfgmg_prec prec, const void* b, void* x, void* stream) {
+  if (!ctx || !b || !x || b == x) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (prec == MFGMG_FP64)
+    vcycle<double>(ctx, 1, static_cast<const double*>(b), static_cast<double*>(x), s);
+  else
+    vcycle<float>(ctx, 1, static_cast<const float*>(b), static_cast<float*>(x), s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_assemble_rhs(mfgmg_ctx* ctx, const double* f_qp, double* rhs_u, void* stream) {
+  if (!ctx || !f_qp || !rhs_u) return MFGMG_ERR_INVALID;
+  if (!ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "finalize the mesh first");
+  int st = upload_mesh(ctx);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLevel& v = ctx->lv[size_t(ctx->mesh->L())].v;
+  const size_t nf = size_t(81 * v.ncell);
+  double* fd = nullptr;
+  HIPCHK(hipMalloc(&fd, nf * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(fd, f_qp, nf * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_rhs(v, fd, rhs_u, s);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFree(fd));
+  return MFGMG_OK;
+}
+
+int mfgmg_apply_div(mfgmg_ctx* ctx, const double* u, double* p_out, void* stream) {
+  if (!ctx || !u || !p_out) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  launch_div(ctx->lv[size_t(ctx->mesh->L())].v, ctx->pres, u, p_out, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_apply_grad(mfgmg_ctx* ctx, const double* p, double* u_out, void* stream) {
+  if (!ctx || !p || !u_out) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  const DevLevel& v = ctx->lv[size_t(ctx->mesh->L())].v;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_fill(3 * v.nnode, 0.0, u_out, s);
+  launch_grad_add(v, ctx->pres, p, u_out, s);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_apply_pmass(mfgmg_ctx* ctx, const double* p, double* p_out, void* stream) {
+  if (!ctx || !p || !p_out || p == p_out) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  launch_pmass(ctx->lv[size_t(ctx->mesh->L())].v, ctx->pres, p, p_out, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
+int mfgmg_default_opts(mfgmg_solve_opts* o) {
+  if (!o) return MFGMG_ERR_INVALID;
+  o->rtol = 1e-8;
+  o->restart = 50;
+  o->max_iter = 1000;
+  o->vcycle_prec = MFGMG_FP32;
+  o->schur_rtol = 1e-6;
+  o->schur_max_iter = 200;
+  o->use_scaling = 0;
+  return MFGMG_OK;
+}
+
+int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p, double* u_out, double* p_out,
+                       const mfgmg_solve_opts* opts, mfgmg_solve_stats* stats, void* stream) {
+  if (!ctx || !rhs_u || !u_out || !p_out) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  mfgmg_solve_opts o;
+  mfgmg_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.restart < 1 || o.restart > 120 || !(o.rtol > 0) || o.max_iter < 1 ||
+      (o.vcycle_prec != MFGMG_FP32 && o.vcycle_prec != MFGMG_FP64))
+    return ctx->set(MFGMG_ERR_INVALID, "bad solver options");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int L = ctx->mesh->L();
+  LevelDev& top = ctx->lv[size_t(L)];
+  const DevLevel& lv = top.v;
+  const DevPressure& P = ctx->pres;
+  const int64_t nu = 3 * lv.nnode, np = P.np, n = nu + np;
+  const int m = o.restart;
+  // Krylov storage: V (m+1 vectors), Z (m), b, x, r, w; FP32 staging; CG vectors
+  double* V = ctx->dalloc<double>(size_t(m + 1) * n);
+  double* Z = ctx->dalloc<double>(size_t(m) * n);
+  double* b = ctx->dalloc<double>(size_t(n));
+  double* x = ctx->dalloc<double>(size_t(n));
+  double* r = ctx->dalloc<double>(size_t(n));
+  double* w = ctx->dalloc<double>(size_t(n));
+  double* tu = ctx->dalloc<double>(size_t(nu));
+  float* bf = ctx->dalloc<float>(size_t(nu));
+  float* xf = ctx->dalloc<float>(size_t(nu));
+  double* cg = ctx->dalloc<double>(size_t(5 * np));   // r, z (contiguous), p, q, x
+  double* yv = ctx->dalloc<double>(size_t(m + 1));
+  std::vector<void*> mine = {V, Z, b, x, r, w, tu, bf, xf, cg, yv};
+  auto release = [&]() {
+    for (void* p : mine) {
+      auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+      if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+      if (p) (void)hipFree(p);
+    }
+  };
+  for (void* p : mine)
+    if (!p) {
+      release();
+      return ctx->set(MFGMG_ERR_NOMEM, "device allocation for the Krylov space failed");
+    }
+  double* cr = cg;
+  double* cz = cg + np;
+  double* cp = cg + 2 * np;
+  double* cq = cg + 3 * np;
+  double* cx = cg + 4 * np;
+  int64_t inner_total = 0;
+  int vcycles = 0;
+
+  auto apply_K = [&](const double* in, double* out) {
+    launch_vmult<double>(lv, in, out, s);
+    launch_grad_add(lv, P, in + nu, out, s);
+    launch_div(lv, P, in, out + nu, s);
+    launch_p_identity(P, in + nu, out + nu, s);
+  };
+  // Jacobi-preconditioned CG on M_p: cx = M_p^{-1} rhs
+  auto schur = [&](const double* rhs) {
+    (void)hipMemcpyAsync(cr, rhs, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    launch_fill(np, 0.0, cx, s);
+    const double bn = std::sqrt(dot_sync(ctx, np, rhs, rhs, s));
+    if (bn == 0.0) return;
+    launch_mul(np, ctx->pmass_minv, cr, cz, s);
+    (void)hipMemcpyAsync(cp, cz, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    double rz = dot_sync(ctx, np, cr, cz, s);
+    for (int it = 1; it <= o.schur_max_iter; ++it) {
+      launch_pmass(lv, P, cp, cq, s);
+      const double alpha = rz / dot_sync(ctx, np, cp, cq, s);
+      launch_axpby(np, alpha, cp, 1.0, cx, s);
+      launch_axpby(np, -alpha, cq, 1.0, cr, s);
+      launch_mul(np, ctx->pmass_minv, cr, cz, s);
+      // [r.r, z.r] in one reduction (r and z are contiguous)
+      launch_mdot(np, 2, cr, np, cr, ctx->red_part, ctx->red_res, s);
+      (void)hipMemcpyAsync(ctx->host_res, ctx->red_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+      ++inner_total;
+      const double rr = ctx->host_res[0], rz_new = ctx->host_res[1];
+      if (std::sqrt(rr) <= o.schur_rtol * bn) break;
+      launch_axpby(np, 1.0, cz, rz_new / rz, cp, s);
+      rz = rz_new;
+    }
+  };
+  // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p)
+  auto precondition = [&](const double* v, double* z) {
+    schur(v + nu);
+    (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    launch_grad_add(lv, P, cx, tu, s);
+    if (o.vcycle_prec == MFGMG_FP64) {
+      vcycle<double>(ctx, L, tu, z, s);
+    } else {
+      launch_to_float(nu, tu, bf, s);
+      vcycle<float>(ctx, L, bf, xf, s);
+      launch_to_double(nu, xf, z, s);
+    }
+    ++vcycles;
+    launch_scale_copy(np, -1.0, cx, z + nu, s);
+  };
+
+  HIPCHK(hipMemcpyAsync(b, rhs_u, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (rhs_p)
+    HIPCHK(hipMemcpyAsync(b + nu, rhs_p, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    launch_fill(np, 0.0, b + nu, s);
+  launch_fill(n, 0.0, x, s);
+  const double bn = std::sqrt(dot_sync(ctx, n, b, b, s));
+  HIPCHK(hipMemcpyAsync(r, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double beta = bn;
+  int its = 0;
+  bool bad = !std::isfinite(bn);
+  std::vector<double> H(static_cast<size_t>((m + 1) * m)), cs(static_cast<size_t>(m)),
+      sn(static_cast<size_t>(m)), g(static_cast<size_t>(m + 1)), y(static_cast<size_t>(m));
+  auto Hij = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
+  while (!bad && bn > 0 && its < o.max_iter && beta > o.rtol * bn) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    launch_scale_copy(n, 1.0 / beta, r, V, s);
+    int jd = 0;
+    for (int j = 0; j < m; ++j) {
+      precondition(V + size_t(j) * n, Z + size_t(j) * n);
+      apply_K(Z + size_t(j) * n, w);
+      // classical Gram-Schmidt, twice
+      launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res, s);
+      (void)hipMemcpyAsync(ctx->host_res, ctx->red_res, size_t(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+      launch_mupdate(n, j + 1, V, n, ctx->red_res, w, s);
+      launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res + 256, s);
+      (void)hipMemcpyAsync(ctx->host_res + 256, ctx->red_res + 256, size_t(j + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, s);
+      launch_mupdate(n, j + 1, V, n, ctx->red_res + 256, w, s);
+      const double hn = std::sqrt(dot_sync(ctx, n, w, w, s));
+      for (int i = 0; i <= j; ++i) Hij(i, j) = ctx->host_res[i] + ctx->host_res[256 + i];
+      Hij(j + 1, j) = hn;
+      if (!std::isfinite(hn)) {
+        bad = true;
+        break;
+      }
+      if (hn > 0) launch_scale_copy(n, 1.0 / hn, w, V + size_t(j + 1) * n, s);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[size_t(i)] * Hij(i, j) + sn[size_t(i)] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[size_t(i)] * Hij(i, j) + cs[size_t(i)] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+      cs[size_t(j)] = Hij(j, j) / den;
+      sn[size_t(j)] = Hij(j + 1, j) / den;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      g[size_t(j + 1)] = -sn[size_t(j)] * g[size_t(j)];
+      g[size_t(j)] = cs[size_t(j)] * g[size_t(j)];
+      ++its;
+      jd = j + 1;
+      if (std::fabs(g[size_t(j + 1)]) <= o.rtol * bn || its >= o.max_iter) break;
+    }
+    if (bad || jd == 0) break;
+    for (int i = jd - 1; i >= 0; --i) {
+      double t = g[size_t(i)];
+      for (int k = i + 1; k < jd; ++k) t -= Hij(i, k) * y[size_t(k)];
+      y[size_t(i)] = t / Hij(i, i);
+    }
+    std::vector<double> ny(static_cast<size_t>(jd));
+    for (int i = 0; i < jd; ++i) ny[size_t(i)] = -y[size_t(i)];
+    HIPCHK(hipMemcpyAsync(yv, ny.data(), size_t(jd) * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_mupdate(n, jd, Z, n, yv, x, s);   // x += Z y
+    apply_K(x, r);
+    launch_axpby(n, 1.0, b, -1.0, r, s);     // r = b - K x
+    beta = std::sqrt(dot_sync(ctx, n, r, r, s));
+    if (!std::isfinite(beta)) bad = true;
+  }
+  // outputs: zero-mean pressure, hanging values interpolated
+  HIPCHK(hipMemcpyAsync(u_out, x, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(p_out, x + nu, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const double mean = dot_sync(ctx, np, ctx->pmean_w, p_out, s) / ctx->pmean_total;
+  launch_fill(np, 1.0, cr, s);
+  launch_axpby(np, -mean, cr, 1.0, p_out, s);
+  launch_distribute_u(lv, u_out, s);
+  launch_distribute_p(P, p_out, s);
+  HIPCHK(hipStreamSynchronize(s));
+  release();
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const bool conv = !bad && (bn == 0 || beta <= o.rtol * bn);
+  if (stats) {
+    stats->iterations = its;
+    stats->vcycles = vcycles;
+    stats->inner_cg_iterations = inner_total;
+    stats->rel_residual = bn > 0 ? beta / bn : 0.0;
+    stats->seconds = secs;
+    stats->converged = conv ? 1 : 0;
+  }
+  if (!conv) return ctx->set(MFGMG_ERR_NOCONV, bad ? "NaN or Inf in the solve" : "tolerance not reached");
+  return MFGMG_OK;
+}
+
+const char* mfgmg_last_error(const mfgmg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+void mfgmg_destroy(mfgmg_ctx* ctx) {
+  if (!ctx) return;
+  for (void* p : ctx->allocs)
+    if (p) (void)hipFree(p);
+  if (ctx->host_res) (void)hipHostFree(ctx->host_res);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Host-side mesh layer: unit-cube octree, 2:1 balance, global-coarsening level
+// meshes, Q2/Q1 node numbering, Dirichlet and hanging-node constraints, level
+// transfers.  Pure C++ (no GPU); the device layer uploads what it needs.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mfgmg {
+
+enum NodeType : uint8_t { NODE_FREE = 0, NODE_DIRICHLET = 1, NODE_HANGING = 2 };
+
+// Hanging-node constraints over the nodes of one level mesh (CSR over the
+// hanging nodes, ordered by node index).  Masters are free nodes only:
+// Dirichlet masters carry zero and are dropped.
+struct Constraints {
+  std::vector<int64_t> node;
+  std::vector<int64_t> ptr{0};
+  std::vector<int32_t> master;
+  std::vector<double> weight;
+  size_t count() const { return node.size(); }
+};
+
+struct Level {
+  int ell = 0;
+  int64_t ncell = 0;
+  std::vector<int32_t> clev;   // [ncell] cell level
+  std::vector<int32_t> cijk;   // [3*ncell] integer position at that level
+  bool uniform = false;        // all 8^ell cells of level ell, lexicographic order
+  int64_t n_edge = 0;          // cells per edge when uniform
+  int min_cell_level = 0;
+
+  int64_t nnode = 0;
+  std::vector<int64_t> key;         // canonical key per node
+  std::vector<int32_t> cell_nodes;  // [27*ncell]
+  std::vector<uint8_t> ntype;       // NodeType per node
+  std::vector<int32_t> hang_index;  // per node: row in `hang` or -1
+  Constraints hang;
+  int64_t nfree_nodes = 0;
+
+  // prolongation from level ell-1 (node level, applied per component);
+  // rows = nodes of this level (constrained rows empty)
+  std::vector<int64_t> P_ptr;
+  std::vector<int32_t> P_col;
+  std::vector<double> P_w;
+  // transpose (rows = nodes of level ell-1)
+  std::vector<int64_t> R_ptr;
+  std::vector<int32_t> R_col;
+  std::vector<double> R_w;
+
+  // viscosity restriction onto this level from level ell+1:
+  // [8*ncell] cell indices in level ell+1 (-1 padded)
+  std::vector<int32_t> mu_src;
+
+  // leaf only: Q1 pressure nodes
+  int64_t npnode = 0;
+  std::vector<int64_t> pkey;
+  std::vector<int32_t> cell_pnodes;  // [8*ncell]
+  std::vector<uint8_t> ptype;
+  std::vector<int32_t> phang_index;
+  Constraints phang;
+};
+
+class Mesh {
+ public:
+  explicit Mesh(int base_level);
+  // refine the listed active cells `times` levels, then 2:1 balance
+  // returns "" on success or an error message
+  std::string refine(const int32_t* cells, int64_t n, int times);
+  std::string finalize();
+
+  bool finalized() const { return finalized_; }
+  int L() const { return L_; }
+  int U() const { return L_ + 1; }
+  int64_t S() const { return int64_t(1) << (L_ + 1); }
+  const Level& level(int ell) const { return levels_[ell]; }
+  Level& level(int ell) { return levels_[ell]; }
+  const Level& leaf() const { return levels_[L_]; }
+  int64_t n_active() const { return int64_t(lev_.size()); }
+
+  // physical Gauss points of the leaf cells [ncell][27][3]
+  void leaf_quadrature_points(double* out) const;
+
+ private:
+  void balance();
+  void build_level(int ell);
+  void build_nodes(Level& lv, bool q1);
+  void build_transfer(int ell);
+  void build_mu_restriction(int ell);
+
+  std::vector<int32_t> lev_;   // active cells
+  std::vector<int32_t> ijk_;
+  bool finalized_ = false;
+  int L_ = 0;
+  std::vector<Level> levels_;
+};
+
+// 1D Q2 Lagrange basis on {0, 1/2, 1} evaluated at t
+void q2_basis_1d(double t, double v[3]);
+void q2_deriv_1d(double t, double v[3]);
+
+}  // namespace mfgmg

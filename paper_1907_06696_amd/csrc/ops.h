@@ -1,0 +1,118 @@
+// Device kernels and their launchers (host-callable, async on a stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfgmg {
+
+// Device view of one level mesh.
+struct DevLevel {
+  int ell = 0;
+  int64_t ncell = 0, nnode = 0;
+  bool uniform = false;
+  int64_t n_edge = 0;
+  // general (non-uniform) levels
+  const int32_t* slots = nullptr;   // [27*ncell]: node >= 0 free, -1 Dirichlet, -(2+h) hanging row h
+  const int8_t* clev = nullptr;     // [ncell]
+  const uint8_t* ntype = nullptr;   // [nnode]
+  const int64_t* hptr = nullptr;    // hanging CSR
+  const int32_t* hmaster = nullptr;
+  const float* hw_f = nullptr;
+  const double* hw_d = nullptr;
+  const int32_t* hang_cells = nullptr;  // cells with at least one hanging node
+  int64_t n_hang_cells = 0;
+  const int32_t* reg_cells = nullptr;   // the other cells
+  int64_t n_reg_cells = 0;
+  const int64_t* cons_nodes = nullptr;  // constrained nodes (Dirichlet + hanging)
+  int64_t n_cons = 0;
+  const int64_t* hnode = nullptr;       // node of each hanging row
+  int64_t nhang = 0;
+  // per-cell viscosity
+  const double* mu_d = nullptr;
+  const float* mu_f = nullptr;
+};
+
+template <typename T>
+const T* mu_of(const DevLevel& L);
+
+// y = A x on a level (identity on constrained dofs).  x, y must not alias.
+template <typename T>
+void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s);
+
+// diag(A) accumulation (free dofs) into d (zeroed by the caller), then
+// minv = 1/d on free dofs and 1 on constrained dofs.
+void launch_diag(const DevLevel& L, const double* khat_full_dev, double* d, hipStream_t s);
+void launch_invert_diag(const DevLevel& L, const double* d, double* minv_d, float* minv_f, hipStream_t s);
+
+// Chebyshev updates (see smoother in api.hip)
+template <typename T>
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double inv_theta, hipStream_t s);
+template <typename T>
+void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double inv_theta,
+                      hipStream_t s);
+template <typename T>
+void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
+                      hipStream_t s);
+
+// transfers (node-level CSR, 3 components)
+template <typename T>
+void launch_prolong(int64_t nfine, const int64_t* ptr, const int32_t* col, const float* w, const T* coarse, T* fine,
+                    bool add, hipStream_t s);
+// coarse = R (b - t) (t may be null: coarse = R b)
+template <typename T>
+void launch_restrict(int64_t ncoarse, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
+                     T* coarse, hipStream_t s);
+
+// coarse solve: x[free] = Ainv b[free], x[constrained] = b
+template <typename T>
+void launch_coarse(const T* Ainv, const int32_t* free_dofs, int nfree, int n, const T* b, T* x, hipStream_t s);
+
+// viscosity
+void launch_harmonic_mu(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s);
+void launch_restrict_mu(int64_t ncell, const int32_t* src, const double* mu_fine, double* mu_coarse, hipStream_t s);
+void launch_to_float(int64_t n, const double* a, float* b, hipStream_t s);
+void launch_to_double(int64_t n, const float* a, double* b, hipStream_t s);
+
+// reductions: result[0] = sum a*b (two-stage, deterministic); partial has >= 1024 doubles
+void launch_dot(int64_t n, const double* a, const double* b, double* partial, double* result, hipStream_t s);
+// result[j] = sum_i V[j*ldv + i] w[i], j < nv; partial has >= nv*256 doubles
+void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* partial, double* result,
+                 hipStream_t s);
+// w -= sum_j h[j] V[j*ldv + i]
+void launch_mupdate(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s);
+// y = a*x + b*y
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+void launch_fill(int64_t n, double v, double* y, hipStream_t s);
+void launch_fill_f(int64_t n, float v, float* y, hipStream_t s);
+void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t s);
+
+// leaf pressure operators (FP64)
+struct DevPressure {
+  int64_t np = 0;
+  const int32_t* pslots = nullptr;   // [8*ncell]: node >= 0 free, -(2+h) hanging row h
+  const int64_t* hptr = nullptr;
+  const int32_t* hmaster = nullptr;
+  const double* hw = nullptr;
+  const int64_t* hang_nodes = nullptr;
+  int64_t nh = 0;
+};
+void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* p_out, hipStream_t s);
+void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* u_out, hipStream_t s);
+void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* p_out, hipStream_t s);
+// copy p_in on hanging pressure nodes into p_out
+void launch_p_identity(const DevPressure& P, const double* p_in, double* p_out, hipStream_t s);
+// resolve hanging values: u[h] = sum w u[m] (velocity) and p likewise
+void launch_distribute_u(const DevLevel& L, double* u, hipStream_t s);
+void launch_distribute_p(const DevPressure& P, double* p, hipStream_t s);
+// zero the constrained velocity entries
+void launch_zero_constrained(const DevLevel& L, double* u, hipStream_t s);
+// rhs: b_u = C^T F from f at the Gauss points [ncell][27][3]
+void launch_rhs(const DevLevel& L, const double* f_qp, double* b, hipStream_t s);
+
+// upload element constants (K_hat diagonal, B_hat, M_hat) to constant memory
+void set_element_constants(const double* khat_diag81, const double* bhat8x81, const double* mhat8x8);
+
+}  // namespace mfgmg

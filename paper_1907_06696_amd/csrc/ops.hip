@@ -1,0 +1,841 @@
+// Device kernels for the matrix-free GMG Stokes path (gfx950, wave64).
+#include "ops.h"
+
+#include "cell_kernel.h"
+
+namespace mfgmg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kCellBlock = 64;     // cells per workgroup for the cell kernels
+constexpr int kRedBlocks = 1024;   // partial sums of the reductions
+
+__constant__ double c_khat_diag[81];
+__constant__ double c_bhat[8 * 81];
+__constant__ double c_mhat[64];
+
+inline unsigned grid_for(int64_t n, int block = kBlock, int64_t cap = 1 << 20) {
+  int64_t g = (n + block - 1) / block;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  atomicAdd(p, v);   // hardware float/double add (built with -munsafe-fp-atomics)
+}
+
+// ----------------------------------------------------------- slot access
+// Velocity slot of local node a (x fastest) of cell c: node index >= 0 for a
+// free node, -1 for a Dirichlet node, -(2+h) for hanging row h.
+struct UniformCell {
+  int64_t n, m, base;
+  bool lo[3], hi[3];
+  __device__ UniformCell(int64_t n_, int64_t c) : n(n_), m(2 * n_ + 1) {
+    const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+    base = 2 * i + m * (2 * j + m * 2 * k);
+    lo[0] = i == 0, lo[1] = j == 0, lo[2] = k == 0;
+    hi[0] = i == n - 1, hi[1] = j == n - 1, hi[2] = k == n - 1;
+  }
+  __device__ __forceinline__ int32_t slot(int x, int y, int z) const {
+    const bool dir = (x == 0 && lo[0]) || (x == 2 && hi[0]) || (y == 0 && lo[1]) || (y == 2 && hi[1]) ||
+                     (z == 0 && lo[2]) || (z == 2 && hi[2]);
+    return dir ? -1 : int32_t(base + x + m * (y + m * z));
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void gather3(int32_t s, int a, const T* __restrict__ x, const int64_t* __restrict__ hptr,
+                                        const int32_t* __restrict__ hm, const T* __restrict__ hw, T (&U)[3][27]) {
+  if (s >= 0) {
+    U[0][a] = x[3 * int64_t(s)];
+    U[1][a] = x[3 * int64_t(s) + 1];
+    U[2][a] = x[3 * int64_t(s) + 2];
+  } else if (s == -1) {
+    U[0][a] = U[1][a] = U[2][a] = T(0);
+  } else {
+    const int64_t h = -int64_t(s) - 2;
+    T v0 = T(0), v1 = T(0), v2 = T(0);
+    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
+      const int64_t mm = 3 * int64_t(hm[q]);
+      const T w = hw[q];
+      v0 += w * x[mm];
+      v1 += w * x[mm + 1];
+      v2 += w * x[mm + 2];
+    }
+    U[0][a] = v0, U[1][a] = v1, U[2][a] = v2;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter3(int32_t s, int a, T* __restrict__ y, const int64_t* __restrict__ hptr,
+                                         const int32_t* __restrict__ hm, const T* __restrict__ hw,
+                                         const T (&U)[3][27]) {
+  if (s >= 0) {
+    atomic_add(&y[3 * int64_t(s)], U[0][a]);
+    atomic_add(&y[3 * int64_t(s) + 1], U[1][a]);
+    atomic_add(&y[3 * int64_t(s) + 2], U[2][a]);
+  } else if (s < -1) {
+    const int64_t h = -int64_t(s) - 2;
+    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
+      const int64_t mm = 3 * int64_t(hm[q]);
+      const T w = hw[q];
+      atomic_add(&y[mm], w * U[0][a]);
+      atomic_add(&y[mm + 1], w * U[1][a]);
+      atomic_add(&y[mm + 2], w * U[2][a]);
+    }
+  }
+}
+
+// ------------------------------------------------------------- vmult
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_out_uniform(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t m = 2 * n + 1, nn = m * m * m;
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
+    const bool b = X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1;
+    y[3 * v] = b ? x[3 * v] : T(0);
+    y[3 * v + 1] = b ? x[3 * v + 1] : T(0);
+    y[3 * v + 2] = b ? x[3 * v + 2] : T(0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_out_general(int64_t nn, const uint8_t* __restrict__ ntype,
+                                                          const T* __restrict__ x, T* __restrict__ y) {
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const bool b = ntype[v] != 0;
+    y[3 * v] = b ? x[3 * v] : T(0);
+    y[3 * v + 1] = b ? x[3 * v + 1] : T(0);
+    y[3 * v + 2] = b ? x[3 * v + 2] : T(0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCellBlock) void k_vmult_uniform(int64_t n, const T* __restrict__ mu,
+                                                              const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= n * n * n) return;
+  const UniformCell cell(n, c);
+  T U[3][27];
+  int32_t sl[27];
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 3; ++xx) {
+        const int a = xx + 3 * yy + 9 * z;
+        sl[a] = cell.slot(xx, yy, z);
+        gather3<T>(sl[a], a, x, nullptr, nullptr, nullptr, U);
+      }
+  cellop::apply_cell<T>(U, mu[c] / T(n));
+#pragma unroll
+  for (int a = 0; a < 27; ++a) scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
+}
+
+template <typename T, bool HANG>
+__global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __restrict__ cells, int64_t ncells,
+                                                              const int32_t* __restrict__ slots,
+                                                              const int8_t* __restrict__ clev,
+                                                              const T* __restrict__ mu,
+                                                              const int64_t* __restrict__ hptr,
+                                                              const int32_t* __restrict__ hm,
+                                                              const T* __restrict__ hw, const T* __restrict__ x,
+                                                              T* __restrict__ y) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= ncells) return;
+  const int64_t c = cells[t];
+  T U[3][27];
+  int32_t sl[27];
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    sl[a] = slots[27 * c + a];
+    if constexpr (HANG)
+      gather3<T>(sl[a], a, x, hptr, hm, hw, U);
+    else
+      gather3<T>(sl[a], a, x, nullptr, nullptr, nullptr, U);
+  }
+  const T h = T(ldexp(1.0, -int(clev[c])));
+  cellop::apply_cell<T>(U, mu[c] * h);
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    if constexpr (HANG)
+      scatter3<T>(sl[a], a, y, hptr, hm, hw, U);
+    else
+      scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
+  }
+}
+
+template <typename T>
+const T* hw_of(const DevLevel& L);
+template <>
+const float* hw_of<float>(const DevLevel& L) {
+  return L.hw_f;
+}
+template <>
+const double* hw_of<double>(const DevLevel& L) {
+  return L.hw_d;
+}
+
+// ------------------------------------------------------------- diagonal
+__global__ __launch_bounds__(kCellBlock) void k_diag_uniform(int64_t n, const double* __restrict__ mu,
+                                                             double* __restrict__ d) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= n * n * n) return;
+  const UniformCell cell(n, c);
+  const double s = mu[c] / double(n);
+  for (int z = 0; z < 3; ++z)
+    for (int y = 0; y < 3; ++y)
+      for (int x = 0; x < 3; ++x) {
+        const int32_t sl = cell.slot(x, y, z);
+        if (sl < 0) continue;
+        const int a = x + 3 * y + 9 * z;
+        for (int cc = 0; cc < 3; ++cc) atomicAdd(&d[3 * int64_t(sl) + cc], s * c_khat_diag[3 * a + cc]);
+      }
+}
+
+__global__ __launch_bounds__(kCellBlock) void k_diag_regular(const int32_t* __restrict__ cells, int64_t ncells,
+                                                             const int32_t* __restrict__ slots,
+                                                             const int8_t* __restrict__ clev,
+                                                             const double* __restrict__ mu, double* __restrict__ d) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= ncells) return;
+  const int64_t c = cells[t];
+  const double s = mu[c] * ldexp(1.0, -int(clev[c]));
+  for (int a = 0; a < 27; ++a) {
+    const int32_t sl = slots[27 * c + a];
+    if (sl < 0) continue;
+    for (int cc = 0; cc < 3; ++cc) atomicAdd(&d[3 * int64_t(sl) + cc], s * c_khat_diag[3 * a + cc]);
+  }
+}
+
+// Cells with hanging nodes: diagonal of the resolved local matrix C_l^T K_e C_l.
+// One workgroup per cell; entry (M, c) gets sum_{p,q} w_p w_q K[(a_p,c),(a_q,c)]
+// over the local nodes a_p, a_q whose expansions contain master M.
+__global__ __launch_bounds__(64) void k_diag_hanging(const int32_t* __restrict__ cells,
+                                                     const int32_t* __restrict__ slots,
+                                                     const int8_t* __restrict__ clev, const double* __restrict__ mu,
+                                                     const int64_t* __restrict__ hptr,
+                                                     const int32_t* __restrict__ hm, const double* __restrict__ hw,
+                                                     const double* __restrict__ khat, double* __restrict__ d) {
+  __shared__ int32_t t_a[256];
+  __shared__ int32_t t_m[256];
+  __shared__ double t_w[256];
+  __shared__ int32_t dm[256];
+  __shared__ int nt, nd;
+  const int64_t c = cells[blockIdx.x];
+  if (threadIdx.x == 0) {
+    int k = 0;
+    for (int a = 0; a < 27; ++a) {
+      const int32_t s = slots[27 * c + a];
+      if (s >= 0) {
+        t_a[k] = a, t_m[k] = s, t_w[k] = 1.0, ++k;
+      } else if (s < -1) {
+        const int64_t h = -int64_t(s) - 2;
+        for (int64_t q = hptr[h]; q < hptr[h + 1] && k < 256; ++q) t_a[k] = a, t_m[k] = hm[q], t_w[k] = hw[q], ++k;
+      }
+    }
+    nt = k;
+    int u = 0;
+    for (int p = 0; p < k; ++p) {
+      bool found = false;
+      for (int q = 0; q < u; ++q)
+        if (dm[q] == t_m[p]) {
+          found = true;
+          break;
+        }
+      if (!found) dm[u++] = t_m[p];
+    }
+    nd = u;
+  }
+  __syncthreads();
+  const double s = mu[c] * ldexp(1.0, -int(clev[c]));
+  for (int r = threadIdx.x; r < nd; r += blockDim.x) {
+    const int32_t M = dm[r];
+    for (int cc = 0; cc < 3; ++cc) {
+      double acc = 0.0;
+      for (int p = 0; p < nt; ++p) {
+        if (t_m[p] != M) continue;
+        for (int q = 0; q < nt; ++q) {
+          if (t_m[q] != M) continue;
+          acc += t_w[p] * t_w[q] * khat[(3 * t_a[p] + cc) * 81 + 3 * t_a[q] + cc];
+        }
+      }
+      atomicAdd(&d[3 * int64_t(M) + cc], s * acc);
+    }
+  }
+}
+
+__global__ void k_invert_diag_uniform(int64_t n, const double* __restrict__ d, double* __restrict__ md,
+                                      float* __restrict__ mf) {
+  const int64_t m = 2 * n + 1, nn = m * m * m;
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
+    const bool b = X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1;
+    for (int c = 0; c < 3; ++c) {
+      const double r = b ? 1.0 : 1.0 / d[3 * v + c];
+      md[3 * v + c] = r;
+      mf[3 * v + c] = float(r);
+    }
+  }
+}
+
+__global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ ntype, const double* __restrict__ d,
+                                      double* __restrict__ md, float* __restrict__ mf) {
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const bool b = ntype[v] != 0;
+    for (int c = 0; c < 3; ++c) {
+      const double r = b ? 1.0 : 1.0 / d[3 * v + c];
+      md[3 * v + c] = r;
+      mf[3 * v + c] = float(r);
+    }
+  }
+}
+
+// ------------------------------------------------------------- Chebyshev
+template <typename T>
+__global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __restrict__ minv, T* __restrict__ r,
+                             T* __restrict__ d, T* __restrict__ x, T it) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const T bi = b[i];
+    const T di = minv[i] * bi * it;
+    r[i] = bi;
+    d[i] = di;
+    x[i] = di;
+  }
+}
+
+template <typename T>
+__global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* __restrict__ t, const T* __restrict__ minv,
+                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const T ri = b[i] - t[i];
+    const T di = minv[i] * ri * it;
+    r[i] = ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+template <typename T>
+__global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restrict__ minv, T* __restrict__ r,
+                            T* __restrict__ d, T* __restrict__ x, T alpha, T beta) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const T ri = r[i] - t[i];
+    const T di = alpha * d[i] + beta * minv[i] * ri;
+    r[i] = ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+// ------------------------------------------------------------- transfers
+template <typename T>
+__global__ void k_prolong(int64_t nf, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                          const float* __restrict__ w, const T* __restrict__ xc, T* __restrict__ xf, bool add) {
+  for (int64_t f = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; f < nf; f += int64_t(gridDim.x) * blockDim.x) {
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int64_t q = ptr[f]; q < ptr[f + 1]; ++q) {
+      const int64_t cc = 3 * int64_t(col[q]);
+      const T ww = T(w[q]);
+      a0 += ww * xc[cc];
+      a1 += ww * xc[cc + 1];
+      a2 += ww * xc[cc + 2];
+    }
+    if (add) {
+      xf[3 * f] += a0;
+      xf[3 * f + 1] += a1;
+      xf[3 * f + 2] += a2;
+    } else {
+      xf[3 * f] = a0;
+      xf[3 * f + 1] = a1;
+      xf[3 * f + 2] = a2;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_restrict(int64_t nc, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                           const float* __restrict__ w, const T* __restrict__ b, const T* __restrict__ t,
+                           T* __restrict__ xc) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < nc; c += int64_t(gridDim.x) * blockDim.x) {
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int64_t q = ptr[c]; q < ptr[c + 1]; ++q) {
+      const int64_t ff = 3 * int64_t(col[q]);
+      const T ww = T(w[q]);
+      if (t) {
+        a0 += ww * (b[ff] - t[ff]);
+        a1 += ww * (b[ff + 1] - t[ff + 1]);
+        a2 += ww * (b[ff + 2] - t[ff + 2]);
+      } else {
+        a0 += ww * b[ff];
+        a1 += ww * b[ff + 1];
+        a2 += ww * b[ff + 2];
+      }
+    }
+    xc[3 * c] = a0;
+    xc[3 * c + 1] = a1;
+    xc[3 * c + 2] = a2;
+  }
+}
+
+// ------------------------------------------------------------- coarse
+template <typename T>
+__global__ __launch_bounds__(128) void k_coarse(const T* __restrict__ Ainv, const int32_t* __restrict__ fd,
+                                                int nfree, int n, const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ T bs[128];
+  for (int i = threadIdx.x; i < nfree; i += blockDim.x) bs[i] = b[fd[i]];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = b[i];
+  __syncthreads();
+  for (int r = threadIdx.x; r < nfree; r += blockDim.x) {
+    T acc = T(0);
+    for (int j = 0; j < nfree; ++j) acc += Ainv[r * nfree + j] * bs[j];
+    x[fd[r]] = acc;
+  }
+}
+
+// ------------------------------------------------------------- viscosity
+__global__ void k_harmonic(int64_t ncell, const double* __restrict__ mq, double* __restrict__ mu) {
+  const double w1[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < ncell;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < 3; ++z)
+      for (int y = 0; y < 3; ++y)
+        for (int x = 0; x < 3; ++x) s += w1[x] * w1[y] * w1[z] / mq[27 * c + x + 3 * y + 9 * z];
+    mu[c] = 1.0 / s;
+  }
+}
+
+__global__ void k_restrict_mu(int64_t ncell, const int32_t* __restrict__ src, const double* __restrict__ mf,
+                              double* __restrict__ mc) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < ncell;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    int k = 0;
+    for (int q = 0; q < 8; ++q) {
+      const int32_t f = src[8 * c + q];
+      if (f >= 0) s += mf[f], ++k;
+    }
+    mc[c] = s / double(k);
+  }
+}
+
+__global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+__global__ void k_to_double(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = double(a[i]);
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sm[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sm[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) r += sm[i];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_partial(int64_t n, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ part) {
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    v += a[i] * b[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(int np, const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+  // block j sums part[j*np .. j*np + np)
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[int64_t(blockIdx.x) * np + i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, int nv, const double* __restrict__ V,
+                                                         int64_t ldv, const double* __restrict__ w,
+                                                         double* __restrict__ part) {
+  // grid (nb, nv): block (b, j) computes a partial of V_j . w
+  const int j = blockIdx.y;
+  double v = 0.0;
+  const double* Vj = V + int64_t(j) * ldv;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    v += Vj[i] * w[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = v;
+}
+
+__global__ void k_mupdate(int64_t n, int nv, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+                          double* __restrict__ w) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    double acc = w[i];
+    for (int j = 0; j < nv; ++j) acc -= h[j] * V[int64_t(j) * ldv + i];
+    w[i] = acc;
+  }
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+__global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = a * x[i];
+}
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = v;
+}
+__global__ void k_fill_f(int64_t n, float v, float* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = v;
+}
+__global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = a[i] * b[i];
+}
+
+// ------------------------------------------------------------- pressure
+__device__ __forceinline__ int32_t vslot(const DevLevel& L, int64_t c, int a) {
+  if (L.uniform) {
+    const UniformCell cell(L.n_edge, c);
+    return cell.slot(a % 3, (a / 3) % 3, a / 9);
+  }
+  return L.slots[27 * c + a];
+}
+
+__device__ __forceinline__ double cell_h(const DevLevel& L, int64_t c) {
+  return L.uniform ? 1.0 / double(L.n_edge) : ldexp(1.0, -int(L.clev[c]));
+}
+
+__device__ __forceinline__ double pgather(const DevPressure& P, int32_t s, const double* p) {
+  if (s >= 0) return p[s];
+  const int64_t h = -int64_t(s) - 2;
+  double v = 0.0;
+  for (int64_t q = P.hptr[h]; q < P.hptr[h + 1]; ++q) v += P.hw[q] * p[P.hmaster[q]];
+  return v;
+}
+
+__device__ __forceinline__ void pscatter(const DevPressure& P, int32_t s, double v, double* p) {
+  if (s >= 0) {
+    atomicAdd(&p[s], v);
+    return;
+  }
+  const int64_t h = -int64_t(s) - 2;
+  for (int64_t q = P.hptr[h]; q < P.hptr[h + 1]; ++q) atomicAdd(&p[P.hmaster[q]], P.hw[q] * v);
+}
+
+__device__ __forceinline__ double vgather1(const DevLevel& L, int32_t s, int comp, const double* u) {
+  if (s >= 0) return u[3 * int64_t(s) + comp];
+  if (s == -1) return 0.0;
+  const int64_t h = -int64_t(s) - 2;
+  double v = 0.0;
+  for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q) v += L.hw_d[q] * u[3 * int64_t(L.hmaster[q]) + comp];
+  return v;
+}
+
+__device__ __forceinline__ void vscatter1(const DevLevel& L, int32_t s, int comp, double v, double* u) {
+  if (s >= 0) {
+    atomicAdd(&u[3 * int64_t(s) + comp], v);
+  } else if (s < -1) {
+    const int64_t h = -int64_t(s) - 2;
+    for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q) atomicAdd(&u[3 * int64_t(L.hmaster[q]) + comp], L.hw_d[q] * v);
+  }
+}
+
+__global__ __launch_bounds__(kCellBlock) void k_div(DevLevel L, DevPressure P, const double* __restrict__ u,
+                                                    double* __restrict__ po) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= L.ncell) return;
+  const double h = cell_h(L, c);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 27; ++a) {
+    const int32_t s = vslot(L, c, a);
+    for (int comp = 0; comp < 3; ++comp) {
+      const double v = vgather1(L, s, comp, u);
+      if (v == 0.0) continue;
+      for (int i = 0; i < 8; ++i) acc[i] += c_bhat[i * 81 + 3 * a + comp] * v;
+    }
+  }
+  for (int i = 0; i < 8; ++i) pscatter(P, P.pslots[8 * c + i], h * h * acc[i], po);
+}
+
+__global__ __launch_bounds__(kCellBlock) void k_grad_add(DevLevel L, DevPressure P, const double* __restrict__ p,
+                                                         double* __restrict__ uo) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= L.ncell) return;
+  const double h = cell_h(L, c);
+  double pl[8];
+  for (int i = 0; i < 8; ++i) pl[i] = h * h * pgather(P, P.pslots[8 * c + i], p);
+  for (int a = 0; a < 27; ++a) {
+    const int32_t s = vslot(L, c, a);
+    if (s == -1) continue;
+    for (int comp = 0; comp < 3; ++comp) {
+      double v = 0.0;
+      for (int i = 0; i < 8; ++i) v += c_bhat[i * 81 + 3 * a + comp] * pl[i];
+      vscatter1(L, s, comp, v, uo);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P, const double* __restrict__ p,
+                                                      double* __restrict__ po) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= L.ncell) return;
+  const double h = cell_h(L, c);
+  const double s = h * h * h / L.mu_d[c];
+  double pl[8];
+  for (int i = 0; i < 8; ++i) pl[i] = pgather(P, P.pslots[8 * c + i], p);
+  for (int i = 0; i < 8; ++i) {
+    double v = 0.0;
+    for (int j = 0; j < 8; ++j) v += c_mhat[i * 8 + j] * pl[j];
+    pscatter(P, P.pslots[8 * c + i], s * v, po);
+  }
+}
+
+__global__ void k_p_identity(int64_t nh, const int64_t* __restrict__ nodes, const double* __restrict__ pin,
+                             double* __restrict__ pout) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nh; i += int64_t(gridDim.x) * blockDim.x)
+    pout[nodes[i]] = pin[nodes[i]];
+}
+
+__global__ void k_distribute_u(int64_t nh, const int64_t* __restrict__ nodes, const int64_t* __restrict__ hptr,
+                               const int32_t* __restrict__ hm, const double* __restrict__ hw, double* __restrict__ u) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nh; i += int64_t(gridDim.x) * blockDim.x) {
+    double v0 = 0, v1 = 0, v2 = 0;
+    for (int64_t q = hptr[i]; q < hptr[i + 1]; ++q) {
+      const int64_t m = 3 * int64_t(hm[q]);
+      v0 += hw[q] * u[m], v1 += hw[q] * u[m + 1], v2 += hw[q] * u[m + 2];
+    }
+    const int64_t n = 3 * nodes[i];
+    u[n] = v0, u[n + 1] = v1, u[n + 2] = v2;
+  }
+}
+
+__global__ void k_distribute_p(int64_t nh, const int64_t* __restrict__ nodes, const int64_t* __restrict__ hptr,
+                               const int32_t* __restrict__ hm, const double* __restrict__ hw, double* __restrict__ p) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nh; i += int64_t(gridDim.x) * blockDim.x) {
+    double v = 0;
+    for (int64_t q = hptr[i]; q < hptr[i + 1]; ++q) v += hw[q] * p[hm[q]];
+    p[nodes[i]] = v;
+  }
+}
+
+__global__ void k_zero_nodes(int64_t n, const int64_t* __restrict__ nodes, double* __restrict__ u) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t v = 3 * nodes[i];
+    u[v] = 0, u[v + 1] = 0, u[v + 2] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kCellBlock) void k_rhs(DevLevel L, const double* __restrict__ f,
+                                                    double* __restrict__ b) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= L.ncell) return;
+  const double h = cell_h(L, c);
+  const double h3 = h * h * h;
+  const double w1[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  double U[3][27];
+  for (int z = 0; z < 3; ++z)
+    for (int y = 0; y < 3; ++y)
+      for (int x = 0; x < 3; ++x) {
+        const int q = x + 3 * y + 9 * z;
+        const double w = w1[x] * w1[y] * w1[z] * h3;
+        for (int comp = 0; comp < 3; ++comp) U[comp][q] = w * f[(27 * c + q) * 3 + comp];
+      }
+  for (int comp = 0; comp < 3; ++comp) cellop::interp_all_t<double>(U[comp]);
+  for (int a = 0; a < 27; ++a) {
+    const int32_t s = vslot(L, c, a);
+    if (s == -1) continue;
+    for (int comp = 0; comp < 3; ++comp) vscatter1(L, s, comp, U[comp][a], b);
+  }
+}
+
+}  // namespace
+
+// =================================================================== launchers
+template <>
+const float* mu_of<float>(const DevLevel& L) {
+  return L.mu_f;
+}
+template <>
+const double* mu_of<double>(const DevLevel& L) {
+  return L.mu_d;
+}
+
+template <typename T>
+void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s) {
+  if (L.uniform) {
+    k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
+    k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.n_edge, mu_of<T>(L), x, y);
+    return;
+  }
+  k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
+  if (L.n_reg_cells)
+    k_vmult_general<T, false><<<unsigned((L.n_reg_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.reg_cells, L.n_reg_cells, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
+  if (L.n_hang_cells)
+    k_vmult_general<T, true><<<unsigned((L.n_hang_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.hang_cells, L.n_hang_cells, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+}
+template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t);
+template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t);
+
+void launch_diag(const DevLevel& L, const double* khat, double* d, hipStream_t s) {
+  if (L.uniform) {
+    k_diag_uniform<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L.n_edge, L.mu_d, d);
+    return;
+  }
+  if (L.n_reg_cells)
+    k_diag_regular<<<unsigned((L.n_reg_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.reg_cells, L.n_reg_cells, L.slots, L.clev, L.mu_d, d);
+  if (L.n_hang_cells)
+    k_diag_hanging<<<unsigned(L.n_hang_cells), 64, 0, s>>>(L.hang_cells, L.slots, L.clev, L.mu_d, L.hptr, L.hmaster,
+                                                          L.hw_d, khat, d);
+}
+
+void launch_invert_diag(const DevLevel& L, const double* d, double* md, float* mf, hipStream_t s) {
+  if (L.uniform)
+    k_invert_diag_uniform<<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, d, md, mf);
+  else
+    k_invert_diag_general<<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, d, md, mf);
+}
+
+template <typename T>
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
+  k_cheb_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, r, d, x, T(it));
+}
+template <typename T>
+void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
+  k_cheb_init<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, r, d, x, T(it));
+}
+template <typename T>
+void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
+                      hipStream_t s) {
+  k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta));
+}
+#define MFGMG_INST_CHEB(T)                                                                                   \
+  template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t);          \
+  template void launch_cheb_init<T>(int64_t, const T*, const T*, const T*, T*, T*, T*, double, hipStream_t); \
+  template void launch_cheb_step<T>(int64_t, const T*, const T*, T*, T*, T*, double, double, hipStream_t);
+MFGMG_INST_CHEB(float)
+MFGMG_INST_CHEB(double)
+
+template <typename T>
+void launch_prolong(int64_t nf, const int64_t* ptr, const int32_t* col, const float* w, const T* xc, T* xf, bool add,
+                    hipStream_t s) {
+  k_prolong<T><<<grid_for(nf), kBlock, 0, s>>>(nf, ptr, col, w, xc, xf, add);
+}
+template <typename T>
+void launch_restrict(int64_t nc, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
+                     T* xc, hipStream_t s) {
+  k_restrict<T><<<grid_for(nc), kBlock, 0, s>>>(nc, ptr, col, w, b, t, xc);
+}
+template void launch_prolong<float>(int64_t, const int64_t*, const int32_t*, const float*, const float*, float*, bool,
+                                    hipStream_t);
+template void launch_prolong<double>(int64_t, const int64_t*, const int32_t*, const float*, const double*, double*,
+                                     bool, hipStream_t);
+template void launch_restrict<float>(int64_t, const int64_t*, const int32_t*, const float*, const float*,
+                                     const float*, float*, hipStream_t);
+template void launch_restrict<double>(int64_t, const int64_t*, const int32_t*, const float*, const double*,
+                                      const double*, double*, hipStream_t);
+
+template <typename T>
+void launch_coarse(const T* Ainv, const int32_t* fd, int nfree, int n, const T* b, T* x, hipStream_t s) {
+  k_coarse<T><<<1, 128, 0, s>>>(Ainv, fd, nfree, n, b, x);
+}
+template void launch_coarse<float>(const float*, const int32_t*, int, int, const float*, float*, hipStream_t);
+template void launch_coarse<double>(const double*, const int32_t*, int, int, const double*, double*, hipStream_t);
+
+void launch_harmonic_mu(int64_t ncell, const double* mq, double* mu, hipStream_t s) {
+  k_harmonic<<<grid_for(ncell), kBlock, 0, s>>>(ncell, mq, mu);
+}
+void launch_restrict_mu(int64_t ncell, const int32_t* src, const double* mf, double* mc, hipStream_t s) {
+  k_restrict_mu<<<grid_for(ncell), kBlock, 0, s>>>(ncell, src, mf, mc);
+}
+void launch_to_float(int64_t n, const double* a, float* b, hipStream_t s) {
+  k_to_float<<<grid_for(n), kBlock, 0, s>>>(n, a, b);
+}
+void launch_to_double(int64_t n, const float* a, double* b, hipStream_t s) {
+  k_to_double<<<grid_for(n), kBlock, 0, s>>>(n, a, b);
+}
+
+void launch_dot(int64_t n, const double* a, const double* b, double* part, double* result, hipStream_t s) {
+  k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, a, b, part);
+  k_sum_partials<<<1, kBlock, 0, s>>>(kRedBlocks, part, result);
+}
+
+void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part, double* result,
+                 hipStream_t s) {
+  const int nb = 256;
+  k_mdot_partial<<<dim3(nb, unsigned(nv)), kBlock, 0, s>>>(n, nv, V, ldv, w, part);
+  k_sum_partials<<<unsigned(nv), kBlock, 0, s>>>(nb, part, result);
+}
+
+void launch_mupdate(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s) {
+  k_mupdate<<<grid_for(n), kBlock, 0, s>>>(n, nv, V, ldv, h, w);
+}
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  k_axpby<<<grid_for(n), kBlock, 0, s>>>(n, a, x, b, y);
+}
+void launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  k_scale_copy<<<grid_for(n), kBlock, 0, s>>>(n, a, x, y);
+}
+void launch_fill(int64_t n, double v, double* y, hipStream_t s) { k_fill<<<grid_for(n), kBlock, 0, s>>>(n, v, y); }
+void launch_fill_f(int64_t n, float v, float* y, hipStream_t s) {
+  k_fill_f<<<grid_for(n), kBlock, 0, s>>>(n, v, y);
+}
+void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStream_t s) {
+  k_mul<<<grid_for(n), kBlock, 0, s>>>(n, a, b, y);
+}
+
+void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* po, hipStream_t s) {
+  k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
+  k_div<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, u, po);
+}
+void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
+  k_grad_add<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, uo);
+}
+void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s) {
+  k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
+  k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, po);
+  if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, p, po);
+}
+void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hipStream_t s) {
+  if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, pin, pout);
+}
+void launch_distribute_u(const DevLevel& L, double* u, hipStream_t s) {
+  if (L.nhang) k_distribute_u<<<grid_for(L.nhang), kBlock, 0, s>>>(L.nhang, L.hnode, L.hptr, L.hmaster, L.hw_d, u);
+}
+void launch_distribute_p(const DevPressure& P, double* p, hipStream_t s) {
+  if (P.nh) k_distribute_p<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, P.hptr, P.hmaster, P.hw, p);
+}
+void launch_zero_constrained(const DevLevel& L, double* u, hipStream_t s) {
+  if (L.n_cons) k_zero_nodes<<<grid_for(L.n_cons), kBlock, 0, s>>>(L.n_cons, L.cons_nodes, u);
+}
+void launch_rhs(const DevLevel& L, const double* f, double* b, hipStream_t s) {
+  k_fill<<<grid_for(3 * L.nnode), kBlock, 0, s>>>(3 * L.nnode, 0.0, b);
+  k_rhs<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, f, b);
+}
+
+void set_element_constants(const double* kd, const double* bh, const double* mh) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_khat_diag), kd, sizeof(double) * 81);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_bhat), bh, sizeof(double) * 8 * 81);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_mhat), mh, sizeof(double) * 64);
+}
+
+}  // namespace mfgmg

@@ -1,0 +1,319 @@
+"""Python binding of libmfgmg.so (ctypes): argument marshalling only.
+
+Every call forwards to the C ABI declared in include/mfgmg.h; all arithmetic
+of the solver runs in the library's HIP kernels.  Device arrays are torch
+tensors on the current HIP device (any object with ``data_ptr()``, ``dtype``
+and ``numel()``); host arrays are numpy arrays.  The library must have been
+built (``python -m paper_1907_06696_amd.build``); loading fails loudly
+otherwise -- there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfgmg.so")
+
+FP32, FP64 = 0, 1
+MAX_LEVELS = 14
+
+OK, ERR_INVALID, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_MESH = 0, -1, -2, -3, -4, -5, -6
+
+# exported names, in the order of include/mfgmg.h
+EXPORTS = [
+    "mfgmg_create", "mfgmg_refine", "mfgmg_finalize_mesh", "mfgmg_info", "mfgmg_cells",
+    "mfgmg_support_points", "mfgmg_node_types", "mfgmg_constraints", "mfgmg_transfer",
+    "mfgmg_leaf_quadrature_points", "mfgmg_set_viscosity", "mfgmg_cell_viscosity",
+    "mfgmg_smoother_lambda", "mfgmg_inverse_diagonal", "mfgmg_vmult", "mfgmg_vcycle",
+    "mfgmg_prolongate", "mfgmg_restrict", "mfgmg_smooth", "mfgmg_coarse_solve",
+    "mfgmg_assemble_rhs", "mfgmg_apply_div", "mfgmg_apply_grad", "mfgmg_apply_pmass",
+    "mfgmg_default_opts", "mfgmg_solve_stokes", "mfgmg_last_error", "mfgmg_destroy",
+]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("unit_exponent", C.c_int32),
+                ("n_cells", C.c_int64 * (MAX_LEVELS + 1)), ("n_nodes", C.c_int64 * (MAX_LEVELS + 1)),
+                ("n_u", C.c_int64 * (MAX_LEVELS + 1)), ("n_free", C.c_int64 * (MAX_LEVELS + 1)),
+                ("n_hanging", C.c_int64 * (MAX_LEVELS + 1)), ("uniform", C.c_int32 * (MAX_LEVELS + 1)),
+                ("n_p", C.c_int64), ("n_p_hanging", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("vcycle_prec", C.c_int32), ("schur_rtol", C.c_double), ("schur_max_iter", C.c_int32),
+                ("use_scaling", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("vcycles", C.c_int32), ("inner_cg_iterations", C.c_int64),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmfgmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1907_06696_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+    sig = {
+        "mfgmg_create": [i32, C.POINTER(vp)],
+        "mfgmg_refine": [vp, vp, i64, i32],
+        "mfgmg_finalize_mesh": [vp],
+        "mfgmg_info": [vp, C.POINTER(Info)],
+        "mfgmg_cells": [vp, i32, vp],
+        "mfgmg_support_points": [vp, i32, i32, vp],
+        "mfgmg_node_types": [vp, i32, i32, vp],
+        "mfgmg_constraints": [vp, i32, i32, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, vp],
+        "mfgmg_transfer": [vp, i32, C.POINTER(i64), vp, vp, vp],
+        "mfgmg_leaf_quadrature_points": [vp, vp],
+        "mfgmg_set_viscosity": [vp, vp, vp],
+        "mfgmg_cell_viscosity": [vp, i32, vp],
+        "mfgmg_smoother_lambda": [vp, i32, C.POINTER(C.c_double)],
+        "mfgmg_inverse_diagonal": [vp, i32, i32, vp, vp],
+        "mfgmg_vmult": [vp, i32, i32, vp, vp, vp],
+        "mfgmg_vcycle": [vp, i32, vp, vp, vp],
+        "mfgmg_prolongate": [vp, i32, i32, vp, vp, vp],
+        "mfgmg_restrict": [vp, i32, i32, vp, vp, vp],
+        "mfgmg_smooth": [vp, i32, i32, vp, vp, i32, vp],
+        "mfgmg_coarse_solve": [vp, i32, vp, vp, vp],
+        "mfgmg_assemble_rhs": [vp, vp, vp, vp],
+        "mfgmg_apply_div": [vp, vp, vp, vp],
+        "mfgmg_apply_grad": [vp, vp, vp, vp],
+        "mfgmg_apply_pmass": [vp, vp, vp, vp],
+        "mfgmg_default_opts": [C.POINTER(SolveOpts)],
+        "mfgmg_solve_stokes": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp],
+        "mfgmg_last_error": [vp],
+        "mfgmg_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.mfgmg_last_error.restype = C.c_char_p
+    lib.mfgmg_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+class MFGMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mfgmg error {code}: {msg}")
+        self.code = code
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _dev_ptr(t):
+    return C.c_void_p(int(t.data_ptr()))
+
+
+def _prec_of(t):
+    name = str(t.dtype)
+    if name.endswith("float64"):
+        return FP64
+    if name.endswith("float32"):
+        return FP32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (0 if torch is unavailable)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(0)
+
+
+class Solver:
+    """Owns one mfgmg context (mesh, level hierarchy, device data)."""
+
+    def __init__(self, base_level):
+        self.lib = load()
+        h = C.c_void_p()
+        self._check(self.lib.mfgmg_create(int(base_level), C.byref(h)), None)
+        self.h = h
+        self._info = None
+
+    def _check(self, code, h="self"):
+        if code != OK:
+            hh = self.h if h == "self" else None
+            msg = self.lib.mfgmg_last_error(hh)
+            raise MFGMGError(code, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mfgmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- mesh
+    def refine(self, cells, levels_up):
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 4)
+        self._check(self.lib.mfgmg_refine(self.h, _np_ptr(cells), len(cells), int(levels_up)))
+
+    def finalize_mesh(self):
+        self._check(self.lib.mfgmg_finalize_mesh(self.h))
+        self._info = None
+
+    def info(self):
+        if self._info is None:
+            inf = Info()
+            self._check(self.lib.mfgmg_info(self.h, C.byref(inf)))
+            L = inf.n_levels
+            self._info = {
+                "L": L, "U": inf.unit_exponent,
+                "n_cells": [int(inf.n_cells[l]) for l in range(L + 1)],
+                "n_nodes": [int(inf.n_nodes[l]) for l in range(L + 1)],
+                "n_u": [int(inf.n_u[l]) for l in range(L + 1)],
+                "n_free": [int(inf.n_free[l]) for l in range(L + 1)],
+                "n_hanging": [int(inf.n_hanging[l]) for l in range(L + 1)],
+                "uniform": [bool(inf.uniform[l]) for l in range(L + 1)],
+                "n_p": int(inf.n_p), "n_p_hanging": int(inf.n_p_hanging),
+            }
+        return self._info
+
+    def cells(self, level):
+        L = self.info()["L"]
+        n = self.info()["n_cells"][level] if 1 <= level <= L else 1   # the library rejects bad levels
+        out = np.empty((n, 4), dtype=np.int32)
+        self._check(self.lib.mfgmg_cells(self.h, level, _np_ptr(out)))
+        return out
+
+    def support_points(self, level, field=0):
+        n = self.info()["n_nodes"][level] if field == 0 else self.info()["n_p"]
+        out = np.empty(n, dtype=np.int64)
+        self._check(self.lib.mfgmg_support_points(self.h, level, field, _np_ptr(out)))
+        return out
+
+    def node_types(self, level, field=0):
+        n = self.info()["n_nodes"][level] if field == 0 else self.info()["n_p"]
+        out = np.empty(n, dtype=np.uint8)
+        self._check(self.lib.mfgmg_node_types(self.h, level, field, _np_ptr(out)))
+        return out
+
+    def constraints(self, level, field=0):
+        nh, nnz = C.c_int64(), C.c_int64()
+        self._check(self.lib.mfgmg_constraints(self.h, level, field, C.byref(nh), C.byref(nnz),
+                                               None, None, None, None))
+        node = np.empty(nh.value, np.int64)
+        ptr = np.empty(nh.value + 1, np.int64)
+        master = np.empty(nnz.value, np.int64)
+        w = np.empty(nnz.value, np.float64)
+        self._check(self.lib.mfgmg_constraints(self.h, level, field, C.byref(nh), C.byref(nnz), _np_ptr(node),
+                                               _np_ptr(ptr), _np_ptr(master), _np_ptr(w)))
+        return node, ptr, master, w
+
+    def transfer(self, level):
+        nnz = C.c_int64()
+        self._check(self.lib.mfgmg_transfer(self.h, level, C.byref(nnz), None, None, None))
+        ptr = np.empty(self.info()["n_nodes"][level] + 1, np.int64)
+        col = np.empty(nnz.value, np.int64)
+        w = np.empty(nnz.value, np.float64)
+        self._check(self.lib.mfgmg_transfer(self.h, level, C.byref(nnz), _np_ptr(ptr), _np_ptr(col), _np_ptr(w)))
+        return ptr, col, w
+
+    def leaf_quadrature_points(self):
+        L = self.info()["L"]
+        out = np.empty((self.info()["n_cells"][L], 27, 3), dtype=np.float64)
+        self._check(self.lib.mfgmg_leaf_quadrature_points(self.h, _np_ptr(out)))
+        return out
+
+    # ------------------------------------------------------------- device
+    def set_viscosity(self, mu_qp, stream=None):
+        mu_qp = np.ascontiguousarray(mu_qp, dtype=np.float64)
+        L = self.info()["L"]
+        if mu_qp.size != 27 * self.info()["n_cells"][L]:
+            raise ValueError("mu_qp must have 27 values per leaf cell")
+        self._check(self.lib.mfgmg_set_viscosity(self.h, _np_ptr(mu_qp), stream or current_stream()))
+
+    def cell_viscosity(self, level):
+        out = np.empty(self.info()["n_cells"][level], np.float64)
+        self._check(self.lib.mfgmg_cell_viscosity(self.h, level, _np_ptr(out)))
+        return out
+
+    def smoother_lambda(self, level):
+        v = C.c_double()
+        self._check(self.lib.mfgmg_smoother_lambda(self.h, level, C.byref(v)))
+        return v.value
+
+    def inverse_diagonal(self, level, dst, stream=None):
+        self._check(self.lib.mfgmg_inverse_diagonal(self.h, level, _prec_of(dst), _dev_ptr(dst),
+                                                    stream or current_stream()))
+
+    def vmult(self, level, src, dst, stream=None):
+        p = _prec_of(src)
+        n = self.info()["n_u"][level]
+        if _prec_of(dst) != p or src.numel() != n or dst.numel() != n:
+            raise ValueError("vmult: src/dst must have n_u[level] entries of one dtype")
+        self._check(self.lib.mfgmg_vmult(self.h, level, p, _dev_ptr(src), _dev_ptr(dst),
+                                         stream or current_stream()))
+
+    def vcycle(self, rhs, x, stream=None):
+        p = _prec_of(rhs)
+        n = self.info()["n_u"][self.info()["L"]]
+        if _prec_of(x) != p or rhs.numel() != n or x.numel() != n:
+            raise ValueError("vcycle: rhs/x must have n_u[L] entries of one dtype")
+        self._check(self.lib.mfgmg_vcycle(self.h, p, _dev_ptr(rhs), _dev_ptr(x), stream or current_stream()))
+
+    def prolongate(self, level, coarse, fine, stream=None):
+        self._check(self.lib.mfgmg_prolongate(self.h, level, _prec_of(coarse), _dev_ptr(coarse), _dev_ptr(fine),
+                                              stream or current_stream()))
+
+    def restrict(self, level, fine, coarse, stream=None):
+        self._check(self.lib.mfgmg_restrict(self.h, level, _prec_of(fine), _dev_ptr(fine), _dev_ptr(coarse),
+                                            stream or current_stream()))
+
+    def smooth(self, level, b, x, x_is_zero=False, stream=None):
+        self._check(self.lib.mfgmg_smooth(self.h, level, _prec_of(b), _dev_ptr(b), _dev_ptr(x), int(x_is_zero),
+                                          stream or current_stream()))
+
+    def coarse_solve(self, b, x, stream=None):
+        self._check(self.lib.mfgmg_coarse_solve(self.h, _prec_of(b), _dev_ptr(b), _dev_ptr(x),
+                                                stream or current_stream()))
+
+    def assemble_rhs(self, f_qp, rhs, stream=None):
+        f_qp = np.ascontiguousarray(f_qp, dtype=np.float64)
+        self._check(self.lib.mfgmg_assemble_rhs(self.h, _np_ptr(f_qp), _dev_ptr(rhs), stream or current_stream()))
+
+    def apply_div(self, u, p_out, stream=None):
+        self._check(self.lib.mfgmg_apply_div(self.h, _dev_ptr(u), _dev_ptr(p_out), stream or current_stream()))
+
+    def apply_grad(self, p, u_out, stream=None):
+        self._check(self.lib.mfgmg_apply_grad(self.h, _dev_ptr(p), _dev_ptr(u_out), stream or current_stream()))
+
+    def apply_pmass(self, p, p_out, stream=None):
+        self._check(self.lib.mfgmg_apply_pmass(self.h, _dev_ptr(p), _dev_ptr(p_out), stream or current_stream()))
+
+    def solve_stokes(self, rhs_u, u_out, p_out, rhs_p=None, stream=None, raise_on_noconv=True, **opts):
+        o = SolveOpts()
+        self.lib.mfgmg_default_opts(C.byref(o))
+        for k, v in opts.items():
+            if k == "vcycle_prec" and isinstance(v, str):
+                v = FP32 if v.lower() == "fp32" else FP64
+            setattr(o, k, v)
+        st = SolveStats()
+        code = self.lib.mfgmg_solve_stokes(self.h, _dev_ptr(rhs_u), _dev_ptr(rhs_p) if rhs_p is not None else None,
+                                           _dev_ptr(u_out), _dev_ptr(p_out), C.byref(o), C.byref(st),
+                                           stream or current_stream())
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+        if code != OK and not (code == ERR_NOCONV and not raise_on_noconv):
+            self._check(code)
+        return stats

@@ -1,0 +1,190 @@
+"""Device parity: every kernel of the path against the CPU FP64 oracle on the
+same seeded inputs, element by element.
+
+Tolerances (relative 2-norm unless stated): operator FP64 1e-12, FP32 1e-5
+(the FP32 input rounded once, oracle applied to the rounded input in FP64);
+V-cycle FP64 1e-11 (eight operator applications, transfers and the coarse
+solve per level compound round-off), FP32 1e-4; integer/structural data
+bit-exact."""
+import numpy as np
+import pytest
+
+from oracle import multigrid as omg, operators as ops
+from paper_1907_06696_amd import inputs
+from tests.parity_cases import Case, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+CASES = {
+    "uniform2": dict(base=2),
+    "uniform3": dict(base=3, dr=1e4, sinkers=8, seed=2),
+    "adaptive2+1": dict(base=2, corners=((1, 1, 1),), times=1),
+    "adaptive2+2": dict(base=2, corners=((0, 1, 0),), times=2, dr=1e6),
+    "adaptive3+2": dict(base=3, corners=((2, 5, 3), (0, 0, 0), (7, 7, 7)), times=2, dr=1e4, sinkers=6, seed=5),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    _need_gpu()
+    c = Case(**CASES[request.param])
+    print(f"\n[case {request.param}] L={c.L} cells={c.info['n_cells'][c.L]} n_u={c.info['n_u'][c.L]} "
+          f"hanging={c.info['n_hanging'][c.L]}", flush=True)
+    c.s.set_viscosity(c.mu_qp_lib)
+    c.gmg = omg.GMG(c.H, c.mus)
+    yield c
+    c.close()
+
+
+def test_cell_viscosity(case):
+    for ell in range(1, case.L + 1):
+        mu = case.s.cell_viscosity(ell)
+        ref = case.mus[ell][case.cell_perm(ell)]
+        assert np.abs(mu - ref).max() <= 1e-13 * ref.max()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_vmult_fp64_fp32(case, seed):
+    for ell in range(1, case.L + 1):
+        n = case.info["n_u"][ell]
+        x_or = inputs.uniform_vector(n, 100 + seed + ell)
+        perm = case.dof_perm(ell)
+        x_lib = x_or[perm]
+        A = case.gmg.A[ell]
+        # FP64
+        y = torch.empty(n, dtype=torch.float64, device=DEV)
+        case.s.vmult(ell, to_dev(x_lib), y)
+        ref = (A @ x_or)[perm]
+        e64 = rel_err(to_host(y), ref)
+        assert e64 <= 1e-12, (ell, e64)
+        # FP32: oracle applied to the rounded input
+        x32 = x_lib.astype(np.float32)
+        y32 = torch.empty(n, dtype=torch.float32, device=DEV)
+        case.s.vmult(ell, to_dev(x32, torch.float32), y32)
+        x32_or = np.empty(n)
+        x32_or[perm] = x32.astype(np.float64)
+        ref32 = (A @ x32_or)[perm]
+        e32 = rel_err(to_host(y32), ref32)
+        assert e32 <= 1e-5, (ell, e32)
+
+
+def test_vmult_zero_and_linearity(case):
+    ell = case.L
+    n = case.info["n_u"][ell]
+    z = torch.zeros(n, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(z)
+    case.s.vmult(ell, z, y)
+    assert float(y.abs().max()) == 0.0
+    a = to_dev(inputs.uniform_vector(n, 7))
+    b = to_dev(inputs.uniform_vector(n, 8))
+    ya, yb, yab = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    case.s.vmult(ell, a, ya)
+    case.s.vmult(ell, b, yb)
+    case.s.vmult(ell, 2 * a - b, yab)
+    assert rel_err(to_host(yab), to_host(2 * ya - yb)) < 1e-13
+
+
+def test_inverse_diagonal_and_lambda(case):
+    for ell in range(1, case.L + 1):
+        n = case.info["n_u"][ell]
+        d = torch.empty(n, dtype=torch.float64, device=DEV)
+        case.s.inverse_diagonal(ell, d)
+        ref = case.gmg.minv[ell][case.dof_perm(ell)]
+        assert np.abs(to_host(d) - ref).max() <= 1e-12 * np.abs(ref).max()
+        if ell >= 2:
+            lam = case.s.smoother_lambda(ell)
+            assert abs(lam - case.gmg.lam[ell]) <= 1e-9 * case.gmg.lam[ell], (ell, lam, case.gmg.lam[ell])
+
+
+def test_transfers(case):
+    for ell in range(2, case.L + 1):
+        nf, nc = case.info["n_u"][ell], case.info["n_u"][ell - 1]
+        pf, pc = case.dof_perm(ell), case.dof_perm(ell - 1)
+        P = case.gmg.P[ell]
+        xc = inputs.uniform_vector(nc, 11 + ell)
+        xf = torch.empty(nf, dtype=torch.float64, device=DEV)
+        case.s.prolongate(ell, to_dev(xc[pc]), xf)
+        assert rel_err(to_host(xf), (P @ xc)[pf]) <= 1e-14
+        rf = inputs.uniform_vector(nf, 21 + ell)
+        rc = torch.empty(nc, dtype=torch.float64, device=DEV)
+        case.s.restrict(ell, to_dev(rf[pf]), rc)
+        assert rel_err(to_host(rc), (P.T @ rf)[pc]) <= 1e-14
+
+
+def test_smoother_and_coarse(case):
+    ell = case.L
+    n = case.info["n_u"][ell]
+    perm = case.dof_perm(ell)
+    free = case.gmg.free[ell]
+    b = inputs.uniform_vector(n, 31) * free
+    x0 = inputs.uniform_vector(n, 32) * free
+    A = case.gmg.A[ell]
+    for zero in (True, False):
+        ref = omg.chebyshev(lambda v: A @ v, case.gmg.minv[ell], b, None if zero else x0,
+                            case.gmg.lam[ell], x_is_zero=zero)
+        x = to_dev(x0[perm])
+        case.s.smooth(ell, to_dev(b[perm]), x, x_is_zero=zero)
+        assert rel_err(to_host(x), ref[perm]) <= 1e-12
+    b1 = inputs.uniform_vector(375, 33) * case.gmg.free[1]
+    x1 = torch.empty(375, dtype=torch.float64, device=DEV)
+    p1 = case.dof_perm(1)
+    case.s.coarse_solve(to_dev(b1[p1]), x1)
+    assert rel_err(to_host(x1), case.gmg.coarse_solve(b1)[p1]) <= 1e-12
+
+
+def test_vcycle_fp64_fp32(case):
+    ell = case.L
+    n = case.info["n_u"][ell]
+    perm = case.dof_perm(ell)
+    b = inputs.uniform_vector(n, 41) * case.gmg.free[ell]
+    ref = case.gmg.vcycle(b)[perm]
+    x = torch.empty(n, dtype=torch.float64, device=DEV)
+    case.s.vcycle(to_dev(b[perm]), x)
+    e64 = rel_err(to_host(x), ref)
+    assert e64 <= 1e-11, e64
+    x32 = torch.empty(n, dtype=torch.float32, device=DEV)
+    case.s.vcycle(to_dev(b[perm], torch.float32), x32)
+    e32 = rel_err(to_host(x32), ref)
+    assert e32 <= 1e-4, e32
+
+
+def test_pressure_operators_and_rhs(case):
+    lf = case.H.leaf
+    L = case.L
+    nu, npp = case.info["n_u"][L], case.info["n_p"]
+    pu, pp = case.dof_perm(L), case.pnode_perm()
+    B = ops.assemble_B(lf)
+    Mp = ops.assemble_Mp(lf, case.mus[L])
+    u = inputs.uniform_vector(nu, 51) * lf.free_dofs_mask()
+    p = inputs.uniform_vector(npp, 52) * lf.pfree
+    out_p = torch.empty(npp, dtype=torch.float64, device=DEV)
+    case.s.apply_div(to_dev(u[pu]), out_p)
+    assert rel_err(to_host(out_p), (B @ u)[pp]) <= 1e-12
+    out_u = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.apply_grad(to_dev(p[pp]), out_u)
+    assert rel_err(to_host(out_u), (B.T @ p)[pu]) <= 1e-12
+    pin = inputs.uniform_vector(npp, 53)
+    case.s.apply_pmass(to_dev(pin[pp]), out_p)
+    assert rel_err(to_host(out_p), (Mp @ pin)[pp]) <= 1e-12
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.assemble_rhs(case.f_qp_lib, rhs)
+    ref = ops.assemble_rhs(lf, case.f_qp_or)
+    assert rel_err(to_host(rhs), ref[pu]) <= 1e-12
