@@ -1,0 +1,195 @@
+"""Benchmark: matrix-free Q2 viscous operator (vmult) throughput on one MI355X.
+
+Workload (the 64^3 sinker configuration): unit cube, 64^3 uniform cells,
+Q2 velocity (6,440,067 dofs), 8 seeded sinkers (centre seed 2), viscosity
+contrast 1e4, operator applied to a seeded uniform[-1, 1] vector (seed 42).
+One step = 100 FP32 operator applications (the configuration's 100
+repetitions); `value` = velocity dofs processed per second over the timed
+steps, in GDoF/s.  Also reported beside it (not part of `value`): the FP64
+operator, one FP32/FP64 V-cycle, and the Stokes solve to 1e-8 with the FP32
+and the FP64 V-cycle inside FP64 FGMRES.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+REPS = 100                      # operator applications per step
+PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (packed FMA), published
+PEAK_HBM_GBS = 8000.0
+# Algorithmic work of the cell kernel per cell (sum factorisation as built,
+# counting an FMA as 2 flops): 810 (interpolation) + 972 (gradients) + 297
+# (stress) + 1215 (transposed gradients) + 729 (transposed interpolation)
+FLOP_PER_CELL = 4023
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-solve", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
+    return p.parse_args()
+
+
+def cpu_baseline(level, centres, dr, seconds=12.0):
+    """The CPU oracle's cellwise FP64 operator on the same workload: applied
+    repeatedly to the same vector until about `seconds` have elapsed."""
+    from oracle import mesh as om, operators as ops
+    from paper_1907_06696_amd import inputs
+    lev, ijk = om.uniform_leaves(level)
+    m = om.LevelMesh(lev, ijk, level + 1)
+    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
+    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, centres, dr).reshape(-1, 27))
+    A = ops.CellwiseA(m, mu)
+    x = inputs.uniform_vector(m.n_u, 42)
+    A.matvec(x)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < seconds or reps < 2:
+        A.matvec(x)
+        reps += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": m.n_u * reps / dt / 1e9, "unit": "GDoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} FP64 applications of the oracle's cellwise operator (numpy BLAS, "
+                      f"{threads} threads) on the full {1 << level}^3 mesh, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1907_06696_amd import inputs, mfgmg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = inputs.CONFIGS["c2_uniform64"]
+    level = args.level
+    centres = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
+    dr = cfg["dr"]
+
+    t_setup = time.perf_counter()
+    s = mfgmg.Solver(level)
+    s.finalize_mesh()
+    info = s.info()
+    L = info["L"]
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    mu_qp = inputs.sinker_mu(qp, centres, dr).reshape(-1, 27)
+    t_mesh = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    s.set_viscosity(mu_qp)
+    torch.cuda.synchronize()
+    t_assemble = time.perf_counter() - t0
+    n = info["n_u"][L]
+    ncell = info["n_cells"][L]
+    x64 = torch.tensor(inputs.uniform_vector(n, cfg["vector_seed"]), dtype=torch.float64, device=dev)
+    x32 = x64.float()
+    y32 = torch.empty_like(x32)
+    y64 = torch.empty_like(x64)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    def step32():
+        for _ in range(REPS):
+            s.vmult(L, x32, y32)
+
+    def step64():
+        for _ in range(REPS):
+            s.vmult(L, x64, y64)
+
+    def cells32():
+        for _ in range(REPS):
+            s.vmult_add(L, x32, y32)
+
+    # the timed region: K steps of 100 FP32 operator applications
+    t32 = timed(step32, args.steps, args.warmup)
+    ms_per_step = t32 / args.steps * 1e3
+    value = n * REPS * args.steps / t32 / 1e9
+    t64 = timed(step64, max(2, args.steps // 4), 1)
+    gdofs64 = n * REPS * max(2, args.steps // 4) / t64 / 1e9
+    tk = timed(cells32, max(2, args.steps // 4), 1)
+    kernel_s = tk / (REPS * max(2, args.steps // 4))
+    flops = FLOP_PER_CELL * ncell
+    alg_bytes = 2 * 4 * n + 4 * ncell        # read x, write y, cell viscosity (FP32)
+    achieved_tflops = flops / kernel_s / 1e12
+    vmult_call_s = t32 / (REPS * args.steps)
+
+    # V-cycles
+    vc = {}
+    for name, xx in (("fp32", x32), ("fp64", x64)):
+        out = torch.empty_like(xx)
+        tv = timed(lambda: s.vcycle(xx, out), 10, 2)
+        vc[name] = tv / 10 * 1e3
+
+    result = {
+        "metric": "Q2 viscous vmult GDoF/s",
+        "value": round(value, 3),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sinker {1 << level}^3 uniform Q2 vmult, 8 sinkers, DR 1e4",
+                   "cells": ncell, "velocity_dofs": n, "reps_per_step": REPS},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_vmult_uniform<float>", "kernel_us": round(kernel_s * 1e6, 2),
+                     "flop_per_launch": flops, "alg_bytes_per_launch": alg_bytes,
+                     "hbm_frac_algorithmic": round(alg_bytes / kernel_s / 1e9 / PEAK_HBM_GBS, 4)},
+        "vmult_fp64_gdofs": round(gdofs64, 3),
+        "vmult_call_us_fp32": round(vmult_call_s * 1e6, 2),
+        "vcycle_ms": {k: round(v, 3) for k, v in vc.items()},
+        "setup_s": {"mesh": round(t_mesh, 2), "assemble": round(t_assemble, 2)},
+    }
+
+    if not args.no_solve:
+        f_qp = inputs.sinker_force(qp, centres).reshape(-1, 27, 3)
+        rhs = torch.empty(n, dtype=torch.float64, device=dev)
+        s.assemble_rhs(f_qp, rhs)
+        u = torch.empty(n, dtype=torch.float64, device=dev)
+        p = torch.empty(info["n_p"], dtype=torch.float64, device=dev)
+        solve = {}
+        for prec in ("fp32", "fp64"):
+            st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, raise_on_noconv=False)
+            solve[prec] = {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
+                           "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
+                           "converged": bool(st["converged"])}
+        result["stokes_solve_1e-8"] = solve
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(level, centres, dr)
+    s.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,14 @@ int mfgmg_inverse_diagonal(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, void*
 int mfgmg_vmult(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src_dev, void* dst_dev,
                 void* stream);
 
+/* dst += (cell contributions of A_level) src: the same cell loop as
+ * mfgmg_vmult but without initialising dst and without the identity rows of
+ * constrained dofs (their entries of dst are left unchanged).  One kernel
+ * launch per call on uniform levels; used to accumulate and to time the cell
+ * loop alone.  Async. */
+int mfgmg_vmult_add(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src_dev, void* dst_dev,
+                    void* stream);
+
 /* x = V(b): one V(1,1)-cycle on the leaf level (Sec. 2.2.1) with degree-4
  * Chebyshev smoothing (Saad, Alg. 12.1) preconditioned by the (scaled)
  * inverse diagonal, global-coarsening transfers, exact coarse solve.

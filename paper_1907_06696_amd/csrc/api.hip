@@ -793,6 +793,21 @@ int mfgmg_vmult(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src,
   return MFGMG_OK;
 }
 
+int mfgmg_vmult_add(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* src, void* dst, void* stream) {
+  int st = check_level(ctx, level);
+  if (st) return st;
+  if (!src || !dst || src == dst || (prec != MFGMG_FP32 && prec != MFGMG_FP64)) return MFGMG_ERR_INVALID;
+  if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLevel& v = ctx->lv[size_t(level)].v;
+  if (prec == MFGMG_FP64)
+    launch_vmult<double>(v, static_cast<const double*>(src), static_cast<double*>(dst), s, false);
+  else
+    launch_vmult<float>(v, static_cast<const float*>(src), static_cast<float*>(dst), s, false);
+  HIPCHK(hipGetLastError());
+  return MFGMG_OK;
+}
+
 int mfgmg_vcycle(mfgmg_ctx* ctx, mfgmg_prec prec, const void* rhs, void* x, void* stream) {
   if (!ctx || !rhs || !x || rhs == x) return MFGMG_ERR_INVALID;
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");

@@ -1,0 +1,162 @@
+// Brick kernel for the Q2 strain-rate operator on uniform levels (device code).
+//
+// One workgroup per brick of BX x BY x BZ cells, one thread per cell; n <= 256
+// cells per edge.  Node-major vectors (3 values per node), lattice numbering
+// node = X + (2n+1)(Y + (2n+1)Z).
+//  1. Stage the brick's node box ((2B+1) nodes per axis) in LDS.  One wave per
+//     node row: lane j holds word j of the row (3 components x (2BX+1) nodes),
+//     so the per-element index work is a few scalar operations; every global
+//     load of a thread is issued before its LDS stores.  Dirichlet nodes are
+//     staged as zero.  LDS layout per component: z-planes of rows of length
+//     24, every axis split into its even then odd local nodes, so that for a
+//     fixed local node the cells of a row read consecutive words (the padded
+//     row keeps a wavefront's 8x4 cells on distinct banks).
+//  2. Each thread gathers its 81 values and applies the cell operator.
+//  3. Accumulate the 81 results into the zeroed LDS box without atomics: the
+//     local nodes are split into classes a in {0,1} | {2} per axis.  Within a
+//     class two (cell, local node) pairs never map to the same node, so a
+//     read-add-write over the class is race free.  Classes along z couple
+//     different waves and are separated by block barriers; classes along x
+//     and y couple lanes of one wave, whose LDS operations complete in
+//     order, and are separated by an LDS wait and a compiler barrier.
+//  4. Write back row by row: nodes inside the brick belong to it alone (plain
+//     store), nodes on its faces are shared with neighbouring bricks (global
+//     atomic add into the initialised output), Dirichlet nodes are skipped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cell_kernel.h"
+
+namespace mfgmg {
+namespace brick {
+
+template <int B>
+__device__ __forceinline__ int split_index(int l) {
+  return (l & 1) ? (B + 1) + (l >> 1) : (l >> 1);
+}
+
+template <typename T, int BX, int BY, int BZ>
+__global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int NT = BX * BY * BZ, NW = NT / 64;
+  constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;
+  constexpr int RX = 24, PL = RX * NY, CS = PL * NZ;
+  constexpr int ROW = 3 * NX;
+  static_assert(ROW <= 64, "row");
+  constexpr int NR = NY * NZ, RPW = (NR + NW - 1) / NW;
+  __shared__ __attribute__((aligned(16))) T buf[3 * CS];
+  const int nbx = n / BX, nby = n / BY;
+  const int b = blockIdx.x;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int m = 2 * n + 1;
+  const int X0 = 2 * BX * bx, Y0 = 2 * BY * by, Z0 = 2 * BZ * bz;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lx = lane / 3, comp = lane - 3 * (lane / 3);
+  const bool lane_ok = lane < ROW;
+  const int X = X0 + lx;
+  const bool xdir = X == 0 || X == m - 1;
+  const int lds_lane = comp * CS + split_index<BX>(lx);
+  const T* xrow = x + 3 * int64_t(X) + comp;
+  T v[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int r = w + k * NW;
+    v[k] = T(0);
+    if (r < NR && lane_ok) {
+      const int ly = r % NY, lz = r / NY;
+      const int Y = Y0 + ly, Z = Z0 + lz;
+      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
+      if (!dir) v[k] = xrow[3 * (int64_t(m) * (Y + int64_t(m) * Z))];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int r = w + k * NW;
+    if (r < NR && lane_ok) {
+      const int ly = r % NY, lz = r / NY;
+      buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX] = v[k];
+    }
+  }
+  __syncthreads();
+  const int cx = t % BX, cy = (t / BX) % BY, cz = t / (BX * BY);
+  T U[3][27];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) U[q][a + 3 * bb + 9 * c] = buf[q * CS + off];
+      }
+  __syncthreads();
+  {
+    constexpr int NV = (3 * CS * int(sizeof(T))) / 16;
+    float4* b4 = reinterpret_cast<float4*>(buf);
+    for (int e = t; e < NV; e += NT) b4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int e = NV * 16 / int(sizeof(T)) + t; e < 3 * CS; e += NT) buf[e] = T(0);
+  }
+  const int64_t cell = (int64_t(bx) * BX + cx) + int64_t(n) * ((int64_t(by) * BY + cy) + int64_t(n) * (int64_t(bz) * BZ + cz));
+  cellop::apply_cell<T>(U, mu[cell] / T(n));
+  __syncthreads();
+  {
+    // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
+    // class the map (cell, local node) -> node is injective, so read-add-write is race free;
+    // c classes are separated by a block barrier (they couple waves), a/b classes by an
+    // in-order LDS wait (they couple lanes of one wave).
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+      for (int ab = 0; ab < 4; ++ab) {
+        const int ac = ab & 1, bc = ab >> 1;
+        T tmp[3][2][2][2];
+#pragma unroll
+        for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+#pragma unroll
+          for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+#pragma unroll
+            for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+              const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) tmp[q][c & 1][bb & 1][a & 1] = buf[q * CS + off];
+            }
+#pragma unroll
+        for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+#pragma unroll
+          for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+#pragma unroll
+            for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+              const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) buf[q * CS + off] = tmp[q][c & 1][bb & 1][a & 1] + U[q][a + 3 * bb + 9 * c];
+            }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        asm volatile("" ::: "memory");
+      }
+      __syncthreads();
+    }
+  }
+  T* yrow = y + 3 * int64_t(X) + comp;
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int r = w + k * NW;
+    if (r < NR && lane_ok) {
+      const int ly = r % NY, lz = r / NY;
+      const int Y = Y0 + ly, Z = Z0 + lz;
+      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
+      if (!dir) {
+        const T val = buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX];
+        T* p = yrow + 3 * (int64_t(m) * (Y + int64_t(m) * Z));
+        const bool inner = lx > 0 && lx < NX - 1 && ly > 0 && ly < NY - 1 && lz > 0 && lz < NZ - 1;
+        if (inner) *p = val;
+        else atomicAdd(p, val);
+      }
+    }
+  }
+}
+
+}  // namespace brick
+}  // namespace mfgmg

@@ -38,8 +38,9 @@ template <typename T>
 const T* mu_of(const DevLevel& L);
 
 // y = A x on a level (identity on constrained dofs).  x, y must not alias.
+// init = false: y += cell contributions only (constrained entries untouched)
 template <typename T>
-void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s);
+void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init = true);
 
 // diag(A) accumulation (free dofs) into d (zeroed by the caller), then
 // minv = 1/d on free dofs and 1 on constrained dofs.

@@ -1,6 +1,7 @@
 // Device kernels for the matrix-free GMG Stokes path (gfx950, wave64).
 #include "ops.h"
 
+#include "brick_kernel.h"
 #include "cell_kernel.h"
 
 namespace mfgmg {
@@ -135,6 +136,17 @@ __global__ __launch_bounds__(kCellBlock) void k_vmult_uniform(int64_t n, const T
 #pragma unroll
   for (int a = 0; a < 27; ++a) scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
 }
+
+template <typename T>
+struct BrickShape;
+template <>
+struct BrickShape<float> {
+  static constexpr int BX = 8, BY = 8, BZ = 4;
+};
+template <>
+struct BrickShape<double> {
+  static constexpr int BX = 8, BY = 4, BZ = 4;
+};
 
 template <typename T, bool HANG>
 __global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __restrict__ cells, int64_t ncells,
@@ -677,14 +689,21 @@ const double* mu_of<double>(const DevLevel& L) {
 }
 
 template <typename T>
-void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s) {
+void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init) {
   if (L.uniform) {
-    k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
-    k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
-        L.n_edge, mu_of<T>(L), x, y);
+    if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
+    constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
+    const int64_t n = L.n_edge;
+    if (n % BX == 0 && n % BY == 0 && n % BZ == 0 && n <= 256) {
+      const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
+      brick::k_vmult_brick<T, BX, BY, BZ><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y);
+    } else {
+      k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+          n, mu_of<T>(L), x, y);
+    }
     return;
   }
-  k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
+  if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
   if (L.n_reg_cells)
     k_vmult_general<T, false><<<unsigned((L.n_reg_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
         L.reg_cells, L.n_reg_cells, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
@@ -692,8 +711,8 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s) {
     k_vmult_general<T, true><<<unsigned((L.n_hang_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
         L.hang_cells, L.n_hang_cells, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
 }
-template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t);
-template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t);
+template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t, bool);
+template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t, bool);
 
 void launch_diag(const DevLevel& L, const double* khat, double* d, hipStream_t s) {
   if (L.uniform) {

@@ -25,7 +25,7 @@ EXPORTS = [
     "mfgmg_create", "mfgmg_refine", "mfgmg_finalize_mesh", "mfgmg_info", "mfgmg_cells",
     "mfgmg_support_points", "mfgmg_node_types", "mfgmg_constraints", "mfgmg_transfer",
     "mfgmg_leaf_quadrature_points", "mfgmg_set_viscosity", "mfgmg_cell_viscosity",
-    "mfgmg_smoother_lambda", "mfgmg_inverse_diagonal", "mfgmg_vmult", "mfgmg_vcycle",
+    "mfgmg_smoother_lambda", "mfgmg_inverse_diagonal", "mfgmg_vmult", "mfgmg_vmult_add", "mfgmg_vcycle",
     "mfgmg_prolongate", "mfgmg_restrict", "mfgmg_smooth", "mfgmg_coarse_solve",
     "mfgmg_assemble_rhs", "mfgmg_apply_div", "mfgmg_apply_grad", "mfgmg_apply_pmass",
     "mfgmg_default_opts", "mfgmg_solve_stokes", "mfgmg_last_error", "mfgmg_destroy",
@@ -79,6 +79,7 @@ def load():
         "mfgmg_smoother_lambda": [vp, i32, C.POINTER(C.c_double)],
         "mfgmg_inverse_diagonal": [vp, i32, i32, vp, vp],
         "mfgmg_vmult": [vp, i32, i32, vp, vp, vp],
+        "mfgmg_vmult_add": [vp, i32, i32, vp, vp, vp],
         "mfgmg_vcycle": [vp, i32, vp, vp, vp],
         "mfgmg_prolongate": [vp, i32, i32, vp, vp, vp],
         "mfgmg_restrict": [vp, i32, i32, vp, vp, vp],
@@ -265,6 +266,14 @@ class Solver:
             raise ValueError("vmult: src/dst must have n_u[level] entries of one dtype")
         self._check(self.lib.mfgmg_vmult(self.h, level, p, _dev_ptr(src), _dev_ptr(dst),
                                          stream or current_stream()))
+
+    def vmult_add(self, level, src, dst, stream=None):
+        p = _prec_of(src)
+        n = self.info()["n_u"][level]
+        if _prec_of(dst) != p or src.numel() != n or dst.numel() != n:
+            raise ValueError("vmult_add: src/dst must have n_u[level] entries of one dtype")
+        self._check(self.lib.mfgmg_vmult_add(self.h, level, p, _dev_ptr(src), _dev_ptr(dst),
+                                             stream or current_stream()))
 
     def vcycle(self, rhs, x, stream=None):
         p = _prec_of(rhs)

@@ -36,6 +36,7 @@ def to_host(t):
 CASES = {
     "uniform2": dict(base=2),
     "uniform3": dict(base=3, dr=1e4, sinkers=8, seed=2),
+    "uniform4": dict(base=4, dr=1e6, sinkers=5, seed=9),
     "adaptive2+1": dict(base=2, corners=((1, 1, 1),), times=1),
     "adaptive2+2": dict(base=2, corners=((0, 1, 0),), times=2, dr=1e6),
     "adaptive3+2": dict(base=3, corners=((2, 5, 3), (0, 0, 0), (7, 7, 7)), times=2, dr=1e4, sinkers=6, seed=5),

@@ -1,0 +1,133 @@
+"""Device Stokes solve and full-size operator parity against the CPU oracle.
+
+* The 8^3 sinker problem (4 sinkers, DR 1e2) and an adaptive mesh: the FP64
+  relative residual ||b - K x|| / ||b|| of the device solution, recomputed by
+  the oracle's assembled FP64 block system, is <= 1e-8 for both the FP64 and
+  the FP32 V-cycle, and the solution matches the oracle's sparse direct solve
+  (relative error bounded by the condition number times the residual).
+* The 64^3 operator (6.44M dofs, the benchmark's launch configuration):
+  every output entry against the oracle's cellwise FP64 operator."""
+import numpy as np
+import pytest
+
+from oracle import krylov, mesh as omesh, operators as ops
+from paper_1907_06696_amd import inputs, mfgmg
+from tests.parity_cases import Case, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solve_and_check(case, precs=("fp64", "fp32"), err_tol=1e-5):
+    L = case.L
+    nu, npp = case.info["n_u"][L], case.info["n_p"]
+    prob = krylov.StokesProblem(case.H, ops.harmonic_cell_viscosity(case.mu_qp_or), case.f_qp_or)
+    xd = prob.solve_direct()
+    pu, pp = case.dof_perm(L), case.pnode_perm()
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.assemble_rhs(case.f_qp_lib, rhs)
+    out = {}
+    for prec in precs:
+        u = torch.empty(nu, dtype=torch.float64, device=DEV)
+        p = torch.empty(npp, dtype=torch.float64, device=DEV)
+        st = case.s.solve_stokes(rhs, u, p, vcycle_prec=prec)
+        torch.cuda.synchronize()
+        x = np.zeros(nu + npp)
+        x[pu] = u.cpu().numpy()
+        x[nu + pp] = p.cpu().numpy()
+        # the system's unknowns: constrained entries are identity rows with zero rhs
+        lf = case.H.leaf
+        x[:nu] *= lf.free_dofs_mask()
+        x[nu:] *= lf.pfree
+        res = prob.residual(x)
+        err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"  {prec}: its={st['iterations']} inner={st['inner_cg_iterations']} lib_res={st['rel_residual']:.2e} "
+              f"oracle_res={res:.2e} err={err:.2e} t={st['seconds']:.3f}s", flush=True)
+        assert st["converged"] == 1
+        assert st["rel_residual"] <= 1e-8
+        assert res <= 1.5e-8, (prec, res)
+        assert err <= err_tol, (prec, err)
+        out[prec] = st
+    return out
+
+
+def test_solve_c1_uniform8():
+    cfg = inputs.CONFIGS["c1_uniform8_fp64"]
+    c = Case(base=cfg["base_level"], sinkers=cfg["sinkers"], dr=cfg["dr"], seed=cfg["centre_seed"])
+    c.s.set_viscosity(c.mu_qp_lib)
+    st = _solve_and_check(c)
+    assert 5 <= st["fp64"]["iterations"] <= 80
+    c.close()
+
+
+def test_solve_adaptive_hanging():
+    c = Case(base=3, corners=((2, 5, 3), (0, 0, 0), (4, 4, 4)), times=1, sinkers=4, dr=1e3, seed=7)
+    assert c.info["n_hanging"][c.L] > 0 and c.info["n_p_hanging"] > 0
+    c.s.set_viscosity(c.mu_qp_lib)
+    _solve_and_check(c)
+    c.close()
+
+
+def test_solve_reports_noconv():
+    c = Case(base=2, sinkers=2, dr=1e2, seed=3, build_oracle=False)
+    c.s.set_viscosity(c.mu_qp_lib)
+    L = c.L
+    rhs = torch.empty(c.info["n_u"][L], dtype=torch.float64, device=DEV)
+    c.s.assemble_rhs(c.f_qp_lib, rhs)
+    u = torch.empty_like(rhs)
+    p = torch.empty(c.info["n_p"], dtype=torch.float64, device=DEV)
+    st = c.s.solve_stokes(rhs, u, p, max_iter=1, raise_on_noconv=False)
+    assert st["converged"] == 0 and st["iterations"] == 1
+    with pytest.raises(mfgmg.MFGMGError) as e:
+        c.s.solve_stokes(rhs, u, p, max_iter=1)
+    assert e.value.code == mfgmg.ERR_NOCONV
+    c.close()
+
+
+def test_vmult_full_size_64():
+    """The benchmark configuration: 64^3 cells, every output entry."""
+    cfg = inputs.CONFIGS["c2_uniform64"]
+    s = mfgmg.Solver(cfg["base_level"])
+    s.finalize_mesh()
+    L = s.info()["L"]
+    cen = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    s.set_viscosity(inputs.sinker_mu(qp, cen, cfg["dr"]).reshape(-1, 27))
+    n = s.info()["n_u"][L]
+    x = inputs.uniform_vector(n, cfg["vector_seed"])
+    y64 = torch.empty(n, dtype=torch.float64, device=DEV)
+    s.vmult(L, torch.tensor(x, device=DEV), y64)
+    x32 = x.astype(np.float32)
+    y32 = torch.empty(n, dtype=torch.float32, device=DEV)
+    s.vmult(L, torch.tensor(x32, device=DEV), y32)
+    torch.cuda.synchronize()
+    keys = s.support_points(L)
+    s.close()
+    lev, ijk = omesh.uniform_leaves(cfg["base_level"])
+    m = omesh.LevelMesh(lev, ijk, cfg["base_level"] + 1)
+    perm = np.searchsorted(m.keys, keys)
+    dperm = (3 * perm[:, None] + np.arange(3)[None, :]).ravel()
+    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
+    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, cen, cfg["dr"]).reshape(-1, 27))
+    A = ops.CellwiseA(m, mu)
+    xo = np.empty(n)
+    xo[dperm] = x
+    e64 = rel_err(y64.cpu().numpy(), A.matvec(xo)[dperm])
+    xo[dperm] = x32.astype(np.float64)
+    ref32 = A.matvec(xo)[dperm]
+    y = y32.cpu().numpy().astype(np.float64)
+    e32 = rel_err(y, ref32)
+    # entrywise: FP32 round-off relative to the size of the row's terms
+    scale = np.abs(ref32).max()
+    print(f"  64^3: fp64 rel {e64:.2e}, fp32 rel {e32:.2e}, fp32 max abs {np.abs(y - ref32).max() / scale:.2e}",
+          flush=True)
+    assert e64 <= 1e-12
+    assert e32 <= 1e-5
+    assert np.abs(y - ref32).max() <= 1e-5 * scale
