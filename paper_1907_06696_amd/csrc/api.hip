@@ -412,9 +412,9 @@ void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
   T* xc = static_cast<T*>(c.work[pi][1]);
   smooth<T>(ctx, ell, b, x, true, s);
   launch_vmult<T>(d.v, x, t, s);
-  launch_restrict<T>(c.v.nnode, d.R_ptr, d.R_col, d.R_w, b, t, bc, s);
+  launch_restrict_level<T>(d.v, c.v, d.R_ptr, d.R_col, d.R_w, b, t, bc, s);
   vcycle<T>(ctx, ell - 1, bc, xc, s);
-  launch_prolong<T>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, xc, x, true, s);
+  launch_prolong_level<T>(d.v, c.v, d.P_ptr, d.P_col, d.P_w, xc, x, true, s);
   smooth<T>(ctx, ell, b, x, false, s);
 }
 
@@ -830,12 +830,13 @@ int mfgmg_prolongate(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void*
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LevelDev& d = ctx->lv[size_t(level)];
+  const DevLevel& cv = ctx->lv[size_t(level - 1)].v;
   if (prec == MFGMG_FP64)
-    launch_prolong<double>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, static_cast<const double*>(coarse),
-                           static_cast<double*>(fine), false, s);
+    launch_prolong_level<double>(d.v, cv, d.P_ptr, d.P_col, d.P_w, static_cast<const double*>(coarse),
+                                 static_cast<double*>(fine), false, s);
   else
-    launch_prolong<float>(d.v.nnode, d.P_ptr, d.P_col, d.P_w, static_cast<const float*>(coarse),
-                          static_cast<float*>(fine), false, s);
+    launch_prolong_level<float>(d.v, cv, d.P_ptr, d.P_col, d.P_w, static_cast<const float*>(coarse),
+                                static_cast<float*>(fine), false, s);
   HIPCHK(hipGetLastError());
   return MFGMG_OK;
 }
@@ -847,13 +848,13 @@ int mfgmg_restrict(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* f
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LevelDev& d = ctx->lv[size_t(level)];
-  const int64_t nc = ctx->lv[size_t(level - 1)].v.nnode;
+  const DevLevel& cv = ctx->lv[size_t(level - 1)].v;
   if (prec == MFGMG_FP64)
-    launch_restrict<double>(nc, d.R_ptr, d.R_col, d.R_w, static_cast<const double*>(fine), nullptr,
-                            static_cast<double*>(coarse), s);
+    launch_restrict_level<double>(d.v, cv, d.R_ptr, d.R_col, d.R_w, static_cast<const double*>(fine), nullptr,
+                                  static_cast<double*>(coarse), s);
   else
-    launch_restrict<float>(nc, d.R_ptr, d.R_col, d.R_w, static_cast<const float*>(fine), nullptr,
-                           static_cast<float*>(coarse), s);
+    launch_restrict_level<float>(d.v, cv, d.R_ptr, d.R_col, d.R_w, static_cast<const float*>(fine), nullptr,
+                                 static_cast<float*>(coarse), s);
   HIPCHK(hipGetLastError());
   return MFGMG_OK;
 }

@@ -66,6 +66,15 @@ template <typename T>
 void launch_restrict(int64_t ncoarse, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
                      T* coarse, hipStream_t s);
 
+// level-aware transfers: structured kernels between two uniform levels,
+// the CSR kernels otherwise
+template <typename T>
+void launch_prolong_level(const DevLevel& fine, const DevLevel& coarse, const int64_t* ptr, const int32_t* col,
+                          const float* w, const T* xc, T* xf, bool add, hipStream_t s);
+template <typename T>
+void launch_restrict_level(const DevLevel& fine, const DevLevel& coarse, const int64_t* ptr, const int32_t* col,
+                           const float* w, const T* b, const T* t, T* xc, hipStream_t s);
+
 // coarse solve: x[free] = Ainv b[free], x[constrained] = b
 template <typename T>
 void launch_coarse(const T* Ainv, const int32_t* free_dofs, int nfree, int n, const T* b, T* x, hipStream_t s);

@@ -394,6 +394,115 @@ __global__ void k_restrict(int64_t nc, const int64_t* __restrict__ ptr, const in
   }
 }
 
+// Transfers between two uniform levels (nc coarse cells per edge, 2nc fine).
+// Prolongation: a fine lattice coordinate X (0..4nc) that is even sits on
+// coarse node X/2; an odd X lies at a quarter point of coarse cell k = X/4,
+// where the coarse Q2 basis takes the values (3/8, 3/4, -1/8) (X = 4k+1) or
+// (-1/8, 3/4, 3/8) (X = 4k+3) on coarse nodes 2k, 2k+1, 2k+2.  Restriction is
+// the exact transpose: coarse node C collects fine X = 2C (weight 1) and, for
+// even C, 2C+-1 (3/8) and 2C+-3 (-1/8); for odd C, 2C+-1 (3/4).  Boundary
+// (Dirichlet) nodes of either level carry and receive nothing.
+template <typename T>
+__device__ __forceinline__ int prolong_axis(int X, int mc, int (&idx)[3], T (&w)[3]) {
+  if (!(X & 1)) {
+    const int c = X >> 1;
+    idx[0] = c, w[0] = T(1);
+    return (c == 0 || c == mc - 1) ? 0 : 1;
+  }
+  const int base = 2 * (X >> 2);
+  const bool q1 = (X & 3) == 1;
+  idx[0] = base, idx[1] = base + 1, idx[2] = base + 2;
+  w[0] = q1 ? T(0.375) : T(-0.125);
+  w[1] = T(0.75);
+  w[2] = q1 ? T(-0.125) : T(0.375);
+  if (base == 0) w[0] = T(0);
+  if (base + 2 == mc - 1) w[2] = T(0);
+  return 3;
+}
+
+template <typename T>
+__global__ void k_prolong_uniform(int nc, const T* __restrict__ xc, T* __restrict__ xf, bool add) {
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int64_t nn = int64_t(mf) * mf * mf;
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const int X = int(v % mf), Y = int((v / mf) % mf), Z = int(v / (int64_t(mf) * mf));
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    const bool dir = X == 0 || Y == 0 || Z == 0 || X == mf - 1 || Y == mf - 1 || Z == mf - 1;
+    if (!dir) {
+      int ix[3], iy[3], iz[3];
+      T wx[3], wy[3], wz[3];
+      const int nx = prolong_axis<T>(X, mc, ix, wx), ny = prolong_axis<T>(Y, mc, iy, wy),
+                nz = prolong_axis<T>(Z, mc, iz, wz);
+      for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+          const T wzy = wz[k] * wy[j];
+          const int64_t rowc = int64_t(mc) * (iy[j] + int64_t(mc) * iz[k]);
+          for (int i = 0; i < nx; ++i) {
+            const T ww = wzy * wx[i];
+            const T* p = xc + 3 * (rowc + ix[i]);
+            a0 += ww * p[0], a1 += ww * p[1], a2 += ww * p[2];
+          }
+        }
+    }
+    T* q = xf + 3 * v;
+    if (add) {
+      q[0] += a0, q[1] += a1, q[2] += a2;
+    } else {
+      q[0] = a0, q[1] = a1, q[2] = a2;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ int restrict_axis(int C, int mf, int (&idx)[5], T (&w)[5]) {
+  int k = 0;
+  const int X = 2 * C;
+  if (C & 1) {
+    const int off[3] = {-1, 0, 1};
+    const T ww[3] = {T(0.75), T(1), T(0.75)};
+    for (int q = 0; q < 3; ++q)
+      if (X + off[q] > 0 && X + off[q] < mf - 1) idx[k] = X + off[q], w[k] = ww[q], ++k;
+  } else {
+    const int off[5] = {-3, -1, 0, 1, 3};
+    const T ww[5] = {T(-0.125), T(0.375), T(1), T(0.375), T(-0.125)};
+    for (int q = 0; q < 5; ++q)
+      if (X + off[q] > 0 && X + off[q] < mf - 1) idx[k] = X + off[q], w[k] = ww[q], ++k;
+  }
+  return k;
+}
+
+template <typename T>
+__global__ void k_restrict_uniform(int nc, const T* __restrict__ b, const T* __restrict__ t, T* __restrict__ xc) {
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int64_t nn = int64_t(mc) * mc * mc;
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const int X = int(v % mc), Y = int((v / mc) % mc), Z = int(v / (int64_t(mc) * mc));
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    const bool dir = X == 0 || Y == 0 || Z == 0 || X == mc - 1 || Y == mc - 1 || Z == mc - 1;
+    if (!dir) {
+      int ix[5], iy[5], iz[5];
+      T wx[5], wy[5], wz[5];
+      const int nx = restrict_axis<T>(X, mf, ix, wx), ny = restrict_axis<T>(Y, mf, iy, wy),
+                nz = restrict_axis<T>(Z, mf, iz, wz);
+      for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+          const T wzy = wz[k] * wy[j];
+          const int64_t rowf = int64_t(mf) * (iy[j] + int64_t(mf) * iz[k]);
+          for (int i = 0; i < nx; ++i) {
+            const T ww = wzy * wx[i];
+            const int64_t f = 3 * (rowf + ix[i]);
+            if (t) {
+              a0 += ww * (b[f] - t[f]), a1 += ww * (b[f + 1] - t[f + 1]), a2 += ww * (b[f + 2] - t[f + 2]);
+            } else {
+              a0 += ww * b[f], a1 += ww * b[f + 1], a2 += ww * b[f + 2];
+            }
+          }
+        }
+    }
+    xc[3 * v] = a0, xc[3 * v + 1] = a1, xc[3 * v + 2] = a2;
+  }
+}
+
 // ------------------------------------------------------------- coarse
 template <typename T>
 __global__ __launch_bounds__(128) void k_coarse(const T* __restrict__ Ainv, const int32_t* __restrict__ fd,
@@ -856,5 +965,37 @@ void set_element_constants(const double* kd, const double* bh, const double* mh)
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_bhat), bh, sizeof(double) * 8 * 81);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_mhat), mh, sizeof(double) * 64);
 }
+
+}  // namespace mfgmg
+
+namespace mfgmg {
+
+template <typename T>
+void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
+                          const float* w, const T* xc, T* xf, bool add, hipStream_t s) {
+  if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
+    k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
+    return;
+  }
+  k_prolong<T><<<grid_for(F.nnode), kBlock, 0, s>>>(F.nnode, ptr, col, w, xc, xf, add);
+}
+
+template <typename T>
+void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
+                           const float* w, const T* b, const T* t, T* xc, hipStream_t s) {
+  if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
+    k_restrict_uniform<T><<<grid_for(Cc.nnode), kBlock, 0, s>>>(int(Cc.n_edge), b, t, xc);
+    return;
+  }
+  k_restrict<T><<<grid_for(Cc.nnode), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b, t, xc);
+}
+
+#define MFGMG_INST_TRANSFER(T)                                                                                \
+  template void launch_prolong_level<T>(const DevLevel&, const DevLevel&, const int64_t*, const int32_t*,    \
+                                        const float*, const T*, T*, bool, hipStream_t);                       \
+  template void launch_restrict_level<T>(const DevLevel&, const DevLevel&, const int64_t*, const int32_t*,   \
+                                         const float*, const T*, const T*, T*, hipStream_t);
+MFGMG_INST_TRANSFER(float)
+MFGMG_INST_TRANSFER(double)
 
 }  // namespace mfgmg
