@@ -1,0 +1,118 @@
+"""Pins of the oracle's learned-scaling part: MLP gradients against central
+finite differences, the first Adam step in closed form, scaling invariance of
+the smoother, the adjoint V-cycle gradient against central finite
+differences (lambda held fixed), and feature values on known fields.
+The fitted targets themselves have no closed form (parity unpinned)."""
+import numpy as np
+import pytest
+
+from oracle import learned as ol, mesh, multigrid as mg, operators as ops
+from tests.test_oracle_mesh import adaptive_hierarchy
+
+
+def test_mlp_backward_matches_finite_differences():
+    rg = np.random.default_rng(0)
+    w = ol.init_params(1) + rg.normal(0, 0.05, ol.N_PARAMS)
+    w[-3 - 192:-3] *= 0.2                        # keep the outputs inside the clamp
+    assert len(w) == ol.N_PARAMS == 6147
+    x = rg.normal(0, 0.5, (7, 27))
+    dy = rg.normal(0, 1, (7, 3))
+    y, cache = ol.mlp_forward(w, x)
+    assert np.all(np.abs(y) < ol.CLAMP)          # FD is valid away from the clamp
+    g = ol.mlp_backward(w, cache, dy)
+    idx = rg.choice(ol.N_PARAMS, 60, replace=False)
+    eps = 1e-6
+    for i in idx:
+        e = np.zeros_like(w)
+        e[i] = eps
+        fd = ((ol.mlp_forward(w + e, x)[0] - ol.mlp_forward(w - e, x)[0]) * dy).sum() / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_gelu_derivative_and_clamp():
+    z = np.linspace(-4, 4, 81)
+    fd = (ol.gelu(z + 1e-6) - ol.gelu(z - 1e-6)) / 2e-6
+    assert np.allclose(fd, ol.gelu_deriv(z), atol=1e-8)
+    assert np.isclose(ol.gelu(np.array([0.0]))[0], 0.0) and np.isclose(ol.gelu(np.array([1.0]))[0], 0.8413447460685429)
+    w = ol.init_params(0)
+    w[-3:] = [5.0, -5.0, 0.5]                        # output biases push two outputs beyond the clamp
+    y, cache = ol.mlp_forward(w, np.zeros((2, 27)))
+    assert np.allclose(y[:, 0], 2.0) and np.allclose(y[:, 1], -2.0)
+    g = ol.mlp_backward(w, cache, np.ones((2, 3)))
+    assert g[-3] == 0 and g[-2] == 0 and g[-1] == 2.0
+
+
+def test_adam_first_step_closed_form():
+    w = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    w1, m, v = ol.adam_step(w, g, np.zeros(3), np.zeros(3), 1, lr=0.1)
+    # bias-corrected moments equal g and g^2 after one step: update = lr g / (|g| + eps)
+    assert np.allclose(w1, w - 0.1 * g / (np.abs(g) + 1e-8))
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def _gmg(H, seed=0):
+    mu = 10 ** np.random.default_rng(seed).uniform(0, 2, H.leaf.ncell)
+    return mg.GMG(H, ops.level_viscosities(H, mu))
+
+
+def test_constant_scaling_is_invariant():
+    H = mesh.Hierarchy.uniform(3)
+    G = _gmg(H)
+    ell = 3
+    nc = H.levels[ell].ncell
+    J0, _ = ol.objective(G, ell, np.zeros((nc, 3)), with_grad=False)
+    J1, _ = ol.objective(G, ell, np.full((nc, 3), 0.7), with_grad=False)
+    assert abs(J0 - J1) <= 1e-10 * abs(J0)
+    s = ol.dof_scaling(H.levels[ell], np.full((nc, 3), 0.7))
+    assert np.allclose(s, np.exp(0.7))
+
+
+@pytest.mark.parametrize("which", ["uniform", "adaptive"])
+def test_adjoint_gradient_matches_finite_differences(which):
+    H = mesh.Hierarchy.uniform(2) if which == "uniform" else adaptive_hierarchy(1, (0, 0, 0), 1)
+    G = _gmg(H, 3)
+    ell = H.L
+    m = H.levels[ell]
+    rg = np.random.default_rng(4)
+    y = rg.uniform(-0.5, 0.5, (m.ncell, 3))
+    lam = ol.ScaledLevel(G, ell, ol.dof_scaling(m, y)).lam
+    J, g = ol.objective(G, ell, y, lam=lam)
+    eps = 1e-5
+    for ci in rg.choice(m.ncell, min(6, m.ncell), replace=False):
+        for c in range(3):
+            e = np.zeros_like(y)
+            e[ci, c] = eps
+            fd = (ol.objective(G, ell, y + e, lam=lam, with_grad=False)[0]
+                  - ol.objective(G, ell, y - e, lam=lam, with_grad=False)[0]) / (2 * eps)
+            assert abs(fd - g[ci, c]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max()), (ci, c, fd, g[ci, c])
+
+
+def test_fitting_decreases_objective():
+    H = mesh.Hierarchy.uniform(3)
+    G = _gmg(H, 5)
+    y, hist = ol.fit_targets(G, 3, steps=8)
+    assert hist[-1] < hist[0]
+    assert np.all(np.abs(y) <= ol.CLAMP)
+
+
+def test_features_known_field():
+    H = mesh.Hierarchy.uniform(2)
+    mu_leaf = np.ones(H.leaf.ncell)
+    mus = ops.level_viscosities(H, mu_leaf)
+    f = ol.features(H, mus, 2)
+    assert np.all(f == 0)
+    # one cell with mu = 100 at (1, 1, 1): neighbours see +2 at the mirrored offset
+    lf = H.leaf
+    hot = np.nonzero(np.all(lf.ijk == [1, 1, 1], axis=1))[0][0]
+    mu_leaf[hot] = 100.0
+    mus = ops.level_viscosities(H, mu_leaf)
+    f = ol.features(H, mus, 2)
+    assert np.allclose(f[hot], np.where(np.arange(27) == 13, 0.0, -2.0))
+    nb = np.nonzero(np.all(lf.ijk == [2, 1, 1], axis=1))[0][0]     # +x neighbour sees the hot cell at offset -x
+    assert np.isclose(f[nb, 12], 2.0) and np.isclose(np.abs(f[nb]).sum(), 2.0)
+    corner = np.nonzero(np.all(lf.ijk == [0, 0, 0], axis=1))[0][0]
+    assert f[corner, 0] == 0.0                                      # outside the domain
+    # coarser level: the parent averages
+    f1 = ol.features(H, mus, 1)
+    assert np.isclose(f1[0, 13], 0.0)
