@@ -232,6 +232,83 @@ int mfgmg_default_opts(mfgmg_solve_opts* opts);
 int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u_dev, const double* rhs_p_dev, double* u_dev,
                        double* p_dev, const mfgmg_solve_opts* opts, mfgmg_solve_stats* stats, void* stream);
 
+/* ------------------------------------------- learned smoother scaling
+ * Not part of the paper: the degree-4 Chebyshev smoother of Sec. 2.2.1 is
+ * preconditioned by diag(s/d) instead of diag(1/d) on chosen levels, with
+ * s_(node, c) = exp(mean of y_{K,c} over the cells K of the level holding the
+ * node) and y_K = MLP(27 relative log10 viscosities of K's 3x3x3
+ * neighbourhood); MLP 27 -> 64 -> 64 -> 3, GELU (erf form), output clamped to
+ * [-2, 2], 6147 FP32 parameters W1[64][27], b1[64], W2[64][64], b2[64],
+ * W3[3][64], b3[3] (row-major [out][in]). */
+
+/* Features of the cells of a level, feat_dev [n_cells[level]][27] FP32:
+ * log10 mu_{K'} - log10 mu_K over the 3x3x3 same-level neighbourhood
+ * (offsets (i-1, j-1, k-1), x fastest); a position covered by a coarser cell
+ * takes that cell's viscosity, one outside the domain takes mu_K.
+ * Synchronises `stream`. */
+int mfgmg_features(mfgmg_ctx* ctx, int32_t level, float* feat_dev, void* stream);
+
+/* Objective of the target fit on a level (2 <= level <= L) for per-cell
+ * log-scalings y_dev [n_cells][3] (FP32 in, FP64 arithmetic):
+ * J = (1/4) sum_k (1/2) log(||E^2 e_k||_A / ||e_k||_A), E = I - V A, V the
+ * V-cycle whose level-`level` smoothers use diag(s/d) (coarser levels plain),
+ * e_k SplitMix64 vectors (seeds 777..780 over 3 key + component).
+ * lam_fixed > 0 holds the Chebyshev bound fixed, else it is re-estimated
+ * (*lam_out receives the value used).  grad_dev (may be NULL):
+ * dJ/dy [n_cells][3] FP32 by the adjoint of the V-cycle with lambda constant.
+ * Synchronises `stream`. */
+int mfgmg_fit_objective(mfgmg_ctx* ctx, int32_t level, const float* y_dev, double lam_fixed, double* J_host,
+                        double* lam_out_host, float* grad_dev, void* stream);
+
+/* Targets of a level: Adam (lr, beta 0.9/0.999, eps 1e-8) on J from y = 0 for
+ * `steps` steps, y clipped to [-2, 2].  y_dev [n_cells][3] FP32 out;
+ * J_hist_host [steps + 1] (may be NULL).  Synchronises `stream`. */
+int mfgmg_fit_targets(mfgmg_ctx* ctx, int32_t level, int32_t steps, double lr, float* y_dev, double* J_hist_host,
+                      void* stream);
+
+/* Install the scaling of a level from per-cell y_dev [n_cells][3] FP32
+ * (re-estimates lambda); y_dev NULL removes it.  Synchronises `stream`. */
+int mfgmg_set_scaling(mfgmg_ctx* ctx, int32_t level, const float* y_dev, void* stream);
+
+/* Whether mfgmg_vcycle / mfgmg_smooth use the installed scalings (default 0);
+ * mfgmg_solve_stokes follows opts->use_scaling instead. */
+int mfgmg_use_scaling(mfgmg_ctx* ctx, int32_t on);
+
+/* A-norm contraction of E = I - V A on the leaf level estimated by three
+ * power steps from a SplitMix64 vector (seed 4242), FP64.  Synchronises. */
+int mfgmg_vcycle_factor(mfgmg_ctx* ctx, double* rho_host, void* stream);
+
+/* MLP over n samples: x_dev [n][27] -> y_dev [n][3]; cache_dev [n][131]
+ * keeps the pre-activations for the backward pass.  Async. */
+int mfgmg_mlp_forward(const float* w_dev, const float* x_dev, int64_t n, float* y_dev, float* cache_dev, void* stream);
+
+/* dw_dev[6147] = gradient of sum(dy * y) w.r.t. the parameters (the clamp
+ * passes gradient strictly inside [-2, 2]); work_dev holds
+ * mfgmg_mlp_work_size(n) floats.  Async. */
+int mfgmg_mlp_backward(const float* w_dev, const float* x_dev, const float* cache_dev, const float* dy_dev, int64_t n,
+                       float* dw_dev, float* work_dev, void* stream);
+int64_t mfgmg_mlp_work_size(int64_t n);
+
+/* One Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected, step >= 1) on the
+ * 6147 parameters.  Async. */
+int mfgmg_mlp_adam(float* w_dev, const float* dw_dev, float* m_dev, float* v_dev, int64_t step, double lr,
+                   void* stream);
+
+/* Train on n (feature, target) pairs: mean-squared error, Adam (lr), epochs of
+ * mini-batches of `batch` samples shuffled by a SplitMix64-driven
+ * Fisher-Yates permutation (seed, epoch).  loss_hist_host [epochs] receives
+ * the mean squared error of each epoch (may be NULL).  w_dev updated in
+ * place.  Synchronises `stream`. */
+int mfgmg_mlp_train(float* w_dev, const float* feats_dev, const float* targets_dev, int64_t n, int32_t epochs,
+                    int32_t batch, double lr, uint64_t seed, double* loss_hist_host, void* stream);
+
+/* Features -> MLP -> scaling on every level 2..L.  guard != 0: keep the
+ * scalings only if they lower the V-cycle contraction estimate
+ * (factors_host[0] plain, [1] learned; may be NULL); *used_host = 1 if kept.
+ * Synchronises `stream`. */
+int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w_dev, int32_t guard, int32_t* used_host, double* factors_host,
+                    void* stream);
+
 /* ---------------------------------------------------------------- misc */
 
 const char* mfgmg_last_error(const mfgmg_ctx* ctx); /* ctx may be NULL */

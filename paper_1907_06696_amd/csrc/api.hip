@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/mfgmg.h"
+#include "ctx.h"
 #include "mesh.h"
 #include "ops.h"
 
@@ -75,7 +76,7 @@ const Element& element() {
 // ------------------------------------------------------------ SplitMix64
 // Steele, Lea & Flood (2014): state += 0x9E3779B97F4A7C15, then the mixing
 // function; counter-based use: value(c) = mix(c + seed * 0xD1B54A32D192ED03 + gamma)
-double splitmix_pm1(uint64_t seed, uint64_t counter) {
+double splitmix_value(uint64_t seed, uint64_t counter) {
   uint64_t z = counter + seed * 0xD1B54A32D192ED03ULL + 0x9E3779B97F4A7C15ULL;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
@@ -144,78 +145,15 @@ bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
-struct LevelDev {
-  DevLevel v;
-  double* mu_d = nullptr;
-  float* mu_f = nullptr;
-  double* minv_d = nullptr;
-  float* minv_f = nullptr;
-  const int64_t* P_ptr = nullptr;
-  const int32_t* P_col = nullptr;
-  const float* P_w = nullptr;
-  const int64_t* R_ptr = nullptr;
-  const int32_t* R_col = nullptr;
-  const float* R_w = nullptr;
-  const int32_t* mu_src = nullptr;
-  double lambda = 0.0;
-  void* work[2][5] = {{nullptr}};   // [prec][b, x, r, d, t]
-  float* scale_f = nullptr;         // optional smoother scaling s (FP32 copy)
-  double* scale_d = nullptr;
-};
-
 }  // namespace
 
-struct mfgmg_ctx {
-  std::unique_ptr<Mesh> mesh;
-  std::string err;
-  bool dev_ready = false;
-  bool mu_ready = false;
-  int device = -1;
-  std::vector<void*> allocs;
-  std::vector<LevelDev> lv;
-  DevPressure pres;
-  double* khat_d = nullptr;
-  double* Ainv_d = nullptr;
-  float* Ainv_f = nullptr;
-  int32_t* coarse_free = nullptr;
-  int ncfree = 0;
-  double* red_part = nullptr;   // reduction partials
-  double* red_res = nullptr;    // device results (up to 128)
-  double* host_res = nullptr;   // pinned host copy
-  double* pmass_minv = nullptr; // Jacobi preconditioner of M_p
-  double* pmean_w = nullptr;    // int psi_j (constrained) for the zero-mean pressure
-  double pmean_total = 0.0;
-  std::vector<double> mu_host_leaf;
-  bool has_scaling = false;
-
-  int set(int code, const std::string& msg) {
-    err = msg;
-    return code;
-  }
-  template <typename T>
-  T* dalloc(size_t n) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
-    allocs.push_back(p);
-    return static_cast<T*>(p);
-  }
-  template <typename T>
-  T* upload(const std::vector<T>& h) {
-    T* p = dalloc<T>(h.size());
-    if (p && !h.empty()) (void)hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
-    return p;
-  }
-};
-
-namespace {
+namespace mfgmg {
+namespace detail {
 
 thread_local std::string g_last_error;
 
-#define HIPCHK(expr)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess) return ctx->set(MFGMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+double splitmix_pm1(uint64_t seed, uint64_t counter) { return splitmix_value(seed, counter); }
+
 
 int upload_mesh(mfgmg_ctx* ctx) {
   if (ctx->dev_ready) return MFGMG_OK;
@@ -360,6 +298,16 @@ template <>
 const double* minv_of<double>(const LevelDev& d) {
   return d.minv_d;
 }
+template <typename T>
+const T* minv_s_of(const LevelDev& d);
+template <>
+const float* minv_s_of<float>(const LevelDev& d) {
+  return d.minv_s_f;
+}
+template <>
+const double* minv_s_of<double>(const LevelDev& d) {
+  return d.minv_s_d;
+}
 
 // Chebyshev smoothing (Saad, Alg. 12.1) on [lambda/15, lambda], M^{-1} = minv
 template <typename T>
@@ -369,8 +317,9 @@ void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t 
   T* r = static_cast<T*>(d.work[prec_index<T>()][2]);
   T* dd = static_cast<T*>(d.work[prec_index<T>()][3]);
   T* t = static_cast<T*>(d.work[prec_index<T>()][4]);
-  const T* minv = minv_of<T>(d);
-  const double lam = d.lambda, lo = lam / 15.0;
+  const bool sc = ctx->use_scaling && d.scaled;
+  const T* minv = sc ? minv_s_of<T>(d) : minv_of<T>(d);
+  const double lam = sc ? d.lambda_s : d.lambda, lo = lam / 15.0;
   const double theta = 0.5 * (lam + lo), delta = 0.5 * (lam - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
   if (x_zero) {
@@ -421,6 +370,11 @@ void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
 // lambda_max of M^{-1} A by 12 steps of preconditioned CG-Lanczos (FP64)
 int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
   LevelDev& d = ctx->lv[size_t(ell)];
+  return lanczos_lambda(ctx, ell, d.minv_d, &d.lambda, s);
+}
+
+int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out, hipStream_t s) {
+  LevelDev& d = ctx->lv[size_t(ell)];
   const Level& h = ctx->mesh->level(ell);
   const int64_t n = 3 * h.nnode;
   std::vector<double> r0(static_cast<size_t>(n));
@@ -432,10 +386,11 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
   double* r = static_cast<double*>(d.work[1][2]);
   double* z = static_cast<double*>(d.work[1][3]);
   double* q = static_cast<double*>(d.work[1][4]);
-  double* p = ctx->dalloc<double>(size_t(n));
+  if (!d.lz_p) d.lz_p = ctx->dalloc<double>(size_t(n));
+  double* p = d.lz_p;
   if (!p) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
   HIPCHK(hipMemcpyAsync(r, r0.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
-  launch_mul(n, d.minv_d, r, z, s);
+  launch_mul(n, minv, r, z, s);
   HIPCHK(hipMemcpyAsync(p, z, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   double rz = dot_sync(ctx, n, r, z, s);
   const double rz0 = rz;
@@ -447,7 +402,7 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
     const double alpha = rz / pq;
     alphas.push_back(alpha);
     launch_axpby(n, -alpha, q, 1.0, r, s);
-    launch_mul(n, d.minv_d, r, z, s);
+    launch_mul(n, minv, r, z, s);
     const double rz_new = dot_sync(ctx, n, r, z, s);
     const double beta = rz_new / rz;
     if (rz_new <= 1e-30 * rz0) break;
@@ -462,9 +417,8 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
     dg[size_t(i)] = 1.0 / alphas[size_t(i)] + (i > 0 ? betas[size_t(i - 1)] / alphas[size_t(i - 1)] : 0.0);
     if (i + 1 < k) e[size_t(i)] = std::sqrt(betas[size_t(i)]) / alphas[size_t(i)];
   }
-  d.lambda = 1.2 * tridiag_max_eig(dg, e);
+  *lam_out = 1.2 * tridiag_max_eig(dg, e);
   HIPCHK(hipStreamSynchronize(s));
-  // the scratch vector p is released with the context; mark it reusable
   return MFGMG_OK;
 }
 
@@ -561,7 +515,15 @@ int check_level(const mfgmg_ctx* ctx, int32_t level) {
   return MFGMG_OK;
 }
 
-}  // namespace
+template void smooth<float>(mfgmg_ctx*, int, const float*, float*, bool, hipStream_t);
+template void smooth<double>(mfgmg_ctx*, int, const double*, double*, bool, hipStream_t);
+template void vcycle<float>(mfgmg_ctx*, int, const float*, float*, hipStream_t);
+template void vcycle<double>(mfgmg_ctx*, int, const double*, double*, hipStream_t);
+
+}  // namespace detail
+}  // namespace mfgmg
+
+using namespace mfgmg::detail;
 
 // =================================================================== C ABI
 extern "C" {
@@ -954,6 +916,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     return ctx->set(MFGMG_ERR_INVALID, "bad solver options");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
+  struct ScalingGuard {   // V-cycles of this solve use the installed scalings iff requested
+    mfgmg_ctx* c;
+    bool saved;
+    ~ScalingGuard() { c->use_scaling = saved; }
+  } scaling_guard{ctx, ctx->use_scaling};
+  ctx->use_scaling = o.use_scaling != 0;
   const int L = ctx->mesh->L();
   LevelDev& top = ctx->lv[size_t(L)];
   const DevLevel& lv = top.v;

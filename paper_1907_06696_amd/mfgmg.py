@@ -28,8 +28,14 @@ EXPORTS = [
     "mfgmg_smoother_lambda", "mfgmg_inverse_diagonal", "mfgmg_vmult", "mfgmg_vmult_add", "mfgmg_vcycle",
     "mfgmg_prolongate", "mfgmg_restrict", "mfgmg_smooth", "mfgmg_coarse_solve",
     "mfgmg_assemble_rhs", "mfgmg_apply_div", "mfgmg_apply_grad", "mfgmg_apply_pmass",
-    "mfgmg_default_opts", "mfgmg_solve_stokes", "mfgmg_last_error", "mfgmg_destroy",
+    "mfgmg_default_opts", "mfgmg_solve_stokes",
+    "mfgmg_features", "mfgmg_fit_objective", "mfgmg_fit_targets", "mfgmg_set_scaling", "mfgmg_use_scaling",
+    "mfgmg_vcycle_factor", "mfgmg_mlp_forward", "mfgmg_mlp_backward", "mfgmg_mlp_work_size", "mfgmg_mlp_adam",
+    "mfgmg_mlp_train", "mfgmg_apply_mlp",
+    "mfgmg_last_error", "mfgmg_destroy",
 ]
+N_PARAMS = 6147
+MLP_CACHE = 131
 
 
 class Info(C.Structure):
@@ -91,6 +97,18 @@ def load():
         "mfgmg_apply_pmass": [vp, vp, vp, vp],
         "mfgmg_default_opts": [C.POINTER(SolveOpts)],
         "mfgmg_solve_stokes": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp],
+        "mfgmg_features": [vp, i32, vp, vp],
+        "mfgmg_fit_objective": [vp, i32, vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), vp, vp],
+        "mfgmg_fit_targets": [vp, i32, i32, C.c_double, vp, vp, vp],
+        "mfgmg_set_scaling": [vp, i32, vp, vp],
+        "mfgmg_use_scaling": [vp, i32],
+        "mfgmg_vcycle_factor": [vp, C.POINTER(C.c_double), vp],
+        "mfgmg_mlp_forward": [vp, vp, i64, vp, vp, vp],
+        "mfgmg_mlp_backward": [vp, vp, vp, vp, i64, vp, vp, vp],
+        "mfgmg_mlp_work_size": [i64],
+        "mfgmg_mlp_adam": [vp, vp, vp, vp, i64, C.c_double, vp],
+        "mfgmg_mlp_train": [vp, vp, vp, i64, i32, i32, C.c_double, C.c_uint64, vp, vp],
+        "mfgmg_apply_mlp": [vp, vp, i32, C.POINTER(i32), vp, vp],
         "mfgmg_last_error": [vp],
         "mfgmg_destroy": [vp],
     }
@@ -100,6 +118,7 @@ def load():
         f.restype = C.c_int
     lib.mfgmg_last_error.restype = C.c_char_p
     lib.mfgmg_destroy.restype = None
+    lib.mfgmg_mlp_work_size.restype = C.c_int64
     _lib = lib
     return lib
 
@@ -326,3 +345,90 @@ class Solver:
         if code != OK and not (code == ERR_NOCONV and not raise_on_noconv):
             self._check(code)
         return stats
+
+    # ------------------------------------------------ learned smoother scaling
+    def features(self, level, out=None, stream=None):
+        import torch
+        n = self.info()["n_cells"][level]
+        out = torch.empty((n, 27), dtype=torch.float32, device="cuda") if out is None else out
+        self._check(self.lib.mfgmg_features(self.h, level, _dev_ptr(out), stream or current_stream()))
+        return out
+
+    def fit_objective(self, level, y, lam_fixed=0.0, grad=True, stream=None):
+        import torch
+        J, lam = C.c_double(), C.c_double()
+        g = torch.empty_like(y) if grad else None
+        self._check(self.lib.mfgmg_fit_objective(self.h, level, _dev_ptr(y), float(lam_fixed), C.byref(J),
+                                                 C.byref(lam), _dev_ptr(g) if grad else None,
+                                                 stream or current_stream()))
+        return J.value, lam.value, g
+
+    def fit_targets(self, level, steps=30, lr=0.05, stream=None):
+        import torch
+        n = self.info()["n_cells"][level]
+        y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        hist = np.zeros(steps + 1)
+        self._check(self.lib.mfgmg_fit_targets(self.h, level, int(steps), float(lr), _dev_ptr(y), _np_ptr(hist),
+                                               stream or current_stream()))
+        return y, hist
+
+    def set_scaling(self, level, y=None, stream=None):
+        self._check(self.lib.mfgmg_set_scaling(self.h, level, _dev_ptr(y) if y is not None else None,
+                                               stream or current_stream()))
+
+    def use_scaling(self, on):
+        self._check(self.lib.mfgmg_use_scaling(self.h, int(bool(on))))
+
+    def vcycle_factor(self, stream=None):
+        r = C.c_double()
+        self._check(self.lib.mfgmg_vcycle_factor(self.h, C.byref(r), stream or current_stream()))
+        return r.value
+
+    def apply_mlp(self, w, guard=True, stream=None):
+        used = C.c_int32()
+        fac = np.zeros(2)
+        self._check(self.lib.mfgmg_apply_mlp(self.h, _dev_ptr(w), int(bool(guard)), C.byref(used), _np_ptr(fac),
+                                             stream or current_stream()))
+        return bool(used.value), fac
+
+
+def _lib_check(code):
+    if code != OK:
+        raise MFGMGError(code, "")
+
+
+def mlp_forward(w, x, stream=None):
+    """y [n,3], cache [n,131] for FP32 device tensors w [6147], x [n,27]."""
+    import torch
+    lib = load()
+    n = x.shape[0]
+    y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+    cache = torch.empty((n, MLP_CACHE), dtype=torch.float32, device=x.device)
+    _lib_check(lib.mfgmg_mlp_forward(_dev_ptr(w), _dev_ptr(x), n, _dev_ptr(y), _dev_ptr(cache),
+                                     stream or current_stream()))
+    return y, cache
+
+
+def mlp_backward(w, x, cache, dy, stream=None):
+    import torch
+    lib = load()
+    n = x.shape[0]
+    dw = torch.empty(N_PARAMS, dtype=torch.float32, device=x.device)
+    work = torch.empty(int(lib.mfgmg_mlp_work_size(n)), dtype=torch.float32, device=x.device)
+    _lib_check(lib.mfgmg_mlp_backward(_dev_ptr(w), _dev_ptr(x), _dev_ptr(cache), _dev_ptr(dy), n, _dev_ptr(dw),
+                                      _dev_ptr(work), stream or current_stream()))
+    return dw
+
+
+def mlp_adam(w, dw, m, v, step, lr, stream=None):
+    _lib_check(load().mfgmg_mlp_adam(_dev_ptr(w), _dev_ptr(dw), _dev_ptr(m), _dev_ptr(v), int(step), float(lr),
+                                     stream or current_stream()))
+
+
+def mlp_train(w, feats, targets, epochs=20, batch=4096, lr=1e-3, seed=0, stream=None):
+    """Train in place; returns the per-epoch mean squared error."""
+    hist = np.zeros(max(epochs, 1))
+    _lib_check(load().mfgmg_mlp_train(_dev_ptr(w), _dev_ptr(feats), _dev_ptr(targets), int(feats.shape[0]),
+                                      int(epochs), int(batch), float(lr), int(seed), _np_ptr(hist),
+                                      stream or current_stream()))
+    return hist[:epochs]
