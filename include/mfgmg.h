@@ -255,8 +255,11 @@ int mfgmg_features(mfgmg_ctx* ctx, int32_t level, float* feat_dev, void* stream)
  * e_k SplitMix64 vectors (seeds 777..780 over 3 key + component).
  * lam_fixed > 0 holds the Chebyshev bound fixed, else it is re-estimated
  * (*lam_out receives the value used).  grad_dev (may be NULL):
- * dJ/dy [n_cells][3] FP32 by the adjoint of the V-cycle with lambda constant.
- * Synchronises `stream`. */
+ * dJ/dy [n_cells][3] FP32: the adjoint of the V-cycle at fixed lambda plus,
+ * when lambda is re-estimated, its dependence on the scaling through the
+ * Ritz pair (theta, v) of the estimate: s_i dlambda/ds_i = lambda v_i^2 M_ii /
+ * (v . M v), M = diag(d/s), with dJ/dlambda = -(s . dJ/ds) / lambda (the
+ * smoother depends on s / lambda only).  Synchronises `stream`. */
 int mfgmg_fit_objective(mfgmg_ctx* ctx, int32_t level, const float* y_dev, double lam_fixed, double* J_host,
                         double* lam_out_host, float* grad_dev, void* stream);
 

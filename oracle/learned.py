@@ -22,9 +22,18 @@ predicted by a small network from the local viscosity.  Definitions:
       J(y) = (1/K) sum_k (1/m) log(||E^m e_k||_A / ||e_k||_A),
   E = I - V_l(y) A_l the error propagation of the V-cycle whose level-l
   smoothers use diag(s/d); m = 2, K = 4 SplitMix64 start vectors.  lambda is
-  re-estimated for every y and held constant in the gradient, which is the
-  adjoint of the linear recurrence (reverse sweep through both Chebyshev
-  smoothers and the coarse correction; V_l is symmetric, so E^T = I - A V_l).
+  re-estimated for every y.  The gradient is the adjoint of the linear
+  recurrence at fixed lambda (reverse sweep through both Chebyshev smoothers
+  and the coarse correction; V_l is symmetric, so E^T = I - A V_l) plus the
+  term through lambda(s): the smoother depends on s and lambda only through
+  s / lambda (the Chebyshev coefficients scale as 1/lambda, the interval
+  ratio is fixed), so dJ/dlambda = -(1/lambda) sum_i s_i dJ/ds_i; and the
+  Ritz value theta of the generalized problem A v = theta diag(d/s) v moves
+  by s_i dtheta/ds_i = theta pi_i, pi_i = v_i^2 d_i/s_i / sum_j v_j^2 d_j/s_j,
+  with v the Ritz vector (derivative of the Rayleigh quotient at v).  In
+  log-scaling form the total gradient is q_i - pi_i sum_j q_j with
+  q_i = s_i dJ/ds_i at fixed lambda: J is invariant under s -> c s, and so
+  is its gradient.
   Adam, lr 0.05, 30 steps from y = 0.
 * training: mean squared error of the network output against the targets,
   Adam (lr 1e-3), mini-batches.
@@ -221,11 +230,61 @@ def cheb_reverse(A, minv, dd, lam, rs, xbar, need_x0bar):
     return rbar, x0bar, sbar
 
 
+def cg_lanczos_ritz(apply_A, minv, r0, steps=mg.LANCZOS_STEPS):
+    """Largest Ritz pair (theta, v) of M^{-1} A, M^{-1} = diag(minv), from
+    ``steps`` PCG iterations on A x = r0 from x = 0.
+
+    The preconditioned residuals z_k = M^{-1} r_k are M-orthogonal; with
+    nu_k = sqrt(r_k . z_k), the vectors (-1)^k z_k / nu_k are an M-orthonormal
+    Lanczos basis in which M^{-1} A is the tridiagonal matrix T of the CG
+    coefficients (diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1}, off-diagonal
+    sqrt(beta_k)/alpha_k, both positive).  v = sum_k c_k (-1)^k z_k / nu_k for
+    the eigenvector c of T's largest eigenvalue theta."""
+    r = np.array(r0, dtype=np.float64)
+    z = minv * r
+    p = z.copy()
+    rz = r @ z
+    rz0 = rz
+    alphas, betas, basis = [], [], []
+    for k in range(steps):
+        q = apply_A(p)
+        pq = p @ q
+        if pq <= 0:
+            break
+        basis.append((-1) ** k * z / np.sqrt(rz))
+        alpha = rz / pq
+        alphas.append(alpha)
+        r = r - alpha * q
+        z = minv * r
+        rz_new = r @ z
+        if rz_new <= 1e-30 * rz0:
+            break
+        betas.append(rz_new / rz)
+        p = z + betas[-1] * p
+        rz = rz_new
+    k = len(alphas)
+    T = np.zeros((k, k))
+    for i in range(k):
+        T[i, i] = 1.0 / alphas[i] + (betas[i - 1] / alphas[i - 1] if i > 0 else 0.0)
+        if i + 1 < k:
+            T[i, i + 1] = T[i + 1, i] = np.sqrt(betas[i]) / alphas[i]
+    ev, evec = np.linalg.eigh(T)
+    c = evec[:, -1]
+    return float(ev[-1]), sum(ci * b for ci, b in zip(c, basis))
+
+
+def lambda_sensitivity(minv, free, v):
+    """pi_i = v_i^2 M_ii / sum_j v_j^2 M_jj over free dofs (M = diag(1/minv)):
+    s_i dlambda/ds_i = lambda pi_i for the Ritz-value estimate of lambda."""
+    wgt = np.where(free, v * v / minv, 0.0)
+    return wgt / wgt.sum()
+
+
 class ScaledLevel:
     """The V-cycle of ``multigrid.GMG`` whose level-l smoothers use diag(s/d),
     with the forward states needed by its adjoint."""
 
-    def __init__(self, gmg, ell, s, lam=None):
+    def __init__(self, gmg, ell, s, lam=None, lanczos_steps=mg.LANCZOS_STEPS):
         self.g, self.ell = gmg, ell
         A = gmg.A[ell]
         self.A = A
@@ -233,9 +292,11 @@ class ScaledLevel:
         self.free = gmg.free[ell]
         self.minv = np.where(self.free, s / self.dd, 1.0)
         mesh = gmg.hier.levels[ell]
+        self.ritz = None
         if lam is None:
             r0 = rng.dof_vector(mesh, mg.LAMBDA_SEED) * self.free
-            lam = mg.LAMBDA_SAFETY * mg.cg_lanczos_lambda_max(lambda v: A @ v, self.minv, r0)
+            theta, self.ritz = cg_lanczos_ritz(lambda v: A @ v, self.minv, r0, lanczos_steps)
+            lam = mg.LAMBDA_SAFETY * theta
         self.lam = lam
 
     def coarse(self, r):
@@ -264,12 +325,12 @@ def fit_vectors(mesh, free, k=FIT_K, seed=FIT_SEED):
     return [rng.dof_vector(mesh, seed + i) * free for i in range(k)]
 
 
-def objective(gmg, ell, y, es=None, m=FIT_M, with_grad=True, lam=None):
+def objective(gmg, ell, y, es=None, m=FIT_M, with_grad=True, lam=None, lanczos_steps=mg.LANCZOS_STEPS):
     """J(y) and dJ/dy (per cell, 3 components); lam: hold the Chebyshev bound
-    fixed instead of re-estimating it (finite-difference checks)."""
+    fixed instead of re-estimating it (then the gradient has no lambda term)."""
     mesh = gmg.hier.levels[ell]
     s = dof_scaling(mesh, y)
-    lv = ScaledLevel(gmg, ell, s, lam)
+    lv = ScaledLevel(gmg, ell, s, lam, lanczos_steps)
     A = lv.A
     es = fit_vectors(mesh, lv.free) if es is None else es
     K = len(es)
@@ -296,7 +357,11 @@ def objective(gmg, ell, y, es=None, m=FIT_M, with_grad=True, lam=None):
                 w = w - A @ lv.forward(w)[0]          # E^T w = w - A V w
     if not with_grad:
         return J, None
-    return J, scaling_grad_to_cells(mesh, s, sbar * lv.free)
+    sbar = sbar * lv.free
+    if lv.ritz is not None:                       # the term through lambda(s)
+        pi = lambda_sensitivity(lv.minv, lv.free, lv.ritz)
+        sbar = sbar - pi * (s * sbar).sum() / s
+    return J, scaling_grad_to_cells(mesh, s, sbar)
 
 
 def fit_targets(gmg, ell, steps=30, lr=0.05, es=None):

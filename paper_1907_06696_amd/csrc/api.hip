@@ -113,6 +113,54 @@ double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& 
   return 0.5 * (lo + hi);
 }
 
+// eigenvector of the largest eigenvalue of a symmetric tridiagonal matrix (cyclic
+// Jacobi rotations on the dense matrix; sizes up to the Lanczos step count)
+std::vector<double> tridiag_top_eigvec(const std::vector<double>& d, const std::vector<double>& e) {
+  const int n = int(d.size());
+  std::vector<double> a(size_t(n) * n, 0.0), v(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    a[size_t(i) * n + i] = d[size_t(i)];
+    v[size_t(i) * n + i] = 1.0;
+    if (i + 1 < n) a[size_t(i) * n + i + 1] = a[size_t(i + 1) * n + i] = e[size_t(i)];
+  }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) (i == j ? tot : off) += a[size_t(i) * n + j] * a[size_t(i) * n + j];
+    if (off <= 1e-30 * (tot + off)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[size_t(p) * n + q];
+        if (apq == 0.0) continue;
+        // rotation that zeroes a_pq: t = tan(phi) from cot(2 phi) = (a_qq - a_pp) / (2 a_pq)
+        const double th = (a[size_t(q) * n + q] - a[size_t(p) * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = a[size_t(k) * n + p], akq = a[size_t(k) * n + q];
+          a[size_t(k) * n + p] = c * akp - sn * akq;
+          a[size_t(k) * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = a[size_t(p) * n + k], aqk = a[size_t(q) * n + k];
+          a[size_t(p) * n + k] = c * apk - sn * aqk;
+          a[size_t(q) * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[size_t(k) * n + p], vkq = v[size_t(k) * n + q];
+          v[size_t(k) * n + p] = c * vkp - sn * vkq;
+          v[size_t(k) * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  int best = 0;
+  for (int i = 1; i < n; ++i)
+    if (a[size_t(i) * n + i] > a[size_t(best) * n + best]) best = i;
+  std::vector<double> out(static_cast<size_t>(n));
+  for (int k = 0; k < n; ++k) out[size_t(k)] = v[size_t(k) * n + best];
+  return out;
+}
+
 // Cholesky factorisation and inverse of a dense SPD matrix (row major)
 bool spd_inverse(std::vector<double>& A, int n) {
   std::vector<double> Lm(size_t(n) * n, 0.0);
@@ -373,7 +421,8 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
   return lanczos_lambda(ctx, ell, d.minv_d, &d.lambda, s);
 }
 
-int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out, hipStream_t s) {
+int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out, hipStream_t s, double* basis,
+                   double* ritz) {
   LevelDev& d = ctx->lv[size_t(ell)];
   const Level& h = ctx->mesh->level(ell);
   const int64_t n = 3 * h.nnode;
@@ -395,10 +444,11 @@ int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out,
   double rz = dot_sync(ctx, n, r, z, s);
   const double rz0 = rz;
   std::vector<double> alphas, betas;
-  for (int it = 0; it < 12; ++it) {
+  for (int it = 0; it < kLanczosSteps; ++it) {
     launch_vmult<double>(d.v, p, q, s);
     const double pq = dot_sync(ctx, n, p, q, s);
     if (!(pq > 0)) break;
+    if (ritz) launch_scale_copy(n, (it % 2 ? -1.0 : 1.0) / std::sqrt(rz), z, basis + size_t(it) * size_t(n), s);
     const double alpha = rz / pq;
     alphas.push_back(alpha);
     launch_axpby(n, -alpha, q, 1.0, r, s);
@@ -418,6 +468,11 @@ int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out,
     if (i + 1 < k) e[size_t(i)] = std::sqrt(betas[size_t(i)]) / alphas[size_t(i)];
   }
   *lam_out = 1.2 * tridiag_max_eig(dg, e);
+  if (ritz) {
+    const std::vector<double> c = tridiag_top_eigvec(dg, e);
+    launch_fill(n, 0.0, ritz, s);
+    for (int i = 0; i < k; ++i) launch_axpby(n, c[size_t(i)], basis + size_t(i) * size_t(n), 1.0, ritz, s);
+  }
   HIPCHK(hipStreamSynchronize(s));
   return MFGMG_OK;
 }

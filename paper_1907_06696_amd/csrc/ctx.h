@@ -100,8 +100,12 @@ void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t 
 template <typename T>
 void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s);
 int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s);
-// largest eigenvalue estimate (x 1.2) of diag(minv) A on a level (FP64 CG-Lanczos)
-int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam, hipStream_t s);
+// largest eigenvalue estimate (x 1.2) of diag(minv) A on a level (FP64 CG-Lanczos);
+// with basis (12 n doubles) and ritz (n) non-null, ritz receives the Ritz vector of
+// that eigenvalue (M-orthonormal Lanczos basis (-1)^k z_k / sqrt(r_k . z_k))
+int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam, hipStream_t s,
+                   double* basis = nullptr, double* ritz = nullptr);
+constexpr int kLanczosSteps = 12;
 double splitmix_pm1(uint64_t seed, uint64_t counter);
 int check_level(const mfgmg_ctx* ctx, int32_t level);
 

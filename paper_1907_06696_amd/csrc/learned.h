@@ -40,6 +40,11 @@ void launch_scaling_grad(const DevLevel& L, const double* sbar, const double* sd
 void launch_chebrev_a(int64_t n, const double* xbar, const double* minv, const double* minv_plain, const double* rk,
                       double* dbar, double* rbar, double* sbar, double beta, double sgn, hipStream_t s);
 void launch_chebrev_b(int64_t n, double* dbar, const double* t, double alpha, hipStream_t s);
+// out = v / minv (the Ritz vector weighted by M = diag(1 / minv))
+void launch_ritz_mass(int64_t n, const double* v, const double* minv, double* out, hipStream_t s);
+// sbar -= coef v^2 / (minv sdof): the part of dJ/ds that goes through lambda(s)
+void launch_lambda_term(int64_t n, const double* v, const double* minv, const double* sdof, double coef, double* sbar,
+                        hipStream_t s);
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 // w -= lr (m / bc1) / (sqrt(v / bc2) + eps), bc = 1 - b^t; clamp > 0 clips w
 template <typename T>

@@ -85,6 +85,20 @@ __global__ void k_chebrev_a(int64_t n, const double* __restrict__ xbar, const do
   }
 }
 
+// M-weight of the Ritz vector: out_i = v_i M_ii = v_i / minv_i
+__global__ void k_ritz_mass(int64_t n, const double* __restrict__ v, const double* __restrict__ minv,
+                            double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = v[i] / minv[i];
+}
+
+// term of dJ/ds through lambda(s): sbar_i -= coef v_i^2 M_ii / s_i
+__global__ void k_lambda_term(int64_t n, const double* __restrict__ v, const double* __restrict__ minv,
+                              const double* __restrict__ sdof, double coef, double* __restrict__ sbar) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    sbar[i] -= coef * v[i] * v[i] / (minv[i] * sdof[i]);
+}
+
 __global__ void k_chebrev_b(int64_t n, double* __restrict__ dbar, const double* __restrict__ t, double alpha) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     dbar[i] = alpha * dbar[i] - t[i];
@@ -288,6 +302,13 @@ void launch_scaling_grad(const DevLevel& L, const double* sbar, const double* sd
 void launch_chebrev_a(int64_t n, const double* xbar, const double* minv, const double* mp, const double* rk,
                       double* dbar, double* rbar, double* sbar, double beta, double sgn, hipStream_t s) {
   k_chebrev_a<<<grid_for(n), kBlock, 0, s>>>(n, xbar, minv, mp, rk, dbar, rbar, sbar, beta, sgn);
+}
+void launch_ritz_mass(int64_t n, const double* v, const double* minv, double* out, hipStream_t s) {
+  k_ritz_mass<<<grid_for(n), kBlock, 0, s>>>(n, v, minv, out);
+}
+void launch_lambda_term(int64_t n, const double* v, const double* minv, const double* sdof, double coef, double* sbar,
+                        hipStream_t s) {
+  k_lambda_term<<<grid_for(n), kBlock, 0, s>>>(n, v, minv, sdof, coef, sbar);
 }
 void launch_chebrev_b(int64_t n, double* dbar, const double* t, double alpha, hipStream_t s) {
   k_chebrev_b<<<grid_for(n), kBlock, 0, s>>>(n, dbar, t, alpha);

@@ -67,10 +67,12 @@ struct Fit {
   DBuf buf;
   double *acc, *cnt, *sdof, *minv_s, *sbar, *ybar;
   double *d, *t, *x, *w, *u1, *u2, *dbar, *rbar, *cx, *x1bar, *x2bar, *xb, *bv;
+  double *ritz, *basis;   // Ritz vector of lambda and the Lanczos basis it is built from
   double* es[kFitK];
   double* rs[2][2][4];   // [application][pre, post][k]
   double ne[kFitK];
   double lam = 0.0;
+  bool lam_free = false;  // lambda re-estimated from the scaling (gradient has a lambda term)
 
   bool init(mfgmg_ctx* c, int l, hipStream_t st) {
     ctx = c, ell = l, s = st;
@@ -82,6 +84,7 @@ struct Fit {
     d = buf.get(N), t = buf.get(N), x = buf.get(N), w = buf.get(N), u1 = buf.get(N), u2 = buf.get(N);
     dbar = buf.get(N), rbar = buf.get(N), cx = buf.get(N), x1bar = buf.get(N), x2bar = buf.get(N), xb = buf.get(N);
     bv = buf.get(N);
+    ritz = buf.get(N), basis = buf.get(N * kLanczosSteps);
     for (auto& e : es) e = buf.get(N);
     for (auto& a : rs)
       for (auto& b : a)
@@ -192,11 +195,21 @@ struct Fit {
     launch_fill(n, 0.0, acc, s);
     launch_scaling_accum(L.v, yd, acc, nullptr, s);
     launch_scaling_finish(L.v.nnode, acc, cnt, L.minv_d, sdof, minv_s, nullptr, s);
-    if (lam_fixed > 0) {
+    lam_free = !(lam_fixed > 0);
+    if (!lam_free) {
       lam = lam_fixed;
       return MFGMG_OK;
     }
-    return lanczos_lambda(ctx, ell, minv_s, &lam, s);
+    return lanczos_lambda(ctx, ell, minv_s, &lam, s, basis, ritz);
+  }
+
+  // J depends on s and lambda only through s / lambda, so dJ/dlambda = -(s . sbar) / lambda;
+  // the Ritz value moves by s_i dlambda/ds_i = lambda pi_i, pi_i = v_i^2 M_ii / (v . M v)
+  void add_lambda_term() {
+    const double q = dot_sync(ctx, n, sdof, sbar, s);
+    launch_ritz_mass(n, ritz, minv_s, t, s);
+    const double vmv = dot_sync(ctx, n, ritz, t, s);
+    if (vmv > 0) launch_lambda_term(n, ritz, minv_s, sdof, q / vmv, sbar, s);
   }
 
   // J and (optionally) ybar
@@ -226,6 +239,7 @@ struct Fit {
       launch_axpby(n, -1.0, t, 1.0, w, s);
       reverse(0, w, -1.0);
     }
+    if (grad && lam_free) add_lambda_term();
     if (grad) launch_scaling_grad(lv(), sbar, sdof, cnt, ybar, s);
     *J_out = J;
     return MFGMG_OK;

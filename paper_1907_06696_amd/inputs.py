@@ -113,3 +113,13 @@ CONFIGS = {
     "c5_uniform128p1": dict(base_level=7, sinkers=32, dr=1e6, centre_seed=5,
                             refine_percentile=97.5, refine_levels=1),
 }
+
+
+def learned_field(seed, sinker_range=(4, 32), log10_dr_range=(2.0, 6.0)):
+    """One field of the learned-smoother workload: (centres [n,3], DR) with n
+    uniform in sinker_range (inclusive) and log10 DR uniform in the range."""
+    g = np.random.default_rng(seed)
+    n = int(g.integers(sinker_range[0], sinker_range[1] + 1))
+    dr = float(10.0 ** g.uniform(*log10_dr_range))
+    centres = g.uniform(0.1, 0.9, size=(n, 3))
+    return centres, dr

@@ -1,8 +1,11 @@
 """Pins of the oracle's learned-scaling part: MLP gradients against central
 finite differences, the first Adam step in closed form, scaling invariance of
-the smoother, the adjoint V-cycle gradient against central finite
-differences (lambda held fixed), and feature values on known fields.
-The fitted targets themselves have no closed form (parity unpinned)."""
+the smoother, the Ritz pair of the lambda estimate (Rayleigh quotient,
+exact eigenvalue when converged), the adjoint V-cycle gradient against central
+finite differences (lambda held fixed, and lambda re-estimated by a converged
+Lanczos run), the invariance of the gradient under y -> y + c, and feature
+values on known fields.  The fitted targets themselves have no closed form
+(parity unpinned)."""
 import numpy as np
 import pytest
 
@@ -86,6 +89,65 @@ def test_adjoint_gradient_matches_finite_differences(which):
             fd = (ol.objective(G, ell, y + e, lam=lam, with_grad=False)[0]
                   - ol.objective(G, ell, y - e, lam=lam, with_grad=False)[0]) / (2 * eps)
             assert abs(fd - g[ci, c]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max()), (ci, c, fd, g[ci, c])
+
+
+def _scaled_problem():
+    H = mesh.Hierarchy.uniform(2)
+    G = _gmg(H, 3)
+    ell = 2
+    m = H.levels[ell]
+    y = np.random.default_rng(4).uniform(-0.5, 0.5, (m.ncell, 3))
+    return H, G, ell, m, y
+
+
+def test_ritz_pair_of_lambda_estimate():
+    import scipy.linalg as sla
+    H, G, ell, m, y = _scaled_problem()
+    A, free = G.A[ell], G.free[ell]
+    minv = np.where(free, ol.dof_scaling(m, y) / A.diagonal(), 1.0)
+    r0 = ol.rng.dof_vector(m, mg.LAMBDA_SEED) * free
+    fi = np.nonzero(free)[0]
+    exact = sla.eigh(A.toarray()[np.ix_(fi, fi)], np.diag(1.0 / minv[fi]), eigvals_only=True)[-1]
+    for steps in (12, 40):
+        theta, v = ol.cg_lanczos_ritz(lambda x: A @ x, minv, r0, steps)
+        assert abs(theta - mg.cg_lanczos_lambda_max(lambda x: A @ x, minv, r0, steps)) <= 1e-12 * theta
+        rq = (v @ (A @ v)) / (v @ np.where(free, v / minv, 0.0))
+        assert abs(rq - theta) <= 1e-10 * theta            # a Ritz pair: its Rayleigh quotient is theta
+        assert np.all(v[~free] == 0)
+        assert theta <= exact * (1 + 1e-12)                 # Ritz values lie inside the spectrum
+    assert abs(theta - exact) <= 1e-10 * exact              # 40 steps: converged
+    # the eigenvector residual of the converged pair vanishes
+    r = A @ v - theta * np.where(free, v / minv, 0.0)
+    assert np.linalg.norm(r[free]) <= 1e-6 * np.linalg.norm((A @ v)[free])
+
+
+def test_gradient_with_reestimated_lambda_matches_finite_differences():
+    """With a converged Lanczos estimate lambda(s) is the extreme eigenvalue,
+    whose derivative is the Rayleigh-quotient derivative at v: the full
+    gradient (fixed-lambda adjoint + lambda term) equals central differences
+    of J with lambda re-estimated at every evaluation."""
+    H, G, ell, m, y = _scaled_problem()
+    J, g = ol.objective(G, ell, y, lanczos_steps=40)
+    rg = np.random.default_rng(1)
+    eps = 1e-5
+    for ci in rg.choice(m.ncell, 4, replace=False):
+        for c in range(3):
+            e = np.zeros_like(y)
+            e[ci, c] = eps
+            fd = (ol.objective(G, ell, y + e, with_grad=False, lanczos_steps=40)[0]
+                  - ol.objective(G, ell, y - e, with_grad=False, lanczos_steps=40)[0]) / (2 * eps)
+            assert abs(fd - g[ci, c]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max()), (ci, c, fd, g[ci, c])
+
+
+def test_gradient_is_shift_invariant():
+    """J(y + c) = J(y) for a constant c (lambda re-estimated), so the total
+    gradient sums to zero; the fixed-lambda gradient alone does not."""
+    H, G, ell, m, y = _scaled_problem()
+    _, g = ol.objective(G, ell, y)
+    assert abs(g.sum()) <= 1e-10 * np.abs(g).sum()
+    lam = ol.ScaledLevel(G, ell, ol.dof_scaling(m, y)).lam
+    _, g_fixed = ol.objective(G, ell, y, lam=lam)
+    assert abs(g_fixed.sum()) > 1e-3 * np.abs(g_fixed).sum()
 
 
 def test_fitting_decreases_objective():
