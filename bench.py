@@ -39,7 +39,30 @@ def parse():
     p.add_argument("--no-solve", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
+    p.add_argument("--solve-workload", choices=["c3_adaptive32p2", "c5_uniform128p1"], default=None,
+                   help="instead of the operator benchmark, compare the Stokes solves on this workload")
+    p.add_argument("--counter-probe", action="store_true",
+                   help="only launch the dominant kernel (vmult_add, FP32) and a plain copy of known size, "
+                        "20 times each, for hardware-counter runs")
     return p.parse_args()
+
+
+COPY_BYTES = 256 << 20          # the calibration copy: 256 MiB read + 256 MiB written
+
+
+def counter_probe(s, L, x32, y32):
+    """Kernels for a rocprofv3 --pmc pass: 20 vmult_add (FP32) and 20 copies of
+    COPY_BYTES, so that FETCH_SIZE / WRITE_SIZE per dispatch of the operator
+    can be scaled by what the same counters read for a copy of known size."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=x32.device)
+    b = torch.empty_like(a)
+    for _ in range(20):
+        s.vmult_add(L, x32, y32)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_probe": True, "copy_bytes": COPY_BYTES, "vmult_launches": 20}), flush=True)
 
 
 def cpu_baseline(level, centres, dr, seconds=12.0):
@@ -66,11 +89,85 @@ def cpu_baseline(level, centres, dr, seconds=12.0):
                       f"{threads} threads) on the full {1 << level}^3 mesh, {dt:.1f} s"}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1907_06696_amd", "data", "mlp_sinker32.npz")
+
+
+def solve_compare(s, qp, centres, max_iter=3000):
+    """Stokes solve to 1e-8 (FP64 FGMRES): plain FP64 V-cycle, FP32 V-cycle,
+    and FP32 V-cycle with the learned smoother scaling (installed with its
+    guard; a failed learned solve is redone plain and both costs counted)."""
+    import torch
+    from paper_1907_06696_amd import inputs
+    info = s.info()
+    L = info["L"]
+    n = info["n_u"][L]
+    rhs = torch.empty(n, dtype=torch.float64, device="cuda")
+    s.assemble_rhs(inputs.sinker_force(qp, centres).reshape(-1, 27, 3), rhs)
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    p = torch.empty(info["n_p"], dtype=torch.float64, device="cuda")
+
+    def one(prec, scaled):
+        st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, use_scaling=int(scaled), raise_on_noconv=False,
+                            max_iter=max_iter)
+        return {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
+                "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
+                "converged": bool(st["converged"])}
+
+    out = {"fp64": one("fp64", False), "fp32": one("fp32", False)}
+    w = torch.tensor(np.load(WEIGHTS)["weights"], device="cuda")
+    t0 = time.perf_counter()
+    used, fac = s.apply_mlp(w, guard=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    lrn = one("fp32", True) if used else dict(out["fp32"])
+    if used and not lrn["converged"]:
+        again = one("fp32", False)
+        lrn = dict(again, seconds=round(lrn["seconds"] + again["seconds"], 3),
+                   iterations=lrn["iterations"] + again["iterations"], fallback=True)
+    lrn.update({"learned_used": used, "setup_s": round(t_setup, 3),
+                "vcycle_factor_plain": round(float(fac[0]), 5), "vcycle_factor_learned": round(float(fac[1]), 5)})
+    out["fp32_learned"] = lrn
+    out["speedup_fp32_learned_vs_fp64"] = round(out["fp64"]["seconds"] / max(lrn["seconds"], 1e-9), 3)
+    for lv in range(2, L + 1):
+        s.set_scaling(lv, None)
+    return out
+
+
+def solve_workload(name):
+    """The adaptive 32^3 + 2 (16 sinkers, DR 1e6) and the 128^3 + 1
+    (32 sinkers, DR 1e6) sinker solves; one JSON line each."""
+    import torch
+    from paper_1907_06696_amd import inputs, mfgmg
+    cfg = inputs.CONFIGS[name]
+    centres = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
+    t0 = time.perf_counter()
+    s = mfgmg.Solver(cfg["base_level"])
+    cells = inputs.refinement_cells(cfg["base_level"], centres, cfg["dr"], cfg["refine_percentile"])
+    s.refine(cells, cfg["refine_levels"])
+    s.finalize_mesh()
+    info = s.info()
+    L = info["L"]
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    s.set_viscosity(inputs.sinker_mu(qp, centres, cfg["dr"]).reshape(-1, 27))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[{name}] L={L} cells={info['n_cells'][L]} n_u={info['n_u'][L]} n_p={info['n_p']} "
+          f"hanging={info['n_hanging'][L]} setup {t_setup:.1f} s", flush=True)
+    res = solve_compare(s, qp, centres)
+    print(json.dumps({"workload": name, "cells": info["n_cells"][L], "velocity_dofs": info["n_u"][L],
+                      "pressure_dofs": info["n_p"], "levels": L, "setup_s": round(t_setup, 2),
+                      "stokes_solve_1e-8": res}), flush=True)
+    s.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.solve_workload:
+        solve_workload(args.solve_workload)
+        return
     import torch
     from paper_1907_06696_amd import inputs, mfgmg
 
@@ -100,6 +197,10 @@ def main():
     x32 = x64.float()
     y32 = torch.empty_like(x32)
     y64 = torch.empty_like(x64)
+    if args.counter_probe:
+        counter_probe(s, L, x32, y32)
+        s.close()
+        return
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -172,18 +273,7 @@ def main():
     }
 
     if not args.no_solve:
-        f_qp = inputs.sinker_force(qp, centres).reshape(-1, 27, 3)
-        rhs = torch.empty(n, dtype=torch.float64, device=dev)
-        s.assemble_rhs(f_qp, rhs)
-        u = torch.empty(n, dtype=torch.float64, device=dev)
-        p = torch.empty(info["n_p"], dtype=torch.float64, device=dev)
-        solve = {}
-        for prec in ("fp32", "fp64"):
-            st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, raise_on_noconv=False)
-            solve[prec] = {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
-                           "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
-                           "converged": bool(st["converged"])}
-        result["stokes_solve_1e-8"] = solve
+        result["stokes_solve_1e-8"] = solve_compare(s, qp, centres)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(level, centres, dr)

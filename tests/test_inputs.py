@@ -42,3 +42,21 @@ def test_refinement_cells_deterministic_fraction():
     assert cells.shape[1] == 4 and np.all(cells[:, 0] == 3)
     assert len(cells) <= round(512 * 0.2)
     assert np.array_equal(cells, inputs.refinement_cells(3, cen, 1e2, 80.0))
+
+
+def test_trained_weights_file():
+    import os
+    from paper_1907_06696_amd import learn
+    path = os.path.join(os.path.dirname(learn.__file__), "data", "mlp_sinker32.npz")
+    d = np.load(path)
+    w = d["weights"]
+    assert w.dtype == np.float32 and w.shape == (6147,) and np.all(np.isfinite(w))
+    assert not np.array_equal(w, learn.init_weights(0))       # trained, not the initial draw
+    assert d["loss"][-1] < d["loss"][0]
+
+
+def test_learned_field_ranges():
+    for seed in (10000, 10255, 20000, 20031):
+        c, dr = inputs.learned_field(seed)
+        assert 4 <= len(c) <= 32 and 1e2 <= dr <= 1e6
+        assert np.all((c >= 0.1) & (c <= 0.9))
