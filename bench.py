@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
     p.add_argument("--solve-workload", choices=["c3_adaptive32p2", "c5_uniform128p1"], default=None,
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
+    p.add_argument("--max-iter", type=int, default=3000, help="FGMRES iteration cap of --solve-workload")
+    p.add_argument("--variants", default="fp64,fp32,fp32_learned",
+                   help="solves of --solve-workload (comma separated: fp64, fp32, fp32_learned)")
     p.add_argument("--counter-probe", action="store_true",
                    help="only launch the dominant kernel (vmult_add, FP32) and a plain copy of known size, "
                         "20 times each, for hardware-counter runs")
@@ -92,7 +95,8 @@ def cpu_baseline(level, centres, dr, seconds=12.0):
 WEIGHTS = os.path.join(ROOT, "paper_1907_06696_amd", "data", "mlp_sinker32.npz")
 
 
-def solve_compare(s, qp, centres, max_iter=3000):
+def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
+                  variants=("fp64", "fp32", "fp32_learned")):
     """Stokes solve to 1e-8 (FP64 FGMRES): plain FP64 V-cycle, FP32 V-cycle,
     and FP32 V-cycle with the learned smoother scaling (installed with its
     guard; a failed learned solve is redone plain and both costs counted)."""
@@ -107,13 +111,21 @@ def solve_compare(s, qp, centres, max_iter=3000):
     p = torch.empty(info["n_p"], dtype=torch.float64, device="cuda")
 
     def one(prec, scaled):
+        if verbose:
+            print(f"[solve] {prec}{' + learned scaling' if scaled else ''}", file=sys.stderr, flush=True)
         st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, use_scaling=int(scaled), raise_on_noconv=False,
-                            max_iter=max_iter)
+                            max_iter=max_iter, verbose=verbose, restart=restart)
         return {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
                 "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
                 "converged": bool(st["converged"])}
 
-    out = {"fp64": one("fp64", False), "fp32": one("fp32", False)}
+    out = {"restart": restart}
+    if "fp64" in variants:
+        out["fp64"] = one("fp64", False)
+    if "fp32" in variants or "fp32_learned" in variants:
+        out["fp32"] = one("fp32", False)
+    if "fp32_learned" not in variants:
+        return out
     w = torch.tensor(np.load(WEIGHTS)["weights"], device="cuda")
     t0 = time.perf_counter()
     used, fac = s.apply_mlp(w, guard=True)
@@ -127,15 +139,19 @@ def solve_compare(s, qp, centres, max_iter=3000):
     lrn.update({"learned_used": used, "setup_s": round(t_setup, 3),
                 "vcycle_factor_plain": round(float(fac[0]), 5), "vcycle_factor_learned": round(float(fac[1]), 5)})
     out["fp32_learned"] = lrn
-    out["speedup_fp32_learned_vs_fp64"] = round(out["fp64"]["seconds"] / max(lrn["seconds"], 1e-9), 3)
+    if "fp64" in out:
+        out["speedup_fp32_learned_vs_fp64"] = round(out["fp64"]["seconds"] / max(lrn["seconds"], 1e-9), 3)
     for lv in range(2, L + 1):
         s.set_scaling(lv, None)
     return out
 
 
-def solve_workload(name):
+def solve_workload(name, variants, max_iter=3000):
     """The adaptive 32^3 + 2 (16 sinkers, DR 1e6) and the 128^3 + 1
-    (32 sinkers, DR 1e6) sinker solves; one JSON line each."""
+    (32 sinkers, DR 1e6) sinker solves; one JSON line each.  FGMRES restarts
+    every 120 iterations here: at this contrast and sinker count restarts
+    every 50 stall (the 32^3 + 2 case stagnates near 4e-6 for thousands of
+    iterations) while 120 converges."""
     import torch
     from paper_1907_06696_amd import inputs, mfgmg
     cfg = inputs.CONFIGS[name]
@@ -153,7 +169,7 @@ def solve_workload(name):
     t_setup = time.perf_counter() - t0
     print(f"[{name}] L={L} cells={info['n_cells'][L]} n_u={info['n_u'][L]} n_p={info['n_p']} "
           f"hanging={info['n_hanging'][L]} setup {t_setup:.1f} s", flush=True)
-    res = solve_compare(s, qp, centres)
+    res = solve_compare(s, qp, centres, verbose=100, restart=120, variants=variants, max_iter=max_iter)
     print(json.dumps({"workload": name, "cells": info["n_cells"][L], "velocity_dofs": info["n_u"][L],
                       "pressure_dofs": info["n_p"], "levels": L, "setup_s": round(t_setup, 2),
                       "stokes_solve_1e-8": res}), flush=True)
@@ -166,7 +182,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.solve_workload:
-        solve_workload(args.solve_workload)
+        solve_workload(args.solve_workload, args.variants.split(","), args.max_iter)
         return
     import torch
     from paper_1907_06696_amd import inputs, mfgmg

@@ -210,6 +210,9 @@ typedef struct {
   double schur_rtol;      /* inner pressure-mass CG tolerance (1e-6) */
   int32_t schur_max_iter; /* (200) */
   int32_t use_scaling;    /* 1: use the installed smoother scaling */
+  int32_t verbose;        /* > 0: every `verbose` outer iterations print the
+                             iteration, the residual estimate and the elapsed
+                             time to stderr (0) */
 } mfgmg_solve_opts;
 
 typedef struct {

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -956,6 +957,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->schur_rtol = 1e-6;
   o->schur_max_iter = 200;
   o->use_scaling = 0;
+  o->verbose = 0;
   return MFGMG_OK;
 }
 
@@ -1117,6 +1119,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       g[size_t(j)] = cs[size_t(j)] * g[size_t(j)];
       ++its;
       jd = j + 1;
+      if (o.verbose > 0 && its % o.verbose == 0) {
+        std::fprintf(stderr, "[mfgmg] fgmres it %d  residual estimate %.3e  %.1f s\n", its,
+                     std::fabs(g[size_t(j + 1)]) / bn,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        std::fflush(stderr);
+      }
       if (std::fabs(g[size_t(j + 1)]) <= o.rtol * bn || its >= o.max_iter) break;
     }
     if (bad || jd == 0) break;
