@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <unordered_map>
 #include <cstdio>
 #include <cmath>
 #include <cstring>
@@ -253,6 +254,66 @@ int upload_mesh(mfgmg_ctx* ctx) {
       v.n_reg_cells = int64_t(reg.size());
       v.hang_cells = ctx->upload(hang);
       v.n_hang_cells = int64_t(hang.size());
+      // operator partition into 4^3 blocks, then 2^3 blocks, then single cells
+      {
+        std::unordered_map<uint64_t, int32_t> at;
+        at.reserve(size_t(h.ncell));
+        auto code = [](int l, int64_t i, int64_t j, int64_t k) {
+          return (uint64_t(l) << 58) | (uint64_t(i) << 38) | (uint64_t(j) << 19) | uint64_t(k);
+        };
+        for (int64_t c = 0; c < h.ncell; ++c)
+          at.emplace(code(h.clev[size_t(c)], h.cijk[size_t(3 * c)], h.cijk[size_t(3 * c + 1)],
+                          h.cijk[size_t(3 * c + 2)]),
+                     int32_t(c));
+        std::vector<char> used(static_cast<size_t>(h.ncell), 0);
+        auto make_blocks = [&](int B, std::vector<int32_t>& bslots, std::vector<int32_t>& bcells) {
+          const int E = 2 * B + 1, NC = B * B * B;
+          std::vector<int32_t> cs(static_cast<size_t>(NC));
+          for (int64_t c = 0; c < h.ncell; ++c) {
+            const int l = h.clev[size_t(c)];
+            const int64_t i = h.cijk[size_t(3 * c)], j = h.cijk[size_t(3 * c + 1)], k = h.cijk[size_t(3 * c + 2)];
+            if (used[size_t(c)] || i % B || j % B || k % B || (int64_t(1) << l) < B) continue;
+            bool ok = true;
+            for (int q = 0; q < NC && ok; ++q) {
+              auto it = at.find(code(l, i + q % B, j + (q / B) % B, k + q / (B * B)));
+              ok = it != at.end() && !used[size_t(it->second)];
+              if (ok) cs[size_t(q)] = it->second;
+            }
+            if (!ok) continue;
+            const size_t b0 = bslots.size();
+            bslots.resize(b0 + size_t(E * E * E));
+            for (int q = 0; q < NC; ++q) {
+              const int32_t cq = cs[size_t(q)];
+              used[size_t(cq)] = 1;
+              bcells.push_back(cq);
+              const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
+              for (int a = 0; a < 27; ++a) {
+                const int p = (2 * qa + a % 3) + E * ((2 * qb + (a / 3) % 3) + E * (2 * qc + a / 9));
+                bslots[b0 + size_t(p)] = slots[size_t(27 * int64_t(cq) + a)];
+              }
+            }
+          }
+        };
+        std::vector<int32_t> s4, c4, s2, c2, sreg, shang;
+        make_blocks(4, s4, c4);
+        make_blocks(2, s2, c2);
+        for (int64_t c = 0; c < h.ncell; ++c) {
+          if (used[size_t(c)]) continue;
+          bool hh = false;
+          for (int a = 0; a < 27; ++a) hh = hh || slots[size_t(27 * c + a)] < -1;
+          (hh ? shang : sreg).push_back(int32_t(c));
+        }
+        v.blk4_slots = ctx->upload(s4);
+        v.blk4_cells = ctx->upload(c4);
+        v.n_blk4 = int64_t(c4.size() / 64);
+        v.blk2_slots = ctx->upload(s2);
+        v.blk2_cells = ctx->upload(c2);
+        v.n_blk2 = int64_t(c2.size() / 8);
+        v.single_reg = ctx->upload(sreg);
+        v.n_single_reg = int64_t(sreg.size());
+        v.single_hang = ctx->upload(shang);
+        v.n_single_hang = int64_t(shang.size());
+      }
       v.hptr = ctx->upload(h.hang.ptr);
       v.hmaster = ctx->upload(h.hang.master);
       v.hw_d = ctx->upload(h.hang.weight);

@@ -25,6 +25,19 @@ struct DevLevel {
   int64_t n_hang_cells = 0;
   const int32_t* reg_cells = nullptr;   // the other cells
   int64_t n_reg_cells = 0;
+  // operator partition: blocks of 4^3 and 2^3 same-level cells (node box
+  // slots [(2B+1)^3] and cell indices [B^3] per block, x fastest), and the
+  // remaining single cells with and without hanging nodes
+  const int32_t* blk4_slots = nullptr;
+  const int32_t* blk4_cells = nullptr;
+  int64_t n_blk4 = 0;
+  const int32_t* blk2_slots = nullptr;
+  const int32_t* blk2_cells = nullptr;
+  int64_t n_blk2 = 0;
+  const int32_t* single_reg = nullptr;
+  int64_t n_single_reg = 0;
+  const int32_t* single_hang = nullptr;
+  int64_t n_single_hang = 0;
   const int64_t* cons_nodes = nullptr;  // constrained nodes (Dirichlet + hanging)
   int64_t n_cons = 0;
   const int64_t* hnode = nullptr;       // node of each hanging row

@@ -181,6 +181,109 @@ __global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __r
   }
 }
 
+// Blocks of B x B x B same-level cells on a non-uniform level (complete
+// sibling groups of the level mesh: the 8 children, or the 64 grandchildren,
+// of one cell).  One wave per workgroup treats 64 / B^3 blocks, one lane per
+// cell.  As in the brick kernel, each block's (2B+1)^3 node box is staged in
+// LDS (hanging values resolved from their masters, Dirichlet values zero),
+// the cells gather from LDS, and their results are accumulated in LDS class
+// by class (local node a in {0,1} | {2} per axis: within a class no two cells
+// of a block share a node).  Nodes strictly inside a block belong to its
+// cells alone and are stored; nodes on the block's faces are added with
+// atomics (hanging ones distributed to their masters).  LDS layout per block
+// and component: every axis split into even then odd lattice points.
+template <int B>
+__device__ __forceinline__ int bsplit(int l) {
+  return (l & 1) ? (B + 1) + (l >> 1) : (l >> 1);
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(64) void k_vmult_blocks(int64_t nblk, const int32_t* __restrict__ bslots,
+                                                     const int32_t* __restrict__ bcells,
+                                                     const int8_t* __restrict__ clev, const T* __restrict__ mu,
+                                                     const int64_t* __restrict__ hptr,
+                                                     const int32_t* __restrict__ hm, const T* __restrict__ hw,
+                                                     const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int NC = B * B * B, NB = 64 / NC;   // cells per block, blocks per wave
+  constexpr int E = 2 * B + 1, P = E * E * E, W = 3 * P;
+  __shared__ T buf[NB * W];
+  const int lane = threadIdx.x;
+  const int64_t blk0 = int64_t(blockIdx.x) * NB;
+  // staging: word e = 3 p + comp of block e / W
+  for (int e = lane; e < NB * W; e += 64) {
+    const int bl = e / W, r = e - bl * W, p = r / 3, comp = r - 3 * p;
+    const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+    const int dst = bl * W + comp * P + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
+    T v = T(0);
+    if (blk0 + bl < nblk) {
+      const int32_t sl = bslots[(blk0 + bl) * P + p];
+      if (sl >= 0) {
+        v = x[3 * int64_t(sl) + comp];
+      } else if (sl < -1) {
+        const int64_t h = -int64_t(sl) - 2;
+        for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) v += hw[q] * x[3 * int64_t(hm[q]) + comp];
+      }
+    }
+    buf[dst] = v;
+  }
+  __syncthreads();
+  const int bl = lane / NC, lc = lane - bl * NC;
+  const int ca = lc % B, cb = (lc / B) % B, cc = lc / (B * B);
+  const bool active = blk0 + bl < nblk;
+  const int base = bl * W;
+  T U[3][27];
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 3; ++xx) {
+        const int off = base + bsplit<B>(2 * ca + xx) + E * bsplit<B>(2 * cb + yy) + E * E * bsplit<B>(2 * cc + z);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) U[q][xx + 3 * yy + 9 * z] = buf[off + q * P];
+      }
+  __syncthreads();
+  for (int e = lane; e < NB * W; e += 64) buf[e] = T(0);
+  T coef = T(0);
+  if (active) {
+    const int32_t c = bcells[(blk0 + bl) * NC + lc];
+    coef = mu[c] * T(ldexp(1.0, -int(clev[c])));
+  }
+  cellop::apply_cell<T>(U, coef);
+  __syncthreads();
+#pragma unroll
+  for (int cls = 0; cls < 8; ++cls) {
+    const int ac = cls & 1, bc = (cls >> 1) & 1, zc = cls >> 2;
+#pragma unroll
+    for (int z = zc ? 2 : 0; z < (zc ? 3 : 2); ++z)
+#pragma unroll
+      for (int yy = bc ? 2 : 0; yy < (bc ? 3 : 2); ++yy)
+#pragma unroll
+        for (int xx = ac ? 2 : 0; xx < (ac ? 3 : 2); ++xx) {
+          const int off = base + bsplit<B>(2 * ca + xx) + E * bsplit<B>(2 * cb + yy) + E * E * bsplit<B>(2 * cc + z);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) buf[off + q * P] += U[q][xx + 3 * yy + 9 * z];
+        }
+    __syncthreads();
+  }
+  // write-back
+  for (int e = lane; e < NB * W; e += 64) {
+    const int b2 = e / W, r = e - b2 * W, p = r / 3, comp = r - 3 * p;
+    if (blk0 + b2 >= nblk) continue;
+    const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+    const T v = buf[b2 * W + comp * P + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz)];
+    const int32_t sl = bslots[(blk0 + b2) * P + p];
+    const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+    if (sl >= 0) {
+      if (inner) y[3 * int64_t(sl) + comp] = v;
+      else atomic_add(&y[3 * int64_t(sl) + comp], v);
+    } else if (sl < -1) {
+      const int64_t h = -int64_t(sl) - 2;
+      for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) atomic_add(&y[3 * int64_t(hm[q]) + comp], hw[q] * v);
+    }
+  }
+}
+
 template <typename T>
 const T* hw_of(const DevLevel& L);
 template <>
@@ -813,12 +916,18 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
     return;
   }
   if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
-  if (L.n_reg_cells)
-    k_vmult_general<T, false><<<unsigned((L.n_reg_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
-        L.reg_cells, L.n_reg_cells, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
-  if (L.n_hang_cells)
-    k_vmult_general<T, true><<<unsigned((L.n_hang_cells + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
-        L.hang_cells, L.n_hang_cells, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+  if (L.n_blk4)
+    k_vmult_blocks<T, 4><<<unsigned(L.n_blk4), 64, 0, s>>>(L.n_blk4, L.blk4_slots, L.blk4_cells, L.clev, mu_of<T>(L),
+                                                          L.hptr, L.hmaster, hw_of<T>(L), x, y);
+  if (L.n_blk2)
+    k_vmult_blocks<T, 2><<<unsigned((L.n_blk2 + 7) / 8), 64, 0, s>>>(L.n_blk2, L.blk2_slots, L.blk2_cells, L.clev,
+                                                                    mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+  if (L.n_single_reg)
+    k_vmult_general<T, false><<<unsigned((L.n_single_reg + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
+  if (L.n_single_hang)
+    k_vmult_general<T, true><<<unsigned((L.n_single_hang + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+        L.single_hang, L.n_single_hang, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
 }
 template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t, bool);
 template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t, bool);
