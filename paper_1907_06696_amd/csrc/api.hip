@@ -266,9 +266,20 @@ int upload_mesh(mfgmg_ctx* ctx) {
                           h.cijk[size_t(3 * c + 2)]),
                      int32_t(c));
         std::vector<char> used(static_cast<size_t>(h.ncell), 0);
-        auto make_blocks = [&](int B, std::vector<int32_t>& bslots, std::vector<int32_t>& bcells) {
-          const int E = 2 * B + 1, NC = B * B * B;
-          std::vector<int32_t> cs(static_cast<size_t>(NC));
+        // A block keeps, per hanging lattice point, its masters as lattice
+        // points of the same block (a hanging node lies on the face shared with
+        // a coarser cell, whose face nodes are all on the block's lattice);
+        // blocks where that fails are left to the single-cell kernel.
+        struct Blocks {
+          std::vector<int32_t> slots, cells, hoff{0}, hent;
+          std::vector<double> hw;
+        };
+        auto make_blocks = [&](int B, Blocks& out) {
+          const int E = 2 * B + 1, NC = B * B * B, P = E * E * E, NB = 64 / NC;
+          std::vector<int32_t> cs(static_cast<size_t>(NC)), bs(static_cast<size_t>(P));
+          std::unordered_map<int32_t, int32_t> at_node;
+          std::vector<int32_t> ent;
+          std::vector<double> wt;
           for (int64_t c = 0; c < h.ncell; ++c) {
             const int l = h.clev[size_t(c)];
             const int64_t i = h.cijk[size_t(3 * c)], j = h.cijk[size_t(3 * c + 1)], k = h.cijk[size_t(3 * c + 2)];
@@ -280,35 +291,63 @@ int upload_mesh(mfgmg_ctx* ctx) {
               if (ok) cs[size_t(q)] = it->second;
             }
             if (!ok) continue;
-            const size_t b0 = bslots.size();
-            bslots.resize(b0 + size_t(E * E * E));
             for (int q = 0; q < NC; ++q) {
-              const int32_t cq = cs[size_t(q)];
-              used[size_t(cq)] = 1;
-              bcells.push_back(cq);
               const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
               for (int a = 0; a < 27; ++a) {
                 const int p = (2 * qa + a % 3) + E * ((2 * qb + (a / 3) % 3) + E * (2 * qc + a / 9));
-                bslots[b0 + size_t(p)] = slots[size_t(27 * int64_t(cq) + a)];
+                bs[size_t(p)] = slots[size_t(27 * int64_t(cs[size_t(q)]) + a)];
               }
             }
+            at_node.clear();
+            for (int p = 0; p < P; ++p)
+              if (bs[size_t(p)] >= 0) at_node[bs[size_t(p)]] = p;
+            ent.clear();
+            wt.clear();
+            const int32_t bl = int32_t((out.cells.size() / size_t(NC)) % size_t(NB));
+            for (int p = 0; p < P && ok; ++p) {
+              if (bs[size_t(p)] >= -1) continue;
+              const int64_t hr = -int64_t(bs[size_t(p)]) - 2;
+              for (int64_t q = h.hang.ptr[size_t(hr)]; q < h.hang.ptr[size_t(hr + 1)] && ok; ++q) {
+                auto it = at_node.find(h.hang.master[size_t(q)]);
+                ok = it != at_node.end();
+                if (ok) {
+                  ent.push_back(p | (it->second << 10) | (bl << 20));
+                  wt.push_back(h.hang.weight[size_t(q)]);
+                }
+              }
+            }
+            if (!ok) continue;
+            for (int q = 0; q < NC; ++q) {
+              used[size_t(cs[size_t(q)])] = 1;
+              out.cells.push_back(cs[size_t(q)]);
+            }
+            for (int p = 0; p < P; ++p) out.slots.push_back(bs[size_t(p)] < -1 ? -2 : bs[size_t(p)]);
+            out.hent.insert(out.hent.end(), ent.begin(), ent.end());
+            out.hw.insert(out.hw.end(), wt.begin(), wt.end());
+            out.hoff.push_back(int32_t(out.hent.size()));
           }
         };
-        std::vector<int32_t> s4, c4, s2, c2, sreg, shang;
-        make_blocks(4, s4, c4);
-        make_blocks(2, s2, c2);
+        Blocks b4, b2;
+        std::vector<int32_t> sreg, shang;
+        make_blocks(4, b4);
+        make_blocks(2, b2);
         for (int64_t c = 0; c < h.ncell; ++c) {
           if (used[size_t(c)]) continue;
           bool hh = false;
           for (int a = 0; a < 27; ++a) hh = hh || slots[size_t(27 * c + a)] < -1;
           (hh ? shang : sreg).push_back(int32_t(c));
         }
-        v.blk4_slots = ctx->upload(s4);
-        v.blk4_cells = ctx->upload(c4);
-        v.n_blk4 = int64_t(c4.size() / 64);
-        v.blk2_slots = ctx->upload(s2);
-        v.blk2_cells = ctx->upload(c2);
-        v.n_blk2 = int64_t(c2.size() / 8);
+        auto upload_blocks = [&](const Blocks& b, DevBlocks& d, int NC) {
+          d.slots = ctx->upload(b.slots);
+          d.cells = ctx->upload(b.cells);
+          d.n = int64_t(b.cells.size() / size_t(NC));
+          d.hoff = ctx->upload(b.hoff);
+          d.hent = ctx->upload(b.hent);
+          d.hw_d = ctx->upload(b.hw);
+          d.hw_f = ctx->upload(std::vector<float>(b.hw.begin(), b.hw.end()));
+        };
+        upload_blocks(b4, v.blk4, 64);
+        upload_blocks(b2, v.blk2, 8);
         v.single_reg = ctx->upload(sreg);
         v.n_single_reg = int64_t(sreg.size());
         v.single_hang = ctx->upload(shang);

@@ -7,6 +7,21 @@
 
 namespace mfgmg {
 
+// Blocks of B^3 same-level cells of a non-uniform level: node-box slots
+// [(2B+1)^3] per block (x fastest; node >= 0 free, -1 Dirichlet, -2
+// hanging), cell indices [B^3], and the hanging points' masters as lattice
+// points of the same block: entries hoff[b] .. hoff[b+1] of block b pack
+// (point | master << 10 | (b mod blocks-per-workgroup) << 20) with weight hw.
+struct DevBlocks {
+  const int32_t* slots = nullptr;
+  const int32_t* cells = nullptr;
+  const int32_t* hoff = nullptr;
+  const int32_t* hent = nullptr;
+  const double* hw_d = nullptr;
+  const float* hw_f = nullptr;
+  int64_t n = 0;
+};
+
 // Device view of one level mesh.
 struct DevLevel {
   int ell = 0;
@@ -25,15 +40,9 @@ struct DevLevel {
   int64_t n_hang_cells = 0;
   const int32_t* reg_cells = nullptr;   // the other cells
   int64_t n_reg_cells = 0;
-  // operator partition: blocks of 4^3 and 2^3 same-level cells (node box
-  // slots [(2B+1)^3] and cell indices [B^3] per block, x fastest), and the
+  // operator partition: blocks of 4^3 and 2^3 same-level cells, and the
   // remaining single cells with and without hanging nodes
-  const int32_t* blk4_slots = nullptr;
-  const int32_t* blk4_cells = nullptr;
-  int64_t n_blk4 = 0;
-  const int32_t* blk2_slots = nullptr;
-  const int32_t* blk2_cells = nullptr;
-  int64_t n_blk2 = 0;
+  DevBlocks blk4, blk2;
   const int32_t* single_reg = nullptr;
   int64_t n_single_reg = 0;
   const int32_t* single_hang = nullptr;

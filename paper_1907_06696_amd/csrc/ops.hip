@@ -1,6 +1,8 @@
 // Device kernels for the matrix-free GMG Stokes path (gfx950, wave64).
 #include "ops.h"
 
+#include <algorithm>
+
 #include "brick_kernel.h"
 #include "cell_kernel.h"
 
@@ -185,51 +187,90 @@ __global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __r
 // sibling groups of the level mesh: the 8 children, or the 64 grandchildren,
 // of one cell).  One wave per workgroup treats 64 / B^3 blocks, one lane per
 // cell.  As in the brick kernel, each block's (2B+1)^3 node box is staged in
-// LDS (hanging values resolved from their masters, Dirichlet values zero),
-// the cells gather from LDS, and their results are accumulated in LDS class
-// by class (local node a in {0,1} | {2} per axis: within a class no two cells
-// of a block share a node).  Nodes strictly inside a block belong to its
-// cells alone and are stored; nodes on the block's faces are added with
-// atomics (hanging ones distributed to their masters).  LDS layout per block
-// and component: every axis split into even then odd lattice points.
+// LDS, the cells gather from LDS, and their results are accumulated in LDS
+// class by class (local node a in {0,1} | {2} per axis: within a class no
+// two cells of a block share a node).  Hanging points are resolved inside
+// the box: their masters are lattice points of the same block, so the
+// gather interpolates them from the staged masters and the write-back first
+// distributes their accumulated values onto the masters (LDS atomics; few
+// points).  Nodes strictly inside a block belong to its cells alone and are
+// stored; nodes on its faces are added with global atomics.  LDS layout per
+// block and component: every axis split into even then odd lattice points.
 template <int B>
 __device__ __forceinline__ int bsplit(int l) {
   return (l & 1) ? (B + 1) + (l >> 1) : (l >> 1);
 }
 
+template <typename T>
+__device__ __forceinline__ const T* blk_hw(const DevBlocks& b);
+template <>
+__device__ __forceinline__ const float* blk_hw<float>(const DevBlocks& b) {
+  return b.hw_f;
+}
+template <>
+__device__ __forceinline__ const double* blk_hw<double>(const DevBlocks& b) {
+  return b.hw_d;
+}
+
 template <typename T, int B>
-__global__ __launch_bounds__(64) void k_vmult_blocks(int64_t nblk, const int32_t* __restrict__ bslots,
-                                                     const int32_t* __restrict__ bcells,
-                                                     const int8_t* __restrict__ clev, const T* __restrict__ mu,
-                                                     const int64_t* __restrict__ hptr,
-                                                     const int32_t* __restrict__ hm, const T* __restrict__ hw,
-                                                     const T* __restrict__ x, T* __restrict__ y) {
+__global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t* __restrict__ clev,
+                                                     const T* __restrict__ mu, const T* __restrict__ x,
+                                                     T* __restrict__ y) {
   constexpr int NC = B * B * B, NB = 64 / NC;   // cells per block, blocks per wave
   constexpr int E = 2 * B + 1, P = E * E * E, W = 3 * P;
+  constexpr int KP = (NB * P + 63) / 64;        // lattice points per lane
   __shared__ T buf[NB * W];
   const int lane = threadIdx.x;
   const int64_t blk0 = int64_t(blockIdx.x) * NB;
-  // staging: word e = 3 p + comp of block e / W
-  for (int e = lane; e < NB * W; e += 64) {
-    const int bl = e / W, r = e - bl * W, p = r / 3, comp = r - 3 * p;
+  const int nb = int(std::min<int64_t>(NB, blk.n - blk0));   // blocks of this wave
+  const int np = nb * P;
+  const T* __restrict__ hw = blk_hw<T>(blk);
+  // lattice point p of the wave (block p / P) -> LDS offset of its component 0
+  auto lds_of = [&](int bl, int p) {
     const int px = p % E, py = (p / E) % E, pz = p / (E * E);
-    const int dst = bl * W + comp * P + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
-    T v = T(0);
-    if (blk0 + bl < nblk) {
-      const int32_t sl = bslots[(blk0 + bl) * P + p];
-      if (sl >= 0) {
-        v = x[3 * int64_t(sl) + comp];
-      } else if (sl < -1) {
-        const int64_t h = -int64_t(sl) - 2;
-        for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) v += hw[q] * x[3 * int64_t(hm[q]) + comp];
+    return bl * W + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
+  };
+  const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
+  // staging: every slot load, then every value load, issued before use;
+  // points of missing blocks, Dirichlet and hanging points store zero
+  {
+    int32_t sl[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      sl[k] = pa < np ? blk.slots[blk0 * P + pa] : -1;
+    }
+    T v[KP][3];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int64_t i = 3 * int64_t(sl[k] >= 0 ? sl[k] : 0);
+      v[k][0] = x[i], v[k][1] = x[i + 1], v[k][2] = x[i + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      if (pa < NB * P) {
+        const int o = lds_of(pa / P, pa % P);
+        const bool f = sl[k] >= 0;
+        buf[o] = f ? v[k][0] : T(0);
+        buf[o + P] = f ? v[k][1] : T(0);
+        buf[o + 2 * P] = f ? v[k][2] : T(0);
       }
     }
-    buf[dst] = v;
+  }
+  __syncthreads();
+  // hanging points: interpolate from their masters in the box
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.hent[e];
+    const int p = en & 1023, pm = (en >> 10) & 1023, bl = en >> 20;
+    const T w = hw[e];
+    const int o = lds_of(bl, p), om = lds_of(bl, pm);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) atomicAdd(&buf[o + q * P], w * buf[om + q * P]);
   }
   __syncthreads();
   const int bl = lane / NC, lc = lane - bl * NC;
   const int ca = lc % B, cb = (lc / B) % B, cc = lc / (B * B);
-  const bool active = blk0 + bl < nblk;
   const int base = bl * W;
   T U[3][27];
 #pragma unroll
@@ -245,8 +286,8 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(int64_t nblk, const int32_t
   __syncthreads();
   for (int e = lane; e < NB * W; e += 64) buf[e] = T(0);
   T coef = T(0);
-  if (active) {
-    const int32_t c = bcells[(blk0 + bl) * NC + lc];
+  if (bl < nb) {
+    const int32_t c = blk.cells[(blk0 + bl) * NC + lc];
     coef = mu[c] * T(ldexp(1.0, -int(clev[c])));
   }
   cellop::apply_cell<T>(U, coef);
@@ -266,20 +307,37 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(int64_t nblk, const int32_t
         }
     __syncthreads();
   }
-  // write-back
-  for (int e = lane; e < NB * W; e += 64) {
-    const int b2 = e / W, r = e - b2 * W, p = r / 3, comp = r - 3 * p;
-    if (blk0 + b2 >= nblk) continue;
+  // hanging points pass their accumulated values on to their masters (the
+  // hanging entries themselves are not read again)
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.hent[e];
+    const int p = en & 1023, pm = (en >> 10) & 1023, bl2 = en >> 20;
+    const T w = hw[e];
+    const int o = lds_of(bl2, p), om = lds_of(bl2, pm);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) atomicAdd(&buf[om + q * P], w * buf[o + q * P]);
+  }
+  __syncthreads();
+  // write-back of the free points: inside the block stored, on its faces added
+  int32_t sl[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int pa = lane + 64 * k;
+    sl[k] = pa < np ? blk.slots[blk0 * P + pa] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (sl[k] < 0) continue;
+    const int pa = lane + 64 * k, p = pa % P;
+    const int o = lds_of(pa / P, p);
+    const T v0 = buf[o], v1 = buf[o + P], v2 = buf[o + 2 * P];
     const int px = p % E, py = (p / E) % E, pz = p / (E * E);
-    const T v = buf[b2 * W + comp * P + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz)];
-    const int32_t sl = bslots[(blk0 + b2) * P + p];
     const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
-    if (sl >= 0) {
-      if (inner) y[3 * int64_t(sl) + comp] = v;
-      else atomic_add(&y[3 * int64_t(sl) + comp], v);
-    } else if (sl < -1) {
-      const int64_t h = -int64_t(sl) - 2;
-      for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) atomic_add(&y[3 * int64_t(hm[q]) + comp], hw[q] * v);
+    T* yp = y + 3 * int64_t(sl[k]);
+    if (inner) {
+      yp[0] = v0, yp[1] = v1, yp[2] = v2;
+    } else {
+      atomic_add(yp, v0), atomic_add(yp + 1, v1), atomic_add(yp + 2, v2);
     }
   }
 }
@@ -916,12 +974,8 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
     return;
   }
   if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
-  if (L.n_blk4)
-    k_vmult_blocks<T, 4><<<unsigned(L.n_blk4), 64, 0, s>>>(L.n_blk4, L.blk4_slots, L.blk4_cells, L.clev, mu_of<T>(L),
-                                                          L.hptr, L.hmaster, hw_of<T>(L), x, y);
-  if (L.n_blk2)
-    k_vmult_blocks<T, 2><<<unsigned((L.n_blk2 + 7) / 8), 64, 0, s>>>(L.n_blk2, L.blk2_slots, L.blk2_cells, L.clev,
-                                                                    mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+  if (L.blk4.n) k_vmult_blocks<T, 4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
+  if (L.blk2.n) k_vmult_blocks<T, 2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
   if (L.n_single_reg)
     k_vmult_general<T, false><<<unsigned((L.n_single_reg + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
         L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
