@@ -231,7 +231,7 @@ int upload_mesh(mfgmg_ctx* ctx) {
       if (h.ntype[size_t(i)] != NODE_FREE) cons.push_back(i);
     v.cons_nodes = ctx->upload(cons);
     v.n_cons = int64_t(cons.size());
-    if (!h.uniform) {
+    if (!h.uniform || ell == L) {   // the leaf keeps cell tables for the pressure operators
       std::vector<int32_t> slots(static_cast<size_t>(27 * h.ncell));
       std::vector<int8_t> clev(static_cast<size_t>(h.ncell));
       std::vector<int32_t> reg, hang;
@@ -368,6 +368,15 @@ int upload_mesh(mfgmg_ctx* ctx) {
       d.R_ptr = ctx->upload(h.R_ptr);
       d.R_col = ctx->upload(h.R_col);
       d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
+    }
+    if (h.uniform) {
+      const int64_t wf = brick_halo_words<float>(h.n_edge), wd = brick_halo_words<double>(h.n_edge);
+      if (wf) v.halo_f = ctx->dalloc<float>(size_t(wf));
+      if (wd) v.halo_d = ctx->dalloc<double>(size_t(wd));
+      if ((wf && !v.halo_f) || (wd && !v.halo_d)) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+      // the zero pad after the slots is read by the halo kernel and never written
+      if (wf) HIPCHK(hipMemset(v.halo_f + (wf - 64), 0, 64 * sizeof(float)));
+      if (wd) HIPCHK(hipMemset(v.halo_d + (wd - 64), 0, 64 * sizeof(double)));
     }
     if (ell < L) d.mu_src = ctx->upload(h.mu_src);
     d.mu_d = ctx->dalloc<double>(size_t(h.ncell));

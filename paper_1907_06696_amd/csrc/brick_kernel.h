@@ -19,9 +19,14 @@
 //     different waves and are separated by block barriers; classes along x
 //     and y couple lanes of one wave, whose LDS operations complete in
 //     order, and are separated by an LDS wait and a compiler barrier.
-//  4. Write back row by row: nodes inside the brick belong to it alone (plain
-//     store), nodes on its faces are shared with neighbouring bricks (global
-//     atomic add into the initialised output), Dirichlet nodes are skipped.
+//  4. Write back row by row, owner computes: a node belongs to the brick whose
+//     half-open box holds it (the last brick along an axis also owns the
+//     closing plane).  Owned nodes are stored (added when accumulating), the
+//     brick's contributions to nodes on its high faces, owned by its upper
+//     neighbours, go to the brick's slot of a halo buffer, and the second
+//     kernel adds every neighbour's halo values into the low-face nodes of
+//     their owner.  No atomics, and no separate initialisation of the output:
+//     owned Dirichlet nodes receive y = x (identity rows) unless accumulating.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,8 +43,18 @@ __device__ __forceinline__ int split_index(int l) {
   return (l & 1) ? (B + 1) + (l >> 1) : (l >> 1);
 }
 
-template <typename T, int BX, int BY, int BZ>
-__global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x, T* __restrict__ y) {
+// ACC: nodes inside the brick are added to y (y += A x); otherwise stored
+// (the caller initialised y to zero on free nodes)
+// halo slot of brick b: [NZ][NY][3 NX] values, x fastest (node-major); the
+// buffer holds one slot per brick followed by a pad of 64 zeros
+template <int BX, int BY, int BZ>
+constexpr int64_t halo_words() {
+  return int64_t(2 * BZ + 1) * (2 * BY + 1) * 3 * (2 * BX + 1);
+}
+
+template <typename T, int BX, int BY, int BZ, bool ACC>
+__global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x,
+                                                              T* __restrict__ y, T* __restrict__ halo) {
   constexpr int NT = BX * BY * BZ, NW = NT / 64;
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;
   constexpr int RX = 24, PL = RX * NY, CS = PL * NZ;
@@ -140,6 +155,27 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
     }
   }
   T* yrow = y + 3 * int64_t(X) + comp;
+  const bool x_own = lx < NX - 1 || bx == nbx - 1;
+  const int nbz = n / BZ;
+  T* hrow = halo + int64_t(b) * halo_words<BX, BY, BZ>() + lane;
+  // values read back before any store (so their latency is paid once):
+  // accumulating, the old values of the owned nodes; otherwise x on the owned
+  // Dirichlet nodes (identity rows)
+  T old[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int r = w + k * NW;
+    old[k] = T(0);
+    if (r < NR && lane_ok) {
+      const int ly = r % NY, lz = r / NY;
+      const int Y = Y0 + ly, Z = Z0 + lz;
+      const bool own = x_own && (ly < NY - 1 || by == nby - 1) && (lz < NZ - 1 || bz == nbz - 1);
+      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
+      const int64_t node3 = 3 * (int64_t(m) * (Y + int64_t(m) * Z));
+      if (ACC && own && !dir) old[k] = yrow[node3];
+      if (!ACC && own && dir) old[k] = xrow[node3];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int r = w + k * NW;
@@ -147,15 +183,81 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
       const int ly = r % NY, lz = r / NY;
       const int Y = Y0 + ly, Z = Z0 + lz;
       const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
+      const bool own = x_own && (ly < NY - 1 || by == nby - 1) && (lz < NZ - 1 || bz == nbz - 1);
+      const int64_t node3 = 3 * (int64_t(m) * (Y + int64_t(m) * Z));
       if (!dir) {
         const T val = buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX];
-        T* p = yrow + 3 * (int64_t(m) * (Y + int64_t(m) * Z));
-        const bool inner = lx > 0 && lx < NX - 1 && ly > 0 && ly < NY - 1 && lz > 0 && lz < NZ - 1;
-        if (inner) *p = val;
-        else atomicAdd(p, val);
+        if (own) yrow[node3] = ACC ? old[k] + val : val;
+        else hrow[(lz * NY + ly) * ROW] = val;
+      } else if (own && !ACC) {
+        yrow[node3] = old[k];   // identity row
       }
     }
   }
+}
+
+// Adds the halo values of a node's lower neighbour bricks into the node, for
+// every free node on a low face of its owner brick.  One workgroup per
+// brick; its low-face nodes are enumerated as the z-face (lz = 0), then the
+// y-face without it, then the x-face without both, thread t taking
+// component t mod 3 of node t / 3 (consecutive threads, consecutive words).
+template <typename T, int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void k_brick_halo_add(int n, const T* __restrict__ halo, T* __restrict__ y) {
+  constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1, ROW = 3 * NX;
+  constexpr int MAXN = NX * NY + NX * (NZ - 1) + (NY - 1) * (NZ - 1);   // low-face nodes, at most
+  constexpr int KT = (3 * MAXN + 255) / 256;                             // items per thread
+  const int nbx = n / BX, nby = n / BY, nbz = n / BZ;
+  const int b = blockIdx.x;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int m = 2 * n + 1;
+  const int X0 = 2 * BX * bx, Y0 = 2 * BY * by, Z0 = 2 * BZ * bz;
+  // owned local extents: [0, e) along each axis
+  const int ex = bx == nbx - 1 ? NX : NX - 1, ey = by == nby - 1 ? NY : NY - 1, ez = bz == nbz - 1 ? NZ : NZ - 1;
+  const int y1 = bz > 0 ? 1 : 0, x1 = by > 0 ? 1 : 0;
+  const int fz = bz > 0 ? ex * ey : 0;
+  const int fy = by > 0 ? ex * (ez - y1) : 0;
+  const int fx = bx > 0 ? (ey - x1) * (ez - y1) : 0;
+  const int total = 3 * (fz + fy + fx);
+  // every load of a thread's items is issued before its first store, without
+  // branches: reads that do not apply go to the zero pad after the last slot
+  const T* zero = halo + int64_t(nbx) * nby * nbz * halo_words<BX, BY, BZ>();
+  T acc[KT], cur[KT];
+  int64_t dst[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int t = threadIdx.x + 256 * k;
+    acc[k] = T(0), cur[k] = T(0), dst[k] = -1;
+    const int tt = t < total ? t : 0;   // items past the end are dead (read the pad, store nothing)
+    const int i = tt / 3, comp = tt - 3 * i;
+    int lx, ly, lz;
+    if (i < fz) {
+      lz = 0, ly = i / ex, lx = i - ly * ex;
+    } else if (i < fz + fy) {
+      const int j = i - fz;
+      ly = 0, lz = y1 + j / ex, lx = j % ex;
+    } else {
+      const int j = i - fz - fy, wd = ey - x1;
+      lx = 0, lz = y1 + j / wd, ly = x1 + j % wd;
+    }
+    const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
+    const bool live = t < total && !(X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1);
+    const bool lowx = live && lx == 0 && bx > 0, lowy = live && ly == 0 && by > 0, lowz = live && lz == 0 && bz > 0;
+#pragma unroll
+    for (int s = 1; s < 8; ++s) {
+      const int sx = s & 1, sy = (s >> 1) & 1, sz = s >> 2;
+      const bool use = !((sx && !lowx) || (sy && !lowy) || (sz && !lowz));
+      const int64_t nb = (bx - sx) + int64_t(nbx) * ((by - sy) + int64_t(nby) * (bz - sz));
+      const int qx = sx ? 2 * BX : lx, qy = sy ? 2 * BY : ly, qz = sz ? 2 * BZ : lz;
+      const T* src = use ? halo + nb * halo_words<BX, BY, BZ>() + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp : zero;
+      acc[k] += *src;
+    }
+    const int64_t d = 3 * (X + int64_t(m) * (Y + int64_t(m) * Z)) + comp;
+    dst[k] = live ? d : -1;
+    cur[k] = *(live ? y + d : zero);
+  }
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if (dst[k] >= 0) y[dst[k]] = cur[k] + acc[k];
 }
 
 }  // namespace brick

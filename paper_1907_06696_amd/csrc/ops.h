@@ -54,7 +54,15 @@ struct DevLevel {
   // per-cell viscosity
   const double* mu_d = nullptr;
   const float* mu_f = nullptr;
+  // uniform levels: halo slots of the brick kernel (brick_halo_words entries)
+  float* halo_f = nullptr;
+  double* halo_d = nullptr;
 };
+
+// entries of the brick kernel's halo buffer on a uniform level of n cells per
+// edge (0 when the brick kernel does not apply)
+template <typename T>
+int64_t brick_halo_words(int64_t n);
 
 template <typename T>
 const T* mu_of(const DevLevel& L);

@@ -2,6 +2,7 @@
 #include "ops.h"
 
 #include <algorithm>
+#include <utility>
 
 #include "brick_kernel.h"
 #include "cell_kernel.h"
@@ -212,7 +213,8 @@ __device__ __forceinline__ const double* blk_hw<double>(const DevBlocks& b) {
   return b.hw_d;
 }
 
-template <typename T, int B>
+// ACC: inner points are added to y (y += A x); otherwise stored (y was initialised to zero there)
+template <typename T, int B, bool ACC>
 __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t* __restrict__ clev,
                                                      const T* __restrict__ mu, const T* __restrict__ x,
                                                      T* __restrict__ y) {
@@ -334,7 +336,9 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     const int px = p % E, py = (p / E) % E, pz = p / (E * E);
     const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
     T* yp = y + 3 * int64_t(sl[k]);
-    if (inner) {
+    if (inner && ACC) {
+      yp[0] += v0, yp[1] += v1, yp[2] += v2;
+    } else if (inner) {
       yp[0] = v0, yp[1] = v1, yp[2] = v2;
     } else {
       atomic_add(yp, v0), atomic_add(yp + 1, v1), atomic_add(yp + 2, v2);
@@ -771,7 +775,7 @@ __global__ void k_mupdate(int64_t n, int nv, const double* __restrict__ V, int64
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    y[i] = a * x[i] + b * y[i];
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];   // b = 0: y is not read (may be uninitialised)
 }
 __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -838,10 +842,12 @@ __device__ __forceinline__ void vscatter1(const DevLevel& L, int32_t s, int comp
   }
 }
 
-__global__ __launch_bounds__(kCellBlock) void k_div(DevLevel L, DevPressure P, const double* __restrict__ u,
+__global__ __launch_bounds__(kCellBlock) void k_div(DevLevel L, DevPressure P, const int32_t* __restrict__ cells,
+                                                    int64_t ncells, const double* __restrict__ u,
                                                     double* __restrict__ po) {
-  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (c >= L.ncell) return;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= ncells) return;
+  const int64_t c = cells ? cells[t] : t;
   const double h = cell_h(L, c);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = 0; a < 27; ++a) {
@@ -855,10 +861,12 @@ __global__ __launch_bounds__(kCellBlock) void k_div(DevLevel L, DevPressure P, c
   for (int i = 0; i < 8; ++i) pscatter(P, P.pslots[8 * c + i], h * h * acc[i], po);
 }
 
-__global__ __launch_bounds__(kCellBlock) void k_grad_add(DevLevel L, DevPressure P, const double* __restrict__ p,
-                                                         double* __restrict__ uo) {
-  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (c >= L.ncell) return;
+__global__ __launch_bounds__(kCellBlock) void k_grad_add(DevLevel L, DevPressure P,
+                                                         const int32_t* __restrict__ cells, int64_t ncells,
+                                                         const double* __restrict__ p, double* __restrict__ uo) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= ncells) return;
+  const int64_t c = cells ? cells[t] : t;
   const double h = cell_h(L, c);
   double pl[8];
   for (int i = 0; i < 8; ++i) pl[i] = h * h * pgather(P, P.pslots[8 * c + i], p);
@@ -886,6 +894,172 @@ __global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P,
     for (int j = 0; j < 8; ++j) v += c_mhat[i * 8 + j] * pl[j];
     pscatter(P, P.pslots[8 * c + i], s * v, po);
   }
+}
+
+// B^T p (added into uo) and B u on the blocks of the leaf (FP64): the
+// velocity side goes through the block's LDS node box exactly as in the
+// operator kernel (hanging points resolved in the box, class-ordered
+// accumulation, atomics only on block faces); the 8 pressure values of a
+// cell are gathered (or scattered) directly.
+template <int B>
+__global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, DevPressure P,
+                                                    const double* __restrict__ p, double* __restrict__ uo) {
+  constexpr int NC = B * B * B, NB = 64 / NC;
+  constexpr int E = 2 * B + 1, PP = E * E * E, W = 3 * PP;
+  constexpr int KP = (NB * PP + 63) / 64;
+  __shared__ double buf[NB * W];
+  const int lane = threadIdx.x;
+  const int64_t blk0 = int64_t(blockIdx.x) * NB;
+  const int nb = int(std::min<int64_t>(NB, blk.n - blk0));
+  const int np = nb * PP;
+  auto lds_of = [&](int bl, int q) {
+    const int px = q % E, py = (q / E) % E, pz = q / (E * E);
+    return bl * W + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
+  };
+  for (int e = lane; e < NB * W; e += 64) buf[e] = 0.0;
+  const int bl = lane / NC, lc = lane - bl * NC;
+  const int ca = lc % B, cb = (lc / B) % B, cc = lc / (B * B);
+  double pl[8];
+  if (bl < nb) {
+    const int64_t c = blk.cells[(blk0 + bl) * NC + lc];
+    const double h = cell_h(L, c);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pl[i] = h * h * pgather(P, P.pslots[8 * c + i], p);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pl[i] = 0.0;
+  }
+  __syncthreads();
+  const int base = bl * W;
+#pragma unroll
+  for (int cls = 0; cls < 8; ++cls) {
+    const int ac = cls & 1, bc = (cls >> 1) & 1, zc = cls >> 2;
+#pragma unroll
+    for (int z = zc ? 2 : 0; z < (zc ? 3 : 2); ++z)
+#pragma unroll
+      for (int yy = bc ? 2 : 0; yy < (bc ? 3 : 2); ++yy)
+#pragma unroll
+        for (int xx = ac ? 2 : 0; xx < (ac ? 3 : 2); ++xx) {
+          const int a = xx + 3 * yy + 9 * z;
+          const int off = base + bsplit<B>(2 * ca + xx) + E * bsplit<B>(2 * cb + yy) + E * E * bsplit<B>(2 * cc + z);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            double v = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v += c_bhat[i * 81 + 3 * a + q] * pl[i];
+            buf[off + q * PP] += v;
+          }
+        }
+    __syncthreads();
+  }
+  const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.hent[e];
+    const int q = en & 1023, qm = (en >> 10) & 1023, b2 = en >> 20;
+    const double w = blk.hw_d[e];
+    const int o = lds_of(b2, q), om = lds_of(b2, qm);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) atomicAdd(&buf[om + k * PP], w * buf[o + k * PP]);
+  }
+  __syncthreads();
+  int32_t sl[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int pa = lane + 64 * k;
+    sl[k] = pa < np ? blk.slots[blk0 * PP + pa] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (sl[k] < 0) continue;
+    const int pa = lane + 64 * k, q = pa % PP;
+    const int o = lds_of(pa / PP, q);
+    const double v0 = buf[o], v1 = buf[o + PP], v2 = buf[o + 2 * PP];
+    const int px = q % E, py = (q / E) % E, pz = q / (E * E);
+    const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+    double* yp = uo + 3 * int64_t(sl[k]);
+    if (inner) {
+      yp[0] += v0, yp[1] += v1, yp[2] += v2;
+    } else {
+      atomicAdd(yp, v0), atomicAdd(yp + 1, v1), atomicAdd(yp + 2, v2);
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, DevPressure P,
+                                                   const double* __restrict__ u, double* __restrict__ po) {
+  constexpr int NC = B * B * B, NB = 64 / NC;
+  constexpr int E = 2 * B + 1, PP = E * E * E, W = 3 * PP;
+  constexpr int KP = (NB * PP + 63) / 64;
+  __shared__ double buf[NB * W];
+  const int lane = threadIdx.x;
+  const int64_t blk0 = int64_t(blockIdx.x) * NB;
+  const int nb = int(std::min<int64_t>(NB, blk.n - blk0));
+  const int np = nb * PP;
+  auto lds_of = [&](int bl, int q) {
+    const int px = q % E, py = (q / E) % E, pz = q / (E * E);
+    return bl * W + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
+  };
+  {
+    int32_t sl[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      sl[k] = pa < np ? blk.slots[blk0 * PP + pa] : -1;
+    }
+    double v[KP][3];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int64_t i = 3 * int64_t(sl[k] >= 0 ? sl[k] : 0);
+      v[k][0] = u[i], v[k][1] = u[i + 1], v[k][2] = u[i + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      if (pa < NB * PP) {
+        const int o = lds_of(pa / PP, pa % PP);
+        const bool f = sl[k] >= 0;
+        buf[o] = f ? v[k][0] : 0.0;
+        buf[o + PP] = f ? v[k][1] : 0.0;
+        buf[o + 2 * PP] = f ? v[k][2] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.hent[e];
+    const int q = en & 1023, qm = (en >> 10) & 1023, b2 = en >> 20;
+    const double w = blk.hw_d[e];
+    const int o = lds_of(b2, q), om = lds_of(b2, qm);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) atomicAdd(&buf[o + k * PP], w * buf[om + k * PP]);
+  }
+  __syncthreads();
+  const int bl = lane / NC, lc = lane - bl * NC;
+  if (bl >= nb) return;
+  const int ca = lc % B, cb = (lc / B) % B, cc = lc / (B * B);
+  const int base = bl * W;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 3; ++xx) {
+        const int a = xx + 3 * yy + 9 * z;
+        const int off = base + bsplit<B>(2 * ca + xx) + E * bsplit<B>(2 * cb + yy) + E * E * bsplit<B>(2 * cc + z);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double v = buf[off + q * PP];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[i] += c_bhat[i * 81 + 3 * a + q] * v;
+        }
+      }
+  const int64_t c = blk.cells[(blk0 + bl) * NC + lc];
+  const double h = cell_h(L, c);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) pscatter(P, P.pslots[8 * c + i], h * h * acc[i], po);
 }
 
 __global__ void k_p_identity(int64_t nh, const int64_t* __restrict__ nodes, const double* __restrict__ pin,
@@ -959,23 +1133,61 @@ const double* mu_of<double>(const DevLevel& L) {
 }
 
 template <typename T>
+T* brick_halo(const DevLevel& L);
+template <>
+float* brick_halo<float>(const DevLevel& L) {
+  return L.halo_f;
+}
+template <>
+double* brick_halo<double>(const DevLevel& L) {
+  return L.halo_d;
+}
+
+template <typename T>
+bool brick_fits(int64_t n) {
+  return n % BrickShape<T>::BX == 0 && n % BrickShape<T>::BY == 0 && n % BrickShape<T>::BZ == 0 && n <= 256;
+}
+
+template <typename T>
+int64_t brick_halo_words(int64_t n) {
+  constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
+  if (!brick_fits<T>(n)) return 0;
+  return (n / BX) * (n / BY) * (n / BZ) * brick::halo_words<BX, BY, BZ>() + 64;   // slots + zero pad
+}
+template int64_t brick_halo_words<float>(int64_t);
+template int64_t brick_halo_words<double>(int64_t);
+
+template <typename T>
 void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init) {
   if (L.uniform) {
-    if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
     constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
     const int64_t n = L.n_edge;
-    if (n % BX == 0 && n % BY == 0 && n % BZ == 0 && n <= 256) {
+    T* halo = brick_halo<T>(L);
+    if (halo && brick_fits<T>(n)) {
+      // owner computes: no output initialisation, no atomics
       const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
-      brick::k_vmult_brick<T, BX, BY, BZ><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y);
+      if (init)
+        brick::k_vmult_brick<T, BX, BY, BZ, false><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y, halo);
+      else
+        brick::k_vmult_brick<T, BX, BY, BZ, true><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y, halo);
+      brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), halo, y);
     } else {
+      if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
       k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
           n, mu_of<T>(L), x, y);
     }
     return;
   }
   if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
-  if (L.blk4.n) k_vmult_blocks<T, 4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
-  if (L.blk2.n) k_vmult_blocks<T, 2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
+  if (L.blk4.n) {
+    if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
+    else k_vmult_blocks<T, 4, true><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
+  }
+  if (L.blk2.n) {
+    const unsigned g = unsigned((L.blk2.n + 7) / 8);
+    if (init) k_vmult_blocks<T, 2, false><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
+    else k_vmult_blocks<T, 2, true><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
+  }
   if (L.n_single_reg)
     k_vmult_general<T, false><<<unsigned((L.n_single_reg + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
         L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
@@ -1096,10 +1308,29 @@ void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStrea
 
 void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* po, hipStream_t s) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
-  k_div<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, u, po);
+  if (L.blk4.n || L.blk2.n) {
+    if (L.blk4.n) k_div_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, u, po);
+    if (L.blk2.n) k_div_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, u, po);
+    for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
+      if (lst.second)
+        k_div<<<unsigned((lst.second + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, lst.first, lst.second,
+                                                                                          u, po);
+  } else {
+    k_div<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, u, po);
+  }
 }
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
-  k_grad_add<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, uo);
+  if (L.blk4.n || L.blk2.n) {
+    if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo);
+    if (L.blk2.n) k_grad_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, p, uo);
+    for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
+      if (lst.second)
+        k_grad_add<<<unsigned((lst.second + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+            L, P, lst.first, lst.second, p, uo);
+  } else {
+    k_grad_add<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, p,
+                                                                                         uo);
+  }
 }
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);

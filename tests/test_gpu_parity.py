@@ -103,6 +103,25 @@ def test_vmult_zero_and_linearity(case):
     assert rel_err(to_host(yab), to_host(2 * ya - yb)) < 1e-13
 
 
+def test_vmult_add_accumulates(case):
+    """vmult_add adds the cell contributions to an arbitrary dst (every node,
+    inside blocks and bricks as well as on their faces) and leaves the
+    constrained entries unchanged; dst + (A x on free dofs) is what it must
+    give, on every level."""
+    for ell in range(1, case.L + 1):
+        n = case.info["n_u"][ell]
+        perm = case.dof_perm(ell)
+        free = case.gmg.free[ell][perm]
+        for dt, npt, tol in ((torch.float64, np.float64, 1e-12), (torch.float32, np.float32, 1e-5)):
+            # inputs rounded to the working precision; reference in FP64 on the rounded values
+            x_or = inputs.uniform_vector(n, 300 + ell).astype(npt).astype(np.float64)
+            y0 = inputs.uniform_vector(n, 400 + ell).astype(npt).astype(np.float64)
+            ref = y0 + np.where(free, (case.gmg.A[ell] @ x_or)[perm], 0.0)
+            y = to_dev(y0, dt)
+            case.s.vmult_add(ell, to_dev(x_or[perm], dt), y)
+            assert rel_err(to_host(y), ref) <= tol, (ell, dt)
+
+
 def test_inverse_diagonal_and_lambda(case):
     for ell in range(1, case.L + 1):
         n = case.info["n_u"][ell]
