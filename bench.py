@@ -44,9 +44,12 @@ def parse():
     p.add_argument("--max-iter", type=int, default=3000, help="FGMRES iteration cap of --solve-workload")
     p.add_argument("--variants", default="fp64,fp32,fp32_learned",
                    help="solves of --solve-workload (comma separated: fp64, fp32, fp32_learned)")
+    p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                   help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE pass over "
+                        "--counter-probe into profiles/vmult_counters_sinker64.json (no GPU needed)")
     p.add_argument("--counter-probe", action="store_true",
-                   help="only launch the dominant kernel (vmult_add, FP32) and a plain copy of known size, "
-                        "20 times each, for hardware-counter runs")
+                   help="only launch the operator (mfgmg_vmult, FP32: brick + halo kernels) and a plain copy of "
+                        "known size, 20 times each, for hardware-counter runs")
     return p.parse_args()
 
 
@@ -54,14 +57,15 @@ COPY_BYTES = 256 << 20          # the calibration copy: 256 MiB read + 256 MiB w
 
 
 def counter_probe(s, L, x32, y32):
-    """Kernels for a rocprofv3 --pmc pass: 20 vmult_add (FP32) and 20 copies of
-    COPY_BYTES, so that FETCH_SIZE / WRITE_SIZE per dispatch of the operator
-    can be scaled by what the same counters read for a copy of known size."""
+    """Kernels for a rocprofv3 --pmc pass: 20 operator applications (FP32) and
+    20 copies of COPY_BYTES, so that FETCH_SIZE / WRITE_SIZE per dispatch of
+    the operator's kernels can be scaled by what the same counters read for a
+    copy of known size."""
     import torch
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=x32.device)
     b = torch.empty_like(a)
     for _ in range(20):
-        s.vmult_add(L, x32, y32)
+        s.vmult(L, x32, y32)
     for _ in range(20):
         b.copy_(a)
     torch.cuda.synchronize()
@@ -93,6 +97,31 @@ def cpu_baseline(level, centres, dr, seconds=12.0):
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1907_06696_amd", "data", "mlp_sinker32.npz")
+COUNTERS = os.path.join(ROOT, "profiles", "vmult_counters_sinker64.json")
+KERNEL_SOURCES = ("brick_kernel.h", "cell_kernel.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_06696_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(level):
+    """HBM bytes per operator application from the committed FETCH_SIZE /
+    WRITE_SIZE passes (scaled by the calibration copy), or None when the
+    counters were taken on other kernel sources or another workload."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except OSError:
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("level") != level:
+        return None
+    return {"bytes": int(c["bytes_per_application"]), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
@@ -176,8 +205,41 @@ def solve_workload(name, variants, max_iter=3000):
     s.close()
 
 
+def summarize_counters(fetch_csv, write_csv, level=6):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the operator's two
+    kernels at the 2^level mesh, each scaled by bytes / counter of the
+    calibration copy (the largest copy dispatches, COPY_BYTES read and
+    written)."""
+    import csv
+    n = 1 << level
+    out = {"level": level, "kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES}
+    total = 0.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        gmax = max(int(r["Grid_Size"]) for r in copies)
+        cal = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == gmax]
+        cal_kib = sorted(cal)[len(cal) // 2]
+        scale = COPY_BYTES / (cal_kib * 1024.0)
+        per = {}
+        for tag in ("k_vmult_brick<float", "k_brick_halo_add<float"):
+            v = [float(r["Counter_Value"]) for r in rows if tag in r["Kernel_Name"] and int(r["Grid_Size"]) == n ** 3]
+            per[tag.split("<")[0]] = {"dispatches": len(v), "kib_per_dispatch": sum(v) / max(len(v), 1)}
+        bytes_ = sum(d["kib_per_dispatch"] for d in per.values()) * 1024.0 * scale
+        out[name] = {"calibration_kib": cal_kib, "scale_bytes_per_counted_byte": scale, "kernels": per,
+                     "bytes_per_application": bytes_}
+        total += bytes_
+    out["bytes_per_application"] = total
+    with open(COUNTERS, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -238,22 +300,21 @@ def main():
         for _ in range(REPS):
             s.vmult(L, x64, y64)
 
-    def cells32():
-        for _ in range(REPS):
-            s.vmult_add(L, x32, y32)
-
     # the timed region: K steps of 100 FP32 operator applications
     t32 = timed(step32, args.steps, args.warmup)
     ms_per_step = t32 / args.steps * 1e3
     value = n * REPS * args.steps / t32 / 1e9
     t64 = timed(step64, max(2, args.steps // 4), 1)
     gdofs64 = n * REPS * max(2, args.steps // 4) / t64 / 1e9
-    tk = timed(cells32, max(2, args.steps // 4), 1)
-    kernel_s = tk / (REPS * max(2, args.steps // 4))
+    # roofline of the operator application timed above (one mfgmg_vmult call =
+    # the owner-computes brick kernel + the halo-add kernel, HIP events on the
+    # stream they are launched on)
+    vmult_call_s = t32 / (REPS * args.steps)
+    kernel_s = vmult_call_s
     flops = FLOP_PER_CELL * ncell
     alg_bytes = 2 * 4 * n + 4 * ncell        # read x, write y, cell viscosity (FP32)
     achieved_tflops = flops / kernel_s / 1e12
-    vmult_call_s = t32 / (REPS * args.steps)
+    traffic = measured_traffic(level)
 
     # V-cycles
     vc = {}
@@ -278,10 +339,13 @@ def main():
         "config": {"workload": f"sinker {1 << level}^3 uniform Q2 vmult, 8 sinkers, DR 1e4",
                    "cells": ncell, "velocity_dofs": n, "reps_per_step": REPS},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_vmult_uniform<float>", "kernel_us": round(kernel_s * 1e6, 2),
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "kernel": "k_vmult_brick<float,8,8,4> + k_brick_halo_add<float,8,8,4> (one mfgmg_vmult)",
+                     "kernel_us": round(kernel_s * 1e6, 2),
                      "flop_per_launch": flops, "alg_bytes_per_launch": alg_bytes,
-                     "hbm_frac_algorithmic": round(alg_bytes / kernel_s / 1e9 / PEAK_HBM_GBS, 4)},
+                     "hbm_frac_algorithmic": round(alg_bytes / kernel_s / 1e9 / PEAK_HBM_GBS, 4),
+                     "traffic_source": traffic["source"] if traffic else "none for this kernel source"},
         "vmult_fp64_gdofs": round(gdofs64, 3),
         "vmult_call_us_fp32": round(vmult_call_s * 1e6, 2),
         "vcycle_ms": {k: round(v, 3) for k, v in vc.items()},

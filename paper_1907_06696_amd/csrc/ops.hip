@@ -14,6 +14,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kCellBlock = 64;     // cells per workgroup for the cell kernels
 constexpr int kRedBlocks = 1024;   // partial sums of the reductions
+#ifndef MFGMG_BRICK_MIN_EDGE
+#define MFGMG_BRICK_MIN_EDGE 32
+#endif
+constexpr int64_t kBrickMinEdge = MFGMG_BRICK_MIN_EDGE;   // smallest uniform level using the brick kernel
 
 __constant__ double c_khat_diag[81];
 __constant__ double c_bhat[8 * 81];
@@ -1145,7 +1149,10 @@ double* brick_halo<double>(const DevLevel& L) {
 
 template <typename T>
 bool brick_fits(int64_t n) {
-  return n % BrickShape<T>::BX == 0 && n % BrickShape<T>::BY == 0 && n % BrickShape<T>::BZ == 0 && n <= 256;
+  // below 32 cells per edge there are too few bricks to fill the chip and a
+  // brick's latency dominates: the cell-parallel kernel is faster there
+  return n % BrickShape<T>::BX == 0 && n % BrickShape<T>::BY == 0 && n % BrickShape<T>::BZ == 0 && n <= 256 &&
+         n >= kBrickMinEdge;
 }
 
 template <typename T>
