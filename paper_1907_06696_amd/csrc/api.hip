@@ -1198,16 +1198,23 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     for (int j = 0; j < m; ++j) {
       precondition(V + size_t(j) * n, Z + size_t(j) * n);
       apply_K(Z + size_t(j) * n, w);
-      // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt, repeated only when the first pass cancelled
+      // much of w (||w'|| < ||w|| / sqrt(2), the criterion of Daniel, Gragg,
+      // Kaufman and Stewart, 1976); each pass reads the whole basis twice
+      const double wn0 = std::sqrt(dot_sync(ctx, n, w, w, s));
       launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res, s);
       (void)hipMemcpyAsync(ctx->host_res, ctx->red_res, size_t(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
       launch_mupdate(n, j + 1, V, n, ctx->red_res, w, s);
-      launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res + 256, s);
-      (void)hipMemcpyAsync(ctx->host_res + 256, ctx->red_res + 256, size_t(j + 1) * sizeof(double),
-                           hipMemcpyDeviceToHost, s);
-      launch_mupdate(n, j + 1, V, n, ctx->red_res + 256, w, s);
-      const double hn = std::sqrt(dot_sync(ctx, n, w, w, s));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = ctx->host_res[i] + ctx->host_res[256 + i];
+      double hn = std::sqrt(dot_sync(ctx, n, w, w, s));
+      for (int i = 0; i <= j; ++i) Hij(i, j) = ctx->host_res[i];
+      if (!(hn >= wn0 * 0.70710678118654752)) {
+        launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res + 256, s);
+        (void)hipMemcpyAsync(ctx->host_res + 256, ctx->red_res + 256, size_t(j + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, s);
+        launch_mupdate(n, j + 1, V, n, ctx->red_res + 256, w, s);
+        hn = std::sqrt(dot_sync(ctx, n, w, w, s));
+        for (int i = 0; i <= j; ++i) Hij(i, j) += ctx->host_res[256 + i];
+      }
       Hij(j + 1, j) = hn;
       if (!std::isfinite(hn)) {
         bad = true;
