@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--no-solve", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
-    p.add_argument("--solve-workload", choices=["c3_adaptive32p2", "c5_uniform128p1"], default=None,
+    p.add_argument("--solve-workload", choices=["adaptive32p2", "uniform128p1"], default=None,
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
     p.add_argument("--max-iter", type=int, default=3000, help="FGMRES iteration cap of --solve-workload")
     p.add_argument("--variants", default="fp64,fp32,fp32_learned",
@@ -252,7 +252,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = inputs.CONFIGS["c2_uniform64"]
+    cfg = inputs.CONFIGS["uniform64"]
     level = args.level
     centres = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
     dr = cfg["dr"]

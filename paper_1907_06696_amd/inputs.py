@@ -104,13 +104,13 @@ def uniform_vector(n, seed):
 
 # Workload recipes (sizes, seeds) of the five benchmark configurations.
 CONFIGS = {
-    "c1_uniform8_fp64": dict(base_level=3, sinkers=4, dr=1e2, centre_seed=1),
-    "c2_uniform64": dict(base_level=6, sinkers=8, dr=1e4, centre_seed=2, vector_seed=42),
-    "c3_adaptive32p2": dict(base_level=5, sinkers=16, dr=1e6, centre_seed=3,
+    "uniform8": dict(base_level=3, sinkers=4, dr=1e2, centre_seed=1),
+    "uniform64": dict(base_level=6, sinkers=8, dr=1e4, centre_seed=2, vector_seed=42),
+    "adaptive32p2": dict(base_level=5, sinkers=16, dr=1e6, centre_seed=3,
                             refine_percentile=80.0, refine_levels=2),
-    "c4_learned": dict(train_level=5, eval_level=6, train_fields=256, eval_fields=32,
+    "learned": dict(train_level=5, eval_level=6, train_fields=256, eval_fields=32,
                        train_seed0=10000, eval_seed0=20000, sinkers=(4, 32), log10_dr=(2.0, 6.0)),
-    "c5_uniform128p1": dict(base_level=7, sinkers=32, dr=1e6, centre_seed=5,
+    "uniform128p1": dict(base_level=7, sinkers=32, dr=1e6, centre_seed=5,
                             refine_percentile=97.5, refine_levels=1),
 }
 

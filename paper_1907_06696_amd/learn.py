@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--json", default=None)
     a = ap.parse_args()
     import torch
-    cfg = inputs.CONFIGS["c4_learned"]
+    cfg = inputs.CONFIGS["learned"]
     res = {}
     if a.weights_in:
         w = torch.tensor(np.load(a.weights_in)["weights"], device="cuda")

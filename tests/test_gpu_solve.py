@@ -58,8 +58,8 @@ def _solve_and_check(case, precs=("fp64", "fp32"), err_tol=1e-5):
     return out
 
 
-def test_solve_c1_uniform8():
-    cfg = inputs.CONFIGS["c1_uniform8_fp64"]
+def test_solve_uniform8():
+    cfg = inputs.CONFIGS["uniform8"]
     c = Case(base=cfg["base_level"], sinkers=cfg["sinkers"], dr=cfg["dr"], seed=cfg["centre_seed"])
     c.s.set_viscosity(c.mu_qp_lib)
     st = _solve_and_check(c)
@@ -93,7 +93,7 @@ def test_solve_reports_noconv():
 
 def test_vmult_full_size_64():
     """The benchmark configuration: 64^3 cells, every output entry."""
-    cfg = inputs.CONFIGS["c2_uniform64"]
+    cfg = inputs.CONFIGS["uniform64"]
     s = mfgmg.Solver(cfg["base_level"])
     s.finalize_mesh()
     L = s.info()["L"]

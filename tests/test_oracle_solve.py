@@ -144,8 +144,8 @@ def test_exact_block_preconditioner_two_iterations():
         assert prob.residual(x) < 1e-10
 
 
-def test_c1_gmg_fgmres_matches_direct():
-    cfg = inputs.CONFIGS['c1_uniform8_fp64']
+def test_uniform8_gmg_fgmres_matches_direct():
+    cfg = inputs.CONFIGS['uniform8']
     H = mesh.Hierarchy.uniform(cfg['base_level'])
     m = H.leaf
     cen = inputs.sinker_centres(cfg['sinkers'], cfg['centre_seed'])
