@@ -1141,23 +1141,22 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     if (bn == 0.0) return;
     launch_mul(np, ctx->pmass_minv, cr, cz, s);
     (void)hipMemcpyAsync(cp, cz, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    double rz = dot_sync(ctx, np, cr, cz, s);
-    for (int it = 1; it <= o.schur_max_iter; ++it) {
-      launch_pmass(lv, P, cp, cq, s);
-      const double alpha = rz / dot_sync(ctx, np, cp, cq, s);
-      launch_axpby(np, alpha, cp, 1.0, cx, s);
-      launch_axpby(np, -alpha, cq, 1.0, cr, s);
-      launch_mul(np, ctx->pmass_minv, cr, cz, s);
-      // [r.r, z.r] in one reduction (r and z are contiguous)
-      launch_mdot(np, 2, cr, np, cr, ctx->red_part, ctx->red_res, s);
-      (void)hipMemcpyAsync(ctx->host_res, ctx->red_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    // the iterations run with their scalars on the device; the host looks at
+    // the stopping flag every kCgBatch iterations
+    double* sc = ctx->red_res + 480;
+    launch_dot(np, cr, cz, ctx->red_part, sc, s);   // sc[0] = r.z
+    const double tol = o.schur_rtol * bn;
+    launch_cg_setup(sc, tol * tol, s);
+    constexpr int kCgBatch = 8;
+    for (int base = 0; base < o.schur_max_iter; base += kCgBatch) {
+      const int kk = std::min(kCgBatch, o.schur_max_iter - base);
+      for (int k = 0; k < kk; ++k)
+        launch_cg_pmass_iteration(lv, P, ctx->pmass_minv, cx, cr, cz, cp, cq, ctx->red_part, sc, s);
+      (void)hipMemcpyAsync(ctx->host_res + 480, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
-      ++inner_total;
-      const double rr = ctx->host_res[0], rz_new = ctx->host_res[1];
-      if (std::sqrt(rr) <= o.schur_rtol * bn) break;
-      launch_axpby(np, 1.0, cz, rz_new / rz, cp, s);
-      rz = rz_new;
+      if (ctx->host_res[485] != 0.0) break;
     }
+    inner_total += int64_t(ctx->host_res[486]);
   };
   // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p)
   auto precondition = [&](const double* v, double* z) {

@@ -886,7 +886,8 @@ __global__ __launch_bounds__(kCellBlock) void k_grad_add(DevLevel L, DevPressure
 }
 
 __global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P, const double* __restrict__ p,
-                                                      double* __restrict__ po) {
+                                                      double* __restrict__ po, const double* __restrict__ gate) {
+  if (gate && *gate != 0.0) return;
   const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (c >= L.ncell) return;
   const double h = cell_h(L, c);
@@ -1339,10 +1340,84 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
                                                                                          uo);
   }
 }
-void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s) {
+void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
+                  const double* gate) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
-  k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, po);
+  k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, po, gate);
   if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, p, po);
+}
+
+// ------------------------------------------------------- device-resident CG
+// Scalars of the Jacobi-CG on M_p live in sc[]: 0 rz, 1 beta, 4 stopping
+// threshold on r.r, 5 done flag, 6 iterations, 7 alpha.  Once done is set
+// every kernel of a further iteration returns at once, so the host may queue
+// several iterations between checks without changing the result.
+namespace {
+__global__ __launch_bounds__(kBlock) void k_cg_setup(double* sc, double tol2) {
+  if (threadIdx.x == 0) sc[1] = 0.0, sc[4] = tol2, sc[5] = 0.0, sc[6] = 0.0, sc[7] = 0.0;
+}
+__global__ __launch_bounds__(kBlock) void k_cg_alpha(int np, const double* __restrict__ part, double* sc) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0 && sc[5] == 0.0) sc[7] = sc[0] / v;
+}
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ sc,
+                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                     const double* __restrict__ minv, double* __restrict__ x,
+                                                     double* __restrict__ r, double* __restrict__ z,
+                                                     double* __restrict__ part) {
+  if (sc[5] != 0.0) return;
+  const double alpha = sc[7];
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    const double zi = minv[i] * ri;
+    r[i] = ri, z[i] = zi;
+    rr += ri * ri, rz += ri * zi;
+  }
+  rr = block_sum(rr);
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr, part[gridDim.x + blockIdx.x] = rz;
+}
+__global__ __launch_bounds__(kBlock) void k_cg_check(int np, const double* __restrict__ part, double* sc) {
+  if (sc[5] != 0.0) return;
+  double rr = 0.0, rz = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) rr += part[i], rz += part[np + i];
+  rr = block_sum(rr);
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) {
+    sc[6] += 1.0;
+    if (rr <= sc[4]) {
+      sc[5] = 1.0;
+    } else {
+      sc[1] = rz / sc[0];
+      sc[0] = rz;
+    }
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double* __restrict__ sc,
+                                                      const double* __restrict__ z, double* __restrict__ p) {
+  if (sc[5] != 0.0) return;
+  const double beta = sc[1];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+}  // namespace
+
+void launch_cg_setup(double* sc, double tol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, tol2); }
+
+void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
+                               double* z, double* p, double* q, double* part, double* sc, hipStream_t s) {
+  const int64_t n = P.np;
+  launch_pmass(L, P, p, q, s, sc + 5);
+  k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, p, q, part);
+  k_cg_alpha<<<1, kBlock, 0, s>>>(kRedBlocks, part, sc);
+  const unsigned g = grid_for(n, kBlock, kRedBlocks);
+  k_cg_update<<<g, kBlock, 0, s>>>(n, sc, p, q, minv, x, r, z, part);
+  k_cg_check<<<1, kBlock, 0, s>>>(int(g), part, sc);
+  k_cg_pupdate<<<grid_for(n), kBlock, 0, s>>>(n, sc, z, p);
 }
 void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hipStream_t s) {
   if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, pin, pout);
