@@ -273,7 +273,10 @@ int upload_mesh(mfgmg_ctx* ctx) {
         struct Blocks {
           std::vector<int32_t> slots, cells, hoff{0}, hent;
           std::vector<double> hw;
+          std::vector<int32_t> pslots, phoff{0}, phent;   // leaf: Q1 pressure lattice
+          std::vector<double> phw;
         };
+        const bool leaf = ell == L;
         auto make_blocks = [&](int B, Blocks& out) {
           const int E = 2 * B + 1, NC = B * B * B, P = E * E * E, NB = 64 / NC;
           std::vector<int32_t> cs(static_cast<size_t>(NC)), bs(static_cast<size_t>(P));
@@ -317,9 +320,48 @@ int upload_mesh(mfgmg_ctx* ctx) {
               }
             }
             if (!ok) continue;
+            // leaf: the pressure lattice of the block, hanging masters on it as well
+            std::vector<int32_t> pb;
+            std::vector<int32_t> pent;
+            std::vector<double> pwt;
+            if (leaf) {
+              const int EP = B + 1, PP = EP * EP * EP;
+              pb.assign(size_t(PP), -1);
+              for (int q = 0; q < NC; ++q) {
+                const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
+                for (int a = 0; a < 8; ++a) {
+                  const int pp = (qa + a % 2) + EP * ((qb + (a / 2) % 2) + EP * (qc + a / 4));
+                  pb[size_t(pp)] = h.cell_pnodes[size_t(8 * int64_t(cs[size_t(q)]) + a)];
+                }
+              }
+              std::unordered_map<int32_t, int32_t> pat;
+              for (int pp = 0; pp < PP; ++pp)
+                if (h.ptype[size_t(pb[size_t(pp)])] != NODE_HANGING) pat[pb[size_t(pp)]] = pp;
+              for (int pp = 0; pp < PP && ok; ++pp) {
+                const int32_t nd = pb[size_t(pp)];
+                if (h.ptype[size_t(nd)] != NODE_HANGING) continue;
+                const int32_t hr = h.phang_index[size_t(nd)];
+                for (int64_t q = h.phang.ptr[size_t(hr)]; q < h.phang.ptr[size_t(hr) + 1] && ok; ++q) {
+                  auto it = pat.find(h.phang.master[size_t(q)]);
+                  ok = it != pat.end();
+                  if (ok) {
+                    pent.push_back(pp | (it->second << 10) | (bl << 20));
+                    pwt.push_back(h.phang.weight[size_t(q)]);
+                  }
+                }
+                pb[size_t(pp)] = -2;
+              }
+              if (!ok) continue;
+            }
             for (int q = 0; q < NC; ++q) {
               used[size_t(cs[size_t(q)])] = 1;
               out.cells.push_back(cs[size_t(q)]);
+            }
+            if (leaf) {
+              out.pslots.insert(out.pslots.end(), pb.begin(), pb.end());
+              out.phent.insert(out.phent.end(), pent.begin(), pent.end());
+              out.phw.insert(out.phw.end(), pwt.begin(), pwt.end());
+              out.phoff.push_back(int32_t(out.phent.size()));
             }
             for (int p = 0; p < P; ++p) out.slots.push_back(bs[size_t(p)] < -1 ? -2 : bs[size_t(p)]);
             out.hent.insert(out.hent.end(), ent.begin(), ent.end());
@@ -345,6 +387,12 @@ int upload_mesh(mfgmg_ctx* ctx) {
           d.hent = ctx->upload(b.hent);
           d.hw_d = ctx->upload(b.hw);
           d.hw_f = ctx->upload(std::vector<float>(b.hw.begin(), b.hw.end()));
+          if (leaf) {
+            d.pslots = ctx->upload(b.pslots);
+            d.phoff = ctx->upload(b.phoff);
+            d.phent = ctx->upload(b.phent);
+            d.phw = ctx->upload(b.phw);
+          }
         };
         upload_blocks(b4, v.blk4, 64);
         upload_blocks(b2, v.blk2, 8);

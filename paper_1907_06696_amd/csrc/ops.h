@@ -20,6 +20,12 @@ struct DevBlocks {
   const double* hw_d = nullptr;
   const float* hw_f = nullptr;
   int64_t n = 0;
+  // leaf only: the Q1 pressure lattice [(B+1)^3] of each block (node >= 0,
+  // -2 hanging) and its hanging points' masters, packed as above
+  const int32_t* pslots = nullptr;
+  const int32_t* phoff = nullptr;
+  const int32_t* phent = nullptr;
+  const double* phw = nullptr;
 };
 
 // Device view of one level mesh.

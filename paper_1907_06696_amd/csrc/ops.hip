@@ -885,11 +885,13 @@ __global__ __launch_bounds__(kCellBlock) void k_grad_add(DevLevel L, DevPressure
   }
 }
 
-__global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P, const double* __restrict__ p,
+__global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P, const int32_t* __restrict__ cells,
+                                                      int64_t ncells, const double* __restrict__ p,
                                                       double* __restrict__ po, const double* __restrict__ gate) {
   if (gate && *gate != 0.0) return;
-  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (c >= L.ncell) return;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= ncells) return;
+  const int64_t c = cells ? cells[t] : t;
   const double h = cell_h(L, c);
   const double s = h * h * h / L.mu_d[c];
   double pl[8];
@@ -1065,6 +1067,103 @@ __global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, De
   const double h = cell_h(L, c);
 #pragma unroll
   for (int i = 0; i < 8; ++i) pscatter(P, P.pslots[8 * c + i], h * h * acc[i], po);
+}
+
+// M_p p on the blocks of the leaf: the block's Q1 lattice ((B+1)^3 points)
+// is staged in LDS with hanging points interpolated from their masters (on
+// the lattice), each cell adds its 8 outputs in LDS (cells of equal index
+// parity share no vertex: 8 classes), hanging outputs are passed on to the
+// masters, and the write-back stores the points inside the block and adds
+// (atomically) those on its faces.
+template <int B>
+__global__ __launch_bounds__(64) void k_pmass_blocks(DevBlocks blk, DevLevel L, const double* __restrict__ p,
+                                                     double* __restrict__ po, const double* __restrict__ gate) {
+  if (gate && *gate != 0.0) return;
+  constexpr int NC = B * B * B, NB = 64 / NC;
+  constexpr int E = B + 1, PP = E * E * E;
+  constexpr int KP = (NB * PP + 63) / 64;
+  __shared__ double buf[NB * PP];
+  const int lane = threadIdx.x;
+  const int64_t blk0 = int64_t(blockIdx.x) * NB;
+  const int nb = int(std::min<int64_t>(NB, blk.n - blk0));
+  const int np = nb * PP;
+  {
+    int32_t sl[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      sl[k] = pa < np ? blk.pslots[blk0 * PP + pa] : -1;
+    }
+    double v[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) v[k] = p[sl[k] >= 0 ? sl[k] : 0];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int pa = lane + 64 * k;
+      if (pa < NB * PP) buf[pa] = sl[k] >= 0 ? v[k] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int h0 = blk.phoff[blk0], h1 = blk.phoff[blk0 + nb];
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.phent[e];
+    const int q = en & 1023, qm = (en >> 10) & 1023, b2 = en >> 20;
+    atomicAdd(&buf[b2 * PP + q], blk.phw[e] * buf[b2 * PP + qm]);
+  }
+  __syncthreads();
+  const int bl = lane / NC, lc = lane - bl * NC;
+  const int ca = lc % B, cb = (lc / B) % B, cc = lc / (B * B);
+  const int base = bl * PP + ca + E * (cb + E * cc);
+  double pl[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) pl[a] = buf[base + (a & 1) + E * (((a >> 1) & 1) + E * (a >> 2))];
+  double sc = 0.0;
+  if (bl < nb) {
+    const int64_t c = blk.cells[(blk0 + bl) * NC + lc];
+    const double h = cell_h(L, c);
+    sc = h * h * h / L.mu_d[c];
+  }
+  double out[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v += c_mhat[i * 8 + j] * pl[j];
+    out[i] = sc * v;
+  }
+  __syncthreads();
+  for (int e = lane; e < NB * PP; e += 64) buf[e] = 0.0;
+  __syncthreads();
+  const int par = (ca & 1) | ((cb & 1) << 1) | ((cc & 1) << 2);
+#pragma unroll
+  for (int cls = 0; cls < 8; ++cls) {
+    if (par == cls) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) buf[base + (a & 1) + E * (((a >> 1) & 1) + E * (a >> 2))] += out[a];
+    }
+    __syncthreads();
+  }
+  for (int e = h0 + lane; e < h1; e += 64) {
+    const int32_t en = blk.phent[e];
+    const int q = en & 1023, qm = (en >> 10) & 1023, b2 = en >> 20;
+    atomicAdd(&buf[b2 * PP + qm], blk.phw[e] * buf[b2 * PP + q]);
+  }
+  __syncthreads();
+  int32_t sl[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int pa = lane + 64 * k;
+    sl[k] = pa < np ? blk.pslots[blk0 * PP + pa] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (sl[k] < 0) continue;
+    const int pa = lane + 64 * k, q = pa % PP;
+    const int px = q % E, py = (q / E) % E, pz = q / (E * E);
+    const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+    if (inner) po[sl[k]] = buf[pa];
+    else atomicAdd(&po[sl[k]], buf[pa]);
+  }
 }
 
 __global__ void k_p_identity(int64_t nh, const int64_t* __restrict__ nodes, const double* __restrict__ pin,
@@ -1343,7 +1442,17 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
                   const double* gate) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
-  k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, p, po, gate);
+  if ((L.blk4.n && L.blk4.pslots) || (L.blk2.n && L.blk2.pslots)) {
+    if (L.blk4.n) k_pmass_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, p, po, gate);
+    if (L.blk2.n) k_pmass_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, p, po, gate);
+    for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
+      if (lst.second)
+        k_pmass<<<unsigned((lst.second + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, lst.first,
+                                                                                            lst.second, p, po, gate);
+  } else {
+    k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, p, po,
+                                                                                        gate);
+  }
   if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, p, po);
 }
 
