@@ -178,9 +178,10 @@ def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
 def solve_workload(name, variants, max_iter=3000):
     """The adaptive 32^3 + 2 (16 sinkers, DR 1e6) and the 128^3 + 1
     (32 sinkers, DR 1e6) sinker solves; one JSON line each.  FGMRES restarts
-    every 120 iterations here: at this contrast and sinker count restarts
+    every 100 iterations here: at this contrast and sinker count restarts
     every 50 stall (the 32^3 + 2 case stagnates near 4e-6 for thousands of
-    iterations) while 120 converges."""
+    iterations; 60 needs twice the iterations), and 100 was the fastest of
+    80, 100 and 120 over both workloads."""
     import torch
     from paper_1907_06696_amd import inputs, mfgmg
     cfg = inputs.CONFIGS[name]
@@ -198,7 +199,7 @@ def solve_workload(name, variants, max_iter=3000):
     t_setup = time.perf_counter() - t0
     print(f"[{name}] L={L} cells={info['n_cells'][L]} n_u={info['n_u'][L]} n_p={info['n_p']} "
           f"hanging={info['n_hanging'][L]} setup {t_setup:.1f} s", flush=True)
-    res = solve_compare(s, qp, centres, verbose=100, restart=120, variants=variants, max_iter=max_iter)
+    res = solve_compare(s, qp, centres, verbose=100, restart=100, variants=variants, max_iter=max_iter)
     print(json.dumps({"workload": name, "cells": info["n_cells"][L], "velocity_dofs": info["n_u"][L],
                       "pressure_dofs": info["n_p"], "levels": L, "setup_s": round(t_setup, 2),
                       "stokes_solve_1e-8": res}), flush=True)
