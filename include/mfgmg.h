@@ -213,6 +213,9 @@ typedef struct {
   int32_t verbose;        /* > 0: every `verbose` outer iterations print the
                              iteration, the residual estimate and the elapsed
                              time to stderr (0) */
+  int32_t use_graph;      /* 1: the V-cycle is captured once per solve as a HIP
+                             graph (on a stream of the context) and replayed on
+                             `stream`; 0: launched kernel by kernel (1) */
 } mfgmg_solve_opts;
 
 typedef struct {

@@ -1115,6 +1115,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->schur_max_iter = 200;
   o->use_scaling = 0;
   o->verbose = 0;
+  o->use_graph = 1;
   return MFGMG_OK;
 }
 
@@ -1154,7 +1155,10 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   float* xf = ctx->dalloc<float>(size_t(nu));
   double* cg = ctx->dalloc<double>(size_t(5 * np));   // r, z (contiguous), p, q, x
   double* yv = ctx->dalloc<double>(size_t(m + 1));
+  const bool fp64 = o.vcycle_prec == MFGMG_FP64;
+  double* zfix = (o.use_graph && fp64) ? ctx->dalloc<double>(size_t(nu)) : nullptr;   // graph's fixed output
   std::vector<void*> mine = {V, Z, b, x, r, w, tu, bf, xf, cg, yv};
+  if (o.use_graph && fp64) mine.push_back(zfix);
   auto release = [&]() {
     for (void* p : mine) {
       auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
@@ -1206,16 +1210,43 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     }
     inner_total += int64_t(ctx->host_res[486]);
   };
+  // the V-cycle as one HIP graph: captured once per solve (nothing it depends
+  // on changes during a solve) and replayed on `s` at every preconditioning
+  hipGraphExec_t vexec = nullptr;
+  if (o.use_graph) {
+    hipError_t e = hipSuccess;
+    if (!ctx->capture_stream) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    hipStream_t cs = ctx->capture_stream;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      if (fp64) vcycle<double>(ctx, L, tu, zfix, cs);
+      else vcycle<float>(ctx, L, bf, xf, cs);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);
+      if (e == hipSuccess) e = hipGraphInstantiate(&vexec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess) {
+      release();
+      return ctx->set(MFGMG_ERR_HIP, std::string("V-cycle graph capture: ") + hipGetErrorString(e));
+    }
+  }
   // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p)
   auto precondition = [&](const double* v, double* z) {
     schur(v + nu);
     (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
     launch_grad_add(lv, P, cx, tu, s);
-    if (o.vcycle_prec == MFGMG_FP64) {
-      vcycle<double>(ctx, L, tu, z, s);
+    if (fp64) {
+      if (vexec) {
+        (void)hipGraphLaunch(vexec, s);
+        launch_scale_copy(nu, 1.0, zfix, z, s);
+      } else {
+        vcycle<double>(ctx, L, tu, z, s);
+      }
     } else {
       launch_to_float(nu, tu, bf, s);
-      vcycle<float>(ctx, L, bf, xf, s);
+      if (vexec) (void)hipGraphLaunch(vexec, s);
+      else vcycle<float>(ctx, L, bf, xf, s);
       launch_to_double(nu, xf, z, s);
     }
     ++vcycles;
@@ -1314,6 +1345,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   launch_distribute_u(lv, u_out, s);
   launch_distribute_p(P, p_out, s);
   HIPCHK(hipStreamSynchronize(s));
+  if (vexec) (void)hipGraphExecDestroy(vexec);
   release();
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   const bool conv = !bad && (bn == 0 || beta <= o.rtol * bn);
@@ -1333,6 +1365,7 @@ const char* mfgmg_last_error(const mfgmg_ctx* ctx) { return ctx ? ctx->err.c_str
 
 void mfgmg_destroy(mfgmg_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   for (void* p : ctx->allocs)
     if (p) (void)hipFree(p);
   if (ctx->host_res) (void)hipHostFree(ctx->host_res);

@@ -63,6 +63,7 @@ struct mfgmg_ctx {
   std::vector<double> mu_host_leaf;
   bool use_scaling = false;     // V-cycles use the installed scalings
   std::vector<void*> scratch;   // learned-part work buffers (released with the context)
+  hipStream_t capture_stream = nullptr;   // V-cycle graph capture (default priority)
 
   int set(int code, const std::string& msg) {
     err = msg;

@@ -49,7 +49,7 @@ class Info(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("vcycle_prec", C.c_int32), ("schur_rtol", C.c_double), ("schur_max_iter", C.c_int32),
-                ("use_scaling", C.c_int32), ("verbose", C.c_int32)]
+                ("use_scaling", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SolveStats(C.Structure):
