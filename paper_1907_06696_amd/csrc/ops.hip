@@ -758,7 +758,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(int np, const double* _
 __global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, int nv, const double* __restrict__ V,
                                                          int64_t ldv, const double* __restrict__ w,
                                                          double* __restrict__ part) {
-  // grid (nb, nv): block (b, j) computes a partial of V_j . w
+  // grid (nb, nv): block (b, j) computes a partial of V_j . w (w stays in
+  // the caches across the j; grouping several j per block measured slower)
   const int j = blockIdx.y;
   double v = 0.0;
   const double* Vj = V + int64_t(j) * ldv;
@@ -989,6 +990,44 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
     } else {
       atomicAdd(yp, v0), atomicAdd(yp + 1, v1), atomicAdd(yp + 2, v2);
     }
+  }
+}
+
+// B^T p added into uo on a uniform leaf, gathered per velocity node (no
+// atomics): the node's value sums, over the (up to 8) cells around it, the
+// cell's B-hat row of the node's local index against the cell's 8 pressure
+// values (Q1 nodes through the cell's pressure slots; no hanging nodes on a
+// uniform level).  Dirichlet nodes are skipped.
+__global__ __launch_bounds__(kBlock) void k_grad_uniform(int64_t n, DevPressure P, const double* __restrict__ p,
+                                                         double* __restrict__ uo) {
+  const int64_t m = 2 * n + 1, nn = m * m * m;
+  const double h2 = 1.0 / double(n * n);
+  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
+    if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) continue;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int dz = 0; dz < 2; ++dz) {
+      const int64_t k = Z / 2 - ((Z & 1) ? 0 : 1 - dz);
+      if ((Z & 1) && dz) break;
+      for (int dy = 0; dy < 2; ++dy) {
+        const int64_t j = Y / 2 - ((Y & 1) ? 0 : 1 - dy);
+        if ((Y & 1) && dy) break;
+        for (int dx = 0; dx < 2; ++dx) {
+          const int64_t i = X / 2 - ((X & 1) ? 0 : 1 - dx);
+          if ((X & 1) && dx) break;
+          const int64_t c = i + n * (j + n * k);
+          const int a = int(X - 2 * i) + 3 * int(Y - 2 * j) + 9 * int(Z - 2 * k);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const double pv = p[P.pslots[8 * c + q]];
+            a0 += c_bhat[q * 81 + 3 * a] * pv;
+            a1 += c_bhat[q * 81 + 3 * a + 1] * pv;
+            a2 += c_bhat[q * 81 + 3 * a + 2] * pv;
+          }
+        }
+      }
+    }
+    uo[3 * v] += h2 * a0, uo[3 * v + 1] += h2 * a1, uo[3 * v + 2] += h2 * a2;
   }
 }
 
@@ -1391,7 +1430,7 @@ void launch_dot(int64_t n, const double* a, const double* b, double* part, doubl
 
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part, double* result,
                  hipStream_t s) {
-  const int nb = 256;
+  const int nb = 256;   // part holds nv x nb partials (65536 from the caller: nv <= 256)
   k_mdot_partial<<<dim3(nb, unsigned(nv)), kBlock, 0, s>>>(n, nv, V, ldv, w, part);
   k_sum_partials<<<unsigned(nv), kBlock, 0, s>>>(nb, part, result);
 }
@@ -1427,7 +1466,9 @@ void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double
   }
 }
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
-  if (L.blk4.n || L.blk2.n) {
+  if (L.uniform) {
+    k_grad_uniform<<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, P, p, uo);
+  } else if (L.blk4.n || L.blk2.n) {
     if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo);
     if (L.blk2.n) k_grad_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, p, uo);
     for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
