@@ -1278,20 +1278,39 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       apply_K(Z + size_t(j) * n, w);
       // classical Gram-Schmidt, repeated only when the first pass cancelled
       // much of w (||w'|| < ||w|| / sqrt(2), the criterion of Daniel, Gragg,
-      // Kaufman and Stewart, 1976); each pass reads the whole basis twice
-      const double wn0 = std::sqrt(dot_sync(ctx, n, w, w, s));
-      launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res, s);
-      (void)hipMemcpyAsync(ctx->host_res, ctx->red_res, size_t(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
-      launch_mupdate(n, j + 1, V, n, ctx->red_res, w, s);
-      double hn = std::sqrt(dot_sync(ctx, n, w, w, s));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = ctx->host_res[i];
+      // Kaufman and Stewart, 1976).  Coefficients in red_res [0, nv] (h1 and
+      // w.w), [256, 256 + nv] (h2 and w'.w') and 400 (w''.w'').  Up to
+      // kMupdateDotsMax basis vectors the update of w and the products of
+      // the second pass share one read of the basis (three basis reads per
+      // step with the repetition instead of four).
+      const int nv = j + 1;
+      double* res = ctx->red_res;
+      double* hres = ctx->host_res;
+      launch_mdot(n, nv, V, n, w, ctx->red_part, res, s, /*with_norm=*/true);
+      const bool fused = launch_mupdate_dots(n, nv, V, n, res, w, ctx->red_part, res + 256, true, s);
+      if (!fused) {
+        launch_mupdate(n, nv, V, n, res, w, s);
+        launch_dot(n, w, w, ctx->red_part, res + 256 + nv, s);
+      }
+      (void)hipMemcpyAsync(hres, res, size_t(nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+      (void)hipMemcpyAsync(hres + 256, res + 256, size_t(nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+      HIPCHK(hipStreamSynchronize(s));
+      const double wn0 = std::sqrt(hres[nv]);
+      double hn = std::sqrt(hres[256 + nv]);
+      for (int i = 0; i < nv; ++i) Hij(i, j) = hres[i];
       if (!(hn >= wn0 * 0.70710678118654752)) {
-        launch_mdot(n, j + 1, V, n, w, ctx->red_part, ctx->red_res + 256, s);
-        (void)hipMemcpyAsync(ctx->host_res + 256, ctx->red_res + 256, size_t(j + 1) * sizeof(double),
-                             hipMemcpyDeviceToHost, s);
-        launch_mupdate(n, j + 1, V, n, ctx->red_res + 256, w, s);
-        hn = std::sqrt(dot_sync(ctx, n, w, w, s));
-        for (int i = 0; i <= j; ++i) Hij(i, j) += ctx->host_res[256 + i];
+        if (fused) {
+          launch_mupdate_dots(n, nv, V, n, res + 256, w, ctx->red_part, res + 400, false, s);
+        } else {
+          launch_mdot(n, nv, V, n, w, ctx->red_part, res + 256, s);
+          (void)hipMemcpyAsync(hres + 256, res + 256, size_t(nv) * sizeof(double), hipMemcpyDeviceToHost, s);
+          launch_mupdate(n, nv, V, n, res + 256, w, s);
+          launch_dot(n, w, w, ctx->red_part, res + 400, s);
+        }
+        (void)hipMemcpyAsync(hres + 400, res + 400, sizeof(double), hipMemcpyDeviceToHost, s);
+        HIPCHK(hipStreamSynchronize(s));
+        hn = std::sqrt(hres[400]);
+        for (int i = 0; i < nv; ++i) Hij(i, j) += hres[256 + i];
       }
       Hij(j + 1, j) = hn;
       if (!std::isfinite(hn)) {

@@ -32,11 +32,21 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "cell_kernel.h"
 
 namespace mfgmg {
 namespace brick {
+
+// f(std::integral_constant<int, w>) for the (wave-uniform) index w < NW
+template <int NW, int W = 0, typename F>
+__device__ __forceinline__ void with_wave(int w, const F& f) {
+  if constexpr (W < NW) {
+    if (w == W) f(std::integral_constant<int, W>());
+    else with_wave<NW, W + 1>(w, f);
+  }
+}
 
 template <int B>
 __device__ __forceinline__ int split_index(int l) {
@@ -62,38 +72,51 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
   static_assert(ROW <= 64, "row");
   constexpr int NR = NY * NZ, RPW = (NR + NW - 1) / NW;
   __shared__ __attribute__((aligned(16))) T buf[3 * CS];
-  const int nbx = n / BX, nby = n / BY;
+  const int nbx = n / BX, nby = n / BY, nbz = n / BZ;
   const int b = blockIdx.x;
   const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
   const int m = 2 * n + 1;
   const int X0 = 2 * BX * bx, Y0 = 2 * BY * by, Z0 = 2 * BZ * bz;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
   const int lx = lane / 3, comp = lane - 3 * (lane / 3);
   const bool lane_ok = lane < ROW;
-  const int X = X0 + lx;
+  const int X = X0 + (lane_ok ? lx : 0);
   const bool xdir = X == 0 || X == m - 1;
-  const int lds_lane = comp * CS + split_index<BX>(lx);
-  const T* xrow = x + 3 * int64_t(X) + comp;
-  T v[RPW];
+  const bool first_y = by == 0, first_z = bz == 0, last_y = by == nby - 1, last_z = bz == nbz - 1;
+  // byte offsets: 3 m^3 sizeof(T) < 2^32 for n <= 256
+  const uint32_t lane_off = uint32_t(3 * X + comp) * uint32_t(sizeof(T));
+  const uint32_t row_stride = uint32_t(3 * m) * uint32_t(sizeof(T));
+  const uint32_t box_off = row_stride * uint32_t(Y0 + m * Z0);
+  const uint32_t plane_stride = row_stride * uint32_t(m);
+  const int lds_lane = comp * CS + split_index<BX>(lane_ok ? lx : 0);
+  // Rows of the node box go to the waves round robin (row r = ly + NY lz to
+  // wave r mod NW).  The row loops are specialised on the wave index, so every
+  // row's local indices, LDS offset and boundary tests are compile-time
+  // constants or single scalar operations.
+  with_wave<NW>(__builtin_amdgcn_readfirstlane(t >> 6), [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    T v[RPW];
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int r = w + k * NW;
-    v[k] = T(0);
-    if (r < NR && lane_ok) {
-      const int ly = r % NY, lz = r / NY;
-      const int Y = Y0 + ly, Z = Z0 + lz;
-      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
-      if (!dir) v[k] = xrow[3 * (int64_t(m) * (Y + int64_t(m) * Z))];
+    for (int k = 0; k < RPW; ++k) {
+      const int r = W + NW * k, ly = r % NY, lz = r / NY;
+      v[k] = T(0);
+      if (r < NR) {
+        const uint32_t off = box_off + uint32_t(ly) * row_stride + uint32_t(lz) * plane_stride + lane_off;
+        v[k] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(x) + off);
+      }
     }
-  }
+    if (lane_ok) {
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int r = w + k * NW;
-    if (r < NR && lane_ok) {
-      const int ly = r % NY, lz = r / NY;
-      buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX] = v[k];
+      for (int k = 0; k < RPW; ++k) {
+        const int r = W + NW * k, ly = r % NY, lz = r / NY;
+        if (r < NR) {
+          const bool rdir = (ly == 0 && first_y) || (ly == NY - 1 && last_y) || (lz == 0 && first_z) ||
+                            (lz == NZ - 1 && last_z);
+          buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX] = (rdir || xdir) ? T(0) : v[k];
+        }
+      }
     }
-  }
+  });
   __syncthreads();
   const int cx = t % BX, cy = (t / BX) % BY, cz = t / (BX * BY);
   T U[3][27];
@@ -154,46 +177,52 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
       __syncthreads();
     }
   }
-  T* yrow = y + 3 * int64_t(X) + comp;
   const bool x_own = lx < NX - 1 || bx == nbx - 1;
-  const int nbz = n / BZ;
-  T* hrow = halo + int64_t(b) * halo_words<BX, BY, BZ>() + lane;
-  // values read back before any store (so their latency is paid once):
-  // accumulating, the old values of the owned nodes; otherwise x on the owned
-  // Dirichlet nodes (identity rows)
-  T old[RPW];
+  T* hslot = halo + int64_t(b) * halo_words<BX, BY, BZ>() + lane;
+  // Owned nodes are stored (added to the old value when accumulating; x on
+  // Dirichlet nodes, identity rows, otherwise), the high-face nodes of the
+  // upper neighbours go to the halo slot.  Accumulating, every old value is
+  // read before the first store, so their latency is paid once.
+  with_wave<NW>(__builtin_amdgcn_readfirstlane(t >> 6), [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    T old[ACC ? RPW : 1];
+    if constexpr (ACC) {
 #pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int r = w + k * NW;
-    old[k] = T(0);
-    if (r < NR && lane_ok) {
-      const int ly = r % NY, lz = r / NY;
-      const int Y = Y0 + ly, Z = Z0 + lz;
-      const bool own = x_own && (ly < NY - 1 || by == nby - 1) && (lz < NZ - 1 || bz == nbz - 1);
-      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
-      const int64_t node3 = 3 * (int64_t(m) * (Y + int64_t(m) * Z));
-      if (ACC && own && !dir) old[k] = yrow[node3];
-      if (!ACC && own && dir) old[k] = xrow[node3];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < RPW; ++k) {
-    const int r = w + k * NW;
-    if (r < NR && lane_ok) {
-      const int ly = r % NY, lz = r / NY;
-      const int Y = Y0 + ly, Z = Z0 + lz;
-      const bool dir = xdir || Y == 0 || Z == 0 || Y == m - 1 || Z == m - 1;
-      const bool own = x_own && (ly < NY - 1 || by == nby - 1) && (lz < NZ - 1 || bz == nbz - 1);
-      const int64_t node3 = 3 * (int64_t(m) * (Y + int64_t(m) * Z));
-      if (!dir) {
-        const T val = buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX];
-        if (own) yrow[node3] = ACC ? old[k] + val : val;
-        else hrow[(lz * NY + ly) * ROW] = val;
-      } else if (own && !ACC) {
-        yrow[node3] = old[k];   // identity row
+      for (int k = 0; k < RPW; ++k) {
+        const int r = W + NW * k, ly = r % NY, lz = r / NY;
+        old[k] = T(0);
+        if (r < NR) {
+          const uint32_t off = box_off + uint32_t(ly) * row_stride + uint32_t(lz) * plane_stride + lane_off;
+          old[k] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(y) + off);
+        }
       }
     }
-  }
+    if (lane_ok) {
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int r = W + NW * k, ly = r % NY, lz = r / NY;
+        if (r < NR) {
+          const bool rdir = (ly == 0 && first_y) || (ly == NY - 1 && last_y) || (lz == 0 && first_z) ||
+                            (lz == NZ - 1 && last_z);
+          const bool row_own = (ly < NY - 1 || last_y) && (lz < NZ - 1 || last_z);
+          const uint32_t off = box_off + uint32_t(ly) * row_stride + uint32_t(lz) * plane_stride + lane_off;
+          const T val = buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX];
+          if (row_own && x_own) {
+            T out;
+            if constexpr (ACC) {
+              out = (rdir || xdir) ? old[k] : old[k] + val;
+            } else {
+              out = val;
+              if (rdir || xdir) out = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(x) + off);
+            }
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(y) + off) = out;
+          } else {
+            hslot[(lz * NY + ly) * ROW] = val;
+          }
+        }
+      }
+    }
+  });
 }
 
 // Adds the halo values of a node's lower neighbour bricks into the node, for

@@ -123,9 +123,17 @@ void launch_to_double(int64_t n, const float* a, double* b, hipStream_t s);
 
 // reductions: result[0] = sum a*b (two-stage, deterministic); partial has >= 1024 doubles
 void launch_dot(int64_t n, const double* a, const double* b, double* partial, double* result, hipStream_t s);
-// result[j] = sum_i V[j*ldv + i] w[i], j < nv; partial has >= nv*256 doubles
+// result[j] = sum_i V[j*ldv + i] w[i], j < nv, and with_norm: result[nv] =
+// w . w; partial has >= (nv + 1)*256 doubles
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* partial, double* result,
-                 hipStream_t s);
+                 hipStream_t s, bool with_norm = false);
+// w -= sum_j h[j] V[j*ldv + i] (j < nv), reading V once, and the products of
+// the new w: dots: result[j] = V_j . w (j < nv), result[nv] = w . w; else
+// result[0] = w . w.  partial has >= 65536 doubles.  Returns false (nothing
+// launched) unless 1 <= nv <= kMupdateDotsMax.
+constexpr int kMupdateDotsMax = 64;
+bool launch_mupdate_dots(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, double* partial,
+                         double* result, bool dots, hipStream_t s);
 // w -= sum_j h[j] V[j*ldv + i]
 void launch_mupdate(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s);
 // y = a*x + b*y

@@ -758,11 +758,12 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(int np, const double* _
 __global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, int nv, const double* __restrict__ V,
                                                          int64_t ldv, const double* __restrict__ w,
                                                          double* __restrict__ part) {
-  // grid (nb, nv): block (b, j) computes a partial of V_j . w (w stays in
-  // the caches across the j; grouping several j per block measured slower)
+  // grid (nb, nv or nv + 1): block (b, j) computes a partial of V_j . w, and
+  // row j = nv (when launched) one of w . w (w stays in the caches across the
+  // j; grouping several j per block measured slower)
   const int j = blockIdx.y;
   double v = 0.0;
-  const double* Vj = V + int64_t(j) * ldv;
+  const double* Vj = j < nv ? V + int64_t(j) * ldv : w;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     v += Vj[i] * w[i];
   v = block_sum(v);
@@ -775,6 +776,56 @@ __global__ void k_mupdate(int64_t n, int nv, const double* __restrict__ V, int64
     double acc = w[i];
     for (int j = 0; j < nv; ++j) acc -= h[j] * V[int64_t(j) * ldv + i];
     w[i] = acc;
+  }
+}
+
+// w <- w - sum_{j < nv} h_j V_j, fused with the block partials that the next
+// Gram-Schmidt step needs of the new w: part[j * gridDim.x + b] = V_j . w for
+// j < nv (DOTS) and, in the last row (j = nv, or 0 without DOTS), w . w.  V is
+// read once: the nv values of an element stay in registers (nv <= NV).
+template <int NV, bool DOTS>
+__global__ __launch_bounds__(kBlock) void k_mupdate_dots(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                         const double* __restrict__ h, double* __restrict__ w,
+                                                         double* __restrict__ part) {
+  constexpr int NA = DOTS ? NV + 1 : 1;
+  double acc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = j < nv ? V[int64_t(j) * ldv + i] : 0.0;
+    double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j < nv) wi -= h[j] * v[j];
+    w[i] = wi;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+        if (j < nv) acc[j] += v[j] * wi;
+    }
+    acc[NA - 1] += wi * wi;
+  }
+  // one wave reduction per row, one barrier, then thread r sums row r
+  __shared__ double sm[kBlock / 64][NA];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    if (a < nv || a == NA - 1) {
+      double val = acc[a];
+      for (int o = 32; o > 0; o >>= 1) val += __shfl_down(val, o, 64);
+      if (lane == 0) sm[wid][a] = val;
+    }
+  }
+  __syncthreads();
+  const int rows = DOTS ? nv + 1 : 1;
+  const int r = threadIdx.x;
+  if (r < rows) {
+    const int a = r < rows - 1 ? r : NA - 1;
+    double sum = 0.0;
+    for (int k = 0; k < int(blockDim.x >> 6); ++k) sum += sm[k][a];
+    part[int64_t(r) * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -1429,10 +1480,34 @@ void launch_dot(int64_t n, const double* a, const double* b, double* part, doubl
 }
 
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part, double* result,
-                 hipStream_t s) {
-  const int nb = 256;   // part holds nv x nb partials (65536 from the caller: nv <= 256)
-  k_mdot_partial<<<dim3(nb, unsigned(nv)), kBlock, 0, s>>>(n, nv, V, ldv, w, part);
-  k_sum_partials<<<unsigned(nv), kBlock, 0, s>>>(nb, part, result);
+                 hipStream_t s, bool with_norm) {
+  const int nb = 256;   // part holds rows x nb partials (65536 from the caller: rows <= 256)
+  const unsigned rows = unsigned(nv + (with_norm ? 1 : 0));
+  k_mdot_partial<<<dim3(nb, rows), kBlock, 0, s>>>(n, nv, V, ldv, w, part);
+  k_sum_partials<<<rows, kBlock, 0, s>>>(nb, part, result);
+}
+
+bool launch_mupdate_dots(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, double* part,
+                         double* result, bool dots, hipStream_t s) {
+  // one wave per SIMD for NV = 64 (about 270 registers): 256 blocks; part
+  // holds at most 65 x 512 partials (65536 from the caller)
+  if (nv < 1 || nv > kMupdateDotsMax) return false;
+  const unsigned rows = dots ? unsigned(nv + 1) : 1u;
+  int nb = 512;
+#define MFGMG_MUD(NVT)                                                                  \
+  if (dots) k_mupdate_dots<NVT, true><<<nb, kBlock, 0, s>>>(n, nv, V, ldv, h, w, part); \
+  else k_mupdate_dots<NVT, false><<<nb, kBlock, 0, s>>>(n, nv, V, ldv, h, w, part);
+  if (nv <= 16) {
+    MFGMG_MUD(16)
+  } else if (nv <= 32) {
+    MFGMG_MUD(32)
+  } else {
+    nb = 256;
+    MFGMG_MUD(64)
+  }
+#undef MFGMG_MUD
+  k_sum_partials<<<rows, kBlock, 0, s>>>(nb, part, result);
+  return true;
 }
 
 void launch_mupdate(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s) {
