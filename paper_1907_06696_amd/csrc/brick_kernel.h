@@ -55,11 +55,22 @@ __device__ __forceinline__ int split_index(int l) {
 
 // ACC: nodes inside the brick are added to y (y += A x); otherwise stored
 // (the caller initialised y to zero on free nodes)
-// halo slot of brick b: [NZ][NY][3 NX] values, x fastest (node-major); the
-// buffer holds one slot per brick followed by a pad of 64 zeros
+// Halo slot of brick b: the box [NZ][NY][3 NX] (x fastest, node-major; only
+// the rows of the high y and z faces are used), then the low and the high x
+// planes packed [NZ][NY][3].  The x planes hold one node per box row, so in
+// the box layout every value would sit on a cache line of its own.  The
+// buffer holds one slot per brick followed by a pad of 64 zeros.
+template <int BX, int BY, int BZ>
+constexpr int64_t halo_box_words() {
+  return int64_t(2 * BZ + 1) * (2 * BY + 1) * 3 * (2 * BX + 1);
+}
+template <int BX, int BY, int BZ>
+constexpr int64_t halo_plane_words() {
+  return int64_t(2 * BZ + 1) * (2 * BY + 1) * 3;
+}
 template <int BX, int BY, int BZ>
 constexpr int64_t halo_words() {
-  return int64_t(2 * BZ + 1) * (2 * BY + 1) * 3 * (2 * BX + 1);
+  return halo_box_words<BX, BY, BZ>() + 2 * halo_plane_words<BX, BY, BZ>();
 }
 
 template <typename T, int BX, int BY, int BZ, bool ACC>
@@ -178,6 +189,10 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
     }
   }
   const bool x_own = lx < NX - 1 || bx == nbx - 1;
+  // lanes of the x planes shared with a neighbour brick: the packed pass below
+  // (FP32; the FP64 kernel, at one wave per SIMD, measured faster without it)
+  constexpr bool PACK = sizeof(T) == 4;
+  const bool x_plane = PACK && ((lx == 0 && bx > 0) || (lx == NX - 1 && bx < nbx - 1));
   T* hslot = halo + int64_t(b) * halo_words<BX, BY, BZ>() + lane;
   // Owned nodes are stored (added to the old value when accumulating; x on
   // Dirichlet nodes, identity rows, otherwise), the high-face nodes of the
@@ -197,7 +212,7 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
         }
       }
     }
-    if (lane_ok) {
+    if (lane_ok && !x_plane) {
 #pragma unroll
       for (int k = 0; k < RPW; ++k) {
         const int r = W + NW * k, ly = r % NY, lz = r / NY;
@@ -223,6 +238,41 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
       }
     }
   });
+  // The x planes shared with a neighbour, one (side, row, component) per
+  // thread.  Rows of the high y or z face belong to an upper neighbour: box
+  // slot, as above.  Otherwise the high plane's contributions go to the
+  // packed high plane, the low plane's (owned) values to the packed low plane,
+  // which the halo kernel completes and stores (accumulating, it adds y);
+  // Dirichlet rows of the low plane are identity rows.
+  if constexpr (PACK) {
+    constexpr int NP = NR * 3;
+    T* slot = halo + int64_t(b) * halo_words<BX, BY, BZ>();
+    T* plane_lo = slot + halo_box_words<BX, BY, BZ>();
+    T* plane_hi = plane_lo + halo_plane_words<BX, BY, BZ>();
+    for (int e = t; e < 2 * NP; e += NT) {
+      const int side = e >= NP ? 1 : 0, rc = e - side * NP;
+      const int row = rc / 3, c = rc - 3 * row;
+      const int ly = row % NY, lz = row / NY;
+      if (side ? bx == nbx - 1 : bx == 0) continue;   // domain boundary plane: written above
+      const int lxs = side ? NX - 1 : 0;
+      const T val = buf[c * CS + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX + split_index<BX>(lxs)];
+      const bool row_own = (ly < NY - 1 || last_y) && (lz < NZ - 1 || last_z);
+      if (!row_own) {
+        slot[(lz * NY + ly) * ROW + 3 * lxs + c] = val;
+      } else if (side) {
+        plane_hi[rc] = val;
+      } else {
+        const bool rdir = (ly == 0 && first_y) || (ly == NY - 1 && last_y) || (lz == 0 && first_z) ||
+                          (lz == NZ - 1 && last_z);
+        if (!rdir) {
+          plane_lo[rc] = val;
+        } else if (!ACC) {
+          const int64_t node3 = 3 * (int64_t(X0) + int64_t(m) * (Y0 + ly + int64_t(m) * (Z0 + lz))) + c;
+          y[node3] = x[node3];
+        }
+      }
+    }
+  }
 }
 
 // Adds the halo values of a node's lower neighbour bricks into the node, for
@@ -230,8 +280,13 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
 // brick; its low-face nodes are enumerated as the z-face (lz = 0), then the
 // y-face without it, then the x-face without both, thread t taking
 // component t mod 3 of node t / 3 (consecutive threads, consecutive words).
+// FP32: a low x-plane node of a brick that is not the first along x holds its
+// own value in the brick's packed low plane (y is then written without being
+// read, unless accumulating), and its x neighbour's contribution in that
+// neighbour's packed high plane.
 template <typename T, int BX, int BY, int BZ>
-__global__ __launch_bounds__(256) void k_brick_halo_add(int n, const T* __restrict__ halo, T* __restrict__ y) {
+__global__ __launch_bounds__(256) void k_brick_halo_add(int n, bool accumulate, const T* __restrict__ halo,
+                                                        T* __restrict__ y) {
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1, ROW = 3 * NX;
   constexpr int MAXN = NX * NY + NX * (NZ - 1) + (NY - 1) * (NZ - 1);   // low-face nodes, at most
   constexpr int KT = (3 * MAXN + 255) / 256;                             // items per thread
@@ -271,18 +326,24 @@ __global__ __launch_bounds__(256) void k_brick_halo_add(int n, const T* __restri
     const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
     const bool live = t < total && !(X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1);
     const bool lowx = live && lx == 0 && bx > 0, lowy = live && ly == 0 && by > 0, lowz = live && lz == 0 && bz > 0;
+    constexpr int64_t HB = halo_box_words<BX, BY, BZ>(), HP = halo_plane_words<BX, BY, BZ>();
+    constexpr bool PACK = sizeof(T) == 4;
 #pragma unroll
     for (int s = 1; s < 8; ++s) {
       const int sx = s & 1, sy = (s >> 1) & 1, sz = s >> 2;
       const bool use = !((sx && !lowx) || (sy && !lowy) || (sz && !lowz));
       const int64_t nb = (bx - sx) + int64_t(nbx) * ((by - sy) + int64_t(nby) * (bz - sz));
       const int qx = sx ? 2 * BX : lx, qy = sy ? 2 * BY : ly, qz = sz ? 2 * BZ : lz;
-      const T* src = use ? halo + nb * halo_words<BX, BY, BZ>() + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp : zero;
-      acc[k] += *src;
+      const T* src = PACK && s == 1 ? halo + nb * halo_words<BX, BY, BZ>() + HB + HP + (int64_t(lz) * NY + ly) * 3 + comp
+                            : halo + nb * halo_words<BX, BY, BZ>() + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp;
+      acc[k] += *(use ? src : zero);
     }
+    const bool packed = PACK && lx == 0 && bx > 0;
+    const T* own = halo + int64_t(b) * halo_words<BX, BY, BZ>() + HB + (int64_t(lz) * NY + ly) * 3 + comp;
+    acc[k] += *(live && packed ? own : zero);
     const int64_t d = 3 * (X + int64_t(m) * (Y + int64_t(m) * Z)) + comp;
     dst[k] = live ? d : -1;
-    cur[k] = *(live ? y + d : zero);
+    cur[k] = *(live && (!packed || accumulate) ? y + d : zero);
   }
 #pragma unroll
   for (int k = 0; k < KT; ++k)

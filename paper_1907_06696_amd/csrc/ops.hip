@@ -1367,7 +1367,7 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
         brick::k_vmult_brick<T, BX, BY, BZ, false><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y, halo);
       else
         brick::k_vmult_brick<T, BX, BY, BZ, true><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y, halo);
-      brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), halo, y);
+      brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
     } else {
       if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
       k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
