@@ -1199,11 +1199,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     launch_dot(np, cr, cz, ctx->red_part, sc, s);   // sc[0] = r.z
     const double tol = o.schur_rtol * bn;
     launch_cg_setup(sc, tol * tol, s);
+    launch_fill(np, 0.0, cq, s);
     constexpr int kCgBatch = 8;
     for (int base = 0; base < o.schur_max_iter; base += kCgBatch) {
       const int kk = std::min(kCgBatch, o.schur_max_iter - base);
       for (int k = 0; k < kk; ++k)
-        launch_cg_pmass_iteration(lv, P, ctx->pmass_minv, cx, cr, cz, cp, cq, ctx->red_part, sc, s);
+        launch_cg_pmass_iteration(lv, P, ctx->pmass_minv, cx, cr, cz, cp, cq, ctx->red_part, sc, base + k, s);
       (void)hipMemcpyAsync(ctx->host_res + 480, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
       if (ctx->host_res[485] != 0.0) break;

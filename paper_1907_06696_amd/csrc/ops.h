@@ -158,12 +158,16 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
 // p_out = M_p p; gate (device, may be null): when *gate != 0 the cell kernel is skipped
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* p_out, hipStream_t s,
                   const double* gate = nullptr);
+// the same without clearing p_out first (p_out must be zero on entry)
+void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, double* p_out, hipStream_t s,
+                      const double* gate = nullptr);
 // Jacobi-CG on M_p with its scalars on the device (see ops.hip): setup of the
-// scalars (sc[0] must hold r.z), and one iteration (no host synchronisation;
-// a no-op once sc[5] is set).  part holds >= 2048 doubles.
+// scalars (sc[0] must hold r.z, q must be zero), and iteration k = 0, 1, ...
+// (no host synchronisation; a no-op once sc[5] is set).  part holds >= 3072
+// doubles.
 void launch_cg_setup(double* sc, double tol2, hipStream_t s);
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
-                               double* z, double* p, double* q, double* part, double* sc, hipStream_t s);
+                               double* z, double* p, double* q, double* part, double* sc, int k, hipStream_t s);
 // copy p_in on hanging pressure nodes into p_out
 void launch_p_identity(const DevPressure& P, const double* p_in, double* p_out, hipStream_t s);
 // resolve hanging values: u[h] = sum w u[m] (velocity) and p likewise

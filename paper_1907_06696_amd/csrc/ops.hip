@@ -1558,6 +1558,10 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
                   const double* gate) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
+  launch_pmass_add(L, P, p, po, s, gate);
+}
+void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
+                      const double* gate) {
   if ((L.blk4.n && L.blk4.pslots) || (L.blk2.n && L.blk2.pslots)) {
     if (L.blk4.n) k_pmass_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, p, po, gate);
     if (L.blk2.n) k_pmass_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, p, po, gate);
@@ -1573,27 +1577,39 @@ void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, doub
 }
 
 // ------------------------------------------------------- device-resident CG
-// Scalars of the Jacobi-CG on M_p live in sc[]: 0 rz, 1 beta, 4 stopping
-// threshold on r.r, 5 done flag, 6 iterations, 7 alpha.  Once done is set
+// Scalars of the Jacobi-CG on M_p live in sc[]: 0, 1 r.z of even and odd
+// iterations (iteration k reads slot k mod 2 and writes the other), 4
+// stopping threshold on r.r, 5 done flag, 6 iterations.  Once done is set
 // every kernel of a further iteration returns at once, so the host may queue
-// several iterations between checks without changing the result.
+// several iterations between checks without changing the result.  The two
+// scalar steps (alpha and the test / beta) are taken by every block of the
+// vector kernels from the previous kernel's block partials (same sums, same
+// order in every block), so an iteration is M_p p, p.q, and two vector
+// kernels; the second also clears q for the next M_p p.
 namespace {
 __global__ __launch_bounds__(kBlock) void k_cg_setup(double* sc, double tol2) {
   if (threadIdx.x == 0) sc[1] = 0.0, sc[4] = tol2, sc[5] = 0.0, sc[6] = 0.0, sc[7] = 0.0;
 }
-__global__ __launch_bounds__(kBlock) void k_cg_alpha(int np, const double* __restrict__ part, double* sc) {
+// sum of part[0, np) in every thread of the block
+__device__ __forceinline__ double block_sum_all(int np, const double* __restrict__ part) {
+  __shared__ double bc;
   double v = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
   v = block_sum(v);
-  if (threadIdx.x == 0 && sc[5] == 0.0) sc[7] = sc[0] / v;
+  if (threadIdx.x == 0) bc = v;
+  __syncthreads();
+  v = bc;
+  __syncthreads();
+  return v;
 }
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ sc,
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int npq, const double* __restrict__ part_pq,
+                                                     const double* __restrict__ sc, int par,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      const double* __restrict__ minv, double* __restrict__ x,
                                                      double* __restrict__ r, double* __restrict__ z,
                                                      double* __restrict__ part) {
   if (sc[5] != 0.0) return;
-  const double alpha = sc[7];
+  const double alpha = sc[par] / block_sum_all(npq, part_pq);
   double rr = 0.0, rz = 0.0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     x[i] += alpha * p[i];
@@ -1606,43 +1622,38 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* _
   rz = block_sum(rz);
   if (threadIdx.x == 0) part[blockIdx.x] = rr, part[gridDim.x + blockIdx.x] = rz;
 }
-__global__ __launch_bounds__(kBlock) void k_cg_check(int np, const double* __restrict__ part, double* sc) {
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int np, const double* __restrict__ part, double* sc,
+                                                      int par, const double* __restrict__ z, double* __restrict__ p,
+                                                      double* __restrict__ q) {
   if (sc[5] != 0.0) return;
-  double rr = 0.0, rz = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) rr += part[i], rz += part[np + i];
-  rr = block_sum(rr);
-  rz = block_sum(rz);
-  if (threadIdx.x == 0) {
-    sc[6] += 1.0;
-    if (rr <= sc[4]) {
-      sc[5] = 1.0;
-    } else {
-      sc[1] = rz / sc[0];
-      sc[0] = rz;
-    }
+  const double rr = block_sum_all(np, part);
+  const double rz = block_sum_all(np, part + np);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (rr <= sc[4]) {
+    if (lead) sc[6] += 1.0, sc[5] = 1.0;
+    return;
   }
-}
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double* __restrict__ sc,
-                                                      const double* __restrict__ z, double* __restrict__ p) {
-  if (sc[5] != 0.0) return;
-  const double beta = sc[1];
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+  const double beta = rz / sc[par];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     p[i] = z[i] + beta * p[i];
+    q[i] = 0.0;
+  }
+  if (lead) sc[6] += 1.0, sc[par ^ 1] = rz;
 }
 }  // namespace
 
 void launch_cg_setup(double* sc, double tol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, tol2); }
 
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
-                               double* z, double* p, double* q, double* part, double* sc, hipStream_t s) {
+                               double* z, double* p, double* q, double* part, double* sc, int k, hipStream_t s) {
   const int64_t n = P.np;
-  launch_pmass(L, P, p, q, s, sc + 5);
+  // q is zero here: cleared by the setup, then by the previous iteration
+  launch_pmass_add(L, P, p, q, s, sc + 5);
   k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, p, q, part);
-  k_cg_alpha<<<1, kBlock, 0, s>>>(kRedBlocks, part, sc);
   const unsigned g = grid_for(n, kBlock, kRedBlocks);
-  k_cg_update<<<g, kBlock, 0, s>>>(n, sc, p, q, minv, x, r, z, part);
-  k_cg_check<<<1, kBlock, 0, s>>>(int(g), part, sc);
-  k_cg_pupdate<<<grid_for(n), kBlock, 0, s>>>(n, sc, z, p);
+  const int par = k & 1;
+  k_cg_update<<<g, kBlock, 0, s>>>(n, kRedBlocks, part, sc, par, p, q, minv, x, r, z, part + kRedBlocks);
+  k_cg_pupdate<<<g, kBlock, 0, s>>>(n, int(g), part + kRedBlocks, sc, par, z, p, q);
 }
 void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hipStream_t s) {
   if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, pin, pout);
