@@ -216,10 +216,30 @@ typedef struct {
   int32_t use_graph;      /* 1: the V-cycle is captured once per solve as a HIP
                              graph (on a stream of the context) and replayed on
                              `stream`; 0: launched kernel by kernel (1) */
+  /* Sec. 3.4 variants.  A Schur approximation that is a fixed linear map lets
+   * plain GMRES (basis only, half the vectors of FGMRES) or IDR(s) (short
+   * recurrences, 4 + 3s vectors) replace FGMRES. */
+  int32_t krylov;         /* MFGMG_FGMRES, MFGMG_GMRES or MFGMG_IDR; the last
+                             two need schur = MFGMG_SCHUR_CHEB (FGMRES) */
+  int32_t idr_s;          /* IDR shadow-space dimension, 1..8 (2) */
+  int32_t block;          /* MFGMG_BLOCK_TRIANGULAR: P of eq. stokes_precond;
+                             MFGMG_BLOCK_DIAGONAL: P_D = diag(A, -S) of
+                             eq. stokes_precond_diag, z_u = V(v_u) (triangular) */
+  int32_t schur;          /* MFGMG_SCHUR_CG: Jacobi CG on M_p to schur_rtol;
+                             MFGMG_SCHUR_CHEB: Chebyshev iteration (Saad,
+                             Alg. 12.1) of degree schur_degree from 0 with
+                             diag(M_p)^-1 over [b/27, b], b = max_i
+                             (M_p 1)_i / (M_p)_ii, a fixed linear map (CG) */
+  int32_t schur_degree;   /* 1..64 (8) */
 } mfgmg_solve_opts;
 
+enum { MFGMG_FGMRES = 0, MFGMG_GMRES = 1, MFGMG_IDR = 2 };
+enum { MFGMG_BLOCK_TRIANGULAR = 0, MFGMG_BLOCK_DIAGONAL = 1 };
+enum { MFGMG_SCHUR_CG = 0, MFGMG_SCHUR_CHEB = 1 };
+
 typedef struct {
-  int32_t iterations;    /* outer FGMRES iterations */
+  int32_t iterations;    /* outer iterations: Arnoldi steps ((F)GMRES) or
+                            K P applications (IDR), one V-cycle each */
   int32_t vcycles;
   int64_t inner_cg_iterations;
   double rel_residual;   /* ||b - K x|| / ||b||, recomputed in FP64 at the end */
@@ -230,11 +250,16 @@ typedef struct {
 /* Fill opts with the defaults above. */
 int mfgmg_default_opts(mfgmg_solve_opts* opts);
 
-/* Solve the block system with FGMRES (x0 = 0) and the block-triangular
- * preconditioner z_p = -S^{-1} r_p, z_u = V(r_u - B^T z_p).  Outputs have
- * hanging values interpolated and the pressure shifted to zero mean.
- * rhs_p_dev may be NULL (zero).  Synchronises `stream`.  Returns
- * ERR_NOCONV (stats and outputs filled) if rtol is not reached. */
+/* Solve the block system (Sec. 2.2) with FGMRES (x0 = 0; GMRES or IDR(s) by
+ * opts->krylov) right preconditioned by the block-triangular z_p =
+ * -S^{-1} r_p, z_u = V(r_u - B^T z_p) (or the block-diagonal P_D).  IDR uses
+ * the shadow space of SplitMix64 columns (seeds 4711 + i over the counters
+ * 3 key + component for velocity dofs and 2^40 + key for pressure nodes),
+ * orthonormalised by classical Gram-Schmidt.  Outputs have hanging values
+ * interpolated and the pressure shifted to zero mean.  rhs_p_dev may be
+ * NULL (zero).  Synchronises `stream`.  Returns ERR_INVALID for options out
+ * of range (GMRES or IDR without the Chebyshev Schur map), ERR_NOCONV
+ * (stats and outputs filled) if rtol is not reached. */
 int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u_dev, const double* rhs_p_dev, double* u_dev,
                        double* p_dev, const mfgmg_solve_opts* opts, mfgmg_solve_stats* stats, void* stream);
 

@@ -1116,6 +1116,11 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->use_scaling = 0;
   o->verbose = 0;
   o->use_graph = 1;
+  o->krylov = MFGMG_FGMRES;
+  o->idr_s = 2;
+  o->block = MFGMG_BLOCK_TRIANGULAR;
+  o->schur = MFGMG_SCHUR_CG;
+  o->schur_degree = 8;
   return MFGMG_OK;
 }
 
@@ -1127,8 +1132,13 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   mfgmg_default_opts(&o);
   if (opts) o = *opts;
   if (o.restart < 1 || o.restart > 120 || !(o.rtol > 0) || o.max_iter < 1 ||
-      (o.vcycle_prec != MFGMG_FP32 && o.vcycle_prec != MFGMG_FP64))
+      (o.vcycle_prec != MFGMG_FP32 && o.vcycle_prec != MFGMG_FP64) || o.krylov < MFGMG_FGMRES ||
+      o.krylov > MFGMG_IDR || o.idr_s < 1 || o.idr_s > 8 || (o.block != MFGMG_BLOCK_TRIANGULAR &&
+      o.block != MFGMG_BLOCK_DIAGONAL) || (o.schur != MFGMG_SCHUR_CG && o.schur != MFGMG_SCHUR_CHEB) ||
+      o.schur_degree < 1 || o.schur_degree > 64)
     return ctx->set(MFGMG_ERR_INVALID, "bad solver options");
+  if (o.krylov != MFGMG_FGMRES && o.schur != MFGMG_SCHUR_CHEB)
+    return ctx->set(MFGMG_ERR_INVALID, "GMRES and IDR need the linear (Chebyshev) Schur approximation");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   struct ScalingGuard {   // V-cycles of this solve use the installed scalings iff requested
@@ -1143,9 +1153,13 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   const DevPressure& P = ctx->pres;
   const int64_t nu = 3 * lv.nnode, np = P.np, n = nu + np;
   const int m = o.restart;
-  // Krylov storage: V (m+1 vectors), Z (m), b, x, r, w; FP32 staging; CG vectors
-  double* V = ctx->dalloc<double>(size_t(m + 1) * n);
-  double* Z = ctx->dalloc<double>(size_t(m) * n);
+  const bool idr = o.krylov == MFGMG_IDR, flex = o.krylov == MFGMG_FGMRES;
+  const int sdim = o.idr_s;
+  // Krylov storage, FGMRES: V (m+1 vectors), Z (m); GMRES: V (m+1), one z;
+  // IDR(s): Q, G, U (s each) in V, v and t in Z.  Then b, x, r, w; FP32
+  // staging; CG vectors
+  double* V = ctx->dalloc<double>(size_t(idr ? 3 * sdim : m + 1) * n);
+  double* Z = ctx->dalloc<double>(size_t(idr ? 2 : flex ? m : 1) * n);
   double* b = ctx->dalloc<double>(size_t(n));
   double* x = ctx->dalloc<double>(size_t(n));
   double* r = ctx->dalloc<double>(size_t(n));
@@ -1154,7 +1168,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   float* bf = ctx->dalloc<float>(size_t(nu));
   float* xf = ctx->dalloc<float>(size_t(nu));
   double* cg = ctx->dalloc<double>(size_t(5 * np));   // r, z (contiguous), p, q, x
-  double* yv = ctx->dalloc<double>(size_t(m + 1));
+  double* yv = ctx->dalloc<double>(size_t(std::max(m + 1, 16)));
   const bool fp64 = o.vcycle_prec == MFGMG_FP64;
   double* zfix = (o.use_graph && fp64) ? ctx->dalloc<double>(size_t(nu)) : nullptr;   // graph's fixed output
   std::vector<void*> mine = {V, Z, b, x, r, w, tu, bf, xf, cg, yv};
@@ -1185,8 +1199,36 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     launch_div(lv, P, in, out + nu, s);
     launch_p_identity(P, in + nu, out + nu, s);
   };
+  // the fixed Chebyshev map: interval [b/27, b], b = max_i (M_p 1)_i minv_i
+  double cheb_hi = 0.0;
+  if (o.schur == MFGMG_SCHUR_CHEB) {
+    launch_fill(np, 1.0, cp, s);
+    launch_pmass(lv, P, cp, cq, s);
+    launch_mul(np, ctx->pmass_minv, cq, cz, s);
+    std::vector<double> h(static_cast<size_t>(np));
+    HIPCHK(hipMemcpyAsync(h.data(), cz, size_t(np) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (double v : h) cheb_hi = std::max(cheb_hi, v);
+  }
+  // Chebyshev iteration (Saad, Alg. 12.1) from 0 on M_p: cx = p(M_p) rhs
+  auto schur_cheb = [&](const double* rhs) {
+    const double hi = cheb_hi, lo = hi / 27.0;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    launch_cheb_init0<double>(np, rhs, ctx->pmass_minv, cr, cz, cx, 1.0 / theta, s);
+    for (int k = 1; k < o.schur_degree; ++k) {
+      launch_pmass(lv, P, cz, cq, s);
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      launch_cheb_step<double>(np, cq, ctx->pmass_minv, cr, cz, cx, rho_new * rho, 2.0 * rho_new / delta, s);
+      rho = rho_new;
+    }
+  };
   // Jacobi-preconditioned CG on M_p: cx = M_p^{-1} rhs
   auto schur = [&](const double* rhs) {
+    if (o.schur == MFGMG_SCHUR_CHEB) {
+      schur_cheb(rhs);
+      return;
+    }
     (void)hipMemcpyAsync(cr, rhs, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
     launch_fill(np, 0.0, cx, s);
     const double bn = std::sqrt(dot_sync(ctx, np, rhs, rhs, s));
@@ -1232,11 +1274,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       return ctx->set(MFGMG_ERR_HIP, std::string("V-cycle graph capture: ") + hipGetErrorString(e));
     }
   }
-  // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p)
+  // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p) (block
+  // triangular) or V(v_u) (block diagonal)
   auto precondition = [&](const double* v, double* z) {
     schur(v + nu);
     (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    launch_grad_add(lv, P, cx, tu, s);
+    if (o.block == MFGMG_BLOCK_TRIANGULAR) launch_grad_add(lv, P, cx, tu, s);
     if (fp64) {
       if (vexec) {
         (void)hipGraphLaunch(vexec, s);
@@ -1268,15 +1311,139 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   std::vector<double> H(static_cast<size_t>((m + 1) * m)), cs(static_cast<size_t>(m)),
       sn(static_cast<size_t>(m)), g(static_cast<size_t>(m + 1)), y(static_cast<size_t>(m));
   auto Hij = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
-  while (!bad && bn > 0 && its < o.max_iter && beta > o.rtol * bn) {
+  if (idr && !bad && bn > 0) {
+    // IDR(s) with biorthogonal basis vectors (van Gijzen and Sonneveld, ACM
+    // TOMS 38:5, 2011), right preconditioned, x0 = 0: per cycle s steps that
+    // keep r orthogonal to Q(:, 0..k), then a dimension-reduction step with
+    // the minimal-residual omega, enlarged when cos(t, r) < 0.7
+    const int ss = sdim;
+    double* Q = V;
+    double* G = V + size_t(ss) * n;
+    double* U = V + size_t(2 * ss) * n;
+    double* vv = Z;
+    double* tt = Z + n;
+    auto col = [&](double* base, int i) { return base + size_t(i) * n; };
+    double* res = ctx->red_res;
+    double* hres = ctx->host_res;
+    {
+      // shadow space: keyed SplitMix64 columns, then Gram-Schmidt
+      const Level& h = ctx->mesh->level(L);
+      std::vector<double> q(static_cast<size_t>(n));
+      for (int i = 0; i < ss; ++i) {
+        const uint64_t seed = uint64_t(4711 + i);
+        for (int64_t k = 0; k < h.nnode; ++k)
+          for (int c = 0; c < 3; ++c) q[size_t(3 * k + c)] = splitmix_pm1(seed, uint64_t(3 * h.key[size_t(k)] + c));
+        for (int64_t k = 0; k < np; ++k)
+          q[size_t(nu + k)] = splitmix_pm1(seed, (uint64_t(1) << 40) + uint64_t(h.pkey[size_t(k)]));
+        HIPCHK(hipMemcpyAsync(col(Q, i), q.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int j = 0; j < i; ++j) {
+          const double a = dot_sync(ctx, n, col(Q, j), col(Q, i), s);
+          launch_axpby(n, -a, col(Q, j), 1.0, col(Q, i), s);
+        }
+        const double nq = std::sqrt(dot_sync(ctx, n, col(Q, i), col(Q, i), s));
+        launch_scale_copy(n, 1.0 / nq, col(Q, i), col(Q, i), s);
+      }
+    }
+    launch_fill(2 * int64_t(ss) * n, 0.0, G, s);   // G and U
+    std::vector<double> M(static_cast<size_t>(ss * ss), 0.0), f(static_cast<size_t>(ss)), cpos(8), cneg(8);
+    auto Mij = [&](int i, int j) -> double& { return M[size_t(i) * ss + j]; };
+    for (int i = 0; i < ss; ++i) Mij(i, i) = 1.0;
+    double om = 1.0, rn = bn;
+    constexpr double kKappa = 0.7;
+    bool done = rn <= o.rtol * bn;
+    int printed = 0;
+    auto progress = [&]() {
+      if (o.verbose > 0 && its / o.verbose > printed) {
+        printed = its / o.verbose;
+        std::fprintf(stderr, "[mfgmg] idr(%d) it %d  residual %.3e  %.1f s\n", ss, its, rn / bn,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        std::fflush(stderr);
+      }
+    };
+    while (!done && !bad && its < o.max_iter) {
+      launch_mdot(n, ss, Q, n, r, ctx->red_part, res, s);   // f = Q^T r
+      (void)hipMemcpyAsync(hres, res, size_t(ss) * sizeof(double), hipMemcpyDeviceToHost, s);
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < ss; ++i) f[size_t(i)] = hres[i];
+      for (int k = 0; k < ss; ++k) {
+        const int q = ss - k;
+        // M(k:, k:) c = f(k:), lower triangular
+        for (int i = 0; i < q; ++i) {
+          double t = f[size_t(k + i)];
+          for (int j = 0; j < i; ++j) t -= Mij(k + i, k + j) * cpos[size_t(j)];
+          cpos[size_t(i)] = t / Mij(k + i, k + i);
+          cneg[size_t(i)] = -cpos[size_t(i)];
+        }
+        HIPCHK(hipMemcpyAsync(yv, cpos.data(), size_t(q) * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(yv + 8, cneg.data(), size_t(q) * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(vv, r, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_mupdate(n, q, col(G, k), n, yv, vv, s);       // v = r - G(:, k:) c
+        precondition(vv, tt);                               // t = P^{-1} v
+        launch_scale_copy(n, om, tt, vv, s);
+        launch_mupdate(n, q, col(U, k), n, yv + 8, vv, s);   // om t + U(:, k:) c
+        HIPCHK(hipMemcpyAsync(col(U, k), vv, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        apply_K(col(U, k), col(G, k));
+        ++its;
+        for (int i = 0; i < k; ++i) {   // biorthogonalise against the earlier columns
+          const double a = dot_sync(ctx, n, col(Q, i), col(G, k), s) / Mij(i, i);
+          launch_axpby(n, -a, col(G, i), 1.0, col(G, k), s);
+          launch_axpby(n, -a, col(U, i), 1.0, col(U, k), s);
+        }
+        launch_mdot(n, q, col(Q, k), n, col(G, k), ctx->red_part, res, s);   // M(k:, k)
+        (void)hipMemcpyAsync(hres, res, size_t(q) * sizeof(double), hipMemcpyDeviceToHost, s);
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < q; ++i) Mij(k + i, k) = hres[i];
+        if (!(Mij(k, k) != 0.0) || !std::isfinite(Mij(k, k))) {
+          bad = true;
+          break;
+        }
+        const double be = f[size_t(k)] / Mij(k, k);
+        launch_axpby(n, -be, col(G, k), 1.0, r, s);
+        launch_axpby(n, be, col(U, k), 1.0, x, s);
+        rn = std::sqrt(dot_sync(ctx, n, r, r, s));
+        progress();
+        if (!std::isfinite(rn)) bad = true;
+        if (bad || rn <= o.rtol * bn || its >= o.max_iter) {
+          done = true;
+          break;
+        }
+        for (int i = k + 1; i < ss; ++i) f[size_t(i)] -= be * Mij(i, k);
+      }
+      if (done || bad) break;
+      precondition(r, vv);   // dimension reduction
+      apply_K(vv, tt);
+      ++its;
+      const double t2 = dot_sync(ctx, n, tt, tt, s), tr = dot_sync(ctx, n, tt, r, s);
+      om = tr / t2;
+      const double rho = std::fabs(tr) / (std::sqrt(t2) * rn);
+      if (rho < kKappa) om *= kKappa / rho;
+      if (!std::isfinite(om)) {
+        bad = true;
+        break;
+      }
+      launch_axpby(n, -om, tt, 1.0, r, s);
+      launch_axpby(n, om, vv, 1.0, x, s);
+      rn = std::sqrt(dot_sync(ctx, n, r, r, s));
+      progress();
+      if (!std::isfinite(rn)) bad = true;
+      done = rn <= o.rtol * bn;
+    }
+    apply_K(x, r);   // the true residual decides
+    launch_axpby(n, 1.0, b, -1.0, r, s);
+    beta = std::sqrt(dot_sync(ctx, n, r, r, s));
+    if (!std::isfinite(beta)) bad = true;
+  }
+  while (!idr && !bad && bn > 0 && its < o.max_iter && beta > o.rtol * bn) {
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     launch_scale_copy(n, 1.0 / beta, r, V, s);
     int jd = 0;
     for (int j = 0; j < m; ++j) {
-      precondition(V + size_t(j) * n, Z + size_t(j) * n);
-      apply_K(Z + size_t(j) * n, w);
+      double* zj = flex ? Z + size_t(j) * n : Z;
+      precondition(V + size_t(j) * n, zj);
+      apply_K(zj, w);
       // classical Gram-Schmidt, repeated only when the first pass cancelled
       // much of w (||w'|| < ||w|| / sqrt(2), the criterion of Daniel, Gragg,
       // Kaufman and Stewart, 1976).  Coefficients in red_res [0, nv] (h1 and
@@ -1350,7 +1517,14 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     std::vector<double> ny(static_cast<size_t>(jd));
     for (int i = 0; i < jd; ++i) ny[size_t(i)] = -y[size_t(i)];
     HIPCHK(hipMemcpyAsync(yv, ny.data(), size_t(jd) * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_mupdate(n, jd, Z, n, yv, x, s);   // x += Z y
+    if (flex) {
+      launch_mupdate(n, jd, Z, n, yv, x, s);   // x += Z y
+    } else {
+      launch_fill(n, 0.0, w, s);
+      launch_mupdate(n, jd, V, n, yv, w, s);   // w = V y
+      precondition(w, Z);
+      launch_axpby(n, 1.0, Z, 1.0, x, s);      // x += P^{-1} V y
+    }
     apply_K(x, r);
     launch_axpby(n, 1.0, b, -1.0, r, s);     // r = b - K x
     beta = std::sqrt(dot_sync(ctx, n, r, r, s));

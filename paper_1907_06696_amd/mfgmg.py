@@ -49,7 +49,9 @@ class Info(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("vcycle_prec", C.c_int32), ("schur_rtol", C.c_double), ("schur_max_iter", C.c_int32),
-                ("use_scaling", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32)]
+                ("use_scaling", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32),
+                ("krylov", C.c_int32), ("idr_s", C.c_int32), ("block", C.c_int32), ("schur", C.c_int32),
+                ("schur_degree", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -333,9 +335,13 @@ class Solver:
     def solve_stokes(self, rhs_u, u_out, p_out, rhs_p=None, stream=None, raise_on_noconv=True, **opts):
         o = SolveOpts()
         self.lib.mfgmg_default_opts(C.byref(o))
+        names = {"krylov": {"fgmres": 0, "gmres": 1, "idr": 2}, "block": {"triangular": 0, "diagonal": 1},
+                 "schur": {"cg": 0, "cheb": 1}}
         for k, v in opts.items():
             if k == "vcycle_prec" and isinstance(v, str):
                 v = FP32 if v.lower() == "fp32" else FP64
+            elif k in names and isinstance(v, str):
+                v = names[k][v.lower()]
             setattr(o, k, v)
         st = SolveStats()
         code = self.lib.mfgmg_solve_stokes(self.h, _dev_ptr(rhs_u), _dev_ptr(rhs_p) if rhs_p is not None else None,
