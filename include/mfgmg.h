@@ -255,7 +255,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* opts);
  * -S^{-1} r_p, z_u = V(r_u - B^T z_p) (or the block-diagonal P_D).  IDR uses
  * the shadow space of SplitMix64 columns (seeds 4711 + i over the counters
  * 3 key + component for velocity dofs and 2^40 + key for pressure nodes),
- * orthonormalised by classical Gram-Schmidt.  Outputs have hanging values
+ * orthonormalised by Gram-Schmidt (each column against the finished ones).  Outputs have hanging values
  * interpolated and the pressure shifted to zero mean.  rhs_p_dev may be
  * NULL (zero).  Synchronises `stream`.  Returns ERR_INVALID for options out
  * of range (GMRES or IDR without the Chebyshev Schur map), ERR_NOCONV

@@ -137,8 +137,8 @@ def gmres(apply_K, apply_P, b, rtol=1e-8, restart=50, maxit=1000):
 def shadow_space(keys_u, keys_p, s, seed=4711):
     """IDR shadow space [n][s] for the block vector [u; p]: column i draws
     SplitMix64 values with seed + i over the counters 3 key + component
-    (velocity) and 2^40 + key (pressure), then classical Gram-Schmidt makes
-    the columns orthonormal."""
+    (velocity) and 2^40 + key (pressure), then Gram-Schmidt (each column
+    against the finished ones in turn) makes the columns orthonormal."""
     from .rng import uniform_pm1
     cu = (3 * np.asarray(keys_u, dtype=np.int64)[:, None] + np.arange(3)[None, :]).ravel()
     cp = (1 << 40) + np.asarray(keys_p, dtype=np.int64)

@@ -132,6 +132,67 @@ __device__ __forceinline__ void quad_point(const T (&W)[3][27], T (&Y)[3][27], T
   deriv_t<qz>(f22, Y[2][q - 9 * qz], Y[2][q - 9 * qz + 9], Y[2][q - 9 * qz + 18]);
 }
 
+// derivative (scaled by g) along direction D at Gauss point (qx, qy, qz) of the
+// collocation values v [27]
+template <int D, int qx, int qy, int qz, typename T>
+__device__ __forceinline__ T line_deriv(const T* v) {
+  constexpr int q = qx + 3 * qy + 9 * qz;
+  if constexpr (D == 0) return deriv<qx>(v[q - qx], v[q - qx + 1], v[q - qx + 2]);
+  else if constexpr (D == 1) return deriv<qy>(v[q - 3 * qy], v[q - 3 * qy + 3], v[q - 3 * qy + 6]);
+  else return deriv<qz>(v[q - 9 * qz], v[q - 9 * qz + 9], v[q - 9 * qz + 18]);
+}
+
+// One Gauss point's contribution to output component C only: row C of F,
+// F_Cd = cq (d_d u_C + d_C u_d) (2 cq d_C u_C on the diagonal), contracted
+// with the derivative in direction d: the operations of row C of quad_point,
+// in the same order (so the results agree bit for bit).
+template <int C, int qx, int qy, int qz, typename T>
+__device__ __forceinline__ void quad_point_row(const T (&W)[3][27], T (&Y)[27], T coef) {
+  constexpr double wx = qx == 1 ? kW1 : kW0;
+  constexpr double wy = qy == 1 ? kW1 : kW0;
+  constexpr double wz = qz == 1 ? kW1 : kW0;
+  constexpr int q = qx + 3 * qy + 9 * qz;
+  const T cq = coef * T(wx * wy * wz);
+  T f[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T gcd;   // d_d u_C
+    if (d == 0) gcd = line_deriv<0, qx, qy, qz>(W[C]);
+    else if (d == 1) gcd = line_deriv<1, qx, qy, qz>(W[C]);
+    else gcd = line_deriv<2, qx, qy, qz>(W[C]);
+    if (d == C) {
+      f[d] = (cq + cq) * gcd;
+    } else {
+      const T gdc = line_deriv<C, qx, qy, qz>(W[d]);   // d_C u_d
+      f[d] = cq * (gcd + gdc);
+    }
+  }
+  deriv_t<qx>(f[0], Y[q - qx], Y[q - qx + 1], Y[q - qx + 2]);
+  deriv_t<qy>(f[1], Y[q - 3 * qy], Y[q - 3 * qy + 3], Y[q - 3 * qy + 6]);
+  deriv_t<qz>(f[2], Y[q - 9 * qz], Y[q - 9 * qz + 9], Y[q - 9 * qz + 18]);
+}
+
+// Output component C of the cell operator from the Gauss-point values W
+// (interp_all already applied to every component); Y: collocation-basis
+// result (interp_all_t still to be applied).  coef = mu * h.
+template <int C, typename T>
+__device__ __forceinline__ void apply_cell_row(const T (&W)[3][27], T (&Y)[27], T mu_h) {
+#pragma unroll
+  for (int a = 0; a < 27; ++a) Y[a] = T(0);
+  const T coef = mu_h * T(kInvG2);
+#define MFGMG_QPR(x, y, z) quad_point_row<C, x, y, z>(W, Y, coef);
+  MFGMG_QPR(0, 0, 0) MFGMG_QPR(1, 0, 0) MFGMG_QPR(2, 0, 0)
+  MFGMG_QPR(0, 1, 0) MFGMG_QPR(1, 1, 0) MFGMG_QPR(2, 1, 0)
+  MFGMG_QPR(0, 2, 0) MFGMG_QPR(1, 2, 0) MFGMG_QPR(2, 2, 0)
+  MFGMG_QPR(0, 0, 1) MFGMG_QPR(1, 0, 1) MFGMG_QPR(2, 0, 1)
+  MFGMG_QPR(0, 1, 1) MFGMG_QPR(1, 1, 1) MFGMG_QPR(2, 1, 1)
+  MFGMG_QPR(0, 2, 1) MFGMG_QPR(1, 2, 1) MFGMG_QPR(2, 2, 1)
+  MFGMG_QPR(0, 0, 2) MFGMG_QPR(1, 0, 2) MFGMG_QPR(2, 0, 2)
+  MFGMG_QPR(0, 1, 2) MFGMG_QPR(1, 1, 2) MFGMG_QPR(2, 1, 2)
+  MFGMG_QPR(0, 2, 2) MFGMG_QPR(1, 2, 2) MFGMG_QPR(2, 2, 2)
+#undef MFGMG_QPR
+}
+
 // U[c][a]: nodal values of component c at local node a (x fastest) on input,
 // the cell's output contributions y_(a,c) on return.  coef = mu * h.
 template <typename T>

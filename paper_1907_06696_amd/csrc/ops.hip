@@ -144,6 +144,57 @@ __global__ __launch_bounds__(kCellBlock) void k_vmult_uniform(int64_t n, const T
   for (int a = 0; a < 27; ++a) scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
 }
 
+// The same operator with three threads per cell, one per output component:
+// on the small levels below the brick kernel the grid is a few waves and the
+// time is the per-thread chain of the cell operator, about 2.5x shorter here.
+// Block: 64 cells x 3 components (wave c holds component c); each thread
+// interpolates its component to the Gauss points, the 81 values are shared
+// through LDS, and each thread produces its component's 27 outputs.
+template <typename T>
+__global__ __launch_bounds__(192) void k_vmult_uniform3(int64_t n, const T* __restrict__ mu, const T* __restrict__ x,
+                                                        T* __restrict__ y) {
+  __shared__ T wsh[3][27][64];
+  const int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int64_t cell = blockIdx.x * int64_t(64) + lane;
+  const bool live = cell < n * n * n;
+  const UniformCell uc(n, live ? cell : 0);
+  T w[27];
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 3; ++xx) {
+        const int32_t sl = uc.slot(xx, yy, z);
+        w[xx + 3 * yy + 9 * z] = sl >= 0 ? x[3 * int64_t(sl) + c] : T(0);
+      }
+  cellop::interp_all(w);
+#pragma unroll
+  for (int a = 0; a < 27; ++a) wsh[c][a][lane] = w[a];
+  __syncthreads();
+  T W[3][27];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int a = 0; a < 27; ++a) W[cc][a] = wsh[cc][a][lane];
+  const T mu_h = mu[live ? cell : 0] / T(n);
+  if (c == 0) cellop::apply_cell_row<0>(W, w, mu_h);
+  else if (c == 1) cellop::apply_cell_row<1>(W, w, mu_h);
+  else cellop::apply_cell_row<2>(W, w, mu_h);
+  cellop::interp_all_t(w);
+  if (!live) return;
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 3; ++xx) {
+        const int32_t sl = uc.slot(xx, yy, z);
+        if (sl >= 0) atomic_add(&y[3 * int64_t(sl) + c], w[xx + 3 * yy + 9 * z]);
+      }
+}
+
 template <typename T>
 struct BrickShape;
 template <>
@@ -1370,8 +1421,7 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
       brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
     } else {
       if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
-      k_vmult_uniform<T><<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
-          n, mu_of<T>(L), x, y);
+      k_vmult_uniform3<T><<<unsigned((L.ncell + 63) / 64), 192, 0, s>>>(n, mu_of<T>(L), x, y);
     }
     return;
   }
