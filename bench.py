@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--solve-workload", choices=["adaptive32p2", "uniform128p1"], default=None,
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
     p.add_argument("--max-iter", type=int, default=3000, help="FGMRES iteration cap of --solve-workload")
-    p.add_argument("--variants", default="fp64,fp32,fp32_learned,fp32_gmres,fp32_idr2,fp32_diag",
+    p.add_argument("--variants", default="fp64,fp32,fp32_learned,fp32_gmres,fp32_idr2,fp64_idr2,fp32_diag",
                    help="solves of --solve-workload (comma separated: fp64, fp32, fp32_learned)")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                    help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE pass over "
@@ -124,14 +124,17 @@ def measured_traffic(level):
     return {"bytes": int(c["bytes_per_application"]), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
-# outer-solver variants of Sec. 3.4 (FP32 V-cycle): plain GMRES and IDR(2)
-# with the fixed Chebyshev Schur map, FGMRES with the block-diagonal P_D;
+# outer-solver variants of Sec. 3.4 (V-cycle precision, options): plain GMRES
+# and IDR(2) with the fixed Chebyshev Schur map (IDR also with the FP64
+# V-cycle: its short recurrences can stall on the FP32 one), FGMRES with the
+# block-diagonal P_D;
 # vectors = FP64 block vectors the Krylov method keeps (FGMRES 2m + 1, GMRES
 # m + 2, IDR(s) 3s + 2, each plus b, x, r, w)
 SOLVER_VARIANTS = {
-    "fp32_gmres": dict(krylov="gmres", schur="cheb"),
-    "fp32_idr2": dict(krylov="idr", schur="cheb", idr_s=2),
-    "fp32_diag": dict(block="diagonal"),
+    "fp32_gmres": ("fp32", dict(krylov="gmres", schur="cheb")),
+    "fp32_idr2": ("fp32", dict(krylov="idr", schur="cheb", idr_s=2)),
+    "fp64_idr2": ("fp64", dict(krylov="idr", schur="cheb", idr_s=2)),
+    "fp32_diag": ("fp32", dict(block="diagonal")),
 }
 
 
@@ -145,7 +148,7 @@ def krylov_vectors(kw, restart):
 
 
 def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
-                  variants=("fp64", "fp32", "fp32_learned", "fp32_gmres", "fp32_idr2", "fp32_diag")):
+                  variants=("fp64", "fp32", "fp32_learned", "fp32_gmres", "fp32_idr2", "fp64_idr2", "fp32_diag")):
     """Stokes solve to 1e-8 (FP64 FGMRES): plain FP64 V-cycle, FP32 V-cycle,
     and FP32 V-cycle with the learned smoother scaling (installed with its
     guard; a failed learned solve is redone plain and both costs counted);
@@ -174,9 +177,9 @@ def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
         out["fp64"] = one("fp64", False)
     if "fp32" in variants or "fp32_learned" in variants:
         out["fp32"] = one("fp32", False)
-    for name, kw in SOLVER_VARIANTS.items():
+    for name, (prec, kw) in SOLVER_VARIANTS.items():
         if name in variants:
-            out[name] = one("fp32", False, **kw)
+            out[name] = one(prec, False, **kw)
     if "fp32_learned" not in variants:
         return out
     w = torch.tensor(np.load(WEIGHTS)["weights"], device="cuda")
