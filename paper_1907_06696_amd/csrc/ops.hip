@@ -644,7 +644,9 @@ template <typename T>
 __global__ void k_prolong_uniform(int nc, const T* __restrict__ xc, T* __restrict__ xf, bool add) {
   const int mc = 2 * nc + 1, mf = 4 * nc + 1;
   const int64_t nn = int64_t(mf) * mf * mf;
-  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+  // XCD-contiguous node ranges: neighbouring fine nodes read the same coarse ones
+  for (int64_t v = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; v < nn;
+       v += int64_t(gridDim.x) * blockDim.x) {
     const int X = int(v % mf), Y = int((v / mf) % mf), Z = int(v / (int64_t(mf) * mf));
     T a0 = T(0), a1 = T(0), a2 = T(0);
     const bool dir = X == 0 || Y == 0 || Z == 0 || X == mf - 1 || Y == mf - 1 || Z == mf - 1;
@@ -695,7 +697,9 @@ template <typename T>
 __global__ void k_restrict_uniform(int nc, const T* __restrict__ b, const T* __restrict__ t, T* __restrict__ xc) {
   const int mc = 2 * nc + 1, mf = 4 * nc + 1;
   const int64_t nn = int64_t(mc) * mc * mc;
-  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
+  // XCD-contiguous node ranges: neighbouring coarse nodes read the same fine ones
+  for (int64_t v = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; v < nn;
+       v += int64_t(gridDim.x) * blockDim.x) {
     const int X = int(v % mc), Y = int((v / mc) % mc), Z = int(v / (int64_t(mc) * mc));
     T a0 = T(0), a1 = T(0), a2 = T(0);
     const bool dir = X == 0 || Y == 0 || Z == 0 || X == mc - 1 || Y == mc - 1 || Z == mc - 1;
