@@ -531,7 +531,9 @@ __global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ nt
 template <typename T>
 __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __restrict__ minv, T* __restrict__ r,
                              T* __restrict__ d, T* __restrict__ x, T it) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+  // XCD-contiguous ranges: t was just written by the operator in the same order
+  for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
     const T bi = b[i];
     const T di = minv[i] * bi * it;
     r[i] = bi;
@@ -543,7 +545,9 @@ __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __rest
 template <typename T>
 __global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* __restrict__ t, const T* __restrict__ minv,
                             T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+  // XCD-contiguous ranges: t was just written by the operator in the same order
+  for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
     const T ri = b[i] - t[i];
     const T di = minv[i] * ri * it;
     r[i] = ri;
@@ -555,7 +559,9 @@ __global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* __restr
 template <typename T>
 __global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restrict__ minv, T* __restrict__ r,
                             T* __restrict__ d, T* __restrict__ x, T alpha, T beta) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+  // XCD-contiguous ranges: t was just written by the operator in the same order
+  for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
     const T ri = r[i] - t[i];
     const T di = alpha * d[i] + beta * minv[i] * ri;
     r[i] = ri;
