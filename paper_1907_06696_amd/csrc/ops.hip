@@ -14,6 +14,14 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kCellBlock = 64;     // cells per workgroup for the cell kernels
 constexpr int kRedBlocks = 1024;   // partial sums of the reductions
+#ifndef MFGMG_RESTRICT_LANES
+#define MFGMG_RESTRICT_LANES 16
+#endif
+#ifndef MFGMG_PROLONG_LANES
+#define MFGMG_PROLONG_LANES 4
+#endif
+constexpr int kRestrictLanes = MFGMG_RESTRICT_LANES;   // lanes per row of the CSR transfers
+constexpr int kProlongLanes = MFGMG_PROLONG_LANES;
 #ifndef MFGMG_BRICK_MIN_EDGE
 #define MFGMG_BRICK_MIN_EDGE 32
 #endif
@@ -571,37 +579,57 @@ __global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restr
 }
 
 // ------------------------------------------------------------- transfers
-template <typename T>
-__global__ void k_prolong(int64_t nf, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                          const float* __restrict__ w, const T* __restrict__ xc, T* __restrict__ xf, bool add) {
-  for (int64_t f = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; f < nf; f += int64_t(gridDim.x) * blockDim.x) {
+// CSR transfers, G lanes per row (rows of R hold up to 125 fine nodes, rows
+// of P up to 27 coarse ones): the lanes of a group read consecutive entries
+// (coalesced column and weight loads, G gathers in flight per row) and
+// reduce with shuffles inside the group.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_prolong(int64_t nf, const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                    const T* __restrict__ xc, T* __restrict__ xf, bool add) {
+  const int sub = int(threadIdx.x) % G;
+  for (int64_t f = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / G; f < nf;
+       f += int64_t(gridDim.x) * (blockDim.x / G)) {
     T a0 = T(0), a1 = T(0), a2 = T(0);
-    for (int64_t q = ptr[f]; q < ptr[f + 1]; ++q) {
+    for (int64_t q = ptr[f] + sub; q < ptr[f + 1]; q += G) {
       const int64_t cc = 3 * int64_t(col[q]);
       const T ww = T(w[q]);
       a0 += ww * xc[cc];
       a1 += ww * xc[cc + 1];
       a2 += ww * xc[cc + 2];
     }
-    if (add) {
-      xf[3 * f] += a0;
-      xf[3 * f + 1] += a1;
-      xf[3 * f + 2] += a2;
-    } else {
-      xf[3 * f] = a0;
-      xf[3 * f + 1] = a1;
-      xf[3 * f + 2] = a2;
+    a0 = group_sum<G>(a0), a1 = group_sum<G>(a1), a2 = group_sum<G>(a2);
+    if (sub == 0) {
+      if (add) {
+        xf[3 * f] += a0;
+        xf[3 * f + 1] += a1;
+        xf[3 * f + 2] += a2;
+      } else {
+        xf[3 * f] = a0;
+        xf[3 * f + 1] = a1;
+        xf[3 * f + 2] = a2;
+      }
     }
   }
 }
 
-template <typename T>
-__global__ void k_restrict(int64_t nc, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                           const float* __restrict__ w, const T* __restrict__ b, const T* __restrict__ t,
-                           T* __restrict__ xc) {
-  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < nc; c += int64_t(gridDim.x) * blockDim.x) {
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const T* __restrict__ b, const T* __restrict__ t,
+                                                     T* __restrict__ xc) {
+  const int sub = int(threadIdx.x) % G;
+  for (int64_t c = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / G; c < nc;
+       c += int64_t(gridDim.x) * (blockDim.x / G)) {
     T a0 = T(0), a1 = T(0), a2 = T(0);
-    for (int64_t q = ptr[c]; q < ptr[c + 1]; ++q) {
+    for (int64_t q = ptr[c] + sub; q < ptr[c + 1]; q += G) {
       const int64_t ff = 3 * int64_t(col[q]);
       const T ww = T(w[q]);
       if (t) {
@@ -614,9 +642,12 @@ __global__ void k_restrict(int64_t nc, const int64_t* __restrict__ ptr, const in
         a2 += ww * b[ff + 2];
       }
     }
-    xc[3 * c] = a0;
-    xc[3 * c + 1] = a1;
-    xc[3 * c + 2] = a2;
+    a0 = group_sum<G>(a0), a1 = group_sum<G>(a1), a2 = group_sum<G>(a2);
+    if (sub == 0) {
+      xc[3 * c] = a0;
+      xc[3 * c + 1] = a1;
+      xc[3 * c + 2] = a2;
+    }
   }
 }
 
@@ -1498,12 +1529,12 @@ MFGMG_INST_CHEB(double)
 template <typename T>
 void launch_prolong(int64_t nf, const int64_t* ptr, const int32_t* col, const float* w, const T* xc, T* xf, bool add,
                     hipStream_t s) {
-  k_prolong<T><<<grid_for(nf), kBlock, 0, s>>>(nf, ptr, col, w, xc, xf, add);
+  k_prolong<T, kProlongLanes><<<grid_for(nf * kProlongLanes), kBlock, 0, s>>>(nf, ptr, col, w, xc, xf, add);
 }
 template <typename T>
 void launch_restrict(int64_t nc, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
                      T* xc, hipStream_t s) {
-  k_restrict<T><<<grid_for(nc), kBlock, 0, s>>>(nc, ptr, col, w, b, t, xc);
+  k_restrict<T, kRestrictLanes><<<grid_for(nc * kRestrictLanes), kBlock, 0, s>>>(nc, ptr, col, w, b, t, xc);
 }
 template void launch_prolong<float>(int64_t, const int64_t*, const int32_t*, const float*, const float*, float*, bool,
                                     hipStream_t);
@@ -1749,7 +1780,8 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
     k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
-  k_prolong<T><<<grid_for(F.nnode), kBlock, 0, s>>>(F.nnode, ptr, col, w, xc, xf, add);
+  k_prolong<T, kProlongLanes><<<grid_for(F.nnode * kProlongLanes), kBlock, 0, s>>>(F.nnode, ptr, col, w, xc, xf,
+                                                                                    add);
 }
 
 template <typename T>
@@ -1759,7 +1791,8 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
     k_restrict_uniform<T><<<grid_for(Cc.nnode), kBlock, 0, s>>>(int(Cc.n_edge), b, t, xc);
     return;
   }
-  k_restrict<T><<<grid_for(Cc.nnode), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b, t, xc);
+  k_restrict<T, kRestrictLanes><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b,
+                                                                                        t, xc);
 }
 
 #define MFGMG_INST_TRANSFER(T)                                                                                \
