@@ -456,6 +456,18 @@ int upload_mesh(mfgmg_ctx* ctx) {
     ctx->pres.hw = ctx->upload(lf.phang.weight);
     ctx->pres.hang_nodes = ctx->upload(lf.phang.node);
     ctx->pres.nh = int64_t(lf.phang.count());
+    if (lf.uniform) {
+      // lattice -> pressure node, from the canonical keys (X + m (Y + m Z) on
+      // the (2n+1)^3 Q2 lattice; Q1 nodes sit at even X, Y, Z)
+      const int64_t n = lf.n_edge, mq = 2 * n + 1, np1 = n + 1;
+      std::vector<int32_t> plat(static_cast<size_t>(np1 * np1 * np1), -1);
+      for (int64_t i = 0; i < lf.npnode; ++i) {
+        const int64_t k = lf.pkey[size_t(i)];
+        const int64_t X = k % mq, Y = (k / mq) % mq, Z = k / (mq * mq);
+        plat[size_t(X / 2 + np1 * (Y / 2 + np1 * (Z / 2)))] = int32_t(i);
+      }
+      ctx->pres.plat = ctx->upload(plat);
+    }
   }
   // coarse level: free dofs of level 1
   {

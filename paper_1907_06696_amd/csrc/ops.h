@@ -152,6 +152,9 @@ struct DevPressure {
   const double* hw = nullptr;
   const int64_t* hang_nodes = nullptr;
   int64_t nh = 0;
+  // uniform leaf only: pressure node of lattice point (Px, Py, Pz) of the
+  // (n+1)^3 Q1 lattice, Px fastest
+  const int32_t* plat = nullptr;
 };
 void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* p_out, hipStream_t s);
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* u_out, hipStream_t s);

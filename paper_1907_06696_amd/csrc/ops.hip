@@ -1137,40 +1137,69 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
 }
 
 // B^T p added into uo on a uniform leaf, gathered per velocity node (no
-// atomics): the node's value sums, over the (up to 8) cells around it, the
-// cell's B-hat row of the node's local index against the cell's 8 pressure
-// values (Q1 nodes through the cell's pressure slots; no hanging nodes on a
-// uniform level).  Dirichlet nodes are skipped.
+// atomics), by sum factorisation: with B_qj = -int psi_q div phi_j and both
+// bases tensor products, the coupling of Q2 node X and Q1 node P is, per
+// axis, the 1D mass int psi phi (M1 = [[1/6, 1/3, 0], [0, 1/3, 1/6]]) or,
+// along the velocity component, the 1D derivative coupling int psi phi'
+// (G1 = [[-5/6, 2/3, 1/6], [-1/6, -2/3, 5/6]]).  Assembled over the cells
+// around a node, an odd coordinate X = 2i+1 couples to P = i, i+1 with mass
+// (1/3, 1/3) and derivative (2/3, -2/3); an even X = 2i to P = i-1, i, i+1
+// with mass (0, 1/3, 0) and derivative (1/6, 0, -1/6).  The node reads the
+// <= 27 pressure values of its 3x3x3 lattice window (through the lattice
+// map) and contracts them axis by axis; the cell size enters as h^2.
 __global__ __launch_bounds__(kBlock) void k_grad_uniform(int64_t n, DevPressure P, const double* __restrict__ p,
                                                          double* __restrict__ uo) {
-  const int64_t m = 2 * n + 1, nn = m * m * m;
+  const int64_t m = 2 * n + 1, nn = m * m * m, np1 = n + 1;
   const double h2 = 1.0 / double(n * n);
   for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
-    if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) continue;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int dz = 0; dz < 2; ++dz) {
-      const int64_t k = Z / 2 - ((Z & 1) ? 0 : 1 - dz);
-      if ((Z & 1) && dz) break;
-      for (int dy = 0; dy < 2; ++dy) {
-        const int64_t j = Y / 2 - ((Y & 1) ? 0 : 1 - dy);
-        if ((Y & 1) && dy) break;
-        for (int dx = 0; dx < 2; ++dx) {
-          const int64_t i = X / 2 - ((X & 1) ? 0 : 1 - dx);
-          if ((X & 1) && dx) break;
-          const int64_t c = i + n * (j + n * k);
-          const int a = int(X - 2 * i) + 3 * int(Y - 2 * j) + 9 * int(Z - 2 * k);
+    const int64_t X[3] = {v % m, (v / m) % m, v / (m * m)};
+    if (X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == m - 1 || X[1] == m - 1 || X[2] == m - 1) continue;
+    int64_t p0[3];
+    double wm[3][3], wg[3][3];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const double pv = p[P.pslots[8 * c + q]];
-            a0 += c_bhat[q * 81 + 3 * a] * pv;
-            a1 += c_bhat[q * 81 + 3 * a + 1] * pv;
-            a2 += c_bhat[q * 81 + 3 * a + 2] * pv;
-          }
+    for (int d = 0; d < 3; ++d) {
+      p0[d] = (X[d] - 1) / 2;
+      if (X[d] & 1) {
+        wm[d][0] = 1.0 / 3.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
+        wg[d][0] = 2.0 / 3.0, wg[d][1] = -2.0 / 3.0, wg[d][2] = 0.0;
+      } else {
+        wm[d][0] = 0.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
+        wg[d][0] = 1.0 / 6.0, wg[d][1] = 0.0, wg[d][2] = -1.0 / 6.0;
+      }
+    }
+    // the window's values (the third point of an odd coordinate may lie past
+    // the lattice: clamped, weight 0)
+    double zm[3][3], zg[3][3];   // contracted along z with mass / derivative weights
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) zm[b][a] = zg[b][a] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t pz = p0[2] + c < np1 ? p0[2] + c : n;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int64_t py = p0[1] + b < np1 ? p0[1] + b : n;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t px = p0[0] + a < np1 ? p0[0] + a : n;
+          const double val = p[P.plat[px + np1 * (py + np1 * pz)]];
+          zm[b][a] += wm[2][c] * val;
+          zg[b][a] += wg[2][c] * val;
         }
       }
     }
-    uo[3 * v] += h2 * a0, uo[3 * v + 1] += h2 * a1, uo[3 * v + 2] += h2 * a2;
+    double ymm[3], ygm[3], ymg[3];   // then along y: (y, z) weights mass/mass, deriv/mass, mass/deriv
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ymm[a] = wm[1][0] * zm[0][a] + wm[1][1] * zm[1][a] + wm[1][2] * zm[2][a];
+      ygm[a] = wg[1][0] * zm[0][a] + wg[1][1] * zm[1][a] + wg[1][2] * zm[2][a];
+      ymg[a] = wm[1][0] * zg[0][a] + wm[1][1] * zg[1][a] + wm[1][2] * zg[2][a];
+    }
+    const double g0 = wg[0][0] * ymm[0] + wg[0][1] * ymm[1] + wg[0][2] * ymm[2];
+    const double g1 = wm[0][0] * ygm[0] + wm[0][1] * ygm[1] + wm[0][2] * ygm[2];
+    const double g2 = wm[0][0] * ymg[0] + wm[0][1] * ymg[1] + wm[0][2] * ymg[2];
+    uo[3 * v] -= h2 * g0, uo[3 * v + 1] -= h2 * g1, uo[3 * v + 2] -= h2 * g2;
   }
 }
 
