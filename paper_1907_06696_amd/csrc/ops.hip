@@ -297,14 +297,15 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
   };
   const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
   // staging: every slot load, then every value load, issued before use;
-  // points of missing blocks, Dirichlet and hanging points store zero
-  {
-    int32_t sl[KP];
+  // points of missing blocks, Dirichlet and hanging points store zero.  The
+  // slots stay in registers for the write-back.
+  int32_t sl[KP];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int pa = lane + 64 * k;
-      sl[k] = pa < np ? blk.slots[blk0 * P + pa] : -1;
-    }
+  for (int k = 0; k < KP; ++k) {
+    const int pa = lane + 64 * k;
+    sl[k] = pa < np ? blk.slots[blk0 * P + pa] : -1;
+  }
+  {
     T v[KP][3];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -384,12 +385,6 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
   }
   __syncthreads();
   // write-back of the free points: inside the block stored, on its faces added
-  int32_t sl[KP];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int pa = lane + 64 * k;
-    sl[k] = pa < np ? blk.slots[blk0 * P + pa] : -1;
-  }
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (sl[k] < 0) continue;
