@@ -271,7 +271,9 @@ class StokesProblem:
     """Block system K_S = [[A, B^T], [B, Pi_cp]] on the leaf mesh of a
     hierarchy with its GMG preconditioner (assembled; small meshes)."""
 
-    def __init__(self, hier, mu_leaf, f_qp, gmg=None, gmg_kwargs=None):
+    def __init__(self, hier, mu_leaf, f_qp, gmg=None, gmg_kwargs=None, rhs_p=None):
+        """rhs_p: right-hand side of the pressure block (B u = rhs_p, i.e.
+        div u = g with rhs_p_i = -int psi_i g); zero by default (Sec. 2.1)."""
         self.hier = hier
         mesh = hier.leaf
         self.mesh = mesh
@@ -281,7 +283,8 @@ class StokesProblem:
         self.Mp = ops.assemble_Mp(mesh, self.mus[hier.L])
         self.nu, self.np_ = mesh.n_u, mesh.npnode
         self.pfree = mesh.pfree
-        self.b = np.concatenate([ops.assemble_rhs(mesh, f_qp), np.zeros(self.np_)])
+        self.b = np.concatenate([ops.assemble_rhs(mesh, f_qp),
+                                 np.zeros(self.np_) if rhs_p is None else np.asarray(rhs_p, dtype=np.float64)])
         self.Pi_cp = sp.diags((~self.pfree).astype(np.float64))
         self.K = sp.bmat([[self.A, self.B.T], [self.B, self.Pi_cp]], format='csr')
         self.mp_minv = 1.0 / self.Mp.diagonal()

@@ -160,3 +160,32 @@ def test_uniform8_gmg_fgmres_matches_direct():
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-5
     # iteration magnitude of the paper's 4-sinker runs (context only)
     assert 10 <= st['iterations'] <= 60
+
+
+def test_nonzero_divergence_manufactured_discrete():
+    """div u = g (next row f4): with b = K [u*; p*] for a discrete u* (zero on
+    constrained dofs) and p* (zero weighted mean), the direct solve returns
+    (u*, p*) up to rounding times the condition number, and the GMG-FGMRES
+    solve to its tolerance; the pressure block of b is B u*, a nonzero
+    divergence."""
+    for H in (mesh.Hierarchy.uniform(2), adaptive_hierarchy(1, (0, 0, 0), 1)):
+        m = H.leaf
+        rg = np.random.default_rng(11)
+        mu = 10 ** rg.uniform(0, 2, m.ncell)
+        f = np.zeros((m.ncell, 27, 3))
+        prob = krylov.StokesProblem(H, mu, f, gmg_kwargs={})
+        us = rg.standard_normal(m.n_u) * m.free_dofs_mask()
+        ps = rg.standard_normal(m.npnode) * m.pfree
+        w = ops.pressure_mean_weights(m)
+        ps = np.where(m.pfree, ps - (w @ ps) / w.sum(), 0.0)
+        xs = np.concatenate([us, ps])
+        prob.b = prob.K @ xs
+        assert np.linalg.norm(prob.b[m.n_u:]) > 0
+        xd = prob.solve_direct()
+        assert np.linalg.norm(xd - xs) <= 1e-7 * np.linalg.norm(xs)
+        # the iterative solve stops on the residual; its error is the
+        # residual times the condition number (~1e5 here: the pressure block
+        # is scaled by h^2)
+        x, st = prob.solve_fgmres(rtol=1e-10)
+        assert prob.residual(x) <= 1e-10
+        assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs), np.linalg.norm(x - xs) / np.linalg.norm(xs)
