@@ -396,6 +396,44 @@ int upload_mesh(mfgmg_ctx* ctx) {
         };
         upload_blocks(b4, v.blk4, 64);
         upload_blocks(b2, v.blk2, 8);
+        // face gather: every free face point of a block -> its slot, grouped by node
+        {
+          std::vector<std::pair<int32_t, int32_t>> nf;   // (node, slot)
+          auto faces = [&](const Blocks& b, int B, int64_t slot0) {
+            const int E = 2 * B + 1, P = E * E * E, NC = B * B * B;
+            const int64_t nb = int64_t(b.cells.size() / size_t(NC));
+            for (int64_t k = 0; k < nb; ++k)
+              for (int p = 0; p < P; ++p) {
+                const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+                const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+                const int32_t nd = b.slots[size_t(k * P + p)];
+                if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
+              }
+            return slot0 + nb * P;
+          };
+          const int64_t s2 = faces(b4, 4, 0);
+          const int64_t ns = faces(b2, 2, s2);
+          std::sort(nf.begin(), nf.end());
+          std::vector<int32_t> fnode, fptr{0}, fent;
+          for (size_t i = 0; i < nf.size(); ++i) {
+            if (i == 0 || nf[i].first != nf[i - 1].first) {
+              if (i) fptr.push_back(int32_t(fent.size()));
+              fnode.push_back(nf[i].first);
+            }
+            fent.push_back(nf[i].second);
+          }
+          if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
+          v.fslot_blk2 = s2;
+          v.n_face = int64_t(fnode.size());
+          if (v.n_face) {
+            v.face_node = ctx->upload(fnode);
+            v.face_ptr = ctx->upload(fptr);
+            v.face_ent = ctx->upload(fent);
+            v.fslot_f = ctx->dalloc<float>(size_t(3 * ns));
+            v.fslot_d = ctx->dalloc<double>(size_t(3 * ns));
+            if (!v.fslot_f || !v.fslot_d) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+          }
+        }
         v.single_reg = ctx->upload(sreg);
         v.n_single_reg = int64_t(sreg.size());
         v.single_hang = ctx->upload(shang);

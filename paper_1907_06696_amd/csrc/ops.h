@@ -63,6 +63,18 @@ struct DevLevel {
   // uniform levels: halo slots of the brick kernel (brick_halo_words entries)
   float* halo_f = nullptr;
   double* halo_d = nullptr;
+  // non-uniform levels: the block kernels write the values of their free
+  // face points to slots (3 values per lattice point of every block: 4^3
+  // blocks first, then 2^3 blocks), and a gather kernel adds, for every node
+  // that is a free face point of some block, its slots into y:
+  // face_ent[face_ptr[i] .. face_ptr[i+1]) are the slots of node face_node[i]
+  float* fslot_f = nullptr;
+  double* fslot_d = nullptr;
+  int64_t fslot_blk2 = 0;               // first slot of the 2^3 blocks
+  const int32_t* face_node = nullptr;
+  const int32_t* face_ptr = nullptr;
+  const int32_t* face_ent = nullptr;
+  int64_t n_face = 0;
 };
 
 // entries of the brick kernel's halo buffer on a uniform level of n cells per

@@ -203,6 +203,34 @@ __global__ __launch_bounds__(192) void k_vmult_uniform3(int64_t n, const T* __re
       }
 }
 
+// y(node) += the face slots of the node (one thread per node, 2-8 slots)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_face_gather(int64_t nf, const int32_t* __restrict__ node,
+                                                        const int32_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ ent,
+                                                        const T* __restrict__ fslot, T* __restrict__ y) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nf; i += int64_t(gridDim.x) * blockDim.x) {
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const T* fs = fslot + 3 * int64_t(ent[e]);
+      a0 += fs[0], a1 += fs[1], a2 += fs[2];
+    }
+    T* yp = y + 3 * int64_t(node[i]);
+    yp[0] += a0, yp[1] += a1, yp[2] += a2;
+  }
+}
+
+template <typename T>
+T* face_slots(const DevLevel& L);
+template <>
+float* face_slots<float>(const DevLevel& L) {
+  return L.fslot_f;
+}
+template <>
+double* face_slots<double>(const DevLevel& L) {
+  return L.fslot_d;
+}
+
 template <typename T>
 struct BrickShape;
 template <>
@@ -280,7 +308,7 @@ __device__ __forceinline__ const double* blk_hw<double>(const DevBlocks& b) {
 template <typename T, int B, bool ACC>
 __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t* __restrict__ clev,
                                                      const T* __restrict__ mu, const T* __restrict__ x,
-                                                     T* __restrict__ y) {
+                                                     T* __restrict__ y, T* __restrict__ fslot) {
   constexpr int NC = B * B * B, NB = 64 / NC;   // cells per block, blocks per wave
   constexpr int E = 2 * B + 1, P = E * E * E, W = 3 * P;
   constexpr int KP = (NB * P + 63) / 64;        // lattice points per lane
@@ -384,7 +412,9 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     for (int q = 0; q < 3; ++q) atomicAdd(&buf[om + q * P], w * buf[o + q * P]);
   }
   __syncthreads();
-  // write-back of the free points: inside the block stored, on its faces added
+  // write-back of the free points: inside the block stored (added when
+  // accumulating); on its faces, where other cells contribute too, to the
+  // block's slots, summed into y by the face gather (no atomics)
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (sl[k] < 0) continue;
@@ -399,7 +429,8 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     } else if (inner) {
       yp[0] = v0, yp[1] = v1, yp[2] = v2;
     } else {
-      atomic_add(yp, v0), atomic_add(yp + 1, v1), atomic_add(yp + 2, v2);
+      T* fs = fslot + 3 * ((blk0 + pa / P) * P + p);
+      fs[0] = v0, fs[1] = v1, fs[2] = v2;
     }
   }
 }
@@ -1491,14 +1522,16 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
     return;
   }
   if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
+  T* fs = face_slots<T>(L);
   if (L.blk4.n) {
-    if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
-    else k_vmult_blocks<T, 4, true><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y);
+    if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
+    else k_vmult_blocks<T, 4, true><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
   }
   if (L.blk2.n) {
     const unsigned g = unsigned((L.blk2.n + 7) / 8);
-    if (init) k_vmult_blocks<T, 2, false><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
-    else k_vmult_blocks<T, 2, true><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y);
+    T* fs2 = fs + 3 * L.fslot_blk2;
+    if (init) k_vmult_blocks<T, 2, false><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y, fs2);
+    else k_vmult_blocks<T, 2, true><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y, fs2);
   }
   if (L.n_single_reg)
     k_vmult_general<T, false><<<unsigned((L.n_single_reg + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
@@ -1506,6 +1539,8 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
   if (L.n_single_hang)
     k_vmult_general<T, true><<<unsigned((L.n_single_hang + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
         L.single_hang, L.n_single_hang, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+  if (L.n_face)
+    k_face_gather<T><<<grid_for(L.n_face), kBlock, 0, s>>>(L.n_face, L.face_node, L.face_ptr, L.face_ent, fs, y);
 }
 template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t, bool);
 template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t, bool);
