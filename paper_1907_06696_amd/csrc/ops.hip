@@ -1080,7 +1080,8 @@ __global__ __launch_bounds__(kCellBlock) void k_pmass(DevLevel L, DevPressure P,
 // cell are gathered (or scattered) directly.
 template <int B>
 __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, DevPressure P,
-                                                    const double* __restrict__ p, double* __restrict__ uo) {
+                                                    const double* __restrict__ p, double* __restrict__ uo,
+                                                    double* __restrict__ fslot) {
   constexpr int NC = B * B * B, NB = 64 / NC;
   constexpr int E = 2 * B + 1, PP = E * E * E, W = 3 * PP;
   constexpr int KP = (NB * PP + 63) / 64;
@@ -1156,8 +1157,9 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
     double* yp = uo + 3 * int64_t(sl[k]);
     if (inner) {
       yp[0] += v0, yp[1] += v1, yp[2] += v2;
-    } else {
-      atomicAdd(yp, v0), atomicAdd(yp + 1, v1), atomicAdd(yp + 2, v2);
+    } else {   // shared face point: the block's slot, added by the face gather
+      double* fs = fslot + 3 * ((blk0 + pa / PP) * PP + q);
+      fs[0] = v0, fs[1] = v1, fs[2] = v2;
     }
   }
 }
@@ -1694,12 +1696,17 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
   if (L.uniform) {
     k_grad_uniform<<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, P, p, uo);
   } else if (L.blk4.n || L.blk2.n) {
-    if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo);
-    if (L.blk2.n) k_grad_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, p, uo);
+    double* fs = L.fslot_d;
+    if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo, fs);
+    if (L.blk2.n)
+      k_grad_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, p, uo, fs + 3 * L.fslot_blk2);
     for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
       if (lst.second)
         k_grad_add<<<unsigned((lst.second + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
             L, P, lst.first, lst.second, p, uo);
+    if (L.n_face)
+      k_face_gather<double><<<grid_for(L.n_face), kBlock, 0, s>>>(L.n_face, L.face_node, L.face_ptr, L.face_ent, fs,
+                                                                   uo);
   } else {
     k_grad_add<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, p,
                                                                                          uo);
