@@ -434,6 +434,41 @@ int upload_mesh(mfgmg_ctx* ctx) {
             if (!v.fslot_f || !v.fslot_d) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
           }
         }
+        // the same for the pressure mass blocks of the leaf ((B+1)^3 Q1 lattices)
+        if (leaf) {
+          std::vector<std::pair<int32_t, int32_t>> nf;
+          auto faces = [&](const Blocks& b, int B, int64_t slot0) {
+            const int E = B + 1, P = E * E * E, NC = B * B * B;
+            const int64_t nb = int64_t(b.cells.size() / size_t(NC));
+            for (int64_t k = 0; k < nb; ++k)
+              for (int p = 0; p < P; ++p) {
+                const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+                const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+                const int32_t nd = b.pslots[size_t(k * P + p)];
+                if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
+              }
+            return slot0 + nb * P;
+          };
+          const int64_t s2 = faces(b4, 4, 0);
+          const int64_t ns = faces(b2, 2, s2);
+          std::sort(nf.begin(), nf.end());
+          std::vector<int32_t> fnode, fptr{0}, fent;
+          for (size_t i = 0; i < nf.size(); ++i) {
+            if (i && nf[i].first != nf[i - 1].first) fptr.push_back(int32_t(fent.size()));
+            if (i == 0 || nf[i].first != nf[i - 1].first) fnode.push_back(nf[i].first);
+            fent.push_back(nf[i].second);
+          }
+          if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
+          v.pfslot_blk2 = s2;
+          v.n_pface = int64_t(fnode.size());
+          if (v.n_pface) {
+            v.pface_node = ctx->upload(fnode);
+            v.pface_ptr = ctx->upload(fptr);
+            v.pface_ent = ctx->upload(fent);
+            v.pfslot = ctx->dalloc<double>(size_t(ns));
+            if (!v.pfslot) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+          }
+        }
         v.single_reg = ctx->upload(sreg);
         v.n_single_reg = int64_t(sreg.size());
         v.single_hang = ctx->upload(shang);
@@ -504,6 +539,8 @@ int upload_mesh(mfgmg_ctx* ctx) {
         const int64_t X = k % mq, Y = (k / mq) % mq, Z = k / (mq * mq);
         plat[size_t(X / 2 + np1 * (Y / 2 + np1 * (Z / 2)))] = int32_t(i);
       }
+      for (const int32_t q : plat)
+        if (q < 0) return ctx->set(MFGMG_ERR_MESH, "uniform leaf: a Q1 lattice point has no pressure node");
       ctx->pres.plat = ctx->upload(plat);
     }
   }
@@ -578,16 +615,32 @@ void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t 
   const double lam = sc ? d.lambda_s : d.lambda, lo = lam / 15.0;
   const double theta = 0.5 * (lam + lo), delta = 0.5 * (lam - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
+  // where the operator starts with an output initialisation kernel, each
+  // update prepares t for the next operator call instead (on d; after the
+  // last update of a pre-smoothing, on x for the V-cycle's residual)
+  const bool prep = vmult_has_init<T>(d.v);
+  ChebPrep cp;
+  if (prep) {
+    cp.tn = t;
+    cp.ntype = d.v.uniform ? nullptr : d.v.ntype;
+    cp.m = d.v.uniform ? 2 * d.v.n_edge + 1 : 0;
+  }
   if (x_zero) {
-    launch_cheb_init0<T>(n, b, minv, r, dd, x, 1.0 / theta, s);
+    launch_cheb_init0<T>(n, b, minv, r, dd, x, 1.0 / theta, s, cp);
   } else {
     launch_vmult<T>(d.v, x, t, s);
-    launch_cheb_init<T>(n, b, t, minv, r, dd, x, 1.0 / theta, s);
+    launch_cheb_init<T>(n, b, t, minv, r, dd, x, 1.0 / theta, s, cp);
   }
   for (int k = 1; k < 4; ++k) {
-    launch_vmult<T>(d.v, dd, t, s);
+    if (prep) launch_vmult_prepared<T>(d.v, dd, t, s);
+    else launch_vmult<T>(d.v, dd, t, s);
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    launch_cheb_step<T>(n, t, minv, r, dd, x, rho_new * rho, 2.0 * rho_new / delta, s);
+    ChebPrep last;
+    if (prep && x_zero) {
+      last = cp;
+      last.from_x = true;
+    }
+    launch_cheb_step<T>(n, t, minv, r, dd, x, rho_new * rho, 2.0 * rho_new / delta, s, k < 3 ? cp : last);
     rho = rho_new;
   }
 }
@@ -616,7 +669,9 @@ void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
   T* bc = static_cast<T*>(c.work[pi][0]);
   T* xc = static_cast<T*>(c.work[pi][1]);
   smooth<T>(ctx, ell, b, x, true, s);
-  launch_vmult<T>(d.v, x, t, s);
+  // the pre-smoothing left t prepared for A x where the operator needs it
+  if (vmult_has_init<T>(d.v)) launch_vmult_prepared<T>(d.v, x, t, s);
+  else launch_vmult<T>(d.v, x, t, s);
   launch_restrict_level<T>(d.v, c.v, d.R_ptr, d.R_col, d.R_w, b, t, bc, s);
   vcycle<T>(ctx, ell - 1, bc, xc, s);
   launch_prolong_level<T>(d.v, c.v, d.P_ptr, d.P_col, d.P_w, xc, x, true, s);

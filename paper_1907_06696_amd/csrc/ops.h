@@ -75,6 +75,14 @@ struct DevLevel {
   const int32_t* face_ptr = nullptr;
   const int32_t* face_ent = nullptr;
   int64_t n_face = 0;
+  // the leaf's pressure mass blocks do the same on their Q1 lattices (one
+  // value per lattice point of every block)
+  double* pfslot = nullptr;
+  int64_t pfslot_blk2 = 0;
+  const int32_t* pface_node = nullptr;
+  const int32_t* pface_ptr = nullptr;
+  const int32_t* pface_ent = nullptr;
+  int64_t n_pface = 0;
 };
 
 // entries of the brick kernel's halo buffer on a uniform level of n cells per
@@ -95,15 +103,35 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init 
 void launch_diag(const DevLevel& L, const double* khat_full_dev, double* d, hipStream_t s);
 void launch_invert_diag(const DevLevel& L, const double* d, double* minv_d, float* minv_f, hipStream_t s);
 
-// Chebyshev updates (see smoother in api.hip)
+// Chebyshev updates (see smoother in api.hip).  With p.tn set the update also
+// prepares the output of the next operator call on a level whose operator
+// starts with an initialisation kernel: tn = (constrained ? src : 0), src the
+// new d (or the new x when from_x); that call is then launch_vmult_prepared.
+// ntype: the level's node types (general levels), else null and m = 2n + 1
+// (uniform levels).
+struct ChebPrep {
+  void* tn = nullptr;
+  const uint8_t* ntype = nullptr;
+  int64_t m = 0;
+  bool from_x = false;
+};
 template <typename T>
-void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double inv_theta, hipStream_t s);
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double inv_theta, hipStream_t s,
+                       const ChebPrep& p = ChebPrep());
 template <typename T>
 void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double inv_theta,
-                      hipStream_t s);
+                      hipStream_t s, const ChebPrep& p = ChebPrep());
 template <typename T>
 void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
-                      hipStream_t s);
+                      hipStream_t s, const ChebPrep& p = ChebPrep());
+// true when launch_vmult<T> on L starts with an output initialisation kernel
+// (every level but the uniform ones the brick kernel takes)
+template <typename T>
+bool vmult_has_init(const DevLevel& L);
+// y = A x like launch_vmult (init), for a y already holding x on the
+// constrained dofs and 0 elsewhere (the initialisation kernel is skipped)
+template <typename T>
+void launch_vmult_prepared(const DevLevel& L, const T* x, T* y, hipStream_t s);
 
 // transfers (node-level CSR, 3 components)
 template <typename T>

@@ -220,6 +220,21 @@ __global__ __launch_bounds__(kBlock) void k_face_gather(int64_t nf, const int32_
   }
 }
 
+// pressure version (one value per slot); returns when the gate is set, as the
+// mass kernels do
+__global__ __launch_bounds__(kBlock) void k_pface_gather(int64_t nf, const int32_t* __restrict__ node,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ ent,
+                                                         const double* __restrict__ fslot, double* __restrict__ po,
+                                                         const double* __restrict__ gate) {
+  if (gate && *gate != 0.0) return;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nf; i += int64_t(gridDim.x) * blockDim.x) {
+    double a = 0.0;
+    for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) a += fslot[ent[e]];
+    po[node[i]] += a;
+  }
+}
+
 template <typename T>
 T* face_slots(const DevLevel& L);
 template <>
@@ -562,9 +577,34 @@ __global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ nt
 }
 
 // ------------------------------------------------------------- Chebyshev
+// The Chebyshev updates can also prepare the output of the next operator call
+// on levels whose operator otherwise starts with an initialisation kernel
+// (k_init_out_*): tn = (constrained dof ? src : 0), src being the new d, or
+// the new x when from_x.  Constrained: ntype != 0 on general levels (ntype
+// given), a boundary node of the m^3 lattice on uniform ones.  tn may be t
+// itself (each entry is read before it is written, by the same thread; t and
+// tn are therefore not restrict).
+template <typename T>
+struct OutPrep {
+  T* tn;
+  const uint8_t* ntype;
+  int64_t m;
+  int from_x;
+};
+__device__ __forceinline__ bool constrained_dof(int64_t i, const uint8_t* ntype, int64_t m) {
+  const int64_t v = i / 3;
+  if (ntype) return ntype[v] != 0;
+  const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
+  return X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1;
+}
+template <typename T>
+__device__ __forceinline__ void out_prep(const OutPrep<T>& o, int64_t i, T di, T xi) {
+  if (o.tn) o.tn[i] = constrained_dof(i, o.ntype, o.m) ? (o.from_x ? xi : di) : T(0);
+}
+
 template <typename T>
 __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __restrict__ minv, T* __restrict__ r,
-                             T* __restrict__ d, T* __restrict__ x, T it) {
+                             T* __restrict__ d, T* __restrict__ x, T it, OutPrep<T> o) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -573,34 +613,39 @@ __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __rest
     r[i] = bi;
     d[i] = di;
     x[i] = di;
+    out_prep(o, i, di, di);
   }
 }
 
 template <typename T>
-__global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* __restrict__ t, const T* __restrict__ minv,
-                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it) {
+__global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* t, const T* __restrict__ minv,
+                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it, OutPrep<T> o) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const T ri = b[i] - t[i];
     const T di = minv[i] * ri * it;
+    const T xi = x[i] + di;
     r[i] = ri;
     d[i] = di;
-    x[i] += di;
+    x[i] = xi;
+    out_prep(o, i, di, xi);
   }
 }
 
 template <typename T>
-__global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restrict__ minv, T* __restrict__ r,
-                            T* __restrict__ d, T* __restrict__ x, T alpha, T beta) {
+__global__ void k_cheb_step(int64_t n, const T* t, const T* __restrict__ minv, T* __restrict__ r,
+                            T* __restrict__ d, T* __restrict__ x, T alpha, T beta, OutPrep<T> o) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const T ri = r[i] - t[i];
     const T di = alpha * d[i] + beta * minv[i] * ri;
+    const T xi = x[i] + di;
     r[i] = ri;
     d[i] = di;
-    x[i] += di;
+    x[i] = xi;
+    out_prep(o, i, di, xi);
   }
 }
 
@@ -1231,6 +1276,90 @@ __global__ __launch_bounds__(kBlock) void k_grad_uniform(int64_t n, DevPressure 
   }
 }
 
+// M_p p on a uniform leaf of n^3 cells, one thread per Q1 lattice point (no
+// atomics).  A workgroup takes an 8 x 8 x 4 tile of points: it stages the
+// tile's window of values and pressure node indices (10 x 10 x 6 points,
+// through the lattice -> pressure node map; points off the lattice are 0) and
+// the scales h^3 / mu of the 9 x 9 x 5 cells around it (0 off the mesh) in
+// LDS.  Each point then
+// contracts its 3 x 3 x 3 window with the 1D linear-element mass (1/3 on the
+// point itself, 1/6 on its neighbour; h^3 comes with the cell scale) cell by
+// cell, axis by axis, and each of the 8 cells around it adds its contraction
+// times its scale.  Every point is written (stored: po is zero on entry and
+// no other kernel adds to it on a uniform leaf).
+constexpr int kPmTX = 8, kPmTY = 8, kPmTZ = 4;
+__global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t n, DevPressure P,
+                                                                         const double* __restrict__ mu,
+                                                                         const double* __restrict__ p,
+                                                                         double* __restrict__ po,
+                                                                         const double* __restrict__ gate) {
+  // the gate is read first and tested before the store, so its latency
+  // overlaps the staging
+  const bool gated = gate && *gate != 0.0;
+  constexpr int WX = kPmTX + 2, WY = kPmTY + 2, WZ = kPmTZ + 2;
+  constexpr int CX = kPmTX + 1, CY = kPmTY + 1, CZ = kPmTZ + 1;
+  constexpr int NT = kPmTX * kPmTY * kPmTZ;
+  __shared__ double sp[WZ * WY * WX];
+  __shared__ int32_t si[WZ * WY * WX];
+  __shared__ double ss[CZ * CY * CX];
+  const int64_t np1 = n + 1;
+  const int64_t ntx = (np1 + kPmTX - 1) / kPmTX, nty = (np1 + kPmTY - 1) / kPmTY;
+  const int64_t tile = blockIdx.x;
+  const int64_t X0 = (tile % ntx) * kPmTX, Y0 = ((tile / ntx) % nty) * kPmTY, Z0 = (tile / (ntx * nty)) * kPmTZ;
+  const double h3 = 1.0 / double(n * n * n);
+  for (int e = threadIdx.x; e < WX * WY * WZ; e += NT) {
+    const int64_t px = X0 - 1 + e % WX, py = Y0 - 1 + (e / WX) % WY, pz = Z0 - 1 + e / (WX * WY);
+    const bool in = px >= 0 && px < np1 && py >= 0 && py < np1 && pz >= 0 && pz < np1;
+    const int32_t id = in ? P.plat[px + np1 * (py + np1 * pz)] : -1;
+    si[e] = id;
+    sp[e] = in ? p[id] : 0.0;
+  }
+  for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
+    const int64_t cx = X0 - 1 + e % CX, cy = Y0 - 1 + (e / CX) % CY, cz = Z0 - 1 + e / (CX * CY);
+    const bool in = cx >= 0 && cx < n && cy >= 0 && cy < n && cz >= 0 && cz < n;
+    ss[e] = in ? h3 / mu[cx + n * (cy + n * cz)] : 0.0;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kPmTX, ly = (threadIdx.x / kPmTX) % kPmTY, lz = threadIdx.x / (kPmTX * kPmTY);
+  const int64_t X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
+  if (gated || X >= np1 || Y >= np1 || Z >= np1) return;
+  // along x: the cell on side ax in {0, 1} covers window points ax, ax + 1,
+  // the point itself being window point 1
+  double wx[3][3][2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double* w = sp + (lz + c) * (WY * WX) + (ly + b) * WX + lx;
+      wx[c][b][0] = w[0] * (1.0 / 6.0) + w[1] * (1.0 / 3.0);
+      wx[c][b][1] = w[1] * (1.0 / 3.0) + w[2] * (1.0 / 6.0);
+    }
+  double wy[3][2][2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+      wy[c][0][ax] = wx[c][0][ax] * (1.0 / 6.0) + wx[c][1][ax] * (1.0 / 3.0);
+      wy[c][1][ax] = wx[c][1][ax] * (1.0 / 3.0) + wx[c][2][ax] * (1.0 / 6.0);
+    }
+  double out = 0.0;
+#pragma unroll
+  for (int az = 0; az < 2; ++az)
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+      for (int ax = 0; ax < 2; ++ax) {
+        const double t = az ? wy[1][ay][ax] * (1.0 / 3.0) + wy[2][ay][ax] * (1.0 / 6.0)
+                            : wy[0][ay][ax] * (1.0 / 6.0) + wy[1][ay][ax] * (1.0 / 3.0);
+        out += ss[(lz + az) * (CY * CX) + (ly + ay) * CX + lx + ax] * t;
+      }
+  po[si[(lz + 1) * (WY * WX) + (ly + 1) * WX + lx + 1]] = out;
+}
+unsigned pmass_uniform_tiles(int64_t n) {
+  const int64_t np1 = n + 1;
+  return unsigned(((np1 + kPmTX - 1) / kPmTX) * ((np1 + kPmTY - 1) / kPmTY) * ((np1 + kPmTZ - 1) / kPmTZ));
+}
+
 template <int B>
 __global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, DevPressure P,
                                                    const double* __restrict__ u, double* __restrict__ po) {
@@ -1312,11 +1441,13 @@ __global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, De
 // is staged in LDS with hanging points interpolated from their masters (on
 // the lattice), each cell adds its 8 outputs in LDS (cells of equal index
 // parity share no vertex: 8 classes), hanging outputs are passed on to the
-// masters, and the write-back stores the points inside the block and adds
-// (atomically) those on its faces.
+// masters, and the write-back stores the points inside the block and writes
+// those on its faces to the block's face slots (fslot, PP per block), which
+// k_pface_gather adds into po.
 template <int B>
 __global__ __launch_bounds__(64) void k_pmass_blocks(DevBlocks blk, DevLevel L, const double* __restrict__ p,
-                                                     double* __restrict__ po, const double* __restrict__ gate) {
+                                                     double* __restrict__ po, const double* __restrict__ gate,
+                                                     double* __restrict__ fslot) {
   if (gate && *gate != 0.0) return;
   constexpr int NC = B * B * B, NB = 64 / NC;
   constexpr int E = B + 1, PP = E * E * E;
@@ -1401,7 +1532,7 @@ __global__ __launch_bounds__(64) void k_pmass_blocks(DevBlocks blk, DevLevel L, 
     const int px = q % E, py = (q / E) % E, pz = q / (E * E);
     const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
     if (inner) po[sl[k]] = buf[pa];
-    else atomicAdd(&po[sl[k]], buf[pa]);
+    else fslot[blk0 * PP + pa] = buf[pa];
   }
 }
 
@@ -1503,8 +1634,9 @@ int64_t brick_halo_words(int64_t n) {
 template int64_t brick_halo_words<float>(int64_t);
 template int64_t brick_halo_words<double>(int64_t);
 
+namespace {
 template <typename T>
-void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init) {
+void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, bool prepared) {
   if (L.uniform) {
     constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
     const int64_t n = L.n_edge;
@@ -1518,12 +1650,12 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
         brick::k_vmult_brick<T, BX, BY, BZ, true><<<unsigned(nb), BX * BY * BZ, 0, s>>>(int(n), mu_of<T>(L), x, y, halo);
       brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
     } else {
-      if (init) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
+      if (init && !prepared) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
       k_vmult_uniform3<T><<<unsigned((L.ncell + 63) / 64), 192, 0, s>>>(n, mu_of<T>(L), x, y);
     }
     return;
   }
-  if (init) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
+  if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
   T* fs = face_slots<T>(L);
   if (L.blk4.n) {
     if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
@@ -1544,6 +1676,23 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init)
   if (L.n_face)
     k_face_gather<T><<<grid_for(L.n_face), kBlock, 0, s>>>(L.n_face, L.face_node, L.face_ptr, L.face_ent, fs, y);
 }
+}  // namespace
+template <typename T>
+void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init) {
+  vmult_impl<T>(L, x, y, s, init, false);
+}
+template <typename T>
+void launch_vmult_prepared(const DevLevel& L, const T* x, T* y, hipStream_t s) {
+  vmult_impl<T>(L, x, y, s, true, true);
+}
+template <typename T>
+bool vmult_has_init(const DevLevel& L) {
+  return !(L.uniform && brick_halo<T>(L) && brick_fits<T>(L.n_edge));
+}
+template void launch_vmult_prepared<float>(const DevLevel&, const float*, float*, hipStream_t);
+template void launch_vmult_prepared<double>(const DevLevel&, const double*, double*, hipStream_t);
+template bool vmult_has_init<float>(const DevLevel&);
+template bool vmult_has_init<double>(const DevLevel&);
 template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStream_t, bool);
 template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t, bool);
 
@@ -1568,22 +1717,32 @@ void launch_invert_diag(const DevLevel& L, const double* d, double* md, float* m
 }
 
 template <typename T>
-void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
-  k_cheb_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, r, d, x, T(it));
+OutPrep<T> out_prep_of(const ChebPrep& p) {
+  OutPrep<T> o{static_cast<T*>(p.tn), p.ntype, p.m, p.from_x ? 1 : 0};
+  return o;
 }
 template <typename T>
-void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
-  k_cheb_init<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, r, d, x, T(it));
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double it, hipStream_t s,
+                       const ChebPrep& p) {
+  k_cheb_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, r, d, x, T(it), out_prep_of<T>(p));
+}
+template <typename T>
+void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double it, hipStream_t s,
+                      const ChebPrep& p) {
+  k_cheb_init<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, r, d, x, T(it), out_prep_of<T>(p));
 }
 template <typename T>
 void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
-                      hipStream_t s) {
-  k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta));
+                      hipStream_t s, const ChebPrep& p) {
+  k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta), out_prep_of<T>(p));
 }
-#define MFGMG_INST_CHEB(T)                                                                                   \
-  template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t);          \
-  template void launch_cheb_init<T>(int64_t, const T*, const T*, const T*, T*, T*, T*, double, hipStream_t); \
-  template void launch_cheb_step<T>(int64_t, const T*, const T*, T*, T*, T*, double, double, hipStream_t);
+#define MFGMG_INST_CHEB(T)                                                                                      \
+  template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t,              \
+                                     const ChebPrep&);                                                          \
+  template void launch_cheb_init<T>(int64_t, const T*, const T*, const T*, T*, T*, T*, double, hipStream_t,     \
+                                    const ChebPrep&);                                                           \
+  template void launch_cheb_step<T>(int64_t, const T*, const T*, T*, T*, T*, double, double, hipStream_t,       \
+                                    const ChebPrep&);
 MFGMG_INST_CHEB(float)
 MFGMG_INST_CHEB(double)
 
@@ -1714,18 +1873,26 @@ void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, d
 }
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
                   const double* gate) {
-  k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
+  // the uniform-leaf kernel writes every entry
+  if (!(L.uniform && P.plat)) k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
   launch_pmass_add(L, P, p, po, s, gate);
 }
 void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
                       const double* gate) {
-  if ((L.blk4.n && L.blk4.pslots) || (L.blk2.n && L.blk2.pslots)) {
-    if (L.blk4.n) k_pmass_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, p, po, gate);
-    if (L.blk2.n) k_pmass_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, p, po, gate);
+  if (L.uniform && P.plat) {
+    k_pmass_uniform<<<pmass_uniform_tiles(L.n_edge), kPmTX * kPmTY * kPmTZ, 0, s>>>(L.n_edge, P, L.mu_d, p, po, gate);
+  } else if ((L.blk4.n && L.blk4.pslots) || (L.blk2.n && L.blk2.pslots)) {
+    double* fs = L.pfslot;
+    if (L.blk4.n) k_pmass_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, p, po, gate, fs);
+    if (L.blk2.n)
+      k_pmass_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, p, po, gate, fs + L.pfslot_blk2);
     for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
       if (lst.second)
         k_pmass<<<unsigned((lst.second + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, lst.first,
                                                                                             lst.second, p, po, gate);
+    if (L.n_pface)
+      k_pface_gather<<<grid_for(L.n_pface), kBlock, 0, s>>>(L.n_pface, L.pface_node, L.pface_ptr, L.pface_ent, fs, po,
+                                                            gate);
   } else {
     k_pmass<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, p, po,
                                                                                         gate);
