@@ -556,7 +556,7 @@ int upload_mesh(mfgmg_ctx* ctx) {
     ctx->Ainv_d = ctx->dalloc<double>(size_t(ctx->ncfree) * ctx->ncfree);
     ctx->Ainv_f = ctx->dalloc<float>(size_t(ctx->ncfree) * ctx->ncfree);
   }
-  ctx->red_part = ctx->dalloc<double>(256 * 256);
+  ctx->red_part = ctx->dalloc<double>(size_t(kRedPartWords));
   ctx->red_res = ctx->dalloc<double>(512);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctx->host_res), 512 * sizeof(double), hipHostMallocDefault));
   ctx->pmass_minv = ctx->dalloc<double>(size_t(lf.npnode));
@@ -1272,7 +1272,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   double* tu = ctx->dalloc<double>(size_t(nu));
   float* bf = ctx->dalloc<float>(size_t(nu));
   float* xf = ctx->dalloc<float>(size_t(nu));
-  double* cg = ctx->dalloc<double>(size_t(5 * np));   // r, z (contiguous), p, q, x
+  double* cg = ctx->dalloc<double>(size_t(6 * np));   // r, z (contiguous), p, q, x, p'
   double* yv = ctx->dalloc<double>(size_t(std::max(m + 1, 16)));
   const bool fp64 = o.vcycle_prec == MFGMG_FP64;
   double* zfix = (o.use_graph && fp64) ? ctx->dalloc<double>(size_t(nu)) : nullptr;   // graph's fixed output
@@ -1295,6 +1295,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   double* cp = cg + 2 * np;
   double* cq = cg + 3 * np;
   double* cx = cg + 4 * np;
+  double* cp2 = cg + 5 * np;
   int64_t inner_total = 0;
   int vcycles = 0;
 
@@ -1351,7 +1352,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     for (int base = 0; base < o.schur_max_iter; base += kCgBatch) {
       const int kk = std::min(kCgBatch, o.schur_max_iter - base);
       for (int k = 0; k < kk; ++k)
-        launch_cg_pmass_iteration(lv, P, ctx->pmass_minv, cx, cr, cz, cp, cq, ctx->red_part, sc, base + k, s);
+        launch_cg_pmass_iteration(lv, P, ctx->pmass_minv, cx, cr, cz, cp, cp2, cq, ctx->red_part, sc, base + k, s);
       (void)hipMemcpyAsync(ctx->host_res + 480, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
       if (ctx->host_res[485] != 0.0) break;

@@ -206,11 +206,18 @@ void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, 
                       const double* gate = nullptr);
 // Jacobi-CG on M_p with its scalars on the device (see ops.hip): setup of the
 // scalars (sc[0] must hold r.z, q must be zero), and iteration k = 0, 1, ...
-// (no host synchronisation; a no-op once sc[5] is set).  part holds >= 3072
-// doubles.
+// (no host synchronisation; a no-op once sc[5] is set).  part holds
+// kRedPartWords doubles.  p holds p_0 at iteration 0; on a uniform leaf the
+// direction alternates between p (even k) and p_alt (odd k), elsewhere p_alt
+// is not used.  On a uniform leaf the test of iteration k's residual runs at
+// the start of iteration k + 1 (a batch that ends on the converging iteration
+// leaves sc[5] for the next one to set, and an iteration cap reached without
+// convergence counts one iteration less in sc[6]).
+constexpr int64_t kRedPartWords = 256 * 256;
 void launch_cg_setup(double* sc, double tol2, hipStream_t s);
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
-                               double* z, double* p, double* q, double* part, double* sc, int k, hipStream_t s);
+                               double* z, double* p, double* p_alt, double* q, double* part, double* sc, int k,
+                               hipStream_t s);
 // copy p_in on hanging pressure nodes into p_out
 void launch_p_identity(const DevPressure& P, const double* p_in, double* p_out, hipStream_t s);
 // resolve hanging values: u[h] = sum w u[m] (velocity) and p likewise

@@ -1288,14 +1288,20 @@ __global__ __launch_bounds__(kBlock) void k_grad_uniform(int64_t n, DevPressure 
 // times its scale.  Every point is written (stored: po is zero on entry and
 // no other kernel adds to it on a uniform leaf).
 constexpr int kPmTX = 8, kPmTY = 8, kPmTZ = 4;
-__global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t n, DevPressure P,
-                                                                         const double* __restrict__ mu,
-                                                                         const double* __restrict__ p,
-                                                                         double* __restrict__ po,
-                                                                         const double* __restrict__ gate) {
-  // the gate is read first and tested before the store, so its latency
-  // overlaps the staging
-  const bool gated = gate && *gate != 0.0;
+// One tile of the uniform-leaf M_p p for the calling workgroup (all its
+// threads must call it): value(id) gives the input at pressure node id (it
+// may compute it, e.g. a CG direction update).  Returns, for the thread's
+// point, whether it lies on the lattice, its node (id), its input value (pv)
+// and its output (the return value).
+struct PmassPoint {
+  bool valid;
+  int32_t id;
+  double pv;
+  double out;
+};
+template <typename F>
+__device__ __forceinline__ PmassPoint pmass_tile(int64_t n, const DevPressure& P, const double* __restrict__ mu,
+                                                 F value) {
   constexpr int WX = kPmTX + 2, WY = kPmTY + 2, WZ = kPmTZ + 2;
   constexpr int CX = kPmTX + 1, CY = kPmTY + 1, CZ = kPmTZ + 1;
   constexpr int NT = kPmTX * kPmTY * kPmTZ;
@@ -1312,7 +1318,7 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t
     const bool in = px >= 0 && px < np1 && py >= 0 && py < np1 && pz >= 0 && pz < np1;
     const int32_t id = in ? P.plat[px + np1 * (py + np1 * pz)] : -1;
     si[e] = id;
-    sp[e] = in ? p[id] : 0.0;
+    sp[e] = in ? value(id) : 0.0;
   }
   for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
     const int64_t cx = X0 - 1 + e % CX, cy = Y0 - 1 + (e / CX) % CY, cz = Z0 - 1 + e / (CX * CY);
@@ -1321,8 +1327,8 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t
   }
   __syncthreads();
   const int lx = threadIdx.x % kPmTX, ly = (threadIdx.x / kPmTX) % kPmTY, lz = threadIdx.x / (kPmTX * kPmTY);
-  const int64_t X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
-  if (gated || X >= np1 || Y >= np1 || Z >= np1) return;
+  PmassPoint r{false, -1, 0.0, 0.0};
+  if (X0 + lx >= np1 || Y0 + ly >= np1 || Z0 + lz >= np1) return r;
   // along x: the cell on side ax in {0, 1} covers window points ax, ax + 1,
   // the point itself being window point 1
   double wx[3][3][2];
@@ -1353,7 +1359,18 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t
                             : wy[0][ay][ax] * (1.0 / 6.0) + wy[1][ay][ax] * (1.0 / 3.0);
         out += ss[(lz + az) * (CY * CX) + (ly + ay) * CX + lx + ax] * t;
       }
-  po[si[(lz + 1) * (WY * WX) + (ly + 1) * WX + lx + 1]] = out;
+  const int c = (lz + 1) * (WY * WX) + (ly + 1) * WX + lx + 1;
+  r.valid = true, r.id = si[c], r.pv = sp[c], r.out = out;
+  return r;
+}
+__global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_pmass_uniform(int64_t n, DevPressure P,
+                                                                         const double* __restrict__ mu,
+                                                                         const double* __restrict__ p,
+                                                                         double* __restrict__ po,
+                                                                         const double* __restrict__ gate) {
+  if (gate && *gate != 0.0) return;
+  const PmassPoint r = pmass_tile(n, P, mu, [&](int32_t id) { return p[id]; });
+  if (r.valid) po[r.id] = r.out;
 }
 unsigned pmass_uniform_tiles(int64_t n) {
   const int64_t np1 = n + 1;
@@ -1964,13 +1981,61 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int np, const 
   }
   if (lead) sc[6] += 1.0, sc[par ^ 1] = rz;
 }
+// Uniform leaf: an iteration in two kernels.  This one takes the previous
+// iteration's test and direction update (from k_cg_update's partials, as
+// k_cg_pupdate does) into the staging of the tiled M_p p: every tile forms
+// p_k = z + beta p_{k-1} on its window (a point staged by several tiles gets
+// the same value in each), stores p_k on its own points into the other
+// direction buffer (p_{k-1} is only read), q = M_p p_k, and its partial of
+// p_k . q.  Iteration 0 takes p_0 from pcur as it is.
+__global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_cg_pmass_uniform(
+    int64_t n, DevPressure P, const double* __restrict__ mu, const double* __restrict__ z,
+    const double* __restrict__ pprev, double* __restrict__ pcur, double* __restrict__ q, int np_part,
+    const double* __restrict__ part, double* sc, int k, double* __restrict__ part_pq) {
+  if (sc[5] != 0.0) return;
+  double beta = 0.0;
+  if (k > 0) {
+    const double rr = block_sum_all(np_part, part);
+    const double rz = block_sum_all(np_part, part + np_part);
+    const int pp = (k - 1) & 1;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (rr <= sc[4]) {
+      if (lead) sc[6] += 1.0, sc[5] = 1.0;
+      return;
+    }
+    beta = rz / sc[pp];
+    if (lead) sc[6] += 1.0, sc[pp ^ 1] = rz;
+  }
+  const PmassPoint r =
+      pmass_tile(n, P, mu, [&](int32_t id) { return k > 0 ? z[id] + beta * pprev[id] : pcur[id]; });
+  if (r.valid) {
+    if (k > 0) pcur[r.id] = r.pv;
+    q[r.id] = r.out;
+  }
+  const double v = block_sum(r.valid ? r.pv * r.out : 0.0);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = v;
+}
 }  // namespace
 
 void launch_cg_setup(double* sc, double tol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, tol2); }
 
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
-                               double* z, double* p, double* q, double* part, double* sc, int k, hipStream_t s) {
+                               double* z, double* p, double* p_alt, double* q, double* part, double* sc, int k,
+                               hipStream_t s) {
   const int64_t n = P.np;
+  if (L.uniform && P.plat && int64_t(pmass_uniform_tiles(L.n_edge)) + 2 * kRedBlocks <= kRedPartWords) {
+    // p_k lives in p for even k, in p_alt for odd k; k_cg_update's partials
+    // at part[0, 2g), the tiles' p.q partials after 2 kRedBlocks
+    const unsigned g = grid_for(n, kBlock, kRedBlocks), nt = pmass_uniform_tiles(L.n_edge);
+    const int par = k & 1;
+    double* pk = par ? p_alt : p;
+    const double* pprev = par ? p : p_alt;
+    double* ppq = part + 2 * kRedBlocks;
+    k_cg_pmass_uniform<<<nt, kPmTX * kPmTY * kPmTZ, 0, s>>>(L.n_edge, P, L.mu_d, z, pprev, pk, q, int(g), part, sc,
+                                                           k, ppq);
+    k_cg_update<<<g, kBlock, 0, s>>>(n, int(nt), ppq, sc, par, pk, q, minv, x, r, z, part);
+    return;
+  }
   // q is zero here: cleared by the setup, then by the previous iteration
   launch_pmass_add(L, P, p, q, s, sc + 5);
   k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, p, q, part);
