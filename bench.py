@@ -271,7 +271,7 @@ def main():
         summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
     if args.solve_workload:
         variants = args.variants
