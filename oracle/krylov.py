@@ -298,16 +298,18 @@ class StokesProblem:
     def apply_K(self, x):
         return self.K @ x
 
-    def precondition(self, r, a_inv=None, s_inv=None, block="triangular", schur="cg", schur_degree=8):
+    def precondition(self, r, a_inv=None, s_inv=None, block="triangular", schur="cg", schur_degree=8,
+                     schur_rtol=1e-6, schur_maxit=200):
         """z = P^{-1} r: z_p = -S_hat^{-1} r_p, z_u = A_hat^{-1}(r_u - B^T z_p)
         (block "triangular", eq. stokes_precond) or A_hat^{-1} r_u (block
-        "diagonal", eq. stokes_precond_diag).  S_hat^{-1}: Jacobi CG ("cg")
-        or the fixed Chebyshev iteration ("cheb") on M_p."""
+        "diagonal", eq. stokes_precond_diag).  S_hat^{-1}: Jacobi CG ("cg", to
+        schur_rtol or at most schur_maxit iterations) or the fixed Chebyshev
+        iteration ("cheb") on M_p."""
         ru, rp = r[:self.nu], r[self.nu:]
         if s_inv is not None:
             zp_pos = s_inv(rp)
         elif schur == "cg":
-            zp_pos, it = cg(lambda v: self.Mp @ v, rp, self.mp_minv, rtol=1e-6, maxit=200)
+            zp_pos, it = cg(lambda v: self.Mp @ v, rp, self.mp_minv, rtol=schur_rtol, maxit=schur_maxit)
             self.inner_cg_its.append(it)
         else:
             lo, hi = self.mp_interval

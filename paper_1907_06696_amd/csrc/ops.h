@@ -211,8 +211,8 @@ void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, 
 // direction alternates between p (even k) and p_alt (odd k), elsewhere p_alt
 // is not used.  On a uniform leaf the test of iteration k's residual runs at
 // the start of iteration k + 1 (a batch that ends on the converging iteration
-// leaves sc[5] for the next one to set, and an iteration cap reached without
-// convergence counts one iteration less in sc[6]).
+// leaves sc[5] for the next one to set); the iteration count in sc[6] is the
+// same on both paths.
 constexpr int64_t kRedPartWords = 256 * 256;
 void launch_cg_setup(double* sc, double tol2, hipStream_t s);
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,

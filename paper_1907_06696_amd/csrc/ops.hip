@@ -1943,14 +1943,17 @@ __device__ __forceinline__ double block_sum_all(int np, const double* __restrict
   __syncthreads();
   return v;
 }
+// count: this kernel counts the iteration in sc[6] (the uniform-leaf path;
+// elsewhere k_cg_pupdate does)
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int npq, const double* __restrict__ part_pq,
-                                                     const double* __restrict__ sc, int par,
+                                                     double* sc, int par, bool count,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      const double* __restrict__ minv, double* __restrict__ x,
                                                      double* __restrict__ r, double* __restrict__ z,
                                                      double* __restrict__ part) {
   if (sc[5] != 0.0) return;
   const double alpha = sc[par] / block_sum_all(npq, part_pq);
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) sc[6] += 1.0;
   double rr = 0.0, rz = 0.0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     x[i] += alpha * p[i];
@@ -1983,7 +1986,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int np, const 
 }
 // Uniform leaf: an iteration in two kernels.  This one takes the previous
 // iteration's test and direction update (from k_cg_update's partials, as
-// k_cg_pupdate does) into the staging of the tiled M_p p: every tile forms
+// k_cg_pupdate does; k_cg_update counts the iterations) into the staging of
+// the tiled M_p p: every tile forms
 // p_k = z + beta p_{k-1} on its window (a point staged by several tiles gets
 // the same value in each), stores p_k on its own points into the other
 // direction buffer (p_{k-1} is only read), q = M_p p_k, and its partial of
@@ -2000,11 +2004,11 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_cg_pmass_uniform(
     const int pp = (k - 1) & 1;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (rr <= sc[4]) {
-      if (lead) sc[6] += 1.0, sc[5] = 1.0;
+      if (lead) sc[5] = 1.0;
       return;
     }
     beta = rz / sc[pp];
-    if (lead) sc[6] += 1.0, sc[pp ^ 1] = rz;
+    if (lead) sc[pp ^ 1] = rz;
   }
   const PmassPoint r =
       pmass_tile(n, P, mu, [&](int32_t id) { return k > 0 ? z[id] + beta * pprev[id] : pcur[id]; });
@@ -2033,7 +2037,7 @@ void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const do
     double* ppq = part + 2 * kRedBlocks;
     k_cg_pmass_uniform<<<nt, kPmTX * kPmTY * kPmTZ, 0, s>>>(L.n_edge, P, L.mu_d, z, pprev, pk, q, int(g), part, sc,
                                                            k, ppq);
-    k_cg_update<<<g, kBlock, 0, s>>>(n, int(nt), ppq, sc, par, pk, q, minv, x, r, z, part);
+    k_cg_update<<<g, kBlock, 0, s>>>(n, int(nt), ppq, sc, par, true, pk, q, minv, x, r, z, part);
     return;
   }
   // q is zero here: cleared by the setup, then by the previous iteration
@@ -2041,7 +2045,7 @@ void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const do
   k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, p, q, part);
   const unsigned g = grid_for(n, kBlock, kRedBlocks);
   const int par = k & 1;
-  k_cg_update<<<g, kBlock, 0, s>>>(n, kRedBlocks, part, sc, par, p, q, minv, x, r, z, part + kRedBlocks);
+  k_cg_update<<<g, kBlock, 0, s>>>(n, kRedBlocks, part, sc, par, false, p, q, minv, x, r, z, part + kRedBlocks);
   k_cg_pupdate<<<g, kBlock, 0, s>>>(n, int(g), part + kRedBlocks, sc, par, z, p, q);
 }
 void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hipStream_t s) {

@@ -212,6 +212,48 @@ def test_solver_variants_match_oracle(name):
         c.close()
 
 
+def test_capped_inner_cg_matches_oracle():
+    """Inner CG stopped by its iteration cap (3 steps, far from its 1e-6
+    tolerance) on a uniform leaf (two-kernel iterations with the direction
+    update fused into M_p p) and on an adaptive leaf (the block kernels): every
+    preconditioner application runs exactly 3 CG steps on both sides, but the
+    first, whose pressure residual is zero (no divergence right-hand side) and
+    takes none, and the outer FGMRES follows the oracle's with the same cap."""
+    for kw in (dict(base=2, sinkers=3, dr=1e2, seed=4),
+               dict(base=3, corners=((2, 5, 3), (0, 0, 0)), times=1, sinkers=4, dr=1e3, seed=7)):
+        c = Case(**kw)
+        c.s.set_viscosity(c.mu_qp_lib)
+        L = c.L
+        nu, npp = c.info["n_u"][L], c.info["n_p"]
+        prob = krylov.StokesProblem(c.H, ops.harmonic_cell_viscosity(c.mu_qp_or), c.f_qp_or, gmg_kwargs={})
+        x_or, st_or = prob.solve(rtol=1e-8, restart=50, maxit=600, schur_maxit=3)
+        assert prob.inner_cg_its[0] == 0 and all(it == 3 for it in prob.inner_cg_its[1:])
+        xd = prob.solve_direct()
+        # both stop at residual 1e-8; the error that leaves depends on the
+        # conditioning, so it is bounded by the oracle's own error
+        err_or = np.linalg.norm(x_or - xd) / np.linalg.norm(xd)
+        pu, pp = c.dof_perm(L), c.pnode_perm()
+        rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+        c.s.assemble_rhs(c.f_qp_lib, rhs)
+        u = torch.empty(nu, dtype=torch.float64, device=DEV)
+        p = torch.empty(npp, dtype=torch.float64, device=DEV)
+        st = c.s.solve_stokes(rhs, u, p, vcycle_prec="fp64", max_iter=600, schur_max_iter=3)
+        torch.cuda.synchronize()
+        x = np.zeros(nu + npp)
+        x[pu] = u.cpu().numpy()
+        x[nu + pp] = p.cpu().numpy()
+        x[:nu] *= c.H.leaf.free_dofs_mask()
+        x[nu:] *= c.H.leaf.pfree
+        res = prob.residual(x)
+        err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"  capped CG: its={st['iterations']} (oracle {st_or['iterations']}) inner={st['inner_cg_iterations']} "
+              f"res={res:.2e} err={err:.2e} (oracle {err_or:.2e})", flush=True)
+        assert st["converged"] == 1 and res <= 1.5e-8 and err <= max(1e-5, 3 * err_or), (res, err, err_or)
+        assert abs(st["iterations"] - st_or["iterations"]) <= 1, (st["iterations"], st_or["iterations"])
+        assert st["inner_cg_iterations"] == 3 * (st["iterations"] - 1), (st["inner_cg_iterations"], st["iterations"])
+        c.close()
+
+
 def test_gmres_needs_the_linear_schur_map():
     c = Case(base=2, sinkers=2, dr=1e2, seed=3, build_oracle=False)
     c.s.set_viscosity(c.mu_qp_lib)
