@@ -783,57 +783,106 @@ __global__ void k_prolong_uniform(int nc, const T* __restrict__ xc, T* __restric
   }
 }
 
+// Restriction between uniform levels, tiled: a workgroup takes TX x TY x TZ
+// coarse nodes and, one velocity component at a time, stages the fine window
+// they restrict from ((2 TX + 5) x (2 TY + 5) x (2 TZ + 5) fine nodes, 0 on
+// the fine boundary and off the lattice) with the residual b - t in LDS, then
+// contracts it axis by axis with the 1D weights of R = P^T: offsets -3, -1,
+// 0, 1, 3 from the fine node 2C, weights (-1/8, 3/8, 1, 3/8, -1/8) for even C
+// and (0, 3/4, 1, 3/4, 0) for odd C.  Coarse boundary nodes get 0.
 template <typename T>
-__device__ __forceinline__ int restrict_axis(int C, int mf, int (&idx)[5], T (&w)[5]) {
-  int k = 0;
-  const int X = 2 * C;
-  if (C & 1) {
-    const int off[3] = {-1, 0, 1};
-    const T ww[3] = {T(0.75), T(1), T(0.75)};
-    for (int q = 0; q < 3; ++q)
-      if (X + off[q] > 0 && X + off[q] < mf - 1) idx[k] = X + off[q], w[k] = ww[q], ++k;
-  } else {
-    const int off[5] = {-3, -1, 0, 1, 3};
-    const T ww[5] = {T(-0.125), T(0.375), T(1), T(0.375), T(-0.125)};
-    for (int q = 0; q < 5; ++q)
-      if (X + off[q] > 0 && X + off[q] < mf - 1) idx[k] = X + off[q], w[k] = ww[q], ++k;
-  }
-  return k;
+__device__ __forceinline__ T restrict_w(int C, int q) {
+  if (C & 1) return q == 0 || q == 4 ? T(0) : (q == 2 ? T(1) : T(0.75));
+  return q == 2 ? T(1) : ((q == 1 || q == 3) ? T(0.375) : T(-0.125));
 }
-
-template <typename T>
-__global__ void k_restrict_uniform(int nc, const T* __restrict__ b, const T* __restrict__ t, T* __restrict__ xc) {
+template <typename T, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void k_restrict_tiled(int nc, const T* __restrict__ b,
+                                                                 const T* __restrict__ t, T* __restrict__ xc) {
+  constexpr int NT = TX * TY * TZ;
+  constexpr int WX = 2 * TX + 5, WY = 2 * TY + 5, WZ = 2 * TZ + 5;
+  constexpr int NW = WZ * WY * WX, KW = (NW + NT - 1) / NT;
+  constexpr int NA = WZ * WY * TX, KA = (NA + NT - 1) / NT;   // after the x pass
+  constexpr int NB = WZ * TY * TX, KB = (NB + NT - 1) / NT;   // after the y pass (aliases the window)
+  static_assert(NB <= NW, "y pass buffer");
+  __shared__ T sw[NW];
+  __shared__ T sa[NA];
   const int mc = 2 * nc + 1, mf = 4 * nc + 1;
-  const int64_t nn = int64_t(mc) * mc * mc;
-  // XCD-contiguous node ranges: neighbouring coarse nodes read the same fine ones
-  for (int64_t v = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; v < nn;
-       v += int64_t(gridDim.x) * blockDim.x) {
-    const int X = int(v % mc), Y = int((v / mc) % mc), Z = int(v / (int64_t(mc) * mc));
-    T a0 = T(0), a1 = T(0), a2 = T(0);
-    const bool dir = X == 0 || Y == 0 || Z == 0 || X == mc - 1 || Y == mc - 1 || Z == mc - 1;
-    if (!dir) {
-      int ix[5], iy[5], iz[5];
-      T wx[5], wy[5], wz[5];
-      const int nx = restrict_axis<T>(X, mf, ix, wx), ny = restrict_axis<T>(Y, mf, iy, wy),
-                nz = restrict_axis<T>(Z, mf, iz, wz);
-      for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j) {
-          const T wzy = wz[k] * wy[j];
-          const int64_t rowf = int64_t(mf) * (iy[j] + int64_t(mf) * iz[k]);
-          for (int i = 0; i < nx; ++i) {
-            const T ww = wzy * wx[i];
-            const int64_t f = 3 * (rowf + ix[i]);
-            if (t) {
-              a0 += ww * (b[f] - t[f]), a1 += ww * (b[f + 1] - t[f + 1]), a2 += ww * (b[f + 2] - t[f + 2]);
-            } else {
-              a0 += ww * b[f], a1 += ww * b[f + 1], a2 += ww * b[f + 2];
-            }
-          }
-        }
-    }
-    xc[3 * v] = a0, xc[3 * v + 1] = a1, xc[3 * v + 2] = a2;
+  const int ntx = (mc + TX - 1) / TX, nty = (mc + TY - 1) / TY;
+  const int tile = int(brick::xcd_order(blockIdx.x, gridDim.x));
+  const int X0 = (tile % ntx) * TX, Y0 = ((tile / ntx) % nty) * TY, Z0 = (tile / (ntx * nty)) * TZ;
+  const int fx0 = 2 * X0 - 3, fy0 = 2 * Y0 - 3, fz0 = 2 * Z0 - 3;
+  const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+  const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
+  // the window's residual values of all three components, loaded at once
+  T v[3][KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int e = int(threadIdx.x) + k * NT;
+    const int fx = fx0 + e % WX, fy = fy0 + (e / WX) % WY, fz = fz0 + e / (WX * WY);
+    const bool in = e < NW && fx > 0 && fx < mf - 1 && fy > 0 && fy < mf - 1 && fz > 0 && fz < mf - 1;
+    const int64_t f = in ? 3 * (int64_t(fx) + int64_t(mf) * (fy + int64_t(mf) * fz)) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][k] = in ? (t ? b[f + c] - t[f + c] : b[f + c]) : T(0);
   }
+  T out[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const int e = int(threadIdx.x) + k * NT;
+      if (e < NW) sw[e] = v[c][k];
+    }
+    __syncthreads();
+    // x: a[z][y][cx] = sum_q w(X0 + cx, q) sw[z][y][2 cx + 3 + off_q]
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+      const int e = int(threadIdx.x) + k * NT;
+      if (e < NA) {
+        const int cx = e % TX, row = e / TX;
+        const T* r = sw + row * WX + 2 * cx + 3;
+        const int C = X0 + cx;
+        sa[e] = restrict_w<T>(C, 0) * r[-3] + restrict_w<T>(C, 1) * r[-1] + r[0] + restrict_w<T>(C, 3) * r[1] +
+                restrict_w<T>(C, 4) * r[3];
+      }
+    }
+    __syncthreads();
+    // y: b2[z][cy][cx] = sum_q w(Y0 + cy, q) a[z][2 cy + 3 + off_q][cx]
+    T* sb = sw;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int e = int(threadIdx.x) + k * NT;
+      if (e < NB) {
+        const int cx = e % TX, cy = (e / TX) % TY, z = e / (TX * TY);
+        const T* col = sa + (z * WY + 2 * cy + 3) * TX + cx;
+        const int C = Y0 + cy;
+        sb[e] = restrict_w<T>(C, 0) * col[-3 * TX] + restrict_w<T>(C, 1) * col[-TX] + col[0] +
+                restrict_w<T>(C, 3) * col[TX] + restrict_w<T>(C, 4) * col[3 * TX];
+      }
+    }
+    __syncthreads();
+    {
+      const T* col = sb + ((2 * lz + 3) * TY + ly) * TX + lx;
+      constexpr int S = TY * TX;
+      out[c] = restrict_w<T>(Z, 0) * col[-3 * S] + restrict_w<T>(Z, 1) * col[-S] + col[0] + restrict_w<T>(Z, 3) * col[S] +
+               restrict_w<T>(Z, 4) * col[3 * S];
+    }
+    __syncthreads();
+  }
+  if (X >= mc || Y >= mc || Z >= mc) return;
+  const bool dir = X == 0 || Y == 0 || Z == 0 || X == mc - 1 || Y == mc - 1 || Z == mc - 1;
+  T* q = xc + 3 * (int64_t(X) + int64_t(mc) * (Y + int64_t(mc) * Z));
+  q[0] = dir ? T(0) : out[0];
+  q[1] = dir ? T(0) : out[1];
+  q[2] = dir ? T(0) : out[2];
 }
+template <typename T>
+struct RestrictTile {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+template <>
+struct RestrictTile<double> {
+  static constexpr int TX = 8, TY = 4, TZ = 4;
+};
 
 // ------------------------------------------------------------- coarse
 template <typename T>
@@ -2090,7 +2139,10 @@ template <typename T>
 void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
                            const float* w, const T* b, const T* t, T* xc, hipStream_t s) {
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
-    k_restrict_uniform<T><<<grid_for(Cc.nnode), kBlock, 0, s>>>(int(Cc.n_edge), b, t, xc);
+    constexpr int TX = RestrictTile<T>::TX, TY = RestrictTile<T>::TY, TZ = RestrictTile<T>::TZ;
+    const int64_t mc = 2 * Cc.n_edge + 1;
+    const unsigned nt = unsigned(((mc + TX - 1) / TX) * ((mc + TY - 1) / TY) * ((mc + TZ - 1) / TZ));
+    k_restrict_tiled<T, TX, TY, TZ><<<nt, TX * TY * TZ, 0, s>>>(int(Cc.n_edge), b, t, xc);
     return;
   }
   k_restrict<T, kRestrictLanes><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b,
