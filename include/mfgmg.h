@@ -37,7 +37,9 @@
  *     `stream` is a hipStream_t (NULL = default stream).  Calls marked async
  *     only enqueue work on that stream.
  *   - One context per host thread; a context is bound to the device that is
- *     current when mfgmg_set_viscosity is first called.
+ *     current when mfgmg_set_viscosity is first called.  Device calls of one
+ *     context share its internal work vectors: work enqueued on different
+ *     streams of one context must not overlap in time.
  */
 #ifndef MFGMG_H
 #define MFGMG_H

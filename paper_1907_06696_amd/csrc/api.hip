@@ -672,7 +672,9 @@ void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
   // the pre-smoothing left t prepared for A x where the operator needs it
   if (vmult_has_init<T>(d.v)) launch_vmult_prepared<T>(d.v, x, t, s);
   else launch_vmult<T>(d.v, x, t, s);
-  launch_restrict_level<T>(d.v, c.v, d.R_ptr, d.R_col, d.R_w, b, t, bc, s);
+  // the smoother's r and d are free here: scratch of the restriction passes
+  launch_restrict_level<T>(d.v, c.v, d.R_ptr, d.R_col, d.R_w, b, t, bc, static_cast<T*>(d.work[pi][2]),
+                           static_cast<T*>(d.work[pi][3]), s);
   vcycle<T>(ctx, ell - 1, bc, xc, s);
   launch_prolong_level<T>(d.v, c.v, d.P_ptr, d.P_col, d.P_w, xc, x, true, s);
   smooth<T>(ctx, ell, b, x, false, s);
@@ -1129,12 +1131,15 @@ int mfgmg_restrict(mfgmg_ctx* ctx, int32_t level, mfgmg_prec prec, const void* f
   hipStream_t s = static_cast<hipStream_t>(stream);
   const LevelDev& d = ctx->lv[size_t(level)];
   const DevLevel& cv = ctx->lv[size_t(level - 1)].v;
+  // scratch: the level's smoother work vectors
   if (prec == MFGMG_FP64)
     launch_restrict_level<double>(d.v, cv, d.R_ptr, d.R_col, d.R_w, static_cast<const double*>(fine), nullptr,
-                                  static_cast<double*>(coarse), s);
+                                  static_cast<double*>(coarse), static_cast<double*>(d.work[1][2]),
+                                  static_cast<double*>(d.work[1][3]), s);
   else
     launch_restrict_level<float>(d.v, cv, d.R_ptr, d.R_col, d.R_w, static_cast<const float*>(fine), nullptr,
-                                 static_cast<float*>(coarse), s);
+                                 static_cast<float*>(coarse), static_cast<float*>(d.work[0][2]),
+                                 static_cast<float*>(d.work[0][3]), s);
   HIPCHK(hipGetLastError());
   return MFGMG_OK;
 }

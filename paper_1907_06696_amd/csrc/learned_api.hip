@@ -123,7 +123,10 @@ struct Fit {
     LevelDev& Cl = ctx->lv[size_t(ell - 1)];
     double* bc = static_cast<double*>(Cl.work[1][0]);
     double* xc = static_cast<double*>(Cl.work[1][1]);
-    launch_restrict_level<double>(F.v, Cl.v, F.R_ptr, F.R_col, F.R_w, v, nullptr, bc, s);
+    // scratch of the restriction: the level's FP64 smoother vectors (this
+    // context keeps its own)
+    launch_restrict_level<double>(F.v, Cl.v, F.R_ptr, F.R_col, F.R_w, v, nullptr, bc,
+                                  static_cast<double*>(F.work[1][2]), static_cast<double*>(F.work[1][3]), s);
     vcycle<double>(ctx, ell - 1, bc, xc, s);
     launch_prolong_level<double>(F.v, Cl.v, F.P_ptr, F.P_col, F.P_w, xc, out, add, s);
   }

@@ -147,9 +147,12 @@ void launch_restrict(int64_t ncoarse, const int64_t* ptr, const int32_t* col, co
 template <typename T>
 void launch_prolong_level(const DevLevel& fine, const DevLevel& coarse, const int64_t* ptr, const int32_t* col,
                           const float* w, const T* xc, T* xf, bool add, hipStream_t s);
+// (between two uniform levels the restriction runs in three one-axis passes
+// through the scratch vectors s1 and s2, each of the fine level's size; they
+// are not read elsewhere)
 template <typename T>
 void launch_restrict_level(const DevLevel& fine, const DevLevel& coarse, const int64_t* ptr, const int32_t* col,
-                           const float* w, const T* b, const T* t, T* xc, hipStream_t s);
+                           const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s);
 
 // coarse solve: x[free] = Ainv b[free], x[constrained] = b
 template <typename T>

@@ -783,106 +783,91 @@ __global__ void k_prolong_uniform(int nc, const T* __restrict__ xc, T* __restric
   }
 }
 
-// Restriction between uniform levels, tiled: a workgroup takes TX x TY x TZ
-// coarse nodes and, one velocity component at a time, stages the fine window
-// they restrict from ((2 TX + 5) x (2 TY + 5) x (2 TZ + 5) fine nodes, 0 on
-// the fine boundary and off the lattice) with the residual b - t in LDS, then
-// contracts it axis by axis with the 1D weights of R = P^T: offsets -3, -1,
-// 0, 1, 3 from the fine node 2C, weights (-1/8, 3/8, 1, 3/8, -1/8) for even C
-// and (0, 3/4, 1, 3/4, 0) for odd C.  Coarse boundary nodes get 0.
+// Restriction between uniform levels, R = P^T, as three one-axis passes
+// (each a bandwidth-bound stream with coalesced neighbours) with the 1D
+// weights of R: offsets -3, -1, 0, 1, 3 from the fine node 2C, weights
+// (-1/8, 3/8, 1, 3/8, -1/8) for even C and (0, 3/4, 1, 3/4, 0) for odd C.
+// x over the residual b - t (fine boundary nodes count 0) into s1, laid out
+// [fz][fy][cx][3]; y into s2 [fz][cy][cx][3]; z into the coarse vector
+// (coarse boundary nodes 0).  s1 and s2 are scratch of 3 mc mf^2 and
+// 3 mc^2 mf values (mc = 2 nc + 1, mf = 4 nc + 1).
 template <typename T>
 __device__ __forceinline__ T restrict_w(int C, int q) {
   if (C & 1) return q == 0 || q == 4 ? T(0) : (q == 2 ? T(1) : T(0.75));
   return q == 2 ? T(1) : ((q == 1 || q == 3) ? T(0.375) : T(-0.125));
 }
-template <typename T, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX * TY * TZ) void k_restrict_tiled(int nc, const T* __restrict__ b,
-                                                                 const T* __restrict__ t, T* __restrict__ xc) {
-  constexpr int NT = TX * TY * TZ;
-  constexpr int WX = 2 * TX + 5, WY = 2 * TY + 5, WZ = 2 * TZ + 5;
-  constexpr int NW = WZ * WY * WX, KW = (NW + NT - 1) / NT;
-  constexpr int NA = WZ * WY * TX, KA = (NA + NT - 1) / NT;   // after the x pass
-  constexpr int NB = WZ * TY * TX, KB = (NB + NT - 1) / NT;   // after the y pass (aliases the window)
-  static_assert(NB <= NW, "y pass buffer");
-  __shared__ T sw[NW];
-  __shared__ T sa[NA];
+__device__ __forceinline__ constexpr int restrict_off(int q) { return q == 0 ? -3 : q == 1 ? -1 : q == 2 ? 0 : q == 3 ? 1 : 3; }
+// one thread per output node (its 3 components)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_x(int nc, const T* __restrict__ b, const T* __restrict__ t,
+                                                      T* __restrict__ s1) {
   const int mc = 2 * nc + 1, mf = 4 * nc + 1;
-  const int ntx = (mc + TX - 1) / TX, nty = (mc + TY - 1) / TY;
-  const int tile = int(brick::xcd_order(blockIdx.x, gridDim.x));
-  const int X0 = (tile % ntx) * TX, Y0 = ((tile / ntx) % nty) * TY, Z0 = (tile / (ntx * nty)) * TZ;
-  const int fx0 = 2 * X0 - 3, fy0 = 2 * Y0 - 3, fz0 = 2 * Z0 - 3;
-  const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-  const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
-  // the window's residual values of all three components, loaded at once
-  T v[3][KW];
+  const int n = mc * mf * mf;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int cx = v % mc, fy = (v / mc) % mf, fz = v / (mc * mf);
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    if (fy > 0 && fy < mf - 1 && fz > 0 && fz < mf - 1) {
+      const int64_t row = 3 * int64_t(mf) * (fy + int64_t(mf) * fz);
 #pragma unroll
-  for (int k = 0; k < KW; ++k) {
-    const int e = int(threadIdx.x) + k * NT;
-    const int fx = fx0 + e % WX, fy = fy0 + (e / WX) % WY, fz = fz0 + e / (WX * WY);
-    const bool in = e < NW && fx > 0 && fx < mf - 1 && fy > 0 && fy < mf - 1 && fz > 0 && fz < mf - 1;
-    const int64_t f = in ? 3 * (int64_t(fx) + int64_t(mf) * (fy + int64_t(mf) * fz)) : 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[c][k] = in ? (t ? b[f + c] - t[f + c] : b[f + c]) : T(0);
-  }
-  T out[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int k = 0; k < KW; ++k) {
-      const int e = int(threadIdx.x) + k * NT;
-      if (e < NW) sw[e] = v[c][k];
-    }
-    __syncthreads();
-    // x: a[z][y][cx] = sum_q w(X0 + cx, q) sw[z][y][2 cx + 3 + off_q]
-#pragma unroll
-    for (int k = 0; k < KA; ++k) {
-      const int e = int(threadIdx.x) + k * NT;
-      if (e < NA) {
-        const int cx = e % TX, row = e / TX;
-        const T* r = sw + row * WX + 2 * cx + 3;
-        const int C = X0 + cx;
-        sa[e] = restrict_w<T>(C, 0) * r[-3] + restrict_w<T>(C, 1) * r[-1] + r[0] + restrict_w<T>(C, 3) * r[1] +
-                restrict_w<T>(C, 4) * r[3];
+      for (int q = 0; q < 5; ++q) {
+        const int fx = 2 * cx + restrict_off(q);
+        if (fx > 0 && fx < mf - 1) {
+          const int64_t f = row + 3 * fx;
+          const T w = restrict_w<T>(cx, q);
+          if (t) {
+            a0 += w * (b[f] - t[f]), a1 += w * (b[f + 1] - t[f + 1]), a2 += w * (b[f + 2] - t[f + 2]);
+          } else {
+            a0 += w * b[f], a1 += w * b[f + 1], a2 += w * b[f + 2];
+          }
+        }
       }
     }
-    __syncthreads();
-    // y: b2[z][cy][cx] = sum_q w(Y0 + cy, q) a[z][2 cy + 3 + off_q][cx]
-    T* sb = sw;
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int e = int(threadIdx.x) + k * NT;
-      if (e < NB) {
-        const int cx = e % TX, cy = (e / TX) % TY, z = e / (TX * TY);
-        const T* col = sa + (z * WY + 2 * cy + 3) * TX + cx;
-        const int C = Y0 + cy;
-        sb[e] = restrict_w<T>(C, 0) * col[-3 * TX] + restrict_w<T>(C, 1) * col[-TX] + col[0] +
-                restrict_w<T>(C, 3) * col[TX] + restrict_w<T>(C, 4) * col[3 * TX];
-      }
-    }
-    __syncthreads();
-    {
-      const T* col = sb + ((2 * lz + 3) * TY + ly) * TX + lx;
-      constexpr int S = TY * TX;
-      out[c] = restrict_w<T>(Z, 0) * col[-3 * S] + restrict_w<T>(Z, 1) * col[-S] + col[0] + restrict_w<T>(Z, 3) * col[S] +
-               restrict_w<T>(Z, 4) * col[3 * S];
-    }
-    __syncthreads();
+    T* o = s1 + 3 * int64_t(v);
+    o[0] = a0, o[1] = a1, o[2] = a2;
   }
-  if (X >= mc || Y >= mc || Z >= mc) return;
-  const bool dir = X == 0 || Y == 0 || Z == 0 || X == mc - 1 || Y == mc - 1 || Z == mc - 1;
-  T* q = xc + 3 * (int64_t(X) + int64_t(mc) * (Y + int64_t(mc) * Z));
-  q[0] = dir ? T(0) : out[0];
-  q[1] = dir ? T(0) : out[1];
-  q[2] = dir ? T(0) : out[2];
 }
 template <typename T>
-struct RestrictTile {
-  static constexpr int TX = 8, TY = 8, TZ = 4;
-};
-template <>
-struct RestrictTile<double> {
-  static constexpr int TX = 8, TY = 4, TZ = 4;
-};
+__global__ __launch_bounds__(kBlock) void k_restrict_y(int nc, const T* __restrict__ s1, T* __restrict__ s2) {
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int n = mc * mc * mf;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int cx = v % mc, cy = (v / mc) % mc, fz = v / (mc * mc);
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int fy = 2 * cy + restrict_off(q);
+      if (fy >= 0 && fy < mf) {
+        const T* p = s1 + 3 * (cx + int64_t(mc) * (fy + int64_t(mf) * fz));
+        const T w = restrict_w<T>(cy, q);
+        a0 += w * p[0], a1 += w * p[1], a2 += w * p[2];
+      }
+    }
+    T* o = s2 + 3 * int64_t(v);
+    o[0] = a0, o[1] = a1, o[2] = a2;
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_z(int nc, const T* __restrict__ s2, T* __restrict__ xc) {
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int n = mc * mc * mc;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int cx = v % mc, cy = (v / mc) % mc, cz = v / (mc * mc);
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    if (cx > 0 && cx < mc - 1 && cy > 0 && cy < mc - 1 && cz > 0 && cz < mc - 1) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const int fz = 2 * cz + restrict_off(q);
+        if (fz >= 0 && fz < mf) {
+          const T* p = s2 + 3 * (cx + int64_t(mc) * (cy + int64_t(mc) * fz));
+          const T w = restrict_w<T>(cz, q);
+          a0 += w * p[0], a1 += w * p[1], a2 += w * p[2];
+        }
+      }
+    }
+    T* o = xc + 3 * int64_t(v);
+    o[0] = a0, o[1] = a1, o[2] = a2;
+  }
+}
 
 // ------------------------------------------------------------- coarse
 template <typename T>
@@ -2137,12 +2122,13 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
 
 template <typename T>
 void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
-                           const float* w, const T* b, const T* t, T* xc, hipStream_t s) {
+                           const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s) {
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
-    constexpr int TX = RestrictTile<T>::TX, TY = RestrictTile<T>::TY, TZ = RestrictTile<T>::TZ;
-    const int64_t mc = 2 * Cc.n_edge + 1;
-    const unsigned nt = unsigned(((mc + TX - 1) / TX) * ((mc + TY - 1) / TY) * ((mc + TZ - 1) / TZ));
-    k_restrict_tiled<T, TX, TY, TZ><<<nt, TX * TY * TZ, 0, s>>>(int(Cc.n_edge), b, t, xc);
+    const int nc = int(Cc.n_edge);
+    const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
+    k_restrict_x<T><<<grid_for(mc * mf * mf), kBlock, 0, s>>>(nc, b, t, s1);
+    k_restrict_y<T><<<grid_for(mc * mc * mf), kBlock, 0, s>>>(nc, s1, s2);
+    k_restrict_z<T><<<grid_for(mc * mc * mc), kBlock, 0, s>>>(nc, s2, xc);
     return;
   }
   k_restrict<T, kRestrictLanes><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b,
@@ -2153,7 +2139,7 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
   template void launch_prolong_level<T>(const DevLevel&, const DevLevel&, const int64_t*, const int32_t*,    \
                                         const float*, const T*, T*, bool, hipStream_t);                       \
   template void launch_restrict_level<T>(const DevLevel&, const DevLevel&, const int64_t*, const int32_t*,   \
-                                         const float*, const T*, const T*, T*, hipStream_t);
+                                         const float*, const T*, const T*, T*, T*, T*, hipStream_t);
 MFGMG_INST_TRANSFER(float)
 MFGMG_INST_TRANSFER(double)
 
