@@ -605,9 +605,11 @@ const double* minv_s_of<double>(const LevelDev& d) {
 // Chebyshev smoothing (Saad, Alg. 12.1) on [lambda/15, lambda], M^{-1} = minv
 template <typename T>
 void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t s) {
+  // Chebyshev iteration (Saad, Alg. 12.1) with the residual formed as b - A x
+  // at each step (the same iterates as the residual recurrence in exact
+  // arithmetic; r is never stored)
   LevelDev& d = ctx->lv[size_t(ell)];
   const int64_t n = 3 * d.v.nnode;
-  T* r = static_cast<T*>(d.work[prec_index<T>()][2]);
   T* dd = static_cast<T*>(d.work[prec_index<T>()][3]);
   T* t = static_cast<T*>(d.work[prec_index<T>()][4]);
   const bool sc = ctx->use_scaling && d.scaled;
@@ -616,31 +618,28 @@ void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t 
   const double theta = 0.5 * (lam + lo), delta = 0.5 * (lam - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
   // where the operator starts with an output initialisation kernel, each
-  // update prepares t for the next operator call instead (on d; after the
-  // last update of a pre-smoothing, on x for the V-cycle's residual)
+  // update prepares t for the next operator call on x instead (after the last
+  // update of a pre-smoothing, for the V-cycle's residual)
   const bool prep = vmult_has_init<T>(d.v);
   ChebPrep cp;
   if (prep) {
     cp.tn = t;
     cp.ntype = d.v.uniform ? nullptr : d.v.ntype;
     cp.m = d.v.uniform ? 2 * d.v.n_edge + 1 : 0;
+    cp.from_x = true;
   }
   if (x_zero) {
-    launch_cheb_init0<T>(n, b, minv, r, dd, x, 1.0 / theta, s, cp);
+    launch_chebx_init0<T>(n, b, minv, dd, x, 1.0 / theta, s, cp);
   } else {
     launch_vmult<T>(d.v, x, t, s);
-    launch_cheb_init<T>(n, b, t, minv, r, dd, x, 1.0 / theta, s, cp);
+    launch_chebx_step<T>(n, b, t, minv, dd, x, 0.0, 1.0 / theta, s, cp);
   }
   for (int k = 1; k < 4; ++k) {
-    if (prep) launch_vmult_prepared<T>(d.v, dd, t, s);
-    else launch_vmult<T>(d.v, dd, t, s);
+    if (prep) launch_vmult_prepared<T>(d.v, x, t, s);
+    else launch_vmult<T>(d.v, x, t, s);
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    ChebPrep last;
-    if (prep && x_zero) {
-      last = cp;
-      last.from_x = true;
-    }
-    launch_cheb_step<T>(n, t, minv, r, dd, x, rho_new * rho, 2.0 * rho_new / delta, s, k < 3 ? cp : last);
+    launch_chebx_step<T>(n, b, t, minv, dd, x, rho_new * rho, 2.0 * rho_new / delta, s,
+                         k < 3 || x_zero ? cp : ChebPrep());
     rho = rho_new;
   }
 }

@@ -124,6 +124,15 @@ void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T*
 template <typename T>
 void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
                       hipStream_t s, const ChebPrep& p = ChebPrep());
+// the smoother's form (residual b - A x formed each step, r not stored):
+// init0 from x = 0; step: d = alpha d + beta minv (b - t), x += d (alpha = 0:
+// d is not read).  p prepares t for the next operator call on x (from_x).
+template <typename T>
+void launch_chebx_init0(int64_t n, const T* b, const T* minv, T* d, T* x, double inv_theta, hipStream_t s,
+                        const ChebPrep& p = ChebPrep());
+template <typename T>
+void launch_chebx_step(int64_t n, const T* b, const T* t, const T* minv, T* d, T* x, double alpha, double beta,
+                       hipStream_t s, const ChebPrep& p = ChebPrep());
 // true when launch_vmult<T> on L starts with an output initialisation kernel
 // (every level but the uniform ones the brick kernel takes)
 template <typename T>

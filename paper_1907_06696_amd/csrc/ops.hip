@@ -649,6 +649,38 @@ __global__ void k_cheb_step(int64_t n, const T* t, const T* __restrict__ minv, T
   }
 }
 
+// The smoother's own form of the same iteration: the residual is formed as
+// b - A x_k instead of by the recurrence r_k = r_{k-1} - A d_{k-1} (equal in
+// exact arithmetic), so r is never stored and the operator is applied to x.
+// x0 = 0: d = (1/theta) M b, x = d; first step from a given x: t = A x,
+// d = (1/theta) M (b - t), x += d; later steps: d = alpha d + beta M (b - t),
+// x += d.  Each prepares t for the next operator call on x (out_prep).
+template <typename T>
+__global__ void k_chebx_init0(int64_t n, const T* __restrict__ b, const T* __restrict__ minv, T* __restrict__ d,
+                              T* __restrict__ x, T it, OutPrep<T> o) {
+  for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const T di = minv[i] * b[i] * it;
+    d[i] = di;
+    x[i] = di;
+    out_prep(o, i, di, di);
+  }
+}
+template <typename T>
+__global__ void k_chebx_step(int64_t n, const T* __restrict__ b, const T* t, const T* __restrict__ minv,
+                             T* __restrict__ d, T* __restrict__ x, T alpha, T beta, OutPrep<T> o) {
+  // alpha = 0: the first step from a given x (d is not read)
+  for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const T ri = b[i] - t[i];
+    const T di = (alpha != T(0) ? alpha * d[i] : T(0)) + beta * minv[i] * ri;
+    const T xi = x[i] + di;
+    d[i] = di;
+    x[i] = xi;
+    out_prep(o, i, di, xi);
+  }
+}
+
 // ------------------------------------------------------------- transfers
 // CSR transfers, G lanes per row (rows of R hold up to 125 fine nodes, rows
 // of P up to 27 coarse ones): the lanes of a group read consecutive entries
@@ -1787,6 +1819,24 @@ void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, do
                       hipStream_t s, const ChebPrep& p) {
   k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta), out_prep_of<T>(p));
 }
+template <typename T>
+void launch_chebx_init0(int64_t n, const T* b, const T* minv, T* d, T* x, double it, hipStream_t s,
+                        const ChebPrep& p) {
+  k_chebx_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, d, x, T(it), out_prep_of<T>(p));
+}
+template <typename T>
+void launch_chebx_step(int64_t n, const T* b, const T* t, const T* minv, T* d, T* x, double alpha, double beta,
+                       hipStream_t s, const ChebPrep& p) {
+  k_chebx_step<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, d, x, T(alpha), T(beta), out_prep_of<T>(p));
+}
+template void launch_chebx_init0<float>(int64_t, const float*, const float*, float*, float*, double, hipStream_t,
+                                        const ChebPrep&);
+template void launch_chebx_init0<double>(int64_t, const double*, const double*, double*, double*, double, hipStream_t,
+                                         const ChebPrep&);
+template void launch_chebx_step<float>(int64_t, const float*, const float*, const float*, float*, float*, double,
+                                       double, hipStream_t, const ChebPrep&);
+template void launch_chebx_step<double>(int64_t, const double*, const double*, const double*, double*, double*,
+                                        double, double, hipStream_t, const ChebPrep&);
 #define MFGMG_INST_CHEB(T)                                                                                      \
   template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t,              \
                                      const ChebPrep&);                                                          \
