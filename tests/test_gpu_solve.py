@@ -133,6 +133,49 @@ def test_vmult_full_size_64():
     assert np.abs(y - ref32).max() <= 1e-5 * scale
 
 
+def test_uniform_transfers_full_size():
+    """Transfers between the large uniform levels of the 64^3 hierarchy (64 ->
+    32 -> 16 cells per edge; restriction by one-axis passes, prolongation by
+    the per-node gather), checked by properties
+    that hold at any size: the Q2 prolongation reproduces the Q2 field
+    (c + 1) x(1-x) y(1-y) z(1-z), which vanishes on the boundary, exactly; and
+    the restriction is its transpose (<R u, v> = <u, P v> for random u, v)."""
+    s = mfgmg.Solver(6)
+    s.finalize_mesh()
+    info = s.info()
+    L = info["L"]
+    s.set_viscosity(np.ones((info["n_cells"][L], 27)))
+    S = 2 ** (L + 1)
+
+    def field(keys):
+        X = keys % (S + 1) / S
+        Y = (keys // (S + 1)) % (S + 1) / S
+        Z = keys // ((S + 1) ** 2) / S
+        g = X * (1 - X) * Y * (1 - Y) * Z * (1 - Z)
+        return (g[:, None] * np.arange(1, 4)[None, :]).ravel()
+
+    rg = np.random.default_rng(8)
+    for level in (L, L - 1):
+        fc, ff = field(s.support_points(level - 1)), field(s.support_points(level))
+        u, v = rg.uniform(-1, 1, ff.size), rg.uniform(-1, 1, fc.size)
+        for dt, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            xf = torch.empty(ff.size, dtype=dt, device=DEV)
+            s.prolongate(level, torch.tensor(fc, dtype=dt, device=DEV), xf)
+            pv = torch.empty(ff.size, dtype=dt, device=DEV)
+            s.prolongate(level, torch.tensor(v, dtype=dt, device=DEV), pv)
+            ru = torch.empty(fc.size, dtype=dt, device=DEV)
+            s.restrict(level, torch.tensor(u, dtype=dt, device=DEV), ru)
+            torch.cuda.synchronize()
+            e_field = np.abs(xf.cpu().numpy().astype(np.float64) - ff).max() / np.abs(ff).max()
+            lhs = float(ru.cpu().numpy().astype(np.float64) @ v)
+            rhs = float(u @ pv.cpu().numpy().astype(np.float64))
+            e_adj = abs(lhs - rhs) / (np.abs(ru.cpu().numpy()).astype(np.float64) @ np.abs(v))
+            print(f"  level {level} {dt}: Q2 field err {e_field:.2e}, <Ru,v> - <u,Pv> {e_adj:.2e}", flush=True)
+            assert e_field <= tol, (level, dt, e_field)
+            assert e_adj <= 10 * tol, (level, dt, e_adj)
+    s.close()
+
+
 def test_graph_replays_match_eager_launches():
     """The solve replays the captured V-cycle graph at every FGMRES iteration,
     with the solver's own eager kernels and host synchronisations between the
