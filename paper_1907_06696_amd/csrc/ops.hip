@@ -1284,62 +1284,79 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
 // around a node, an odd coordinate X = 2i+1 couples to P = i, i+1 with mass
 // (1/3, 1/3) and derivative (2/3, -2/3); an even X = 2i to P = i-1, i, i+1
 // with mass (0, 1/3, 0) and derivative (1/6, 0, -1/6).  The node reads the
-// <= 27 pressure values of its 3x3x3 lattice window (through the lattice
-// map) and contracts them axis by axis; the cell size enters as h^2.
-__global__ __launch_bounds__(kBlock) void k_grad_uniform(int64_t n, DevPressure P, const double* __restrict__ p,
-                                                         double* __restrict__ uo) {
-  const int64_t m = 2 * n + 1, nn = m * m * m, np1 = n + 1;
+// <= 27 pressure values of its 3x3x3 lattice window and contracts them axis
+// by axis; the cell size enters as h^2.
+// A workgroup takes a 16 x 4 x 4 tile of velocity nodes and first stages the
+// pressure values of the lattice window its nodes read (11 x 5 x 5 points,
+// 0 off the lattice) in LDS.
+constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 4;
+__global__ __launch_bounds__(kGradTX * kGradTY * kGradTZ) void k_grad_uniform(int64_t n, DevPressure P,
+                                                                            const double* __restrict__ p,
+                                                                            double* __restrict__ uo) {
+  constexpr int NT = kGradTX * kGradTY * kGradTZ;
+  constexpr int WX = kGradTX / 2 + 3, WY = kGradTY / 2 + 3, WZ = kGradTZ / 2 + 3;
+  __shared__ double sp[WZ * WY * WX];
+  const int64_t m = 2 * n + 1, np1 = n + 1;
+  const int64_t ntx = (m + kGradTX - 1) / kGradTX, nty = (m + kGradTY - 1) / kGradTY;
+  const int64_t tile = blockIdx.x;
+  const int64_t X0 = (tile % ntx) * kGradTX, Y0 = ((tile / ntx) % nty) * kGradTY, Z0 = (tile / (ntx * nty)) * kGradTZ;
+  // the first window point of each axis: the lowest P0 = (X - 1) / 2 of the
+  // tile's interior nodes
+  const int64_t q0[3] = {X0 > 0 ? (X0 - 1) / 2 : 0, Y0 > 0 ? (Y0 - 1) / 2 : 0, Z0 > 0 ? (Z0 - 1) / 2 : 0};
+  for (int e = threadIdx.x; e < WX * WY * WZ; e += NT) {
+    const int64_t px = q0[0] + e % WX, py = q0[1] + (e / WX) % WY, pz = q0[2] + e / (WX * WY);
+    sp[e] = px < np1 && py < np1 && pz < np1 ? p[P.plat[px + np1 * (py + np1 * pz)]] : 0.0;
+  }
+  __syncthreads();
   const double h2 = 1.0 / double(n * n);
-  for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t X[3] = {v % m, (v / m) % m, v / (m * m)};
-    if (X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == m - 1 || X[1] == m - 1 || X[2] == m - 1) continue;
-    int64_t p0[3];
-    double wm[3][3], wg[3][3];
+  const int64_t X[3] = {X0 + int(threadIdx.x) % kGradTX, Y0 + (int(threadIdx.x) / kGradTX) % kGradTY,
+                        Z0 + int(threadIdx.x) / (kGradTX * kGradTY)};
+  if (X[0] >= m || X[1] >= m || X[2] >= m) return;
+  if (X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == m - 1 || X[1] == m - 1 || X[2] == m - 1) return;
+  int o[3];   // window offset of the node's first pressure point per axis
+  double wm[3][3], wg[3][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      p0[d] = (X[d] - 1) / 2;
-      if (X[d] & 1) {
-        wm[d][0] = 1.0 / 3.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
-        wg[d][0] = 2.0 / 3.0, wg[d][1] = -2.0 / 3.0, wg[d][2] = 0.0;
-      } else {
-        wm[d][0] = 0.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
-        wg[d][0] = 1.0 / 6.0, wg[d][1] = 0.0, wg[d][2] = -1.0 / 6.0;
-      }
+  for (int d = 0; d < 3; ++d) {
+    o[d] = int((X[d] - 1) / 2 - q0[d]);
+    if (X[d] & 1) {
+      wm[d][0] = 1.0 / 3.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
+      wg[d][0] = 2.0 / 3.0, wg[d][1] = -2.0 / 3.0, wg[d][2] = 0.0;
+    } else {
+      wm[d][0] = 0.0, wm[d][1] = 1.0 / 3.0, wm[d][2] = 0.0;
+      wg[d][0] = 1.0 / 6.0, wg[d][1] = 0.0, wg[d][2] = -1.0 / 6.0;
     }
-    // the window's values (the third point of an odd coordinate may lie past
-    // the lattice: clamped, weight 0)
-    double zm[3][3], zg[3][3];   // contracted along z with mass / derivative weights
+  }
+  double zm[3][3], zg[3][3];   // contracted along z with mass / derivative weights
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zm[b][a] = zg[b][a] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) zm[b][a] = zg[b][a] = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t pz = p0[2] + c < np1 ? p0[2] + c : n;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int64_t py = p0[1] + b < np1 ? p0[1] + b : n;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int64_t px = p0[0] + a < np1 ? p0[0] + a : n;
-          const double val = p[P.plat[px + np1 * (py + np1 * pz)]];
-          zm[b][a] += wm[2][c] * val;
-          zg[b][a] += wg[2][c] * val;
-        }
+      for (int a = 0; a < 3; ++a) {
+        const double val = sp[(o[2] + c) * (WY * WX) + (o[1] + b) * WX + o[0] + a];
+        zm[b][a] += wm[2][c] * val;
+        zg[b][a] += wg[2][c] * val;
       }
-    }
-    double ymm[3], ygm[3], ymg[3];   // then along y: (y, z) weights mass/mass, deriv/mass, mass/deriv
+  double ymm[3], ygm[3], ymg[3];   // then along y: (y, z) weights mass/mass, deriv/mass, mass/deriv
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      ymm[a] = wm[1][0] * zm[0][a] + wm[1][1] * zm[1][a] + wm[1][2] * zm[2][a];
-      ygm[a] = wg[1][0] * zm[0][a] + wg[1][1] * zm[1][a] + wg[1][2] * zm[2][a];
-      ymg[a] = wm[1][0] * zg[0][a] + wm[1][1] * zg[1][a] + wm[1][2] * zg[2][a];
-    }
-    const double g0 = wg[0][0] * ymm[0] + wg[0][1] * ymm[1] + wg[0][2] * ymm[2];
-    const double g1 = wm[0][0] * ygm[0] + wm[0][1] * ygm[1] + wm[0][2] * ygm[2];
-    const double g2 = wm[0][0] * ymg[0] + wm[0][1] * ymg[1] + wm[0][2] * ymg[2];
-    uo[3 * v] -= h2 * g0, uo[3 * v + 1] -= h2 * g1, uo[3 * v + 2] -= h2 * g2;
+  for (int a = 0; a < 3; ++a) {
+    ymm[a] = wm[1][0] * zm[0][a] + wm[1][1] * zm[1][a] + wm[1][2] * zm[2][a];
+    ygm[a] = wg[1][0] * zm[0][a] + wg[1][1] * zm[1][a] + wg[1][2] * zm[2][a];
+    ymg[a] = wm[1][0] * zg[0][a] + wm[1][1] * zg[1][a] + wm[1][2] * zg[2][a];
   }
+  const double g0 = wg[0][0] * ymm[0] + wg[0][1] * ymm[1] + wg[0][2] * ymm[2];
+  const double g1 = wm[0][0] * ygm[0] + wm[0][1] * ygm[1] + wm[0][2] * ygm[2];
+  const double g2 = wm[0][0] * ymg[0] + wm[0][1] * ymg[1] + wm[0][2] * ymg[2];
+  const int64_t v = X[0] + m * (X[1] + m * X[2]);
+  uo[3 * v] -= h2 * g0, uo[3 * v + 1] -= h2 * g1, uo[3 * v + 2] -= h2 * g2;
+}
+unsigned grad_uniform_tiles(int64_t n) {
+  const int64_t m = 2 * n + 1;
+  return unsigned(((m + kGradTX - 1) / kGradTX) * ((m + kGradTY - 1) / kGradTY) * ((m + kGradTZ - 1) / kGradTZ));
 }
 
 // M_p p on a uniform leaf of n^3 cells, one thread per Q1 lattice point (no
@@ -1954,7 +1971,7 @@ void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double
 }
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
   if (L.uniform) {
-    k_grad_uniform<<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, P, p, uo);
+    k_grad_uniform<<<grad_uniform_tiles(L.n_edge), kGradTX * kGradTY * kGradTZ, 0, s>>>(L.n_edge, P, p, uo);
   } else if (L.blk4.n || L.blk2.n) {
     double* fs = L.fslot_d;
     if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo, fs);
