@@ -103,27 +103,28 @@ void launch_vmult(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init 
 void launch_diag(const DevLevel& L, const double* khat_full_dev, double* d, hipStream_t s);
 void launch_invert_diag(const DevLevel& L, const double* d, double* minv_d, float* minv_f, hipStream_t s);
 
-// Chebyshev updates (see smoother in api.hip).  With p.tn set the update also
-// prepares the output of the next operator call on a level whose operator
-// starts with an initialisation kernel: tn = (constrained ? src : 0), src the
-// new d (or the new x when from_x); that call is then launch_vmult_prepared.
-// ntype: the level's node types (general levels), else null and m = 2n + 1
-// (uniform levels).
+// Chebyshev updates in the residual-recurrence form of Saad's Alg. 12.1
+// (r -= t; d = alpha d + beta minv r; x += d), used by the learned-scaling
+// fit and the pressure Chebyshev map.
+template <typename T>
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double inv_theta, hipStream_t s);
+template <typename T>
+void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double inv_theta,
+                      hipStream_t s);
+template <typename T>
+void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
+                      hipStream_t s);
+// With p.tn set, the smoother's updates (launch_chebx_*) also prepare the
+// output of the next operator call on a level whose operator starts with an
+// initialisation kernel: tn = (constrained ? src : 0), src the new x (from_x)
+// or the new d; that call is then launch_vmult_prepared.  ntype: the level's
+// node types (general levels), else null and m = 2n + 1 (uniform levels).
 struct ChebPrep {
   void* tn = nullptr;
   const uint8_t* ntype = nullptr;
   int64_t m = 0;
   bool from_x = false;
 };
-template <typename T>
-void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double inv_theta, hipStream_t s,
-                       const ChebPrep& p = ChebPrep());
-template <typename T>
-void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double inv_theta,
-                      hipStream_t s, const ChebPrep& p = ChebPrep());
-template <typename T>
-void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
-                      hipStream_t s, const ChebPrep& p = ChebPrep());
 // the smoother's form (residual b - A x formed each step, r not stored):
 // init0 from x = 0; step: d = alpha d + beta minv (b - t), x += d (alpha = 0:
 // d is not read).  p prepares t for the next operator call on x (from_x).

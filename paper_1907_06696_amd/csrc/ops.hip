@@ -577,13 +577,13 @@ __global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ nt
 }
 
 // ------------------------------------------------------------- Chebyshev
-// The Chebyshev updates can also prepare the output of the next operator call
-// on levels whose operator otherwise starts with an initialisation kernel
-// (k_init_out_*): tn = (constrained dof ? src : 0), src being the new d, or
-// the new x when from_x.  Constrained: ntype != 0 on general levels (ntype
-// given), a boundary node of the m^3 lattice on uniform ones.  tn may be t
-// itself (each entry is read before it is written, by the same thread; t and
-// tn are therefore not restrict).
+// The smoother's Chebyshev updates (k_chebx_*) can also prepare the output of
+// the next operator call on levels whose operator otherwise starts with an
+// initialisation kernel (k_init_out_*): tn = (constrained dof ? src : 0), src
+// being the new d, or the new x when from_x.  Constrained: ntype != 0 on
+// general levels (ntype given), a boundary node of the m^3 lattice on uniform
+// ones.  tn may be t itself (each entry is read before it is written, by the
+// same thread; t and tn are therefore not restrict).
 template <typename T>
 struct OutPrep {
   T* tn;
@@ -604,7 +604,7 @@ __device__ __forceinline__ void out_prep(const OutPrep<T>& o, int64_t i, T di, T
 
 template <typename T>
 __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __restrict__ minv, T* __restrict__ r,
-                             T* __restrict__ d, T* __restrict__ x, T it, OutPrep<T> o) {
+                             T* __restrict__ d, T* __restrict__ x, T it) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -613,13 +613,12 @@ __global__ void k_cheb_init0(int64_t n, const T* __restrict__ b, const T* __rest
     r[i] = bi;
     d[i] = di;
     x[i] = di;
-    out_prep(o, i, di, di);
   }
 }
 
 template <typename T>
-__global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* t, const T* __restrict__ minv,
-                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it, OutPrep<T> o) {
+__global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* __restrict__ t, const T* __restrict__ minv,
+                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T it) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -629,13 +628,12 @@ __global__ void k_cheb_init(int64_t n, const T* __restrict__ b, const T* t, cons
     r[i] = ri;
     d[i] = di;
     x[i] = xi;
-    out_prep(o, i, di, xi);
   }
 }
 
 template <typename T>
-__global__ void k_cheb_step(int64_t n, const T* t, const T* __restrict__ minv, T* __restrict__ r,
-                            T* __restrict__ d, T* __restrict__ x, T alpha, T beta, OutPrep<T> o) {
+__global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restrict__ minv, T* __restrict__ r,
+                            T* __restrict__ d, T* __restrict__ x, T alpha, T beta) {
   // XCD-contiguous ranges: t was just written by the operator in the same order
   for (int64_t i = brick::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -645,7 +643,6 @@ __global__ void k_cheb_step(int64_t n, const T* t, const T* __restrict__ minv, T
     r[i] = ri;
     d[i] = di;
     x[i] = xi;
-    out_prep(o, i, di, xi);
   }
 }
 
@@ -1822,19 +1819,17 @@ OutPrep<T> out_prep_of(const ChebPrep& p) {
   return o;
 }
 template <typename T>
-void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double it, hipStream_t s,
-                       const ChebPrep& p) {
-  k_cheb_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, r, d, x, T(it), out_prep_of<T>(p));
+void launch_cheb_init0(int64_t n, const T* b, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
+  k_cheb_init0<T><<<grid_for(n), kBlock, 0, s>>>(n, b, minv, r, d, x, T(it));
 }
 template <typename T>
-void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double it, hipStream_t s,
-                      const ChebPrep& p) {
-  k_cheb_init<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, r, d, x, T(it), out_prep_of<T>(p));
+void launch_cheb_init(int64_t n, const T* b, const T* t, const T* minv, T* r, T* d, T* x, double it, hipStream_t s) {
+  k_cheb_init<T><<<grid_for(n), kBlock, 0, s>>>(n, b, t, minv, r, d, x, T(it));
 }
 template <typename T>
 void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, double alpha, double beta,
-                      hipStream_t s, const ChebPrep& p) {
-  k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta), out_prep_of<T>(p));
+                      hipStream_t s) {
+  k_cheb_step<T><<<grid_for(n), kBlock, 0, s>>>(n, t, minv, r, d, x, T(alpha), T(beta));
 }
 template <typename T>
 void launch_chebx_init0(int64_t n, const T* b, const T* minv, T* d, T* x, double it, hipStream_t s,
@@ -1854,13 +1849,10 @@ template void launch_chebx_step<float>(int64_t, const float*, const float*, cons
                                        double, hipStream_t, const ChebPrep&);
 template void launch_chebx_step<double>(int64_t, const double*, const double*, const double*, double*, double*,
                                         double, double, hipStream_t, const ChebPrep&);
-#define MFGMG_INST_CHEB(T)                                                                                      \
-  template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t,              \
-                                     const ChebPrep&);                                                          \
-  template void launch_cheb_init<T>(int64_t, const T*, const T*, const T*, T*, T*, T*, double, hipStream_t,     \
-                                    const ChebPrep&);                                                           \
-  template void launch_cheb_step<T>(int64_t, const T*, const T*, T*, T*, T*, double, double, hipStream_t,       \
-                                    const ChebPrep&);
+#define MFGMG_INST_CHEB(T)                                                                                   \
+  template void launch_cheb_init0<T>(int64_t, const T*, const T*, T*, T*, T*, double, hipStream_t);          \
+  template void launch_cheb_init<T>(int64_t, const T*, const T*, const T*, T*, T*, T*, double, hipStream_t); \
+  template void launch_cheb_step<T>(int64_t, const T*, const T*, T*, T*, T*, double, double, hipStream_t);
 MFGMG_INST_CHEB(float)
 MFGMG_INST_CHEB(double)
 
