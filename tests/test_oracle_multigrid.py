@@ -108,3 +108,38 @@ def test_vcycle_factor_h_independent():
         rhos.append(rho)
     assert max(rhos) < 0.3
     assert rhos[-1] < rhos[-2] * 1.25
+
+
+def test_chebyshev_residual_form_matches_recurrence():
+    """The device smoother forms the residual as b - A x at every step instead
+    of by the recurrence r -= A d of Saad's Alg. 12.1; in exact arithmetic the
+    iterates are the same.  Written out here in that form, it agrees with the
+    oracle's recurrence to rounding, from x = 0 and from a given x."""
+    rg = np.random.default_rng(12)
+    n = 60
+    Q = rg.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    minv = 1.0 / np.diag(A)
+    b = rg.standard_normal(n)
+    lam = 1.2 * np.linalg.eigvals(minv[:, None] * A).real.max()
+
+    def residual_form(x0, zero):
+        lo = lam / 15.0
+        theta, delta = 0.5 * (lam + lo), 0.5 * (lam - lo)
+        sigma = theta / delta
+        rho = 1.0 / sigma
+        x = np.zeros(n) if zero else x0.copy()
+        d = minv * (b - A @ x) / theta
+        x = x + d
+        for _ in range(3):
+            rho_new = 1.0 / (2.0 * sigma - rho)
+            d = rho_new * rho * d + (2.0 * rho_new / delta) * (minv * (b - A @ x))
+            x = x + d
+            rho = rho_new
+        return x
+
+    x0 = rg.standard_normal(n)
+    for zero in (True, False):
+        ref = mg.chebyshev(lambda v: A @ v, minv, b, x0, lam, degree=4, x_is_zero=zero)
+        got = residual_form(x0, zero)
+        assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref), zero
