@@ -2182,9 +2182,10 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
 template <typename T>
 void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
                            const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s) {
-  if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
+  // (the passes index nodes with 32-bit integers: levels up to 512^3 cells)
+  const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
+  if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge && mc * mf * mf < (int64_t(1) << 31)) {
     const int nc = int(Cc.n_edge);
-    const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
     k_restrict_x<T><<<grid_for(mc * mf * mf), kBlock, 0, s>>>(nc, b, t, s1);
     k_restrict_y<T><<<grid_for(mc * mc * mf), kBlock, 0, s>>>(nc, s1, s2);
     k_restrict_z<T><<<grid_for(mc * mc * mc), kBlock, 0, s>>>(nc, s2, xc);
