@@ -2116,6 +2116,11 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_cg_pmass_uniform(
 
 void launch_cg_setup(double* sc, double tol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, tol2); }
 
+// workgroups of the CG vector kernels: every workgroup of the next kernel
+// sums all their partials, so few partials keep that read small (the vectors
+// are short: a pressure field)
+constexpr int kCgBlocks = 256;
+
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
                                double* z, double* p, double* p_alt, double* q, double* part, double* sc, int k,
                                hipStream_t s) {
@@ -2123,7 +2128,7 @@ void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const do
   if (L.uniform && P.plat && int64_t(pmass_uniform_tiles(L.n_edge)) + 2 * kRedBlocks <= kRedPartWords) {
     // p_k lives in p for even k, in p_alt for odd k; k_cg_update's partials
     // at part[0, 2g), the tiles' p.q partials after 2 kRedBlocks
-    const unsigned g = grid_for(n, kBlock, kRedBlocks), nt = pmass_uniform_tiles(L.n_edge);
+    const unsigned g = grid_for(n, kBlock, kCgBlocks), nt = pmass_uniform_tiles(L.n_edge);
     const int par = k & 1;
     double* pk = par ? p_alt : p;
     const double* pprev = par ? p : p_alt;
@@ -2135,10 +2140,10 @@ void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const do
   }
   // q is zero here: cleared by the setup, then by the previous iteration
   launch_pmass_add(L, P, p, q, s, sc + 5);
-  k_dot_partial<<<kRedBlocks, kBlock, 0, s>>>(n, p, q, part);
-  const unsigned g = grid_for(n, kBlock, kRedBlocks);
+  k_dot_partial<<<kCgBlocks, kBlock, 0, s>>>(n, p, q, part);
+  const unsigned g = grid_for(n, kBlock, kCgBlocks);
   const int par = k & 1;
-  k_cg_update<<<g, kBlock, 0, s>>>(n, kRedBlocks, part, sc, par, false, p, q, minv, x, r, z, part + kRedBlocks);
+  k_cg_update<<<g, kBlock, 0, s>>>(n, kCgBlocks, part, sc, par, false, p, q, minv, x, r, z, part + kRedBlocks);
   k_cg_pupdate<<<g, kBlock, 0, s>>>(n, int(g), part + kRedBlocks, sc, par, z, p, q);
 }
 void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hipStream_t s) {
