@@ -62,49 +62,6 @@ struct UniformCell {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ void gather3(int32_t s, int a, const T* __restrict__ x, const int64_t* __restrict__ hptr,
-                                        const int32_t* __restrict__ hm, const T* __restrict__ hw, T (&U)[3][27]) {
-  if (s >= 0) {
-    U[0][a] = x[3 * int64_t(s)];
-    U[1][a] = x[3 * int64_t(s) + 1];
-    U[2][a] = x[3 * int64_t(s) + 2];
-  } else if (s == -1) {
-    U[0][a] = U[1][a] = U[2][a] = T(0);
-  } else {
-    const int64_t h = -int64_t(s) - 2;
-    T v0 = T(0), v1 = T(0), v2 = T(0);
-    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
-      const int64_t mm = 3 * int64_t(hm[q]);
-      const T w = hw[q];
-      v0 += w * x[mm];
-      v1 += w * x[mm + 1];
-      v2 += w * x[mm + 2];
-    }
-    U[0][a] = v0, U[1][a] = v1, U[2][a] = v2;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void scatter3(int32_t s, int a, T* __restrict__ y, const int64_t* __restrict__ hptr,
-                                         const int32_t* __restrict__ hm, const T* __restrict__ hw,
-                                         const T (&U)[3][27]) {
-  if (s >= 0) {
-    atomic_add(&y[3 * int64_t(s)], U[0][a]);
-    atomic_add(&y[3 * int64_t(s) + 1], U[1][a]);
-    atomic_add(&y[3 * int64_t(s) + 2], U[2][a]);
-  } else if (s < -1) {
-    const int64_t h = -int64_t(s) - 2;
-    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
-      const int64_t mm = 3 * int64_t(hm[q]);
-      const T w = hw[q];
-      atomic_add(&y[mm], w * U[0][a]);
-      atomic_add(&y[mm + 1], w * U[1][a]);
-      atomic_add(&y[mm + 2], w * U[2][a]);
-    }
-  }
-}
-
 // ------------------------------------------------------------- vmult
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_out_uniform(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
@@ -129,32 +86,10 @@ __global__ __launch_bounds__(256) void k_init_out_general(int64_t nn, const uint
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCellBlock) void k_vmult_uniform(int64_t n, const T* __restrict__ mu,
-                                                              const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (c >= n * n * n) return;
-  const UniformCell cell(n, c);
-  T U[3][27];
-  int32_t sl[27];
-#pragma unroll
-  for (int z = 0; z < 3; ++z)
-#pragma unroll
-    for (int yy = 0; yy < 3; ++yy)
-#pragma unroll
-      for (int xx = 0; xx < 3; ++xx) {
-        const int a = xx + 3 * yy + 9 * z;
-        sl[a] = cell.slot(xx, yy, z);
-        gather3<T>(sl[a], a, x, nullptr, nullptr, nullptr, U);
-      }
-  cellop::apply_cell<T>(U, mu[c] / T(n));
-#pragma unroll
-  for (int a = 0; a < 27; ++a) scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
-}
-
-// The same operator with three threads per cell, one per output component:
-// on the small levels below the brick kernel the grid is a few waves and the
-// time is the per-thread chain of the cell operator, about 2.5x shorter here.
+// The operator on a uniform level below the brick kernel's sizes, three
+// threads per cell, one per output component: there the grid is a few waves
+// and the time is the per-thread chain of the cell operator, about 2.5x
+// shorter than with one thread per cell.
 // Block: 64 cells x 3 components (wave c holds component c); each thread
 // interpolates its component to the Gauss points, the 81 values are shared
 // through LDS, and each thread produces its component's 27 outputs.
@@ -257,36 +192,79 @@ struct BrickShape<double> {
   static constexpr int BX = 8, BY = 4, BZ = 4;
 };
 
+// The single cells of a non-uniform level (those in no block): the cell
+// operator with three threads per cell, one velocity component each (a wave
+// per component, as k_vmult_uniform3), hanging nodes resolved through the
+// level's constraint rows (HANG).  A thread gathers,
+// interpolates and scatters its component's 27 values and computes its
+// component's row of the cell operator from all three interpolated
+// components, exchanged through LDS.  The single cells are few, so the kernel
+// is latency-bound; this cuts each thread's chain of dependent loads,
+// arithmetic and atomics to about a third.
+template <typename T>
+__device__ __forceinline__ T gather1(int32_t s, int comp, const T* __restrict__ x, const int64_t* __restrict__ hptr,
+                                     const int32_t* __restrict__ hm, const T* __restrict__ hw) {
+  if (s >= 0) return x[3 * int64_t(s) + comp];
+  if (s == -1) return T(0);
+  const int64_t h = -int64_t(s) - 2;
+  T v = T(0);
+  for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) v += hw[q] * x[3 * int64_t(hm[q]) + comp];
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void scatter1(int32_t s, int comp, T v, T* __restrict__ y, const int64_t* __restrict__ hptr,
+                                         const int32_t* __restrict__ hm, const T* __restrict__ hw) {
+  if (s >= 0) {
+    atomic_add(&y[3 * int64_t(s) + comp], v);
+  } else if (s < -1) {
+    const int64_t h = -int64_t(s) - 2;
+    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) atomic_add(&y[3 * int64_t(hm[q]) + comp], hw[q] * v);
+  }
+}
 template <typename T, bool HANG>
-__global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __restrict__ cells, int64_t ncells,
-                                                              const int32_t* __restrict__ slots,
-                                                              const int8_t* __restrict__ clev,
-                                                              const T* __restrict__ mu,
-                                                              const int64_t* __restrict__ hptr,
-                                                              const int32_t* __restrict__ hm,
-                                                              const T* __restrict__ hw, const T* __restrict__ x,
-                                                              T* __restrict__ y) {
-  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (t >= ncells) return;
-  const int64_t c = cells[t];
-  T U[3][27];
+__global__ __launch_bounds__(192) void k_vmult_general3(const int32_t* __restrict__ cells, int64_t ncells,
+                                                        const int32_t* __restrict__ slots,
+                                                        const int8_t* __restrict__ clev, const T* __restrict__ mu,
+                                                        const int64_t* __restrict__ hptr,
+                                                        const int32_t* __restrict__ hm, const T* __restrict__ hw,
+                                                        const T* __restrict__ x, T* __restrict__ y) {
+  __shared__ T wsh[3][27][64];
+  const int lane = threadIdx.x & 63;
+  const int comp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int64_t t = blockIdx.x * int64_t(64) + lane;
+  const bool live = t < ncells;
+  const int64_t c = live ? cells[t] : 0;   // a dead lane works on cell 0 and writes nothing
   int32_t sl[27];
+  T w[27];
 #pragma unroll
   for (int a = 0; a < 27; ++a) {
     sl[a] = slots[27 * c + a];
     if constexpr (HANG)
-      gather3<T>(sl[a], a, x, hptr, hm, hw, U);
+      w[a] = gather1<T>(sl[a], comp, x, hptr, hm, hw);
     else
-      gather3<T>(sl[a], a, x, nullptr, nullptr, nullptr, U);
+      w[a] = sl[a] >= 0 ? x[3 * int64_t(sl[a]) + comp] : T(0);
   }
-  const T h = T(ldexp(1.0, -int(clev[c])));
-  cellop::apply_cell<T>(U, mu[c] * h);
+  cellop::interp_all(w);
+#pragma unroll
+  for (int a = 0; a < 27; ++a) wsh[comp][a][lane] = w[a];
+  __syncthreads();
+  T W[3][27];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int a = 0; a < 27; ++a) W[cc][a] = wsh[cc][a][lane];
+  const T mu_h = mu[c] * T(ldexp(1.0, -int(clev[c])));
+  if (comp == 0) cellop::apply_cell_row<0>(W, w, mu_h);
+  else if (comp == 1) cellop::apply_cell_row<1>(W, w, mu_h);
+  else cellop::apply_cell_row<2>(W, w, mu_h);
+  cellop::interp_all_t(w);
+  if (!live) return;
 #pragma unroll
   for (int a = 0; a < 27; ++a) {
     if constexpr (HANG)
-      scatter3<T>(sl[a], a, y, hptr, hm, hw, U);
-    else
-      scatter3<T>(sl[a], a, y, nullptr, nullptr, nullptr, U);
+      scatter1<T>(sl[a], comp, w[a], y, hptr, hm, hw);
+    else if (sl[a] >= 0)
+      atomic_add(&y[3 * int64_t(sl[a]) + comp], w[a]);
   }
 }
 
@@ -301,8 +279,9 @@ __global__ __launch_bounds__(kCellBlock) void k_vmult_general(const int32_t* __r
 // gather interpolates them from the staged masters and the write-back first
 // distributes their accumulated values onto the masters (LDS atomics; few
 // points).  Nodes strictly inside a block belong to its cells alone and are
-// stored; nodes on its faces are added with global atomics.  LDS layout per
-// block and component: every axis split into even then odd lattice points.
+// stored; the values of its free face nodes go to the block's face slots
+// and k_face_gather adds each node's slots into y.  LDS layout per block and
+// component: every axis split into even then odd lattice points.
 template <int B>
 __device__ __forceinline__ int bsplit(int l) {
   return (l & 1) ? (B + 1) + (l >> 1) : (l >> 1);
@@ -1765,10 +1744,10 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
     else k_vmult_blocks<T, 2, true><<<g, 64, 0, s>>>(L.blk2, L.clev, mu_of<T>(L), x, y, fs2);
   }
   if (L.n_single_reg)
-    k_vmult_general<T, false><<<unsigned((L.n_single_reg + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+    k_vmult_general3<T, false><<<unsigned((L.n_single_reg + 63) / 64), 192, 0, s>>>(
         L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
   if (L.n_single_hang)
-    k_vmult_general<T, true><<<unsigned((L.n_single_hang + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(
+    k_vmult_general3<T, true><<<unsigned((L.n_single_hang + 63) / 64), 192, 0, s>>>(
         L.single_hang, L.n_single_hang, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
   if (L.n_face)
     k_face_gather<T><<<grid_for(L.n_face), kBlock, 0, s>>>(L.n_face, L.face_node, L.face_ptr, L.face_ent, fs, y);
