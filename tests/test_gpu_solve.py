@@ -133,6 +133,52 @@ def test_vmult_full_size_64():
     assert np.abs(y - ref32).max() <= 1e-5 * scale
 
 
+def test_pressure_operators_full_size_64():
+    """Closed forms at the benchmark's 64^3 uniform leaf (the tiled M_p and B^T
+    kernels): M_p applied to the constant 1 gives, at each pressure node, the
+    sum over the cells around it of h^3 / (8 mu_K) (each Q1 basis function
+    integrates to h^3 / 8 per cell); B^T applied to a constant pressure
+    vanishes at every free velocity node (-int div phi = 0 for a basis function
+    that vanishes on the boundary)."""
+    cfg = inputs.CONFIGS["uniform64"]
+    s = mfgmg.Solver(cfg["base_level"])
+    s.finalize_mesh()
+    info = s.info()
+    L = info["L"]
+    cen = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    s.set_viscosity(inputs.sinker_mu(qp, cen, cfg["dr"]).reshape(-1, 27))
+    mu = s.cell_viscosity(L)
+    cells = s.cells(L).astype(np.int64)
+    pk = s.support_points(L, field=1)
+    types = s.node_types(L)
+    npp, nu = info["n_p"], info["n_u"][L]
+    S = 2 ** (L + 1)
+    h = 1.0 / 2 ** L
+    order = np.argsort(pk)
+    expected = np.zeros(npp)
+    for dz in (0, 2):
+        for dy in (0, 2):
+            for dx in (0, 2):
+                key = (2 * cells[:, 1] + dx) + (S + 1) * ((2 * cells[:, 2] + dy) + (S + 1) * (2 * cells[:, 3] + dz))
+                idx = order[np.searchsorted(pk, key, sorter=order)]
+                assert np.array_equal(pk[idx], key)
+                np.add.at(expected, idx, h ** 3 / (8.0 * mu))
+    one = torch.ones(npp, dtype=torch.float64, device=DEV)
+    mp1 = torch.empty(npp, dtype=torch.float64, device=DEV)
+    s.apply_pmass(one, mp1)
+    g1 = torch.empty(nu, dtype=torch.float64, device=DEV)
+    s.apply_grad(one, g1)
+    torch.cuda.synchronize()
+    s.close()
+    e_mass = rel_err(mp1.cpu().numpy(), expected)
+    free = np.repeat(types == 0, 3)
+    e_grad = np.abs(g1.cpu().numpy()[free]).max() / h ** 2
+    print(f"  64^3: M_p 1 rel err {e_mass:.2e}, max |B^T 1| on free dofs / h^2 {e_grad:.2e}", flush=True)
+    assert e_mass <= 1e-13
+    assert e_grad <= 1e-13
+
+
 def test_uniform_transfers_full_size():
     """Transfers between the large uniform levels of the 64^3 hierarchy (64 ->
     32 -> 16 cells per edge; restriction by one-axis passes, prolongation by
