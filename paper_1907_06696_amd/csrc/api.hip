@@ -1339,19 +1339,14 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       schur_cheb(rhs);
       return;
     }
-    (void)hipMemcpyAsync(cr, rhs, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    launch_fill(np, 0.0, cx, s);
-    const double bn = std::sqrt(dot_sync(ctx, np, rhs, rhs, s));
-    if (bn == 0.0) return;
-    launch_mul(np, ctx->pmass_minv, cr, cz, s);
-    (void)hipMemcpyAsync(cp, cz, size_t(np) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    // the iterations run with their scalars on the device; the host looks at
-    // the stopping flag every kCgBatch iterations
+    // the iterations run with their scalars on the device (no host
+    // synchronisation before the first check); the host looks at the
+    // stopping flag every kCgBatch iterations
+    launch_cg_start(np, rhs, ctx->pmass_minv, cr, cz, cp, cx, cq, s);
     double* sc = ctx->red_res + 480;
-    launch_dot(np, cr, cz, ctx->red_part, sc, s);   // sc[0] = r.z
-    const double tol = o.schur_rtol * bn;
-    launch_cg_setup(sc, tol * tol, s);
-    launch_fill(np, 0.0, cq, s);
+    launch_dot(np, cr, cz, ctx->red_part, sc, s);       // sc[0] = r.z
+    launch_dot(np, cr, cr, ctx->red_part, sc + 7, s);   // sc[7] = r.r
+    launch_cg_setup(sc, o.schur_rtol * o.schur_rtol, s);
     constexpr int kCgBatch = 8;
     for (int base = 0; base < o.schur_max_iter; base += kCgBatch) {
       const int kk = std::min(kCgBatch, o.schur_max_iter - base);

@@ -227,7 +227,12 @@ void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, 
 // leaves sc[5] for the next one to set); the iteration count in sc[6] is the
 // same on both paths.
 constexpr int64_t kRedPartWords = 256 * 256;
-void launch_cg_setup(double* sc, double tol2, hipStream_t s);
+// start vectors: r = rhs, z = p = minv rhs, x = q = 0
+void launch_cg_start(int64_t n, const double* rhs, const double* minv, double* r, double* z, double* p, double* x,
+                     double* q, hipStream_t s);
+// scalars: sc[0] must hold r.z and sc[7] r.r of the start residual; the
+// threshold on r.r becomes rtol2 r.r (a zero r is done at once)
+void launch_cg_setup(double* sc, double rtol2, hipStream_t s);
 void launch_cg_pmass_iteration(const DevLevel& L, const DevPressure& P, const double* minv, double* x, double* r,
                                double* z, double* p, double* p_alt, double* q, double* part, double* sc, int k,
                                hipStream_t s);

@@ -2000,8 +2000,23 @@ void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, 
 // order in every block), so an iteration is M_p p, p.q, and two vector
 // kernels; the second also clears q for the next M_p p.
 namespace {
-__global__ __launch_bounds__(kBlock) void k_cg_setup(double* sc, double tol2) {
-  if (threadIdx.x == 0) sc[1] = 0.0, sc[4] = tol2, sc[5] = 0.0, sc[6] = 0.0, sc[7] = 0.0;
+// sc[7] holds r.r of the start residual (the right-hand side): the stopping
+// threshold is rtol2 r.r, and a zero right-hand side is done at once (x = 0)
+__global__ __launch_bounds__(kBlock) void k_cg_setup(double* sc, double rtol2) {
+  if (threadIdx.x == 0) {
+    const double rr = sc[7];
+    sc[1] = 0.0, sc[4] = rtol2 * rr, sc[5] = rr == 0.0 ? 1.0 : 0.0, sc[6] = 0.0;
+  }
+}
+// r = rhs, z = p = minv rhs, x = q = 0
+__global__ __launch_bounds__(kBlock) void k_cg_start(int64_t n, const double* __restrict__ rhs,
+                                                    const double* __restrict__ minv, double* __restrict__ r,
+                                                    double* __restrict__ z, double* __restrict__ p,
+                                                    double* __restrict__ x, double* __restrict__ q) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double ri = rhs[i], zi = minv[i] * ri;
+    r[i] = ri, z[i] = zi, p[i] = zi, x[i] = 0.0, q[i] = 0.0;
+  }
 }
 // sum of part[0, np) in every thread of the block
 __device__ __forceinline__ double block_sum_all(int np, const double* __restrict__ part) {
@@ -2093,7 +2108,11 @@ __global__ __launch_bounds__(kPmTX * kPmTY * kPmTZ) void k_cg_pmass_uniform(
 }
 }  // namespace
 
-void launch_cg_setup(double* sc, double tol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, tol2); }
+void launch_cg_start(int64_t n, const double* rhs, const double* minv, double* r, double* z, double* p, double* x,
+                     double* q, hipStream_t s) {
+  k_cg_start<<<grid_for(n), kBlock, 0, s>>>(n, rhs, minv, r, z, p, x, q);
+}
+void launch_cg_setup(double* sc, double rtol2, hipStream_t s) { k_cg_setup<<<1, kBlock, 0, s>>>(sc, rtol2); }
 
 // workgroups of the CG vector kernels: every workgroup of the next kernel
 // sums all their partials, so few partials keep that read small (the vectors
