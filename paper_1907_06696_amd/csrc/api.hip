@@ -1383,8 +1383,8 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   // triangular) or V(v_u) (block diagonal)
   auto precondition = [&](const double* v, double* z) {
     schur(v + nu);
-    (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (o.block == MFGMG_BLOCK_TRIANGULAR) launch_grad_add(lv, P, cx, tu, s);
+    if (o.block == MFGMG_BLOCK_TRIANGULAR) launch_grad_from(lv, P, cx, v, tu, s);
+    else (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (fp64) {
       if (vexec) {
         (void)hipGraphLaunch(vexec, s);

@@ -211,6 +211,9 @@ struct DevPressure {
 };
 void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* p_out, hipStream_t s);
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* u_out, hipStream_t s);
+// u_out = src + B^T p (src and u_out distinct)
+void launch_grad_from(const DevLevel& L, const DevPressure& P, const double* p, const double* src, double* u_out,
+                      hipStream_t s);
 // p_out = M_p p; gate (device, may be null): when *gate != 0 the cell kernel is skipped
 void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, double* p_out, hipStream_t s,
                   const double* gate = nullptr);

@@ -1265,9 +1265,13 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
 // A workgroup takes a 16 x 4 x 4 tile of velocity nodes and first stages the
 // pressure values of the lattice window its nodes read (11 x 5 x 5 points,
 // 0 off the lattice) in LDS.
+// FROM: uo = src + B^T p (every node written; src may not alias uo),
+// otherwise uo += B^T p.
 constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 4;
+template <bool FROM>
 __global__ __launch_bounds__(kGradTX * kGradTY * kGradTZ) void k_grad_uniform(int64_t n, DevPressure P,
                                                                             const double* __restrict__ p,
+                                                                            const double* __restrict__ src,
                                                                             double* __restrict__ uo) {
   constexpr int NT = kGradTX * kGradTY * kGradTZ;
   constexpr int WX = kGradTX / 2 + 3, WY = kGradTY / 2 + 3, WZ = kGradTZ / 2 + 3;
@@ -1288,7 +1292,11 @@ __global__ __launch_bounds__(kGradTX * kGradTY * kGradTZ) void k_grad_uniform(in
   const int64_t X[3] = {X0 + int(threadIdx.x) % kGradTX, Y0 + (int(threadIdx.x) / kGradTX) % kGradTY,
                         Z0 + int(threadIdx.x) / (kGradTX * kGradTY)};
   if (X[0] >= m || X[1] >= m || X[2] >= m) return;
-  if (X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == m - 1 || X[1] == m - 1 || X[2] == m - 1) return;
+  const int64_t v = X[0] + m * (X[1] + m * X[2]);
+  if (X[0] == 0 || X[1] == 0 || X[2] == 0 || X[0] == m - 1 || X[1] == m - 1 || X[2] == m - 1) {
+    if (FROM) uo[3 * v] = src[3 * v], uo[3 * v + 1] = src[3 * v + 1], uo[3 * v + 2] = src[3 * v + 2];
+    return;
+  }
   int o[3];   // window offset of the node's first pressure point per axis
   double wm[3][3], wg[3][3];
 #pragma unroll
@@ -1327,8 +1335,12 @@ __global__ __launch_bounds__(kGradTX * kGradTY * kGradTZ) void k_grad_uniform(in
   const double g0 = wg[0][0] * ymm[0] + wg[0][1] * ymm[1] + wg[0][2] * ymm[2];
   const double g1 = wm[0][0] * ygm[0] + wm[0][1] * ygm[1] + wm[0][2] * ygm[2];
   const double g2 = wm[0][0] * ymg[0] + wm[0][1] * ymg[1] + wm[0][2] * ymg[2];
-  const int64_t v = X[0] + m * (X[1] + m * X[2]);
-  uo[3 * v] -= h2 * g0, uo[3 * v + 1] -= h2 * g1, uo[3 * v + 2] -= h2 * g2;
+  if (FROM) {
+    uo[3 * v] = src[3 * v] - h2 * g0, uo[3 * v + 1] = src[3 * v + 1] - h2 * g1;
+    uo[3 * v + 2] = src[3 * v + 2] - h2 * g2;
+  } else {
+    uo[3 * v] -= h2 * g0, uo[3 * v + 1] -= h2 * g1, uo[3 * v + 2] -= h2 * g2;
+  }
 }
 unsigned grad_uniform_tiles(int64_t n) {
   const int64_t m = 2 * n + 1;
@@ -1940,9 +1952,20 @@ void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double
     k_div<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, P, nullptr, L.ncell, u, po);
   }
 }
+void launch_grad_from(const DevLevel& L, const DevPressure& P, const double* p, const double* src, double* uo,
+                      hipStream_t s) {
+  if (L.uniform) {
+    k_grad_uniform<true><<<grad_uniform_tiles(L.n_edge), kGradTX * kGradTY * kGradTZ, 0, s>>>(L.n_edge, P, p, src,
+                                                                                              uo);
+    return;
+  }
+  (void)hipMemcpyAsync(uo, src, size_t(3 * L.nnode) * sizeof(double), hipMemcpyDeviceToDevice, s);
+  launch_grad_add(L, P, p, uo, s);
+}
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
   if (L.uniform) {
-    k_grad_uniform<<<grad_uniform_tiles(L.n_edge), kGradTX * kGradTY * kGradTZ, 0, s>>>(L.n_edge, P, p, uo);
+    k_grad_uniform<false><<<grad_uniform_tiles(L.n_edge), kGradTX * kGradTY * kGradTZ, 0, s>>>(L.n_edge, P, p,
+                                                                                               nullptr, uo);
   } else if (L.blk4.n || L.blk2.n) {
     double* fs = L.fslot_d;
     if (L.blk4.n) k_grad_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, p, uo, fs);
