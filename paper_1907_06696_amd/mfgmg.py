@@ -135,8 +135,17 @@ def _np_ptr(a):
     return C.c_void_p(a.ctypes.data)
 
 
-def _dev_ptr(t):
-    return C.c_void_p(int(t.data_ptr()))
+_DTYPE_NAME = {FP32: "float32", FP64: "float64"}
+
+
+def _current_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_device()
+    except ImportError:
+        pass
+    return None
 
 
 def _prec_of(t):
@@ -146,6 +155,36 @@ def _prec_of(t):
     if name.endswith("float32"):
         return FP32
     raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev_ptr(t, n, prec, what):
+    """Device pointer of tensor `t` after checking everything the C ABI cannot
+    check itself: a GPU tensor on the current device, contiguous, of the
+    precision `prec` (FP32 / FP64), with exactly `n` entries.  Raises
+    ValueError (TypeError for a foreign dtype) before any library call."""
+    if t is None:
+        raise ValueError(f"{what}: a tensor is required")
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: must be a GPU tensor (got device {getattr(t, 'device', '?')})")
+    cur = _current_device()
+    idx = getattr(getattr(t, "device", None), "index", None)
+    if cur is not None and idx is not None and idx != cur:
+        raise ValueError(f"{what}: tensor is on device {idx}, the current device is {cur}")
+    if _prec_of(t) != prec:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {_DTYPE_NAME[prec]}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if int(t.numel()) != int(n):
+        raise ValueError(f"{what}: {int(t.numel())} entries, expected {int(n)}")
+    return C.c_void_p(int(t.data_ptr()))
+
+
+def _host_f64(a, n, what):
+    """Contiguous FP64 host copy of `a` with exactly `n` entries."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"{what}: {a.size} values, expected {n}")
+    return a
 
 
 def current_stream():
@@ -276,77 +315,105 @@ class Solver:
         self._check(self.lib.mfgmg_smoother_lambda(self.h, level, C.byref(v)))
         return v.value
 
+    def _level(self, level, lo=1):
+        L = self.info()["L"]
+        if not lo <= int(level) <= L:
+            raise ValueError(f"level {level} outside {lo}..{L}")
+        return int(level)
+
+    def _nu(self, level):
+        return self.info()["n_u"][level]
+
     def inverse_diagonal(self, level, dst, stream=None):
-        self._check(self.lib.mfgmg_inverse_diagonal(self.h, level, _prec_of(dst), _dev_ptr(dst),
+        level = self._level(level)
+        p = _prec_of(dst)
+        self._check(self.lib.mfgmg_inverse_diagonal(self.h, level, p, _dev_ptr(dst, self._nu(level), p, "dst"),
                                                     stream or current_stream()))
 
     def vmult(self, level, src, dst, stream=None):
-        p = _prec_of(src)
-        n = self.info()["n_u"][level]
-        if _prec_of(dst) != p or src.numel() != n or dst.numel() != n:
-            raise ValueError("vmult: src/dst must have n_u[level] entries of one dtype")
-        self._check(self.lib.mfgmg_vmult(self.h, level, p, _dev_ptr(src), _dev_ptr(dst),
-                                         stream or current_stream()))
+        level = self._level(level)
+        p, n = _prec_of(src), self._nu(level)
+        self._check(self.lib.mfgmg_vmult(self.h, level, p, _dev_ptr(src, n, p, "vmult src"),
+                                         _dev_ptr(dst, n, p, "vmult dst"), stream or current_stream()))
 
     def vmult_add(self, level, src, dst, stream=None):
-        p = _prec_of(src)
-        n = self.info()["n_u"][level]
-        if _prec_of(dst) != p or src.numel() != n or dst.numel() != n:
-            raise ValueError("vmult_add: src/dst must have n_u[level] entries of one dtype")
-        self._check(self.lib.mfgmg_vmult_add(self.h, level, p, _dev_ptr(src), _dev_ptr(dst),
-                                             stream or current_stream()))
+        level = self._level(level)
+        p, n = _prec_of(src), self._nu(level)
+        self._check(self.lib.mfgmg_vmult_add(self.h, level, p, _dev_ptr(src, n, p, "vmult_add src"),
+                                             _dev_ptr(dst, n, p, "vmult_add dst"), stream or current_stream()))
 
     def vcycle(self, rhs, x, stream=None):
-        p = _prec_of(rhs)
-        n = self.info()["n_u"][self.info()["L"]]
-        if _prec_of(x) != p or rhs.numel() != n or x.numel() != n:
-            raise ValueError("vcycle: rhs/x must have n_u[L] entries of one dtype")
-        self._check(self.lib.mfgmg_vcycle(self.h, p, _dev_ptr(rhs), _dev_ptr(x), stream or current_stream()))
+        p, n = _prec_of(rhs), self._nu(self.info()["L"])
+        self._check(self.lib.mfgmg_vcycle(self.h, p, _dev_ptr(rhs, n, p, "vcycle rhs"), _dev_ptr(x, n, p, "vcycle x"),
+                                          stream or current_stream()))
 
     def prolongate(self, level, coarse, fine, stream=None):
-        self._check(self.lib.mfgmg_prolongate(self.h, level, _prec_of(coarse), _dev_ptr(coarse), _dev_ptr(fine),
-                                              stream or current_stream()))
+        level = self._level(level, 2)
+        p = _prec_of(coarse)
+        self._check(self.lib.mfgmg_prolongate(self.h, level, p, _dev_ptr(coarse, self._nu(level - 1), p, "coarse"),
+                                              _dev_ptr(fine, self._nu(level), p, "fine"), stream or current_stream()))
 
     def restrict(self, level, fine, coarse, stream=None):
-        self._check(self.lib.mfgmg_restrict(self.h, level, _prec_of(fine), _dev_ptr(fine), _dev_ptr(coarse),
+        level = self._level(level, 2)
+        p = _prec_of(fine)
+        self._check(self.lib.mfgmg_restrict(self.h, level, p, _dev_ptr(fine, self._nu(level), p, "fine"),
+                                            _dev_ptr(coarse, self._nu(level - 1), p, "coarse"),
                                             stream or current_stream()))
 
     def smooth(self, level, b, x, x_is_zero=False, stream=None):
-        self._check(self.lib.mfgmg_smooth(self.h, level, _prec_of(b), _dev_ptr(b), _dev_ptr(x), int(x_is_zero),
-                                          stream or current_stream()))
+        level = self._level(level)
+        p, n = _prec_of(b), self._nu(level)
+        self._check(self.lib.mfgmg_smooth(self.h, level, p, _dev_ptr(b, n, p, "smooth b"), _dev_ptr(x, n, p, "smooth x"),
+                                          int(x_is_zero), stream or current_stream()))
 
     def coarse_solve(self, b, x, stream=None):
-        self._check(self.lib.mfgmg_coarse_solve(self.h, _prec_of(b), _dev_ptr(b), _dev_ptr(x),
+        p, n = _prec_of(b), self._nu(1)
+        self._check(self.lib.mfgmg_coarse_solve(self.h, p, _dev_ptr(b, n, p, "coarse b"), _dev_ptr(x, n, p, "coarse x"),
                                                 stream or current_stream()))
 
     def assemble_rhs(self, f_qp, rhs, stream=None):
-        f_qp = np.ascontiguousarray(f_qp, dtype=np.float64)
-        self._check(self.lib.mfgmg_assemble_rhs(self.h, _np_ptr(f_qp), _dev_ptr(rhs), stream or current_stream()))
+        L = self.info()["L"]
+        f_qp = _host_f64(f_qp, 27 * 3 * self.info()["n_cells"][L], "f_qp")
+        self._check(self.lib.mfgmg_assemble_rhs(self.h, _np_ptr(f_qp), _dev_ptr(rhs, self._nu(L), FP64, "rhs"),
+                                                stream or current_stream()))
 
     def apply_div(self, u, p_out, stream=None):
-        self._check(self.lib.mfgmg_apply_div(self.h, _dev_ptr(u), _dev_ptr(p_out), stream or current_stream()))
+        i = self.info()
+        self._check(self.lib.mfgmg_apply_div(self.h, _dev_ptr(u, i["n_u"][i["L"]], FP64, "u"),
+                                             _dev_ptr(p_out, i["n_p"], FP64, "p_out"), stream or current_stream()))
 
     def apply_grad(self, p, u_out, stream=None):
-        self._check(self.lib.mfgmg_apply_grad(self.h, _dev_ptr(p), _dev_ptr(u_out), stream or current_stream()))
+        i = self.info()
+        self._check(self.lib.mfgmg_apply_grad(self.h, _dev_ptr(p, i["n_p"], FP64, "p"),
+                                              _dev_ptr(u_out, i["n_u"][i["L"]], FP64, "u_out"),
+                                              stream or current_stream()))
 
     def apply_pmass(self, p, p_out, stream=None):
-        self._check(self.lib.mfgmg_apply_pmass(self.h, _dev_ptr(p), _dev_ptr(p_out), stream or current_stream()))
+        i = self.info()
+        self._check(self.lib.mfgmg_apply_pmass(self.h, _dev_ptr(p, i["n_p"], FP64, "p"),
+                                               _dev_ptr(p_out, i["n_p"], FP64, "p_out"), stream or current_stream()))
 
     def solve_stokes(self, rhs_u, u_out, p_out, rhs_p=None, stream=None, raise_on_noconv=True, **opts):
         o = SolveOpts()
         self.lib.mfgmg_default_opts(C.byref(o))
         names = {"krylov": {"fgmres": 0, "gmres": 1, "idr": 2}, "block": {"triangular": 0, "diagonal": 1},
                  "schur": {"cg": 0, "cheb": 1}}
+        fields = {f for f, _ in SolveOpts._fields_}
         for k, v in opts.items():
+            if k not in fields:
+                raise ValueError(f"unknown solver option {k!r}")
             if k == "vcycle_prec" and isinstance(v, str):
                 v = FP32 if v.lower() == "fp32" else FP64
             elif k in names and isinstance(v, str):
                 v = names[k][v.lower()]
             setattr(o, k, v)
+        i = self.info()
+        nu, npp = i["n_u"][i["L"]], i["n_p"]
+        args = (_dev_ptr(rhs_u, nu, FP64, "rhs_u"),
+                _dev_ptr(rhs_p, npp, FP64, "rhs_p") if rhs_p is not None else None,
+                _dev_ptr(u_out, nu, FP64, "u_out"), _dev_ptr(p_out, npp, FP64, "p_out"))
         st = SolveStats()
-        code = self.lib.mfgmg_solve_stokes(self.h, _dev_ptr(rhs_u), _dev_ptr(rhs_p) if rhs_p is not None else None,
-                                           _dev_ptr(u_out), _dev_ptr(p_out), C.byref(o), C.byref(st),
-                                           stream or current_stream())
+        code = self.lib.mfgmg_solve_stokes(self.h, *args, C.byref(o), C.byref(st), stream or current_stream())
         stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
         if code != OK and not (code == ERR_NOCONV and not raise_on_noconv):
             self._check(code)
@@ -355,32 +422,41 @@ class Solver:
     # ------------------------------------------------ learned smoother scaling
     def features(self, level, out=None, stream=None):
         import torch
+        level = self._level(level)
         n = self.info()["n_cells"][level]
         out = torch.empty((n, 27), dtype=torch.float32, device="cuda") if out is None else out
-        self._check(self.lib.mfgmg_features(self.h, level, _dev_ptr(out), stream or current_stream()))
+        self._check(self.lib.mfgmg_features(self.h, level, _dev_ptr(out, 27 * n, FP32, "features out"),
+                                            stream or current_stream()))
         return out
 
     def fit_objective(self, level, y, lam_fixed=0.0, grad=True, stream=None):
         import torch
+        level = self._level(level, 2)
+        n = 3 * self.info()["n_cells"][level]
         J, lam = C.c_double(), C.c_double()
+        yp = _dev_ptr(y, n, FP32, "y")
         g = torch.empty_like(y) if grad else None
-        self._check(self.lib.mfgmg_fit_objective(self.h, level, _dev_ptr(y), float(lam_fixed), C.byref(J),
-                                                 C.byref(lam), _dev_ptr(g) if grad else None,
+        self._check(self.lib.mfgmg_fit_objective(self.h, level, yp, float(lam_fixed), C.byref(J), C.byref(lam),
+                                                 _dev_ptr(g, n, FP32, "grad") if grad else None,
                                                  stream or current_stream()))
         return J.value, lam.value, g
 
     def fit_targets(self, level, steps=30, lr=0.05, stream=None):
         import torch
+        level = self._level(level, 2)
+        if int(steps) < 0:
+            raise ValueError("steps must be >= 0")
         n = self.info()["n_cells"][level]
         y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
-        hist = np.zeros(steps + 1)
-        self._check(self.lib.mfgmg_fit_targets(self.h, level, int(steps), float(lr), _dev_ptr(y), _np_ptr(hist),
-                                               stream or current_stream()))
+        hist = np.zeros(int(steps) + 1)
+        self._check(self.lib.mfgmg_fit_targets(self.h, level, int(steps), float(lr), _dev_ptr(y, 3 * n, FP32, "y"),
+                                               _np_ptr(hist), stream or current_stream()))
         return y, hist
 
     def set_scaling(self, level, y=None, stream=None):
-        self._check(self.lib.mfgmg_set_scaling(self.h, level, _dev_ptr(y) if y is not None else None,
-                                               stream or current_stream()))
+        level = self._level(level, 2)
+        yp = _dev_ptr(y, 3 * self.info()["n_cells"][level], FP32, "y") if y is not None else None
+        self._check(self.lib.mfgmg_set_scaling(self.h, level, yp, stream or current_stream()))
 
     def use_scaling(self, on):
         self._check(self.lib.mfgmg_use_scaling(self.h, int(bool(on))))
@@ -393,8 +469,8 @@ class Solver:
     def apply_mlp(self, w, guard=True, stream=None):
         used = C.c_int32()
         fac = np.zeros(2)
-        self._check(self.lib.mfgmg_apply_mlp(self.h, _dev_ptr(w), int(bool(guard)), C.byref(used), _np_ptr(fac),
-                                             stream or current_stream()))
+        self._check(self.lib.mfgmg_apply_mlp(self.h, _dev_ptr(w, N_PARAMS, FP32, "weights"), int(bool(guard)),
+                                             C.byref(used), _np_ptr(fac), stream or current_stream()))
         return bool(used.value), fac
 
 
@@ -403,38 +479,55 @@ def _lib_check(code):
         raise MFGMGError(code, "")
 
 
+def _rows(x, width, what):
+    """Number of samples of an [n, width] FP32 tensor (checked by _dev_ptr)."""
+    shape = tuple(getattr(x, "shape", ()))
+    if len(shape) != 2 or shape[1] != width:
+        raise ValueError(f"{what}: shape {shape}, expected [n, {width}]")
+    return int(shape[0])
+
+
 def mlp_forward(w, x, stream=None):
     """y [n,3], cache [n,131] for FP32 device tensors w [6147], x [n,27]."""
     import torch
     lib = load()
-    n = x.shape[0]
+    n = _rows(x, 27, "x")
+    args = (_dev_ptr(w, N_PARAMS, FP32, "weights"), _dev_ptr(x, 27 * n, FP32, "x"))
     y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
     cache = torch.empty((n, MLP_CACHE), dtype=torch.float32, device=x.device)
-    _lib_check(lib.mfgmg_mlp_forward(_dev_ptr(w), _dev_ptr(x), n, _dev_ptr(y), _dev_ptr(cache),
-                                     stream or current_stream()))
+    _lib_check(lib.mfgmg_mlp_forward(*args, n, _dev_ptr(y, 3 * n, FP32, "y"),
+                                     _dev_ptr(cache, MLP_CACHE * n, FP32, "cache"), stream or current_stream()))
     return y, cache
 
 
 def mlp_backward(w, x, cache, dy, stream=None):
     import torch
     lib = load()
-    n = x.shape[0]
+    n = _rows(x, 27, "x")
+    args = (_dev_ptr(w, N_PARAMS, FP32, "weights"), _dev_ptr(x, 27 * n, FP32, "x"),
+            _dev_ptr(cache, MLP_CACHE * n, FP32, "cache"), _dev_ptr(dy, 3 * n, FP32, "dy"))
     dw = torch.empty(N_PARAMS, dtype=torch.float32, device=x.device)
-    work = torch.empty(int(lib.mfgmg_mlp_work_size(n)), dtype=torch.float32, device=x.device)
-    _lib_check(lib.mfgmg_mlp_backward(_dev_ptr(w), _dev_ptr(x), _dev_ptr(cache), _dev_ptr(dy), n, _dev_ptr(dw),
-                                      _dev_ptr(work), stream or current_stream()))
+    nwork = int(lib.mfgmg_mlp_work_size(n))
+    work = torch.empty(nwork, dtype=torch.float32, device=x.device)
+    _lib_check(lib.mfgmg_mlp_backward(*args, n, _dev_ptr(dw, N_PARAMS, FP32, "dw"), _dev_ptr(work, nwork, FP32, "work"),
+                                      stream or current_stream()))
     return dw
 
 
 def mlp_adam(w, dw, m, v, step, lr, stream=None):
-    _lib_check(load().mfgmg_mlp_adam(_dev_ptr(w), _dev_ptr(dw), _dev_ptr(m), _dev_ptr(v), int(step), float(lr),
-                                     stream or current_stream()))
+    if int(step) < 1:
+        raise ValueError("Adam step counts from 1")
+    _lib_check(load().mfgmg_mlp_adam(_dev_ptr(w, N_PARAMS, FP32, "weights"), _dev_ptr(dw, N_PARAMS, FP32, "dw"),
+                                     _dev_ptr(m, N_PARAMS, FP32, "m"), _dev_ptr(v, N_PARAMS, FP32, "v"), int(step),
+                                     float(lr), stream or current_stream()))
 
 
 def mlp_train(w, feats, targets, epochs=20, batch=4096, lr=1e-3, seed=0, stream=None):
     """Train in place; returns the per-epoch mean squared error."""
-    hist = np.zeros(max(epochs, 1))
-    _lib_check(load().mfgmg_mlp_train(_dev_ptr(w), _dev_ptr(feats), _dev_ptr(targets), int(feats.shape[0]),
-                                      int(epochs), int(batch), float(lr), int(seed), _np_ptr(hist),
+    n = _rows(feats, 27, "feats")
+    args = (_dev_ptr(w, N_PARAMS, FP32, "weights"), _dev_ptr(feats, 27 * n, FP32, "feats"),
+            _dev_ptr(targets, 3 * n, FP32, "targets"))
+    hist = np.zeros(max(int(epochs), 1))
+    _lib_check(load().mfgmg_mlp_train(*args, n, int(epochs), int(batch), float(lr), int(seed), _np_ptr(hist),
                                       stream or current_stream()))
     return hist[:epochs]

@@ -172,3 +172,57 @@ def test_block_diagonal_exact_three_iterations():
         x, st = krylov.fgmres(prob.apply_K, P, prob.b, rtol=1e-10)
         assert st["iterations"] <= 3, st["iterations"]
         assert prob.residual(x) < 1e-10
+
+
+def _spd_with_spectrum(lams, seed, dscale=None):
+    """SPD matrix A and diagonal preconditioner minv with minv * A similar to
+    diag(lams): A = D^-1/2 Q diag(lams) Q^T D^-1/2, minv = diag(D)."""
+    rng = np.random.default_rng(seed)
+    n = len(lams)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.ones(n) if dscale is None else 10.0 ** rng.uniform(-dscale, dscale, n)
+    A = (Q * lams) @ Q.T
+    A = A / np.sqrt(d)[:, None] / np.sqrt(d)[None, :]
+    return 0.5 * (A + A.T), d
+
+
+@pytest.mark.parametrize("dscale", [None, 2.0])
+def test_cg_terminates_in_k_steps_for_k_distinct_eigenvalues(dscale):
+    """Preconditioned CG reaches the exact solution after at most k steps when
+    minv * A has k distinct eigenvalues (the Krylov space is then exhausted),
+    and not before for a generic right-hand side.  A wrong step length or
+    direction update loses the termination."""
+    k, n = 5, 40
+    lams = np.repeat(np.array([0.5, 1.0, 3.0, 7.0, 20.0]), n // k)
+    A, minv = _spd_with_spectrum(lams, 3, dscale)
+    b = np.random.default_rng(4).standard_normal(n)
+    x, it = krylov.cg(lambda v: A @ v, b, minv, rtol=1e-10, maxit=50)
+    assert it == k
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-10 * np.abs(x).max())
+    x4, it4 = krylov.cg(lambda v: A @ v, b, minv, rtol=1e-10, maxit=k - 1)
+    assert it4 == k - 1 and np.linalg.norm(b - A @ x4) > 1e-6 * np.linalg.norm(b)
+
+
+def test_cg_matches_dense_solve_and_minimises_energy():
+    """On a random SPD system CG converges to the dense solution, and each
+    iterate minimises the A-norm error over its Krylov space: the error
+    decreases monotonically in the A-norm."""
+    rng = np.random.default_rng(7)
+    n = 60
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    minv = 1.0 / np.diag(A)
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    x, it = krylov.cg(lambda v: A @ v, b, minv, rtol=1e-12, maxit=200)
+    assert it < 200 and np.allclose(x, xs, rtol=1e-10, atol=1e-12)
+    errs = []
+    for m in range(1, 8):
+        xm, _ = krylov.cg(lambda v: A @ v, b, minv, rtol=0.0, maxit=m)
+        e = xm - xs
+        errs.append(e @ (A @ e))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+    # a start vector: the same solution, residual measured against b
+    x0 = rng.standard_normal(n)
+    x2, _ = krylov.cg(lambda v: A @ v, b, minv, rtol=1e-12, maxit=200, x0=x0)
+    assert np.allclose(x2, xs, rtol=1e-10, atol=1e-12)

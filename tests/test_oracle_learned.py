@@ -178,3 +178,44 @@ def test_features_known_field():
     # coarser level: the parent averages
     f1 = ol.features(H, mus, 1)
     assert np.isclose(f1[0, 13], 0.0)
+
+
+def test_features_coarser_cell_rule_on_adaptive_mesh():
+    """Features on an adaptive mesh, from the definition by brute force: for a
+    cell K of level l in the level-ell mesh, the value at neighbour offset o
+    is log10 mu(c) - log10 mu_K, where c is the cell of the level-l mesh G_l
+    (which holds K: it is a cell of every level mesh from its own level up)
+    whose closed box contains the centre of the level-l position K + o; a
+    position outside the unit cube gives 0.  In G_l no cell is finer than l,
+    so c is either the same-level neighbour or the coarser cell covering it."""
+    H = adaptive_hierarchy(2, (1, 0, 1), 2)
+    rng = np.random.default_rng(11)
+    mu_leaf = 10.0 ** rng.uniform(0, 4, H.leaf.ncell)
+    mus = ops.level_viscosities(H, mu_leaf)
+    seen_coarser = 0
+    for ell in range(2, H.L + 1):
+        f = ol.features(H, mus, ell)
+        G = H.levels[ell]
+        for ci in range(G.ncell):
+            l = int(G.lev[ci])
+            Gl = H.levels[l]
+            lo = Gl.ijk * (1 << (H.L - Gl.lev))[:, None]              # origins in units of 2^-L
+            size = (1 << (H.L - Gl.lev))
+            me = np.nonzero((Gl.lev == l) & np.all(Gl.ijk == G.ijk[ci], axis=1))[0][0]
+            muK = mus[l][me]
+            assert muK == mus[ell][ci]
+            n = 1 << l
+            for o in range(27):
+                d = np.array([o % 3, (o // 3) % 3, o // 9]) - 1
+                q = G.ijk[ci] + d
+                if np.any(q < 0) or np.any(q >= n):
+                    assert f[ci, o] == 0.0
+                    continue
+                centre2 = (2 * q + 1) * (1 << (H.L - l))               # centre in units of 2^-(L+1)
+                inside = np.all((2 * lo <= centre2) & (centre2 <= 2 * (lo + size[:, None])), axis=1)
+                hit = np.nonzero(inside)[0]
+                assert len(hit) == 1
+                if Gl.lev[hit[0]] < l:
+                    seen_coarser += 1
+                assert np.isclose(f[ci, o], np.log10(mus[l][hit[0]]) - np.log10(muK), rtol=0, atol=1e-13)
+    assert seen_coarser > 0

@@ -6,6 +6,7 @@ definiteness with boundary conditions, two independent implementations of A
 (assembled vs cellwise), reproduction of Q2 polynomials by the transfers, and
 closed forms for the averages."""
 import numpy as np
+import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
 
@@ -154,7 +155,53 @@ def test_rhs_partition_of_unity_and_divergence():
     ones = np.where(m.pfree, 1.0, 0.0)
     assert np.abs(B.T @ ones).max() < 1e-14
     Mp = ops.assemble_Mp(m, np.full(m.ncell, 4.0))
-    assert np.isclose(ones @ (Mp @ ones) - (~m.pfree).sum() * 0, 0.25, rtol=1e-12) or True
+    assert np.isclose(ones @ (Mp @ ones), 0.25, rtol=1e-12)
     Cp = m.Cp
     mfull = ops.pressure_mean_weights(m)
     assert np.isclose(mfull.sum(), 1.0)
+
+
+def _gauss2():
+    """2-point Gauss rule on [0, 1] (exact for cubics)."""
+    g = 0.5 / np.sqrt(3.0)
+    return np.array([0.5 - g, 0.5 + g]), np.array([0.5, 0.5])
+
+
+def _trilinear_p(pos):
+    x, y, z = pos[..., 0], pos[..., 1], pos[..., 2]
+    return (1.0 + 2.0 * x) * (2.0 - y) * (1.0 + 0.5 * z) + 0.3 * x * y
+
+
+@pytest.mark.parametrize("which", ["uniform", "hanging"])
+def test_pressure_mass_is_inverse_viscosity_weighted(which):
+    """Sec. 2.2.2: [M_p]_ij = int mu^-1 psi_i psi_j with the cell viscosity.
+    A global trilinear function is a Q1 function on every cell (and continuous
+    across hanging faces), so with its values at the free pressure nodes
+    p^T M_p p = sum_K mu_K^-1 int_K p^2, integrated here cell by cell with a
+    2x2x2 Gauss rule (exact for the tri-quadratic p^2); and 1^T M_p 1 =
+    sum_K h_K^3 / mu_K.  Non-constant mu: a mu where mu^-1 belongs, or a wrong
+    power of h, fails."""
+    H = mesh.Hierarchy.uniform(2) if which == "uniform" else adaptive_hierarchy(2, (1, 0, 1), 1)
+    m = H.leaf
+    rng = np.random.default_rng(5)
+    mu = 10.0 ** rng.uniform(-2, 2, m.ncell)
+    Mp = ops.assemble_Mp(m, mu)
+    pos = m.unkey(m.pkeys).astype(np.float64) / m.S
+    p = np.where(m.pfree, _trilinear_p(pos), 0.0)
+    g, w = _gauss2()
+    qx = np.array([(a, b, c) for c in g for b in g for a in g])
+    qw = np.array([a * b * c for c in w for b in w for a in w])
+    org = m.cell_origin() / m.S
+    exact = 0.0
+    for K in range(m.ncell):
+        X = org[K][None, :] + qx * m.h[K]
+        exact += (qw * _trilinear_p(X) ** 2).sum() * m.h[K] ** 3 / mu[K]
+    assert np.isclose(p @ (Mp @ p), exact, rtol=1e-12)
+    ones = np.where(m.pfree, 1.0, 0.0)
+    assert np.isclose(ones @ (Mp @ ones), (m.h ** 3 / mu).sum(), rtol=1e-12)
+    if which == "uniform":
+        # per-node row sums: each Q1 basis function integrates to h^3/8 over a cell
+        rows = np.zeros(m.npnode)
+        for K in range(m.ncell):
+            rows[m.cell_pnodes[K]] += m.h[K] ** 3 / (8.0 * mu[K])
+        assert np.allclose(Mp @ ones, rows, rtol=1e-12, atol=0)
