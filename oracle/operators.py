@@ -167,10 +167,17 @@ class CellwiseA:
         reg = ~has_hang
         d += np.bincount(self.dofs[reg].ravel(),
                          weights=(self.scale[reg, None] * kd[None, :]).ravel(), minlength=self.n)
-        for c in np.nonzero(has_hang)[0]:
-            Cl = self.Cu[self.dofs[c]]                     # [81, n] resolved local rows
-            KCl = sp.csr_matrix(self.scale[c] * _KHAT) @ Cl
-            d += np.asarray(Cl.multiply(KCl).sum(axis=0)).ravel()
+        # the same per-cell sum diag(C_l^T K_e C_l), taken for a batch of cells
+        # at once: stacked resolved rows G = [C_l1; C_l2; ...] and the block
+        # diagonal of their K_e give sum_cells diag(C_l^T K_e C_l) as the
+        # column sums of G .* (blockdiag(K_e) G)
+        hc = np.nonzero(has_hang)[0]
+        kh = sp.csr_matrix(_KHAT)
+        for s in range(0, len(hc), 2048):
+            cs = hc[s:s + 2048]
+            G = self.Cu[self.dofs[cs].ravel()]             # [81 nc, n] resolved local rows
+            KG = sp.kron(sp.diags(self.scale[cs]), kh, format='csr') @ G
+            d += np.asarray(G.multiply(KG).sum(axis=0)).ravel()
         return np.where(self.free, d, 1.0)
 
 

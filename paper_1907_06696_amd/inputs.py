@@ -3,8 +3,9 @@
 This module holds the *problem* definitions only (viscosity field, body
 force, refinement flags of the adaptive workloads, random test vectors).  It
 contains none of the solver's arithmetic (no basis, quadrature, operator or
-smoother) and imports nothing but numpy, so that both the device library's
-callers and the CPU oracle can draw the same inputs from it.
+smoother) and imports nothing but numpy and the standard library, so that
+both the device library's callers and the CPU oracle can draw the same inputs
+from it.
 
 Sinker benchmark (paper, Sec. 3.2, after May et al. and Rudi et al.):
     X(x)  = prod_i [1 - exp(-delta max(0, |c_i - x| - omega/2)^2)],
@@ -16,6 +17,9 @@ workloads use mu_min = 1, mu_max = DR, a global factor that leaves pressure,
 relative residuals and iteration counts unchanged (velocity scales by 1/c).
 Sinker centres are uniform in [0.1, 0.9]^3 from numpy's default generator.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 DELTA = 200.0
@@ -36,12 +40,37 @@ def _dist_terms(points, centres):
     return p, diff, r, s, e
 
 
-def sinker_chi(points, centres, chunk=1 << 20):
+def _chi_chunk(p, centres):
+    """X at the points p [m, 3]: the product over the sinkers in their order,
+    each factor 1 - exp(-delta max(0, |x - c_i| - omega/2)^2)."""
+    X = np.ones(len(p))
+    for c in centres:
+        d2 = (p[:, 0] - c[0]) ** 2 + (p[:, 1] - c[1]) ** 2 + (p[:, 2] - c[2]) ** 2
+        s = np.maximum(0.0, np.sqrt(d2) - OMEGA / 2.0)
+        X *= 1.0 - np.exp(-DELTA * s * s)
+    return X
+
+
+def _threads():
+    return max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+
+
+def sinker_chi(points, centres, chunk=1 << 18):
+    """X at the points, evaluated in chunks on a thread pool (numpy releases
+    the interpreter lock inside its array loops)."""
     p = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     out = np.empty(len(p))
-    for a in range(0, len(p), chunk):
-        _, _, _, _, e = _dist_terms(p[a:a + chunk], centres)
-        out[a:a + chunk] = np.prod(1.0 - e, axis=1)
+    starts = range(0, len(p), chunk)
+
+    def work(a):
+        out[a:a + chunk] = _chi_chunk(p[a:a + chunk], centres)
+
+    if len(p) <= chunk:
+        work(0)
+    else:
+        with ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(work, starts))
     return out
 
 

@@ -68,3 +68,32 @@ class Case:
 def rel_err(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def abs_bound(mesh, mu, x, chunk=65536):
+    """(|C|^T |K| |C| + Pi_c) |x| with |K| = sum over cells of mu_K h |K_hat|:
+    an entrywise upper bound of |A| |x| for A = C^T K C + Pi_c.  Rounding in
+    any evaluation order of A x is bounded row by row by a multiple of this
+    (the terms a computation gathers through the constraints and the cell
+    matrices), however small the row's viscosity is against the largest."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    Cu = abs(mesh.Cu())
+    kabs = np.abs(ops.khat())
+    dofs = mesh.cell_dofs()
+    scale = np.asarray(mu) * mesh.h
+    xf = Cu @ x
+    y = np.zeros(mesh.n_u)
+    for s in range(0, len(dofs), chunk):
+        d = dofs[s:s + chunk]
+        loc = xf[d] @ kabs.T * scale[s:s + chunk, None]
+        y += np.bincount(d.ravel(), weights=loc.ravel(), minlength=mesh.n_u)
+    return Cu.T @ y + np.where(mesh.free_dofs_mask(), 0.0, x)
+
+
+def row_err(a, b, bound):
+    """max_i |a_i - b_i| / bound_i over the rows with bound_i > 0 (rows whose
+    bound is 0 must match exactly)."""
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    pos = bound > 0
+    assert np.all(d[~pos] == 0)
+    return float((d[pos] / bound[pos]).max()) if pos.any() else 0.0

@@ -4,19 +4,32 @@ same seeded inputs, element by element.
 Tolerances (relative 2-norm unless stated): operator FP64 1e-12, FP32 1e-5
 (the FP32 input rounded once, oracle applied to the rounded input in FP64);
 V-cycle FP64 1e-11 (eight operator applications, transfers and the coarse
-solve per level compound round-off), FP32 1e-4; integer/structural data
-bit-exact."""
+solve per level compound round-off), FP32 1e-4; smoother FP64 1e-12, FP32
+1e-5; integer/structural data bit-exact.  Row by row, the operator's error
+is also bounded against (|C|^T |K| |C| + Pi_c)|x| (``abs_bound``): FP64
+ROW64, FP32 ROW32, so that rows of low-viscosity cells, 1e4-1e6 times
+smaller than the largest rows, are held to the same relative accuracy.
+
+The 32^3 case runs the uniform-level kernels used at full size (the brick
+operator with its halo pass, its accumulating form, the structured
+transfers) inside vmult, vmult_add, the smoother and the V-cycle."""
 import numpy as np
 import pytest
 
 from oracle import multigrid as omg, operators as ops
 from paper_1907_06696_amd import inputs
-from tests.parity_cases import Case, rel_err
+from tests.parity_cases import Case, abs_bound, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+# row-scaled bounds: u times a chain of about 32 roundings (gather through the
+# constraints, three interpolation and three derivative sweeps, the stress,
+# the transposed sweeps, the scatter over up to 8 cells) times a factor 10 for
+# intermediate values larger than the row bound (u = 2^-53 and 2^-24)
+ROW64 = 32 * 10 * 2.0 ** -53
+ROW32 = 32 * 10 * 2.0 ** -24
 
 
 def _need_gpu():
@@ -40,6 +53,7 @@ CASES = {
     "adaptive2+1": dict(base=2, corners=((1, 1, 1),), times=1),
     "adaptive2+2": dict(base=2, corners=((0, 1, 0),), times=2, dr=1e6),
     "adaptive3+2": dict(base=3, corners=((2, 5, 3), (0, 0, 0), (7, 7, 7)), times=2, dr=1e4, sinkers=6, seed=5),
+    "uniform5": dict(base=5, dr=1e4, sinkers=8, seed=2),
 }
 
 
@@ -70,12 +84,16 @@ def test_vmult_fp64_fp32(case, seed):
         perm = case.dof_perm(ell)
         x_lib = x_or[perm]
         A = case.gmg.A[ell]
+        mesh, mu = case.H.levels[ell], case.mus[ell]
         # FP64
         y = torch.empty(n, dtype=torch.float64, device=DEV)
         case.s.vmult(ell, to_dev(x_lib), y)
         ref = (A @ x_or)[perm]
-        e64 = rel_err(to_host(y), ref)
-        assert e64 <= 1e-12, (ell, e64)
+        yh = to_host(y)
+        e64 = rel_err(yh, ref)
+        r64 = row_err(yh, ref, abs_bound(mesh, mu, x_or)[perm])
+        print(f"[vmult] level {ell} seed {seed}: FP64 rel {e64:.2e} row {r64:.2e}", flush=True)
+        assert e64 <= 1e-12 and r64 <= ROW64, (ell, e64, r64)
         # FP32: oracle applied to the rounded input
         x32 = x_lib.astype(np.float32)
         y32 = torch.empty(n, dtype=torch.float32, device=DEV)
@@ -83,8 +101,11 @@ def test_vmult_fp64_fp32(case, seed):
         x32_or = np.empty(n)
         x32_or[perm] = x32.astype(np.float64)
         ref32 = (A @ x32_or)[perm]
-        e32 = rel_err(to_host(y32), ref32)
-        assert e32 <= 1e-5, (ell, e32)
+        yh32 = to_host(y32)
+        e32 = rel_err(yh32, ref32)
+        r32 = row_err(yh32, ref32, abs_bound(mesh, mu, x32_or)[perm])
+        print(f"[vmult] level {ell} seed {seed}: FP32 rel {e32:.2e} row {r32:.2e}", flush=True)
+        assert e32 <= 1e-5 and r32 <= ROW32, (ell, e32, r32)
 
 
 def test_vmult_zero_and_linearity(case):
@@ -107,19 +128,27 @@ def test_vmult_add_accumulates(case):
     """vmult_add adds the cell contributions to an arbitrary dst (every node,
     inside blocks and bricks as well as on their faces) and leaves the
     constrained entries unchanged; dst + (A x on free dofs) is what it must
-    give, on every level."""
+    give, on every level (the 32^3 case: the accumulating brick kernel)."""
     for ell in range(1, case.L + 1):
         n = case.info["n_u"][ell]
         perm = case.dof_perm(ell)
         free = case.gmg.free[ell][perm]
-        for dt, npt, tol in ((torch.float64, np.float64, 1e-12), (torch.float32, np.float32, 1e-5)):
+        mesh, mu = case.H.levels[ell], case.mus[ell]
+        for dt, npt, tol, rtol in ((torch.float64, np.float64, 1e-12, ROW64),
+                                   (torch.float32, np.float32, 1e-5, ROW32)):
             # inputs rounded to the working precision; reference in FP64 on the rounded values
             x_or = inputs.uniform_vector(n, 300 + ell).astype(npt).astype(np.float64)
             y0 = inputs.uniform_vector(n, 400 + ell).astype(npt).astype(np.float64)
             ref = y0 + np.where(free, (case.gmg.A[ell] @ x_or)[perm], 0.0)
             y = to_dev(y0, dt)
             case.s.vmult_add(ell, to_dev(x_or[perm], dt), y)
-            assert rel_err(to_host(y), ref) <= tol, (ell, dt)
+            yh = to_host(y)
+            # the sum's own rounding is relative to |y0| + |A||x|
+            bound = np.abs(y0) + np.where(free, abs_bound(mesh, mu, x_or)[perm], 0.0)
+            e, r = rel_err(yh, ref), row_err(yh, ref, bound)
+            print(f"[vmult_add] level {ell} {dt}: rel {e:.2e} row {r:.2e}", flush=True)
+            assert e <= tol and r <= rtol, (ell, dt, e, r)
+            assert np.array_equal(yh[~free], y0[~free])
 
 
 def test_inverse_diagonal_and_lambda(case):
@@ -154,15 +183,18 @@ def test_smoother_and_coarse(case):
     n = case.info["n_u"][ell]
     perm = case.dof_perm(ell)
     free = case.gmg.free[ell]
-    b = inputs.uniform_vector(n, 31) * free
-    x0 = inputs.uniform_vector(n, 32) * free
     A = case.gmg.A[ell]
-    for zero in (True, False):
-        ref = omg.chebyshev(lambda v: A @ v, case.gmg.minv[ell], b, None if zero else x0,
-                            case.gmg.lam[ell], x_is_zero=zero)
-        x = to_dev(x0[perm])
-        case.s.smooth(ell, to_dev(b[perm]), x, x_is_zero=zero)
-        assert rel_err(to_host(x), ref[perm]) <= 1e-12
+    for dt, npt, tol in ((torch.float64, np.float64, 1e-12), (torch.float32, np.float32, 1e-5)):
+        b = (inputs.uniform_vector(n, 31) * free).astype(npt).astype(np.float64)
+        x0 = (inputs.uniform_vector(n, 32) * free).astype(npt).astype(np.float64)
+        for zero in (True, False):
+            ref = omg.chebyshev(lambda v: A @ v, case.gmg.minv[ell], b, None if zero else x0,
+                                case.gmg.lam[ell], x_is_zero=zero)
+            x = to_dev(x0[perm], dt)
+            case.s.smooth(ell, to_dev(b[perm], dt), x, x_is_zero=zero)
+            e = rel_err(to_host(x), ref[perm])
+            print(f"[smooth] level {ell} {dt} from {'zero' if zero else 'x0'}: rel {e:.2e}", flush=True)
+            assert e <= tol, (dt, zero, e)
     b1 = inputs.uniform_vector(375, 33) * case.gmg.free[1]
     x1 = torch.empty(375, dtype=torch.float64, device=DEV)
     p1 = case.dof_perm(1)
@@ -179,10 +211,11 @@ def test_vcycle_fp64_fp32(case):
     x = torch.empty(n, dtype=torch.float64, device=DEV)
     case.s.vcycle(to_dev(b[perm]), x)
     e64 = rel_err(to_host(x), ref)
-    assert e64 <= 1e-11, e64
     x32 = torch.empty(n, dtype=torch.float32, device=DEV)
     case.s.vcycle(to_dev(b[perm], torch.float32), x32)
     e32 = rel_err(to_host(x32), ref)
+    print(f"[vcycle] L {ell}: FP64 rel {e64:.2e}, FP32 rel {e32:.2e}", flush=True)
+    assert e64 <= 1e-11, e64
     assert e32 <= 1e-4, e32
 
 
