@@ -1,15 +1,22 @@
-"""Benchmark: matrix-free Q2 viscous operator (vmult) throughput on one MI355X.
+"""Benchmark: matrix-free Q2 viscous operator throughput and Stokes solves on one MI355X.
 
-Workload (the 64^3 sinker configuration): unit cube, 64^3 uniform cells,
-Q2 velocity (6,440,067 dofs), 8 seeded sinkers (centre seed 2), viscosity
-contrast 1e4, operator applied to a seeded uniform[-1, 1] vector (seed 42).
-One step = 100 FP32 operator applications (the configuration's 100
-repetitions); `value` = velocity dofs processed per second over the timed
-steps, in GDoF/s.  Also reported beside it (not part of `value`): the FP64
-operator, one FP32/FP64 V-cycle, and the Stokes solve to 1e-8 with the FP32
-and the FP64 V-cycle inside FP64 FGMRES.
+Operator workload (the 64^3 sinker configuration): unit cube, 64^3 uniform
+cells, Q2 velocity (6,440,067 dofs), 8 seeded sinkers (centre seed 2),
+viscosity contrast 1e4, operator applied to seeded uniform[-1, 1] vectors
+(seeds 42, 43, ...).  One step = 100 FP64 operator applications (the
+configuration's 100 repetitions), cycling through 6 (x, y) vector pairs
+(618 MB, more than the 256 MB last-level cache, so every application reads x
+and writes y in HBM); `value` = velocity dofs processed per second over the
+timed steps, in GDoF/s.  Reported beside it (not part of `value`): the same
+with one pair (cache-warm), the FP32 operator (cold and warm), the cell loop
+alone, one FP32/FP64 V-cycle, and the Stokes solves to 1e-8 (FP64 FGMRES with
+the FP64 V-cycle, the FP32 V-cycle, and the FP32 V-cycle with the learned
+smoother scaling) on the 64^3 workload and on the adaptive 32^3 + 2 workload
+(16 sinkers, contrast 1e6).  The CPU leg times the oracle's operator and
+recomputes the FP64 residual of every solve with the oracle's cellwise
+operators.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-adaptive] [--no-cpu]
 """
 import argparse
 import json
@@ -23,7 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 REPS = 100                      # operator applications per step
+ROTATE = {"f64": 6, "f32": 8}   # (x, y) pairs cycled through: 618 MB / 412 MB > 256 MB cache
+PEAK_FP64_TFLOPS = 78.6         # MI355X FP64 vector, published
 PEAK_FP32_TFLOPS = 157.3        # MI355X FP32 vector (packed FMA), published
+PEAK_FP32_UNPACKED_TFLOPS = 78.6   # the rate without packed FP32 instructions, which this build does not use
 PEAK_HBM_GBS = 8000.0
 # Algorithmic work of the cell kernel per cell (sum factorisation as built,
 # counting an FMA as 2 flops): 810 (interpolation) + 972 (gradients) + 297
@@ -36,8 +46,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--no-solve", action="store_true")
-    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-solve", action="store_true", help="skip every Stokes solve")
+    p.add_argument("--no-adaptive", action="store_true", help="skip the adaptive 32^3 + 2 solves")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (oracle timing and residual checks)")
     p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
     p.add_argument("--solve-workload", choices=["adaptive32p2", "uniform128p1"], default=None,
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
@@ -46,61 +57,48 @@ def parse():
                    help="solves of --solve-workload, comma separated from fp64, fp32, fp32_learned, fp32_gmres, "
                         "fp32_idr2, fp64_idr2, fp32_diag (default: all on adaptive32p2; on uniform128p1 all but "
                         "fp32_idr2, which stalls near 1e-5 there, and fp32_diag, which needs ~4x the iterations)")
+    p.add_argument("--oracle-residual", action="store_true",
+                   help="with --solve-workload: recompute every solve's FP64 residual with the oracle")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                    help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE pass over "
                         "--counter-probe into profiles/vmult_counters_sinker64.json (no GPU needed)")
+    p.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV", default=None,
+                   help="print a markdown table of a rocprofv3 kernel trace: per kernel and grid, calls, mean, "
+                        "median and total duration, registers and LDS (no GPU needed)")
     p.add_argument("--counter-probe", action="store_true",
-                   help="only launch the operator (mfgmg_vmult, FP32: brick + halo kernels) and a plain copy of "
-                        "known size, 20 times each, for hardware-counter runs")
+                   help="only launch the operator (mfgmg_vmult: brick + halo kernels) 20 times in FP64 and 20 "
+                        "times in FP32 on rotating vector pairs, and a plain copy of known size 20 times, for "
+                        "hardware-counter runs")
     return p.parse_args()
 
 
 COPY_BYTES = 256 << 20          # the calibration copy: 256 MiB read + 256 MiB written
 
 
-def counter_probe(s, L, x32, y32):
-    """Kernels for a rocprofv3 --pmc pass: 20 operator applications (FP32) and
-    20 copies of COPY_BYTES, so that FETCH_SIZE / WRITE_SIZE per dispatch of
-    the operator's kernels can be scaled by what the same counters read for a
-    copy of known size."""
+def counter_probe(s, L, pairs):
+    """Kernels for a rocprofv3 --pmc pass: 20 operator applications per
+    precision on rotating pairs (as timed) and 20 copies of COPY_BYTES, so that
+    FETCH_SIZE / WRITE_SIZE per dispatch of the operator's kernels can be
+    scaled by what the same counters read for a copy of known size."""
     import torch
-    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=x32.device)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(20):
-        s.vmult(L, x32, y32)
+    for prec in ("f64", "f32"):
+        xs, ys = pairs[prec]
+        for r in range(20):
+            s.vmult(L, xs[r % len(xs)], ys[r % len(xs)])
     for _ in range(20):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"counter_probe": True, "copy_bytes": COPY_BYTES, "vmult_launches": 20}), flush=True)
-
-
-def cpu_baseline(level, centres, dr, seconds=12.0):
-    """The CPU oracle's cellwise FP64 operator on the same workload: applied
-    repeatedly to the same vector until about `seconds` have elapsed."""
-    from oracle import mesh as om, operators as ops
-    from paper_1907_06696_amd import inputs
-    lev, ijk = om.uniform_leaves(level)
-    m = om.LevelMesh(lev, ijk, level + 1)
-    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
-    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, centres, dr).reshape(-1, 27))
-    A = ops.CellwiseA(m, mu)
-    x = inputs.uniform_vector(m.n_u, 42)
-    A.matvec(x)
-    t0 = time.perf_counter()
-    reps = 0
-    while time.perf_counter() - t0 < seconds or reps < 2:
-        A.matvec(x)
-        reps += 1
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": m.n_u * reps / dt / 1e9, "unit": "GDoF/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} FP64 applications of the oracle's cellwise operator (numpy BLAS, "
-                      f"{threads} threads) on the full {1 << level}^3 mesh, {dt:.1f} s"}
+    print(json.dumps({"counter_probe": True, "copy_bytes": COPY_BYTES, "vmult_launches_per_precision": 20}),
+          flush=True)
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1907_06696_amd", "data", "mlp_sinker32.npz")
 COUNTERS = os.path.join(ROOT, "profiles", "vmult_counters_sinker64.json")
 KERNEL_SOURCES = ("brick_kernel.h", "cell_kernel.h")
+KERNEL_TAGS = {"f64": ("k_vmult_brick<double", "k_brick_halo_add<double"),
+               "f32": ("k_vmult_brick<float", "k_brick_halo_add<float")}
 
 
 def kernel_source_hash():
@@ -112,7 +110,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(level):
+def measured_traffic(level, prec):
     """HBM bytes per operator application from the committed FETCH_SIZE /
     WRITE_SIZE passes (scaled by the calibration copy), or None when the
     counters were taken on other kernel sources or another workload."""
@@ -121,9 +119,9 @@ def measured_traffic(level):
             c = json.load(f)
     except OSError:
         return None
-    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("level") != level:
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("level") != level or prec not in c:
         return None
-    return {"bytes": int(c["bytes_per_application"]), "source": os.path.relpath(COUNTERS, ROOT)}
+    return {"bytes": int(c[prec]["bytes_per_application"]), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 # outer-solver variants of Sec. 3.4 (V-cycle precision, options): plain GMRES
@@ -149,12 +147,14 @@ def krylov_vectors(kw, restart):
     return 2 * restart + 1 + 4
 
 
-def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
+def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50, keep=None,
                   variants=("fp64", "fp32", "fp32_learned", "fp32_gmres", "fp32_idr2", "fp64_idr2", "fp32_diag")):
     """Stokes solve to 1e-8 (FP64 FGMRES): plain FP64 V-cycle, FP32 V-cycle,
-    and FP32 V-cycle with the learned smoother scaling (installed with its
-    guard; a failed learned solve is redone plain and both costs counted);
-    then the outer-solver variants in SOLVER_VARIANTS."""
+    and FP32 V-cycle with the learned smoother scaling (installed behind its
+    guard, estimated with the FP64 V-cycle; a failed learned solve is redone
+    plain and both costs counted); then the outer-solver variants in
+    SOLVER_VARIANTS.  keep: dict that receives each solution (u, p) on the
+    host, for the oracle's residual check."""
     import torch
     from paper_1907_06696_amd import inputs
     info = s.info()
@@ -165,52 +165,57 @@ def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50,
     u = torch.empty(n, dtype=torch.float64, device="cuda")
     p = torch.empty(info["n_p"], dtype=torch.float64, device="cuda")
 
-    def one(prec, scaled, **kw):
+    def one(name, prec, scaled, **kw):
         if verbose:
-            print(f"[solve] {prec}{' + learned scaling' if scaled else ''} {kw}", file=sys.stderr, flush=True)
+            print(f"[solve] {name}: {prec}{' + learned scaling' if scaled else ''} {kw}", file=sys.stderr, flush=True)
         st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, use_scaling=int(scaled), raise_on_noconv=False,
                             max_iter=max_iter, verbose=verbose, restart=restart, **kw)
+        if keep is not None:
+            keep[name] = (u.cpu().numpy(), p.cpu().numpy())
         return {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
                 "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
                 "converged": bool(st["converged"]), "vectors": krylov_vectors(kw, restart)}
 
     out = {"restart": restart}
     if "fp64" in variants:
-        out["fp64"] = one("fp64", False)
+        out["fp64"] = one("fp64", "fp64", False)
     if "fp32" in variants or "fp32_learned" in variants:
-        out["fp32"] = one("fp32", False)
+        out["fp32"] = one("fp32", "fp32", False)
     for name, (prec, kw) in SOLVER_VARIANTS.items():
         if name in variants:
-            out[name] = one(prec, False, **kw)
+            out[name] = one(name, prec, False, **kw)
     if "fp32_learned" not in variants:
         return out
     w = torch.tensor(np.load(WEIGHTS)["weights"], device="cuda")
     t0 = time.perf_counter()
-    used, fac = s.apply_mlp(w, guard=True)
+    used, fac = s.apply_mlp(w, guard="fp64")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    lrn = one("fp32", True) if used else dict(out["fp32"])
-    if used and not lrn["converged"]:
-        again = one("fp32", False)
-        lrn = dict(again, seconds=round(lrn["seconds"] + again["seconds"], 3),
-                   iterations=lrn["iterations"] + again["iterations"], fallback=True)
+    if used:
+        lrn = one("fp32_learned", "fp32", True)
+        if not lrn["converged"]:
+            again = one("fp32_learned", "fp32", False)
+            lrn = dict(again, seconds=round(lrn["seconds"] + again["seconds"], 3),
+                       iterations=lrn["iterations"] + again["iterations"], fallback=True)
+    else:
+        lrn = dict(out["fp32"])
+        if keep is not None and "fp32" in keep:
+            keep["fp32_learned"] = keep["fp32"]
     lrn.update({"learned_used": used, "setup_s": round(t_setup, 3),
+                "seconds_with_setup": round(lrn["seconds"] + t_setup, 3),
                 "vcycle_factor_plain": round(float(fac[0]), 5), "vcycle_factor_learned": round(float(fac[1]), 5)})
     out["fp32_learned"] = lrn
     if "fp64" in out:
-        out["speedup_fp32_learned_vs_fp64"] = round(out["fp64"]["seconds"] / max(lrn["seconds"], 1e-9), 3)
+        out["speedup_fp32_vs_fp64"] = round(out["fp64"]["seconds"] / max(out["fp32"]["seconds"], 1e-9), 3)
+        out["speedup_fp32_learned_vs_fp64"] = round(out["fp64"]["seconds"] / max(lrn["seconds_with_setup"], 1e-9), 3)
+    out["speedup_fp32_learned_vs_fp32"] = round(out["fp32"]["seconds"] / max(lrn["seconds_with_setup"], 1e-9), 3)
     for lv in range(2, L + 1):
         s.set_scaling(lv, None)
     return out
 
 
-def solve_workload(name, variants, max_iter=3000):
-    """The adaptive 32^3 + 2 (16 sinkers, DR 1e6) and the 128^3 + 1
-    (32 sinkers, DR 1e6) sinker solves; one JSON line each.  FGMRES restarts
-    every 100 iterations here: at this contrast and sinker count restarts
-    every 50 stall (the 32^3 + 2 case stagnates near 4e-6 for thousands of
-    iterations; 60 needs twice the iterations), and 100 was the fastest of
-    80, 100 and 120 over both workloads."""
+def adaptive_solver(name):
+    """Library context of an adaptive workload with its viscosity set."""
     import torch
     from paper_1907_06696_amd import inputs, mfgmg
     cfg = inputs.CONFIGS[name]
@@ -220,53 +225,170 @@ def solve_workload(name, variants, max_iter=3000):
     cells = inputs.refinement_cells(cfg["base_level"], centres, cfg["dr"], cfg["refine_percentile"])
     s.refine(cells, cfg["refine_levels"])
     s.finalize_mesh()
-    info = s.info()
-    L = info["L"]
     qp = s.leaf_quadrature_points().reshape(-1, 3)
     s.set_viscosity(inputs.sinker_mu(qp, centres, cfg["dr"]).reshape(-1, 27))
     torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
+    return s, qp, centres, cells, time.perf_counter() - t0
+
+
+def solve_workload(name, variants, max_iter=3000, verbose=100, oracle_check=False):
+    """The adaptive 32^3 + 2 (16 sinkers, DR 1e6) and the 128^3 + 1
+    (32 sinkers, DR 1e6) sinker solves.  FGMRES restarts every 100 iterations
+    here: at this contrast and sinker count restarts every 50 stall (the
+    32^3 + 2 case stagnates near 4e-6 for thousands of iterations; 60 needs
+    twice the iterations), and 100 was the fastest of 80, 100 and 120 over
+    both workloads."""
+    s, qp, centres, cells, t_setup = adaptive_solver(name)
+    info = s.info()
+    L = info["L"]
     print(f"[{name}] L={L} cells={info['n_cells'][L]} n_u={info['n_u'][L]} n_p={info['n_p']} "
-          f"hanging={info['n_hanging'][L]} setup {t_setup:.1f} s", flush=True)
-    res = solve_compare(s, qp, centres, verbose=100, restart=100, variants=variants, max_iter=max_iter)
-    print(json.dumps({"workload": name, "cells": info["n_cells"][L], "velocity_dofs": info["n_u"][L],
-                      "pressure_dofs": info["n_p"], "levels": L, "setup_s": round(t_setup, 2),
-                      "stokes_solve_1e-8": res}), flush=True)
+          f"hanging={info['n_hanging'][L]} setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+    keep = {} if oracle_check else None
+    res = solve_compare(s, qp, centres, verbose=verbose, restart=100, variants=variants, max_iter=max_iter, keep=keep)
+    out = {"workload": name, "cells": info["n_cells"][L], "velocity_dofs": info["n_u"][L],
+           "pressure_dofs": info["n_p"], "levels": L, "setup_s": round(t_setup, 2), "stokes_solve_1e-8": res}
+    keys = (s.support_points(L, 0), s.support_points(L, 1))
     s.close()
+    return out, keep, keys, cells, centres
+
+
+# ------------------------------------------------------------------- CPU leg
+def oracle_operator_timing(level, centres, dr, seconds=12.0):
+    """The CPU oracle's cellwise FP64 operator on the same workload: applied
+    repeatedly to the same vector until about `seconds` have elapsed."""
+    from oracle import mesh as om, operators as ops
+    from paper_1907_06696_amd import inputs
+    lev, ijk = om.uniform_leaves(level)
+    m = om.LevelMesh(lev, ijk, level + 1)
+    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
+    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, centres, dr).reshape(-1, 27))
+    A = ops.CellwiseA(m, mu)
+    x = inputs.uniform_vector(m.n_u, 42)
+    A.matvec(x)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < seconds or reps < 2:
+        A.matvec(x)
+        reps += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": m.n_u * reps / dt / 1e9, "unit": "GDoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} FP64 applications of the oracle's cellwise operator (numpy BLAS, "
+                      f"{threads} threads) on the full {1 << level}^3 mesh, {dt:.1f} s"}
+
+
+def oracle_residuals(lev, ijk, centres, dr, keys, sols):
+    """FP64 relative residual ||b - K x|| / ||b|| of each device solution,
+    recomputed by the oracle's cellwise operators on its own mesh, viscosity
+    and right-hand side (vectors matched by canonical node keys)."""
+    from oracle import mesh as om, operators as ops
+    from paper_1907_06696_amd import inputs
+    t0 = time.perf_counter()
+    lev, ijk = om.morton_sort(np.asarray(lev, np.int64), np.asarray(ijk, np.int64))
+    m = om.LevelMesh(lev, ijk, int(lev.max()) + 1, with_pressure=True)
+    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
+    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, centres, dr).reshape(-1, 27))
+    b_u = ops.assemble_rhs(m, inputs.sinker_force(X, centres).reshape(-1, 27, 3))
+    ku, kp = keys
+    node = np.searchsorted(m.keys, ku)
+    pnode = np.searchsorted(m.pkeys, kp)
+    assert np.array_equal(m.keys[node], ku) and np.array_equal(m.pkeys[pnode], kp)
+    dof = (3 * node[:, None] + np.arange(3)[None, :]).ravel()
+    AB = (ops.CellwiseA(m, mu), ops.CellwiseB(m))
+    out = {}
+    for name, (u_lib, p_lib) in sols.items():
+        u = np.empty(m.n_u)
+        u[dof] = u_lib
+        p = np.empty(m.npnode)
+        p[pnode] = p_lib
+        out[name] = ops.stokes_residual(m, mu, b_u, u, p, ops_AB=AB)
+    return out, time.perf_counter() - t0
+
+
+def adaptive_leaves(cfg, cells):
+    from oracle import mesh as om
+    lev, ijk = om.uniform_leaves(cfg["base_level"])
+    mask = np.isin(om.cell_code(lev, ijk), om.cell_code(cells[:, 0], cells[:, 1:]))
+    lev, ijk = om.refine(lev, ijk, mask, cfg["refine_levels"])
+    return om.balance(lev, ijk)
+
+
+def cpu_leg(level, centres, dr, checks):
+    """The CPU baseline: the oracle's operator timed on the host cores, and
+    the oracle's FP64 residual of every device solution (not timed)."""
+    res = oracle_operator_timing(level, centres, dr)
+    out = {}
+    for name, (lev, ijk, cen, d, keys, sols) in checks.items():
+        r, dt = oracle_residuals(lev, ijk, cen, d, keys, sols)
+        out[name] = {k: float(f"{v:.3e}") for k, v in r.items()}
+        out[name]["oracle_seconds"] = round(dt, 1)
+    res["oracle_fp64_residual_of_device_solutions"] = out
+    return res
 
 
 def summarize_counters(fetch_csv, write_csv, level=6):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the operator's two
-    kernels at the 2^level mesh, each scaled by bytes / counter of the
-    calibration copy (the largest copy dispatches, COPY_BYTES read and
+    kernels at the 2^level mesh, per precision, each scaled by bytes / counter
+    of the calibration copy (the largest copy dispatches, COPY_BYTES read and
     written)."""
     import csv
     n = 1 << level
-    out = {"level": level, "kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES}
-    total = 0.0
+    out = {"level": level, "kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
+           "note": "operator applications on rotating vector pairs (618 MB FP64, 412 MB FP32)"}
+    scale = {}
+    rows = {}
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
-        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        rows[name] = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
+        copies = [r for r in rows[name] if "copyBuffer" in r["Kernel_Name"]]
         gmax = max(int(r["Grid_Size"]) for r in copies)
-        cal = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == gmax]
-        cal_kib = sorted(cal)[len(cal) // 2]
-        scale = COPY_BYTES / (cal_kib * 1024.0)
-        per = {}
-        for tag in ("k_vmult_brick<float", "k_brick_halo_add<float"):
-            v = [float(r["Counter_Value"]) for r in rows if tag in r["Kernel_Name"] and int(r["Grid_Size"]) == n ** 3]
-            per[tag.split("<")[0]] = {"dispatches": len(v), "kib_per_dispatch": sum(v) / max(len(v), 1)}
-        bytes_ = sum(d["kib_per_dispatch"] for d in per.values()) * 1024.0 * scale
-        out[name] = {"calibration_kib": cal_kib, "scale_bytes_per_counted_byte": scale, "kernels": per,
-                     "bytes_per_application": bytes_}
-        total += bytes_
-    out["bytes_per_application"] = total
+        cal = sorted(float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == gmax)
+        scale[name] = (cal[len(cal) // 2], COPY_BYTES / (cal[len(cal) // 2] * 1024.0))
+    for prec, tags in KERNEL_TAGS.items():
+        entry = {}
+        total = 0.0
+        for name in ("FETCH_SIZE", "WRITE_SIZE"):
+            per = {}
+            for tag in tags:
+                # the probe's 20 applications: the last 20 dispatches at the leaf's
+                # grid (set-up also applies the leaf operator, to estimate lambda)
+                v = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows[name]
+                           if tag in r["Kernel_Name"] and int(r["Grid_Size"]) in (n ** 3, 2 * n ** 3))[-20:]
+                per[tag.split("<")[0]] = {"dispatches": len(v), "kib_per_dispatch": sum(c for _, c in v) / max(len(v), 1)}
+            b = sum(d["kib_per_dispatch"] for d in per.values()) * 1024.0 * scale[name][1]
+            entry[name] = {"calibration_kib": scale[name][0], "scale_bytes_per_counted_byte": scale[name][1],
+                           "kernels": per, "bytes_per_application": b}
+            total += b
+        entry["bytes_per_application"] = total
+        out[prec] = entry
     with open(COUNTERS, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
 
+def summarize_trace(path, top=14):
+    """Markdown table of a rocprofv3 kernel trace grouped by (kernel, grid)."""
+    import csv
+    groups = {}
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"] or "(unnamed)"
+        name = name.replace("void ", "").split("(")[0].replace("mfgmg::", "").replace("(anonymous namespace)::", "")
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        g = groups.setdefault((name, grid), {"d": [], "vgpr": r["VGPR_Count"], "agpr": r["Accum_VGPR_Count"],
+                                             "lds": r["LDS_Block_Size"]})
+        g["d"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print("| kernel | grid | calls | mean us | median us | total ms | VGPR(+AGPR) | LDS B |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (name, grid), g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"]))[:top]:
+        d = sorted(g["d"])
+        print(f"| {name} | {grid} | {len(d)} | {sum(d) / len(d):.2f} | {d[len(d) // 2]:.2f} | {sum(d) / 1e3:.2f} | "
+              f"{g['vgpr']}+{g['agpr']} | {g['lds']} |")
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
         return
@@ -278,7 +400,16 @@ def main():
         if variants is None:
             skip = ("fp32_idr2", "fp32_diag") if args.solve_workload == "uniform128p1" else ()
             variants = ",".join(["fp64", "fp32", "fp32_learned"] + [v for v in SOLVER_VARIANTS if v not in skip])
-        solve_workload(args.solve_workload, variants.split(","), args.max_iter)
+        out, keep, keys, cells, centres = solve_workload(args.solve_workload, variants.split(","), args.max_iter,
+                                                         oracle_check=args.oracle_residual)
+        if args.oracle_residual:
+            from paper_1907_06696_amd import inputs
+            cfg = inputs.CONFIGS[args.solve_workload]
+            lev, ijk = adaptive_leaves(cfg, cells)
+            r, dt = oracle_residuals(lev, ijk, centres, cfg["dr"], keys, keep)
+            out["oracle_fp64_residual"] = {k: float(f"{v:.3e}") for k, v in r.items()}
+            out["oracle_seconds"] = round(dt, 1)
+        print(json.dumps(out), flush=True)
         return
     import torch
     from paper_1907_06696_amd import inputs, mfgmg
@@ -305,12 +436,13 @@ def main():
     t_assemble = time.perf_counter() - t0
     n = info["n_u"][L]
     ncell = info["n_cells"][L]
-    x64 = torch.tensor(inputs.uniform_vector(n, cfg["vector_seed"]), dtype=torch.float64, device=dev)
-    x32 = x64.float()
-    y32 = torch.empty_like(x32)
-    y64 = torch.empty_like(x64)
+    pairs = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        xs = [torch.tensor(inputs.uniform_vector(n, cfg["vector_seed"] + i), dtype=dt, device=dev)
+              for i in range(ROTATE[prec])]
+        pairs[prec] = (xs, [torch.empty_like(xs[0]) for _ in xs])
     if args.counter_probe:
-        counter_probe(s, L, x32, y32)
+        counter_probe(s, L, pairs)
         s.close()
         return
 
@@ -326,33 +458,56 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    def step32():
-        for _ in range(REPS):
-            s.vmult(L, x32, y32)
+    def op_step(prec, rotate, add=False):
+        xs, ys = pairs[prec]
+        k = [0]
+        f = s.vmult_add if add else s.vmult
 
-    def step64():
-        for _ in range(REPS):
-            s.vmult(L, x64, y64)
+        def step():
+            for r in range(REPS):
+                i = (k[0] + r) % len(xs) if rotate else 0
+                f(L, xs[i], ys[i])
+            k[0] += REPS
+        return step
 
-    # the timed region: K steps of 100 FP32 operator applications
-    t32 = timed(step32, args.steps, args.warmup)
-    ms_per_step = t32 / args.steps * 1e3
-    value = n * REPS * args.steps / t32 / 1e9
-    t64 = timed(step64, max(2, args.steps // 4), 1)
-    gdofs64 = n * REPS * max(2, args.steps // 4) / t64 / 1e9
-    # roofline of the operator application timed above (one mfgmg_vmult call =
-    # the owner-computes brick kernel + the halo-add kernel, HIP events on the
-    # stream they are launched on)
-    vmult_call_s = t32 / (REPS * args.steps)
-    kernel_s = vmult_call_s
+    # the timed region: K steps of 100 FP64 operator applications on rotating pairs
+    t64 = timed(op_step("f64", True), args.steps, args.warmup)
+    ms_per_step = t64 / args.steps * 1e3
+    value = n * REPS * args.steps / t64 / 1e9
+    sub = max(2, args.steps // 4)
+    times = {("f64", "cold"): t64 / (REPS * args.steps)}
+    times[("f64", "warm")] = timed(op_step("f64", False), sub, 1) / (REPS * sub)
+    times[("f32", "cold")] = timed(op_step("f32", True), sub, 1) / (REPS * sub)
+    times[("f32", "warm")] = timed(op_step("f32", False), sub, 1) / (REPS * sub)
+    # the cell loop alone (mfgmg_vmult_add: one brick-kernel launch per call)
+    cell_loop = {p: timed(op_step(p, True, add=True), sub, 1) / (REPS * sub) for p in ("f64", "f32")}
+
     flops = FLOP_PER_CELL * ncell
-    alg_bytes = 2 * 4 * n + 4 * ncell        # read x, write y, cell viscosity (FP32)
-    achieved_tflops = flops / kernel_s / 1e12
-    traffic = measured_traffic(level)
+
+    def roof(prec, peak, extra=None):
+        """Roofline of one operator application (brick kernel + halo-add
+        kernel, HIP events on the stream they are launched on), cold."""
+        call = times[(prec, "cold")]
+        word = 8 if prec == "f64" else 4
+        alg_bytes = 2 * word * n + word * ncell        # read x, write y, cell viscosity
+        ach = flops / call / 1e12
+        tr = measured_traffic(level, prec)
+        tname = "double, 8, 4, 4" if prec == "f64" else "float, 8, 8, 4"
+        out = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+               "frac": round(ach / peak, 4), "traffic": tr["bytes"] if tr else None,
+               "kernel": f"k_vmult_brick<{tname}> + k_brick_halo_add<{tname}> (one mfgmg_vmult)",
+               "call_us": round(call * 1e6, 2), "cell_loop_us": round(cell_loop[prec] * 1e6, 2),
+               "cell_loop_frac": round(flops / cell_loop[prec] / 1e12 / peak, 4),
+               "flop_per_launch": flops, "alg_bytes_per_launch": alg_bytes,
+               "hbm_frac_algorithmic": round(alg_bytes / call / 1e9 / PEAK_HBM_GBS, 4),
+               "hbm_frac_measured": round(tr["bytes"] / call / 1e9 / PEAK_HBM_GBS, 4) if tr else None,
+               "traffic_source": tr["source"] if tr else "none for this kernel source"}
+        out.update(extra or {})
+        return out
 
     # V-cycles
     vc = {}
-    for name, xx in (("fp32", x32), ("fp64", x64)):
+    for name, xx in (("fp32", pairs["f32"][0][0]), ("fp64", pairs["f64"][0][0])):
         out = torch.empty_like(xx)
         tv = timed(lambda: s.vcycle(xx, out), 10, 2)
         vc[name] = tv / 10 * 1e3
@@ -368,30 +523,44 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"sinker {1 << level}^3 uniform Q2 vmult, 8 sinkers, DR 1e4",
+        "config": {"workload": f"sinker {1 << level}^3 uniform Q2 vmult, 8 sinkers, DR 1e4, FP64, "
+                               f"{ROTATE['f64']} rotating vector pairs",
                    "cells": ncell, "velocity_dofs": n, "reps_per_step": REPS},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic["bytes"] if traffic else None,
-                     "kernel": "k_vmult_brick<float,8,8,4> + k_brick_halo_add<float,8,8,4> (one mfgmg_vmult)",
-                     "kernel_us": round(kernel_s * 1e6, 2),
-                     "flop_per_launch": flops, "alg_bytes_per_launch": alg_bytes,
-                     "hbm_frac_algorithmic": round(alg_bytes / kernel_s / 1e9 / PEAK_HBM_GBS, 4),
-                     "traffic_source": traffic["source"] if traffic else "none for this kernel source"},
-        "vmult_fp64_gdofs": round(gdofs64, 3),
-        "vmult_call_us_fp32": round(vmult_call_s * 1e6, 2),
+        "roofline": roof("f64", PEAK_FP64_TFLOPS),
+        "vmult_gdofs": {f"{p}_{c}": round(n / t / 1e9, 3) for (p, c), t in times.items()},
+        "roofline_fp32": roof("f32", PEAK_FP32_TFLOPS, {
+            "frac_unpacked_peak": round(flops / times[("f32", "cold")] / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 4),
+            "unpacked_peak": PEAK_FP32_UNPACKED_TFLOPS}),
         "vcycle_ms": {k: round(v, 3) for k, v in vc.items()},
         "setup_s": {"mesh": round(t_mesh, 2), "assemble": round(t_assemble, 2)},
     }
+    print(f"[bench] operator done: {json.dumps(result['vmult_gdofs'])}", file=sys.stderr, flush=True)
 
+    checks = {}
     if not args.no_solve:
-        result["stokes_solve_1e-8"] = solve_compare(s, qp, centres)
+        keep = {} if not args.no_cpu else None
+        result["stokes_solve_1e-8"] = solve_compare(s, qp, centres, keep=keep)
+        if keep is not None:
+            from oracle import mesh as om
+            lev, ijk = om.uniform_leaves(level)
+            checks[f"uniform{1 << level}"] = (lev, ijk, centres, dr, (s.support_points(L, 0),
+                                                                       s.support_points(L, 1)), keep)
+        print("[bench] 64^3 solves done", file=sys.stderr, flush=True)
+    s.close()
+    if not args.no_solve and not args.no_adaptive:
+        out, keep, keys, cells, cen = solve_workload("adaptive32p2", ("fp64", "fp32", "fp32_learned"),
+                                                     verbose=0, oracle_check=not args.no_cpu)
+        result["adaptive32p2"] = out
+        if keep is not None:
+            acfg = inputs.CONFIGS["adaptive32p2"]
+            lev, ijk = adaptive_leaves(acfg, cells)
+            checks["adaptive32p2"] = (lev, ijk, cen, acfg["dr"], keys, keep)
+        print("[bench] adaptive 32^3+2 solves done", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(level, centres, dr)
-    s.close()
+        result["cpu_baseline"] = cpu_leg(level, centres, dr, checks)
     print(json.dumps(result), flush=True)
 
 

@@ -338,10 +338,16 @@ int mfgmg_mlp_adam(float* w_dev, const float* dw_dev, float* m_dev, float* v_dev
 int mfgmg_mlp_train(float* w_dev, const float* feats_dev, const float* targets_dev, int64_t n, int32_t epochs,
                     int32_t batch, double lr, uint64_t seed, double* loss_hist_host, void* stream);
 
-/* Features -> MLP -> scaling on every level 2..L.  guard != 0: keep the
- * scalings only if they lower the V-cycle contraction estimate
- * (factors_host[0] plain, [1] learned; may be NULL); *used_host = 1 if kept.
- * Synchronises `stream`. */
+/* Features -> MLP -> scaling on every level 2..L, then the guard:
+ *   MFGMG_GUARD_NONE: keep the scalings;
+ *   MFGMG_GUARD_FP64 / MFGMG_GUARD_FP32: estimate the A-norm contraction of
+ *   E = I - V A on the leaf with and without the scalings (6 power steps from
+ *   a SplitMix64 vector, seed 4242, the V-cycle in FP64 / FP32: pass the
+ *   precision of the solve the scaling is for) and keep the scalings only if
+ *   the learned factor is below 0.95 times the plain one.
+ * factors_host[0] plain, [1] learned (may be NULL); *used_host = 1 if kept.
+ * ERR_INVALID for another guard value.  Synchronises `stream`. */
+enum { MFGMG_GUARD_NONE = 0, MFGMG_GUARD_FP64 = 1, MFGMG_GUARD_FP32 = 2 };
 int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w_dev, int32_t guard, int32_t* used_host, double* factors_host,
                     void* stream);
 

@@ -181,6 +181,56 @@ class CellwiseA:
         return np.where(self.free, d, 1.0)
 
 
+class CellwiseB:
+    """B = C_p^T B_full C_u (rows of hanging pressure nodes zero) and its
+    transpose applied cell by cell with the 8x81 B_hat scaled by h^2; the same
+    operator as ``assemble_B`` for meshes where the assembled matrix (8 x 81
+    entries per cell) would not fit in memory."""
+
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self.dofs = mesh.cell_dofs()
+        self.pn = mesh.cell_pnodes
+        self.h2 = mesh.h ** 2
+        self.Cu = mesh.Cu()
+        self.CuT = self.Cu.T.tocsr()
+        self.Cp = mesh.Cp
+        self.CpT = mesh.Cp.T.tocsr()
+
+    def matvec(self, u, chunk=65536):
+        """B u -> [n_p]"""
+        uf = self.Cu @ np.asarray(u, dtype=np.float64)
+        out = np.zeros(self.mesh.npnode)
+        for s in range(0, len(self.dofs), chunk):
+            loc = uf[self.dofs[s:s + chunk]] @ _BHAT.T * self.h2[s:s + chunk, None]
+            out += np.bincount(self.pn[s:s + chunk].ravel(), weights=loc.ravel(), minlength=self.mesh.npnode)
+        return self.CpT @ out
+
+    def rmatvec(self, p, chunk=65536):
+        """B^T p -> [n_u]"""
+        pf = self.Cp @ np.asarray(p, dtype=np.float64)
+        out = np.zeros(self.mesh.n_u)
+        for s in range(0, len(self.dofs), chunk):
+            loc = pf[self.pn[s:s + chunk]] @ _BHAT * self.h2[s:s + chunk, None]
+            out += np.bincount(self.dofs[s:s + chunk].ravel(), weights=loc.ravel(), minlength=self.mesh.n_u)
+        return self.CuT @ out
+
+
+def stokes_residual(mesh, mu, rhs_u, u, p, rhs_p=None, ops_AB=None):
+    """Relative residual ||b - K x||_2 / ||b||_2 of the block system of
+    Sec. 2.1 (constrained rows identity, R4) for velocity u and pressure p
+    given on the mesh's dofs (constrained entries are taken as zero), by the
+    cellwise operators (ops_AB: a prebuilt (CellwiseA, CellwiseB) pair)."""
+    A, B = ops_AB if ops_AB is not None else (CellwiseA(mesh, mu), CellwiseB(mesh))
+    u = np.where(mesh.free_dofs_mask(), u, 0.0)
+    p = np.where(mesh.pfree, p, 0.0)
+    ru = rhs_u - A.matvec(u) - B.rmatvec(p)
+    bp = np.zeros(mesh.npnode) if rhs_p is None else rhs_p
+    rp = bp - B.matvec(u)
+    nb = np.sqrt(np.dot(rhs_u, rhs_u) + np.dot(bp, bp))
+    return float(np.sqrt(np.dot(ru, ru) + np.dot(rp, rp)) / nb)
+
+
 # ---------------------------------------------------------------- transfers
 _P1D = np.array([[1, 0, 0], [3 / 8, 3 / 4, -1 / 8], [0, 1, 0], [-1 / 8, 3 / 4, 3 / 8], [0, 0, 1]])
 

@@ -30,6 +30,12 @@ constexpr int kFitK = 4;
 constexpr int kFitM = 2;
 constexpr uint64_t kFitSeed = 777;
 constexpr uint64_t kGuardSeed = 4242;
+// Guard: power steps per factor estimate, and the relative margin by which the
+// learned factor must undercut the plain one.  Three steps from the same start
+// vector leave the two estimates' ratio uncertain by a few per cent; a 0.3%
+// lower learned estimate once came with two more outer iterations than plain.
+constexpr int kGuardSteps = 6;
+constexpr double kGuardMargin = 0.05;
 
 struct DBuf {
   std::vector<double*> v;
@@ -264,14 +270,21 @@ inline uint64_t cell_code(int l, int64_t i, int64_t j, int64_t k) {
 }
 
 // V-cycle contraction estimate: three power steps of E = I - V A in the A-norm (FP64)
-double vcycle_factor(mfgmg_ctx* ctx, hipStream_t s) {
+// A-norm contraction of E = I - V A on the leaf by `steps` power steps from
+// a SplitMix64 vector (seed 4242), the V-cycle in precision `prec` (the
+// residual and the error in FP64).  Negative on allocation failure.
+double vcycle_factor(mfgmg_ctx* ctx, hipStream_t s, int prec, int steps) {
   const int L = ctx->mesh->L();
   const Level& h = ctx->mesh->level(L);
   const DevLevel& v = ctx->lv[size_t(L)].v;
   const int64_t n = 3 * h.nnode;
   DBuf buf;
   double *e = buf.get(size_t(n)), *t = buf.get(size_t(n)), *x = buf.get(size_t(n));
-  if (!e || !t || !x) return -1.0;
+  // FP32 V-cycle: its right-hand side and result in the two halves of one buffer
+  double* fbuf = prec == MFGMG_FP32 ? buf.get(size_t(n)) : nullptr;
+  if (!e || !t || !x || (prec == MFGMG_FP32 && !fbuf)) return -1.0;
+  float* tf = reinterpret_cast<float*>(fbuf);
+  float* xf = tf + n;
   std::vector<double> hv(static_cast<size_t>(n));
   for (int64_t i = 0; i < h.nnode; ++i)
     for (int q = 0; q < 3; ++q)
@@ -279,10 +292,16 @@ double vcycle_factor(mfgmg_ctx* ctx, hipStream_t s) {
           h.ntype[size_t(i)] == NODE_FREE ? splitmix_pm1(kGuardSeed, uint64_t(3 * h.key[size_t(i)] + q)) : 0.0;
   (void)hipMemcpyAsync(e, hv.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s);
   double rho = 0.0;
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < steps; ++it) {
     launch_vmult<double>(v, e, t, s);
     const double ne = dot_sync(ctx, n, e, t, s);
-    vcycle<double>(ctx, L, t, x, s);
+    if (prec == MFGMG_FP32) {
+      launch_to_float(n, t, tf, s);
+      vcycle<float>(ctx, L, tf, xf, s);
+      launch_to_double(n, xf, x, s);
+    } else {
+      vcycle<double>(ctx, L, t, x, s);
+    }
     launch_axpby(n, -1.0, x, 1.0, e, s);
     launch_vmult<double>(v, e, t, s);
     const double nn = dot_sync(ctx, n, e, t, s);
@@ -472,7 +491,7 @@ int mfgmg_use_scaling(mfgmg_ctx* ctx, int32_t on) {
 int mfgmg_vcycle_factor(mfgmg_ctx* ctx, double* rho, void* stream) {
   if (!ctx || !rho) return MFGMG_ERR_INVALID;
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
-  *rho = vcycle_factor(ctx, static_cast<hipStream_t>(stream));
+  *rho = vcycle_factor(ctx, static_cast<hipStream_t>(stream), MFGMG_FP64, 3);
   return *rho >= 0 ? MFGMG_OK : ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
 }
 
@@ -560,7 +579,7 @@ int mfgmg_mlp_train(float* w, const float* feats, const float* targets, int64_t 
 }
 
 int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w, int32_t guard, int32_t* used, double* factors, void* stream) {
-  if (!ctx || !w) return MFGMG_ERR_INVALID;
+  if (!ctx || !w || guard < MFGMG_GUARD_NONE || guard > MFGMG_GUARD_FP32) return MFGMG_ERR_INVALID;
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int L = ctx->mesh->L();
@@ -582,14 +601,17 @@ int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w, int32_t guard, int32_t* used
   }
   int32_t use = 1;
   if (guard) {
+    // both factors with the V-cycle precision of the solve the scaling is for
+    const int prec = guard == MFGMG_GUARD_FP32 ? MFGMG_FP32 : MFGMG_FP64;
     const bool saved = ctx->use_scaling;
     ctx->use_scaling = false;
-    const double plain = vcycle_factor(ctx, s);
+    const double plain = vcycle_factor(ctx, s, prec, kGuardSteps);
     ctx->use_scaling = true;
-    const double lrn = vcycle_factor(ctx, s);
+    const double lrn = vcycle_factor(ctx, s, prec, kGuardSteps);
     ctx->use_scaling = saved;
+    if (plain < 0 || lrn < 0) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
     if (factors) factors[0] = plain, factors[1] = lrn;
-    if (!(lrn < plain)) {
+    if (!(lrn < (1.0 - kGuardMargin) * plain)) {
       use = 0;
       for (int l = 2; l <= L; ++l) ctx->lv[size_t(l)].scaled = false;
     }

@@ -94,7 +94,7 @@ def evaluate(w, base=6, seeds=range(20000, 20032), prec="fp32", log=_log, max_it
         plain = s.solve_stokes(rhs, u, p, vcycle_prec=prec, use_scaling=0, raise_on_noconv=False,
                                max_iter=max_iter)
         t0 = time.perf_counter()
-        used, fac = s.apply_mlp(w, guard=True)
+        used, fac = s.apply_mlp(w, guard="fp64")
         t_apply = time.perf_counter() - t0
         lrn = s.solve_stokes(rhs, u, p, vcycle_prec=prec, use_scaling=1, raise_on_noconv=False,
                              max_iter=max_iter) if used else plain
@@ -108,7 +108,7 @@ def evaluate(w, base=6, seeds=range(20000, 20032), prec="fp32", log=_log, max_it
                "plain_its": plain["iterations"], "plain_s": plain["seconds"], "plain_res": plain["rel_residual"],
                "learned_used": used, "factor_plain": fac[0], "factor_learned": fac[1],
                "learned_its": lrn["iterations"], "learned_s": lrn["seconds"], "learned_res": lrn["rel_residual"],
-               "apply_s": t_apply, "fallback": fallback, "plain_converged": bool(plain["converged"])}
+               "apply_s": t_apply, "learned_s_with_setup": lrn["seconds"] + t_apply, "fallback": fallback, "plain_converged": bool(plain["converged"])}
         rows.append(row)
         s.close()
         if log:
@@ -123,8 +123,11 @@ def summarize(rows):
     li = np.array([r["learned_its"] for r in rows])
     ps = np.array([r["plain_s"] for r in rows])
     ls = np.array([r["learned_s"] for r in rows])
+    lt = np.array([r["learned_s_with_setup"] for r in rows])
     return {"fields": len(rows), "median_plain_its": float(np.median(pi)), "median_learned_its": float(np.median(li)),
             "median_plain_s": float(np.median(ps)), "median_learned_s": float(np.median(ls)),
+            "median_learned_s_with_setup": float(np.median(lt)),
+            "total_plain_s": float(ps.sum()), "total_learned_s_with_setup": float(lt.sum()),
             "used": int(sum(r["learned_used"] for r in rows)),
             "fields_fewer_its": int((li < pi).sum()), "fields_more_its": int((li > pi).sum())}
 

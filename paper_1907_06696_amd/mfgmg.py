@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfgmg.so")
 
 FP32, FP64 = 0, 1
+GUARD_NONE, GUARD_FP64, GUARD_FP32 = 0, 1, 2
 MAX_LEVELS = 14
 
 OK, ERR_INVALID, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_MESH = 0, -1, -2, -3, -4, -5, -6
@@ -466,10 +467,15 @@ class Solver:
         self._check(self.lib.mfgmg_vcycle_factor(self.h, C.byref(r), stream or current_stream()))
         return r.value
 
-    def apply_mlp(self, w, guard=True, stream=None):
+    def apply_mlp(self, w, guard="fp32", stream=None):
+        """Install the network's scalings; guard None/False, "fp64" or "fp32"
+        (the V-cycle precision of the solve they are for; True means "fp64")."""
+        g = {None: GUARD_NONE, False: GUARD_NONE, True: GUARD_FP64, "fp64": GUARD_FP64, "fp32": GUARD_FP32}
+        if guard not in g:
+            raise ValueError(f"guard must be one of {list(g)}")
         used = C.c_int32()
         fac = np.zeros(2)
-        self._check(self.lib.mfgmg_apply_mlp(self.h, _dev_ptr(w, N_PARAMS, FP32, "weights"), int(bool(guard)),
+        self._check(self.lib.mfgmg_apply_mlp(self.h, _dev_ptr(w, N_PARAMS, FP32, "weights"), g[guard],
                                              C.byref(used), _np_ptr(fac), stream or current_stream()))
         return bool(used.value), fac
 

@@ -123,8 +123,11 @@ def test_training_and_guard(case):
     w = torch.tensor(ol.init_params(0).astype(np.float32), device=DEV)
     hist = mfgmg.mlp_train(w, feats, y.contiguous(), epochs=30, batch=64, lr=3e-3, seed=1)
     assert hist[-1] < hist[0]
-    used, fac = case.s.apply_mlp(w, guard=True)
-    assert fac[0] > 0 and fac[1] > 0
-    assert used == (fac[1] < fac[0])
+    for guard in ("fp64", "fp32"):
+        used, fac = case.s.apply_mlp(w, guard=guard)
+        assert fac[0] > 0 and fac[1] > 0
+        assert used == (fac[1] < 0.95 * fac[0]), (guard, fac)
+    used, fac = case.s.apply_mlp(w, guard=None)
+    assert used
     for ell in range(2, L + 1):
         case.s.set_scaling(ell, None)

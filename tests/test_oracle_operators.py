@@ -205,3 +205,35 @@ def test_pressure_mass_is_inverse_viscosity_weighted(which):
         for K in range(m.ncell):
             rows[m.cell_pnodes[K]] += m.h[K] ** 3 / (8.0 * mu[K])
         assert np.allclose(Mp @ ones, rows, rtol=1e-12, atol=0)
+
+
+def test_cellwise_B_equals_assembled_and_residual_of_direct_solve():
+    """The cellwise B, B^T equal the assembled B on uniform and hanging
+    meshes; the cellwise Stokes residual of the direct solve is at round-off,
+    and of a perturbed solution it equals ||b - K x|| / ||b|| from the
+    assembled block matrix."""
+    from oracle import krylov
+    for H in _hierarchies():
+        m = H.leaf
+        B = ops.assemble_B(m)
+        Bc = ops.CellwiseB(m)
+        rng = np.random.default_rng(3)
+        u = rng.uniform(-1, 1, m.n_u) * m.free_dofs_mask()
+        p = rng.uniform(-1, 1, m.npnode) * m.pfree
+        assert np.abs(Bc.matvec(u) - B @ u).max() <= 1e-14 * np.abs(B @ u).max()
+        assert np.abs(Bc.rmatvec(p) - B.T @ p).max() <= 1e-14 * np.abs(B.T @ p).max()
+    H = adaptive_hierarchy(2, (1, 0, 1), 1)
+    m = H.leaf
+    X = ops.gauss_points_of_cells(m).reshape(-1, 3)
+    from paper_1907_06696_amd import inputs
+    c = inputs.sinker_centres(3, 1)
+    mu = ops.harmonic_cell_viscosity(inputs.sinker_mu(X, c, 1e3).reshape(-1, 27))
+    f = inputs.sinker_force(X, c).reshape(-1, 27, 3)
+    prob = krylov.StokesProblem(H, mu, f)
+    x = prob.solve_direct()
+    nu = m.n_u
+    assert ops.stokes_residual(m, mu, prob.b[:nu], x[:nu], x[nu:]) <= 1e-12
+    xp = x + 1e-3 * np.random.default_rng(4).uniform(-1, 1, len(x)) * np.concatenate(
+        [m.free_dofs_mask(), m.pfree])
+    ref = np.linalg.norm(prob.b - prob.apply_K(xp)) / np.linalg.norm(prob.b)
+    assert np.isclose(ops.stokes_residual(m, mu, prob.b[:nu], xp[:nu], xp[nu:]), ref, rtol=1e-10)
