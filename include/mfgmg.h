@@ -351,6 +351,25 @@ enum { MFGMG_GUARD_NONE = 0, MFGMG_GUARD_FP64 = 1, MFGMG_GUARD_FP32 = 2 };
 int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w_dev, int32_t guard, int32_t* used_host, double* factors_host,
                     void* stream);
 
+/* ------------------------------------------- operator without allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operator of mfgmg_vmult on the uniform n x n x n mesh of the unit cube
+ * (n_edge = 32 or 64), without a context.  mu_dev: cell viscosity [n^3]
+ * (cell i + n (j + n k)), src_dev, dst_dev: [3 (2n+1)^3] velocity values,
+ * node X + (2n+1)(Y + (2n+1) Z) with X, Y, Z the lattice coordinates in units
+ * of 1/(2n), all in the precision `prec`; boundary nodes are Dirichlet
+ * (identity rows: dst = src there).  Identical results to mfgmg_vmult on the
+ * leaf of a uniform context with the same cell viscosities.  Work memory:
+ * the library's static device array (75.6 MB per GPU, held until the process
+ * ends); no allocation, no host synchronisation.  Calls on one GPU share that
+ * array: calls whose work overlaps in time (other streams or threads) race.
+ * Errors: ERR_INVALID for n_edge above 64 (the array's limit) or other than
+ * 32 and 64, null or aliased pointers; ERR_HIP if the array's device address
+ * cannot be found.  Async. */
+int mfgmg_vmult_uniform_noalloc(int32_t n_edge, mfgmg_prec prec, const void* mu_dev, const void* src_dev,
+                                void* dst_dev, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 
 const char* mfgmg_last_error(const mfgmg_ctx* ctx); /* ctx may be NULL */

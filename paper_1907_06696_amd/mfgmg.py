@@ -32,7 +32,7 @@ EXPORTS = [
     "mfgmg_default_opts", "mfgmg_solve_stokes",
     "mfgmg_features", "mfgmg_fit_objective", "mfgmg_fit_targets", "mfgmg_set_scaling", "mfgmg_use_scaling",
     "mfgmg_vcycle_factor", "mfgmg_mlp_forward", "mfgmg_mlp_backward", "mfgmg_mlp_work_size", "mfgmg_mlp_adam",
-    "mfgmg_mlp_train", "mfgmg_apply_mlp",
+    "mfgmg_mlp_train", "mfgmg_apply_mlp", "mfgmg_vmult_uniform_noalloc",
     "mfgmg_last_error", "mfgmg_destroy",
 ]
 N_PARAMS = 6147
@@ -112,6 +112,7 @@ def load():
         "mfgmg_mlp_adam": [vp, vp, vp, vp, i64, C.c_double, vp],
         "mfgmg_mlp_train": [vp, vp, vp, i64, i32, i32, C.c_double, C.c_uint64, vp, vp],
         "mfgmg_apply_mlp": [vp, vp, i32, C.POINTER(i32), vp, vp],
+        "mfgmg_vmult_uniform_noalloc": [i32, i32, vp, vp, vp, vp],
         "mfgmg_last_error": [vp],
         "mfgmg_destroy": [vp],
     }
@@ -537,3 +538,20 @@ def mlp_train(w, feats, targets, epochs=20, batch=4096, lr=1e-3, seed=0, stream=
     _lib_check(load().mfgmg_mlp_train(*args, n, int(epochs), int(batch), float(lr), int(seed), _np_ptr(hist),
                                       stream or current_stream()))
     return hist[:epochs]
+
+
+def vmult_uniform_noalloc(n_edge, mu, src, dst, stream=None):
+    """dst = A src on the uniform n_edge^3 mesh (32 or 64) with cell viscosity
+    mu [n^3], without a context and without any allocation in the library
+    (its static work array is shared by every call on a GPU)."""
+    n = int(n_edge)
+    if n not in (32, 64):
+        raise ValueError("n_edge must be 32 or 64")
+    p = _prec_of(src)
+    nu = 3 * (2 * n + 1) ** 3
+    args = (_dev_ptr(mu, n ** 3, p, "mu"), _dev_ptr(src, nu, p, "src"), _dev_ptr(dst, nu, p, "dst"))
+    lib = load()
+    code = lib.mfgmg_vmult_uniform_noalloc(n, p, *args, stream or current_stream())
+    if code != OK:
+        msg = lib.mfgmg_last_error(None)
+        raise MFGMGError(code, msg.decode() if msg else "")
