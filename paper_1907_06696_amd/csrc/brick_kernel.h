@@ -83,8 +83,62 @@ constexpr int64_t halo_words() {
   return halo_box_words<BX, BY, BZ>() + 2 * halo_plane_words<BX, BY, BZ>();
 }
 
-template <typename T, int BX, int BY, int BZ, bool ACC>
-__global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x,
+// An empty asm that the compiler must assume reads and changes v: values
+// computed from v cannot move above it.  Arithmetic otherwise moves freely
+// across block barriers, and computing a later component's gradients early
+// keeps them live beside the current component's results.
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
+// Output component C of the cell operator from the Gauss-point values W
+// (all three components), transformed back to the nodes and added into
+// component C of the zeroed LDS box with the class-ordered scheme of the
+// kernel below.  Ends with a block barrier.
+template <int C, int BX, int BY, int BZ, int CS, int PL, int RX, typename T>
+__device__ __forceinline__ void component_pass(T (&W)[3][27], T mu_h, T* buf, int cx, int cy, int cz) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 27; ++a) pin(W[c][a]);
+  T Y[27];
+  cellop::apply_cell_row<C>(W, Y, mu_h);
+  cellop::interp_all_t(Y);
+  T* bc = buf + C * CS;
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) {
+      const int ac = ab & 1, bcl = ab >> 1;
+      T tmp[2][2][2];
+#pragma unroll
+      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+#pragma unroll
+        for (int bb = bcl ? 2 : 0; bb < (bcl ? 3 : 2); ++bb)
+#pragma unroll
+          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+            tmp[c & 1][bb & 1][a & 1] = bc[off];
+          }
+#pragma unroll
+      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+#pragma unroll
+        for (int bb = bcl ? 2 : 0; bb < (bcl ? 3 : 2); ++bb)
+#pragma unroll
+          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+            bc[off] = tmp[c & 1][bb & 1][a & 1] + Y[a + 3 * bb + 9 * c];
+          }
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      asm volatile("" ::: "memory");
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int BX, int BY, int BZ, bool ACC, bool ROWS>
+__global__ __launch_bounds__(BX * BY * BZ, ROWS ? 3 : 1) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x,
                                                               T* __restrict__ y, T* __restrict__ halo) {
   constexpr int NT = BX * BY * BZ, NW = NT / 64;
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;
@@ -159,44 +213,57 @@ __global__ __launch_bounds__(BX * BY * BZ) void k_vmult_brick(int n, const T* __
     for (int e = NV * 16 / int(sizeof(T)) + t; e < 3 * CS; e += NT) buf[e] = T(0);
   }
   const int64_t cell = (int64_t(bx) * BX + cx) + int64_t(n) * ((int64_t(by) * BY + cy) + int64_t(n) * (int64_t(bz) * BZ + cz));
-  cellop::apply_cell<T>(U, mu[cell] / T(n));
-  __syncthreads();
-  {
-    // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
-    // class the map (cell, local node) -> node is injective, so read-add-write is race free;
-    // c classes are separated by a block barrier (they couple waves), a/b classes by an
-    // in-order LDS wait (they couple lanes of one wave).
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-#pragma unroll
-      for (int ab = 0; ab < 4; ++ab) {
-        const int ac = ab & 1, bc = ab >> 1;
-        T tmp[3][2][2][2];
-#pragma unroll
-        for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-#pragma unroll
-          for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
-#pragma unroll
-            for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-              const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-#pragma unroll
-              for (int q = 0; q < 3; ++q) tmp[q][c & 1][bb & 1][a & 1] = buf[q * CS + off];
-            }
-#pragma unroll
-        for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-#pragma unroll
-          for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
-#pragma unroll
-            for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-              const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-#pragma unroll
-              for (int q = 0; q < 3; ++q) buf[q * CS + off] = tmp[q][c & 1][bb & 1][a & 1] + U[q][a + 3 * bb + 9 * c];
-            }
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        asm volatile("" ::: "memory");
+  const T mu_h = mu[cell] / T(n);
+  if constexpr (!ROWS) {
+    cellop::apply_cell<T>(U, mu_h);
+    __syncthreads();
+    {
+      // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
+      // class the map (cell, local node) -> node is injective, so read-add-write is race free;
+      // c classes are separated by a block barrier (they couple waves), a/b classes by an
+      // in-order LDS wait (they couple lanes of one wave).
+  #pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+  #pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+          const int ac = ab & 1, bc = ab >> 1;
+          T tmp[3][2][2][2];
+  #pragma unroll
+          for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+  #pragma unroll
+            for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+  #pragma unroll
+              for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+  #pragma unroll
+                for (int q = 0; q < 3; ++q) tmp[q][c & 1][bb & 1][a & 1] = buf[q * CS + off];
+              }
+  #pragma unroll
+          for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+  #pragma unroll
+            for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+  #pragma unroll
+              for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+  #pragma unroll
+                for (int q = 0; q < 3; ++q) buf[q * CS + off] = tmp[q][c & 1][bb & 1][a & 1] + U[q][a + 3 * bb + 9 * c];
+              }
+          __builtin_amdgcn_s_waitcnt(0xc07f);
+          asm volatile("" ::: "memory");
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
+  } else {
+    // one output component at a time: the 81 Gauss-point values stay in
+    // registers, the 27 results of component C are formed, transformed back
+    // and added into the box before the next component's
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cellop::interp_all(U[c]);
+    __syncthreads();
+    component_pass<0, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
+    component_pass<1, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
+    component_pass<2, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
   }
   const bool x_own = lx < NX - 1 || bx == nbx - 1;
   // lanes of the x planes shared with a neighbour brick: the packed pass below
