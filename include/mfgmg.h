@@ -233,11 +233,19 @@ typedef struct {
                              diag(M_p)^-1 over [b/27, b], b = max_i
                              (M_p 1)_i / (M_p)_ii, a fixed linear map (CG) */
   int32_t schur_degree;   /* 1..64 (8) */
+  int32_t hierarchy;      /* MFGMG_GLOBAL_COARSENING: level l = the leaf mesh
+                             with finer cells replaced by their level-l
+                             ancestors (hanging nodes on every level);
+                             MFGMG_LOCAL_SMOOTHING: level l = the cells of
+                             refinement level exactly l, smoothed with the
+                             refinement edge fixed (mfgmg_vcycle_local)
+                             (MFGMG_GLOBAL_COARSENING) */
 } mfgmg_solve_opts;
 
 enum { MFGMG_FGMRES = 0, MFGMG_GMRES = 1, MFGMG_IDR = 2 };
 enum { MFGMG_BLOCK_TRIANGULAR = 0, MFGMG_BLOCK_DIAGONAL = 1 };
 enum { MFGMG_SCHUR_CG = 0, MFGMG_SCHUR_CHEB = 1 };
+enum { MFGMG_GLOBAL_COARSENING = 0, MFGMG_LOCAL_SMOOTHING = 1 };
 
 typedef struct {
   int32_t iterations;    /* outer iterations: Arnoldi steps ((F)GMRES) or
@@ -264,6 +272,42 @@ int mfgmg_default_opts(mfgmg_solve_opts* opts);
  * (stats and outputs filled) if rtol is not reached. */
 int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u_dev, const double* rhs_p_dev, double* u_dev,
                        double* p_dev, const mfgmg_solve_opts* opts, mfgmg_solve_stats* stats, void* stream);
+
+/* ------------------------------------------------ local smoothing
+ * The level hierarchy of the multigrid method cited in Sec. 2.2.1 (local
+ * smoothing): levels 1 .. base are the uniform levels (every cell of the
+ * level exists; there it equals the global-coarsening hierarchy); a finer
+ * level l holds only the cells of refinement level l.  Its smoother keeps the
+ * nodes on the refinement edge (on the boundary of the refined part, inside
+ * the domain) fixed; the coupling of inner and edge nodes is carried between
+ * the levels: t = d - K y (edge rows included) is restricted, the coarse
+ * correction is kept on the edge, and the post-smoothing solves
+ * A_II y_I = d_I - K_IE y_E.  Every free leaf node is copied to and from the
+ * finest level whose cells hold it.  Level cell viscosities are those of the
+ * same octree nodes on the global-coarsening levels (Sec. 2.3). */
+
+/* Host only.  *base_host: the finest uniform level (L for a uniform leaf
+ * mesh); n_cells_host[l], n_nodes_host[l] ([MFGMG_MAX_LEVELS + 1]) of every
+ * level (the uniform ones included). */
+int mfgmg_local_levels(const mfgmg_ctx* ctx, int32_t* base_host, int64_t* n_cells_host, int64_t* n_nodes_host);
+
+/* Host only.  Canonical keys and kinds (0 inner, 1 domain boundary,
+ * 2 refinement edge) of the Q2 nodes of local level `level` (base < level
+ * <= L), in storage order: keys_host, kinds_host [n_nodes[level]]. */
+int mfgmg_local_nodes(const mfgmg_ctx* ctx, int32_t level, int64_t* keys_host, uint8_t* kinds_host);
+
+/* Host only.  Node-level prolongation to local level `level` from the level
+ * below (the base level or the local level below) as CSR over the level's
+ * nodes (as mfgmg_transfer): boundary rows empty, edge rows kept.
+ * NULL arrays: *nnz only. */
+int mfgmg_local_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* ptr_host, int64_t* col_host,
+                         double* weight_host);
+
+/* x = one local-smoothing V(1,1)-cycle on leaf vectors (same smoother,
+ * Chebyshev bounds rule and coarse solve as mfgmg_vcycle; x is zero on the
+ * constrained leaf dofs).  The first call after mfgmg_set_viscosity sets up
+ * the local levels (synchronises `stream`).  Async otherwise. */
+int mfgmg_vcycle_local(mfgmg_ctx* ctx, mfgmg_prec prec, const void* rhs_dev, void* x_dev, void* stream);
 
 /* ------------------------------------------- learned smoother scaling
  * Not part of the paper: the degree-4 Chebyshev smoother of Sec. 2.2.1 is

@@ -21,7 +21,8 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-munsafe-fp-atomics",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-Wall", "-Wno-unused-function"]
 SOURCES = [("mesh.cpp", False), ("ops.hip", True), ("api.hip", True), ("learned.hip", True), ("learned_api.hip", True),
-           ("noalloc.hip", True)]
+           ("noalloc.hip", True),
+           ("local_api.hip", True)]
 
 
 def _run(cmd):

@@ -205,6 +205,308 @@ thread_local std::string g_last_error;
 double splitmix_pm1(uint64_t seed, uint64_t counter) { return splitmix_value(seed, counter); }
 
 
+// Device data of one level from its host mesh: node lists, cell tables and
+// the operator's block partition (non-uniform levels; the leaf also keeps
+// its cell tables and pressure blocks), transfers from the level below,
+// brick halo slots (uniform levels), viscosity, inverse diagonal and work
+// vectors (work = false: the operator data only).
+int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool top, bool transfers, bool work) {
+  DevLevel& v = d.v;
+  v.ell = h.ell;
+  v.ncell = h.ncell;
+  v.nnode = h.nnode;
+  v.uniform = h.uniform;
+  v.n_edge = h.n_edge;
+  // constrained and hanging node lists
+  std::vector<int64_t> cons;
+  for (int64_t i = 0; i < h.nnode; ++i)
+    if (h.ntype[size_t(i)] != NODE_FREE) cons.push_back(i);
+  v.cons_nodes = ctx->upload(cons);
+  v.n_cons = int64_t(cons.size());
+  if (!h.uniform || leaf) {   // the leaf keeps cell tables for the pressure operators
+    std::vector<int32_t> slots(static_cast<size_t>(27 * h.ncell));
+    std::vector<int8_t> clev(static_cast<size_t>(h.ncell));
+    std::vector<int32_t> reg, hang;
+    for (int64_t c = 0; c < h.ncell; ++c) {
+      bool hh = false;
+      for (int a = 0; a < 27; ++a) {
+        const int32_t n = h.cell_nodes[size_t(27 * c + a)];
+        int32_t s = n;
+        if (h.ntype[size_t(n)] == NODE_DIRICHLET) s = -1;
+        else if (h.ntype[size_t(n)] == NODE_HANGING) s = -(2 + h.hang_index[size_t(n)]), hh = true;
+        slots[size_t(27 * c + a)] = s;
+      }
+      clev[size_t(c)] = int8_t(h.clev[size_t(c)]);
+      (hh ? hang : reg).push_back(int32_t(c));
+    }
+    v.slots = ctx->upload(slots);
+    v.clev = ctx->upload(clev);
+    v.ntype = ctx->upload(h.ntype);
+    v.reg_cells = ctx->upload(reg);
+    v.n_reg_cells = int64_t(reg.size());
+    v.hang_cells = ctx->upload(hang);
+    v.n_hang_cells = int64_t(hang.size());
+    // operator partition into 4^3 blocks, then 2^3 blocks, then single cells
+    {
+      std::unordered_map<uint64_t, int32_t> at;
+      at.reserve(size_t(h.ncell));
+      auto code = [](int l, int64_t i, int64_t j, int64_t k) {
+        return (uint64_t(l) << 58) | (uint64_t(i) << 38) | (uint64_t(j) << 19) | uint64_t(k);
+      };
+      for (int64_t c = 0; c < h.ncell; ++c)
+        at.emplace(code(h.clev[size_t(c)], h.cijk[size_t(3 * c)], h.cijk[size_t(3 * c + 1)],
+                        h.cijk[size_t(3 * c + 2)]),
+                   int32_t(c));
+      std::vector<char> used(static_cast<size_t>(h.ncell), 0);
+      // A block keeps, per hanging lattice point, its masters as lattice
+      // points of the same block (a hanging node lies on the face shared with
+      // a coarser cell, whose face nodes are all on the block's lattice);
+      // blocks where that fails are left to the single-cell kernel.
+      struct Blocks {
+        std::vector<int32_t> slots, cells, hoff{0}, hent;
+        std::vector<double> hw;
+        std::vector<int32_t> pslots, phoff{0}, phent;   // leaf: Q1 pressure lattice
+        std::vector<double> phw;
+      };
+      auto make_blocks = [&](int B, Blocks& out) {
+        const int E = 2 * B + 1, NC = B * B * B, P = E * E * E, NB = 64 / NC;
+        std::vector<int32_t> cs(static_cast<size_t>(NC)), bs(static_cast<size_t>(P));
+        std::unordered_map<int32_t, int32_t> at_node;
+        std::vector<int32_t> ent;
+        std::vector<double> wt;
+        for (int64_t c = 0; c < h.ncell; ++c) {
+          const int l = h.clev[size_t(c)];
+          const int64_t i = h.cijk[size_t(3 * c)], j = h.cijk[size_t(3 * c + 1)], k = h.cijk[size_t(3 * c + 2)];
+          if (used[size_t(c)] || i % B || j % B || k % B || (int64_t(1) << l) < B) continue;
+          bool ok = true;
+          for (int q = 0; q < NC && ok; ++q) {
+            auto it = at.find(code(l, i + q % B, j + (q / B) % B, k + q / (B * B)));
+            ok = it != at.end() && !used[size_t(it->second)];
+            if (ok) cs[size_t(q)] = it->second;
+          }
+          if (!ok) continue;
+          for (int q = 0; q < NC; ++q) {
+            const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
+            for (int a = 0; a < 27; ++a) {
+              const int p = (2 * qa + a % 3) + E * ((2 * qb + (a / 3) % 3) + E * (2 * qc + a / 9));
+              bs[size_t(p)] = slots[size_t(27 * int64_t(cs[size_t(q)]) + a)];
+            }
+          }
+          at_node.clear();
+          for (int p = 0; p < P; ++p)
+            if (bs[size_t(p)] >= 0) at_node[bs[size_t(p)]] = p;
+          ent.clear();
+          wt.clear();
+          const int32_t bl = int32_t((out.cells.size() / size_t(NC)) % size_t(NB));
+          for (int p = 0; p < P && ok; ++p) {
+            if (bs[size_t(p)] >= -1) continue;
+            const int64_t hr = -int64_t(bs[size_t(p)]) - 2;
+            for (int64_t q = h.hang.ptr[size_t(hr)]; q < h.hang.ptr[size_t(hr + 1)] && ok; ++q) {
+              auto it = at_node.find(h.hang.master[size_t(q)]);
+              ok = it != at_node.end();
+              if (ok) {
+                ent.push_back(p | (it->second << 10) | (bl << 20));
+                wt.push_back(h.hang.weight[size_t(q)]);
+              }
+            }
+          }
+          if (!ok) continue;
+          // leaf: the pressure lattice of the block, hanging masters on it as well
+          std::vector<int32_t> pb;
+          std::vector<int32_t> pent;
+          std::vector<double> pwt;
+          if (leaf) {
+            const int EP = B + 1, PP = EP * EP * EP;
+            pb.assign(size_t(PP), -1);
+            for (int q = 0; q < NC; ++q) {
+              const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
+              for (int a = 0; a < 8; ++a) {
+                const int pp = (qa + a % 2) + EP * ((qb + (a / 2) % 2) + EP * (qc + a / 4));
+                pb[size_t(pp)] = h.cell_pnodes[size_t(8 * int64_t(cs[size_t(q)]) + a)];
+              }
+            }
+            std::unordered_map<int32_t, int32_t> pat;
+            for (int pp = 0; pp < PP; ++pp)
+              if (h.ptype[size_t(pb[size_t(pp)])] != NODE_HANGING) pat[pb[size_t(pp)]] = pp;
+            for (int pp = 0; pp < PP && ok; ++pp) {
+              const int32_t nd = pb[size_t(pp)];
+              if (h.ptype[size_t(nd)] != NODE_HANGING) continue;
+              const int32_t hr = h.phang_index[size_t(nd)];
+              for (int64_t q = h.phang.ptr[size_t(hr)]; q < h.phang.ptr[size_t(hr) + 1] && ok; ++q) {
+                auto it = pat.find(h.phang.master[size_t(q)]);
+                ok = it != pat.end();
+                if (ok) {
+                  pent.push_back(pp | (it->second << 10) | (bl << 20));
+                  pwt.push_back(h.phang.weight[size_t(q)]);
+                }
+              }
+              pb[size_t(pp)] = -2;
+            }
+            if (!ok) continue;
+          }
+          for (int q = 0; q < NC; ++q) {
+            used[size_t(cs[size_t(q)])] = 1;
+            out.cells.push_back(cs[size_t(q)]);
+          }
+          if (leaf) {
+            out.pslots.insert(out.pslots.end(), pb.begin(), pb.end());
+            out.phent.insert(out.phent.end(), pent.begin(), pent.end());
+            out.phw.insert(out.phw.end(), pwt.begin(), pwt.end());
+            out.phoff.push_back(int32_t(out.phent.size()));
+          }
+          for (int p = 0; p < P; ++p) out.slots.push_back(bs[size_t(p)] < -1 ? -2 : bs[size_t(p)]);
+          out.hent.insert(out.hent.end(), ent.begin(), ent.end());
+          out.hw.insert(out.hw.end(), wt.begin(), wt.end());
+          out.hoff.push_back(int32_t(out.hent.size()));
+        }
+      };
+      Blocks b4, b2;
+      std::vector<int32_t> sreg, shang;
+      make_blocks(4, b4);
+      make_blocks(2, b2);
+      for (int64_t c = 0; c < h.ncell; ++c) {
+        if (used[size_t(c)]) continue;
+        bool hh = false;
+        for (int a = 0; a < 27; ++a) hh = hh || slots[size_t(27 * c + a)] < -1;
+        (hh ? shang : sreg).push_back(int32_t(c));
+      }
+      auto upload_blocks = [&](const Blocks& b, DevBlocks& d, int NC) {
+        d.slots = ctx->upload(b.slots);
+        d.cells = ctx->upload(b.cells);
+        d.n = int64_t(b.cells.size() / size_t(NC));
+        d.hoff = ctx->upload(b.hoff);
+        d.hent = ctx->upload(b.hent);
+        d.hw_d = ctx->upload(b.hw);
+        d.hw_f = ctx->upload(std::vector<float>(b.hw.begin(), b.hw.end()));
+        if (leaf) {
+          d.pslots = ctx->upload(b.pslots);
+          d.phoff = ctx->upload(b.phoff);
+          d.phent = ctx->upload(b.phent);
+          d.phw = ctx->upload(b.phw);
+        }
+      };
+      upload_blocks(b4, v.blk4, 64);
+      upload_blocks(b2, v.blk2, 8);
+      // face gather: every free face point of a block -> its slot, grouped by node
+      {
+        std::vector<std::pair<int32_t, int32_t>> nf;   // (node, slot)
+        auto faces = [&](const Blocks& b, int B, int64_t slot0) {
+          const int E = 2 * B + 1, P = E * E * E, NC = B * B * B;
+          const int64_t nb = int64_t(b.cells.size() / size_t(NC));
+          for (int64_t k = 0; k < nb; ++k)
+            for (int p = 0; p < P; ++p) {
+              const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+              const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+              const int32_t nd = b.slots[size_t(k * P + p)];
+              if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
+            }
+          return slot0 + nb * P;
+        };
+        const int64_t s2 = faces(b4, 4, 0);
+        const int64_t ns = faces(b2, 2, s2);
+        std::sort(nf.begin(), nf.end());
+        std::vector<int32_t> fnode, fptr{0}, fent;
+        for (size_t i = 0; i < nf.size(); ++i) {
+          if (i == 0 || nf[i].first != nf[i - 1].first) {
+            if (i) fptr.push_back(int32_t(fent.size()));
+            fnode.push_back(nf[i].first);
+          }
+          fent.push_back(nf[i].second);
+        }
+        if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
+        v.fslot_blk2 = s2;
+        v.n_face = int64_t(fnode.size());
+        if (v.n_face) {
+          v.face_node = ctx->upload(fnode);
+          v.face_ptr = ctx->upload(fptr);
+          v.face_ent = ctx->upload(fent);
+          v.fslot_f = ctx->dalloc<float>(size_t(3 * ns));
+          v.fslot_d = ctx->dalloc<double>(size_t(3 * ns));
+          if (!v.fslot_f || !v.fslot_d) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+        }
+      }
+      // the same for the pressure mass blocks of the leaf ((B+1)^3 Q1 lattices)
+      if (leaf) {
+        std::vector<std::pair<int32_t, int32_t>> nf;
+        auto faces = [&](const Blocks& b, int B, int64_t slot0) {
+          const int E = B + 1, P = E * E * E, NC = B * B * B;
+          const int64_t nb = int64_t(b.cells.size() / size_t(NC));
+          for (int64_t k = 0; k < nb; ++k)
+            for (int p = 0; p < P; ++p) {
+              const int px = p % E, py = (p / E) % E, pz = p / (E * E);
+              const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
+              const int32_t nd = b.pslots[size_t(k * P + p)];
+              if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
+            }
+          return slot0 + nb * P;
+        };
+        const int64_t s2 = faces(b4, 4, 0);
+        const int64_t ns = faces(b2, 2, s2);
+        std::sort(nf.begin(), nf.end());
+        std::vector<int32_t> fnode, fptr{0}, fent;
+        for (size_t i = 0; i < nf.size(); ++i) {
+          if (i && nf[i].first != nf[i - 1].first) fptr.push_back(int32_t(fent.size()));
+          if (i == 0 || nf[i].first != nf[i - 1].first) fnode.push_back(nf[i].first);
+          fent.push_back(nf[i].second);
+        }
+        if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
+        v.pfslot_blk2 = s2;
+        v.n_pface = int64_t(fnode.size());
+        if (v.n_pface) {
+          v.pface_node = ctx->upload(fnode);
+          v.pface_ptr = ctx->upload(fptr);
+          v.pface_ent = ctx->upload(fent);
+          v.pfslot = ctx->dalloc<double>(size_t(ns));
+          if (!v.pfslot) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+        }
+      }
+      v.single_reg = ctx->upload(sreg);
+      v.n_single_reg = int64_t(sreg.size());
+      v.single_hang = ctx->upload(shang);
+      v.n_single_hang = int64_t(shang.size());
+    }
+    v.hptr = ctx->upload(h.hang.ptr);
+    v.hmaster = ctx->upload(h.hang.master);
+    v.hw_d = ctx->upload(h.hang.weight);
+    std::vector<float> wf(h.hang.weight.begin(), h.hang.weight.end());
+    v.hw_f = ctx->upload(wf);
+    v.hnode = ctx->upload(h.hang.node);
+    v.nhang = int64_t(h.hang.count());
+  }
+  if (transfers) {
+    d.P_ptr = ctx->upload(h.P_ptr);
+    d.P_col = ctx->upload(h.P_col);
+    d.P_w = ctx->upload(std::vector<float>(h.P_w.begin(), h.P_w.end()));
+    d.R_ptr = ctx->upload(h.R_ptr);
+    d.R_col = ctx->upload(h.R_col);
+    d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
+  }
+  if (h.uniform) {
+    const int64_t wf = brick_halo_words<float>(h.n_edge), wd = brick_halo_words<double>(h.n_edge);
+    if (wf) v.halo_f = ctx->dalloc<float>(size_t(wf));
+    if (wd) v.halo_d = ctx->dalloc<double>(size_t(wd));
+    if ((wf && !v.halo_f) || (wd && !v.halo_d)) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
+    // the zero pad after the slots is read by the halo kernel and never written
+    if (wf) HIPCHK(hipMemset(v.halo_f + (wf - 64), 0, 64 * sizeof(float)));
+    if (wd) HIPCHK(hipMemset(v.halo_d + (wd - 64), 0, 64 * sizeof(double)));
+  }
+  if (!h.mu_src.empty()) d.mu_src = ctx->upload(h.mu_src);
+  if (!work) return MFGMG_OK;   // an operator only (it shares the viscosity of another level)
+  d.mu_d = ctx->dalloc<double>(size_t(h.ncell));
+  d.mu_f = ctx->dalloc<float>(size_t(h.ncell));
+  v.mu_d = d.mu_d;
+  v.mu_f = d.mu_f;
+  d.minv_d = ctx->dalloc<double>(size_t(3 * h.nnode));
+  d.minv_f = ctx->dalloc<float>(size_t(3 * h.nnode));
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 5; ++k) {
+      if (top && k < 2) continue;   // top-level b, x come from the caller
+      d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
+                            : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
+    }
+  return MFGMG_OK;
+}
+
 int upload_mesh(mfgmg_ctx* ctx) {
   if (ctx->dev_ready) return MFGMG_OK;
   HIPCHK(hipGetDevice(&ctx->device));
@@ -217,301 +519,8 @@ int upload_mesh(mfgmg_ctx* ctx) {
   set_element_constants(kd, E.B, E.M);
   ctx->khat_d = ctx->upload(std::vector<double>(E.K, E.K + 81 * 81));
   for (int ell = 1; ell <= L; ++ell) {
-    const Level& h = m.level(ell);
-    LevelDev& d = ctx->lv[size_t(ell)];
-    DevLevel& v = d.v;
-    v.ell = ell;
-    v.ncell = h.ncell;
-    v.nnode = h.nnode;
-    v.uniform = h.uniform;
-    v.n_edge = h.n_edge;
-    // constrained and hanging node lists
-    std::vector<int64_t> cons;
-    for (int64_t i = 0; i < h.nnode; ++i)
-      if (h.ntype[size_t(i)] != NODE_FREE) cons.push_back(i);
-    v.cons_nodes = ctx->upload(cons);
-    v.n_cons = int64_t(cons.size());
-    if (!h.uniform || ell == L) {   // the leaf keeps cell tables for the pressure operators
-      std::vector<int32_t> slots(static_cast<size_t>(27 * h.ncell));
-      std::vector<int8_t> clev(static_cast<size_t>(h.ncell));
-      std::vector<int32_t> reg, hang;
-      for (int64_t c = 0; c < h.ncell; ++c) {
-        bool hh = false;
-        for (int a = 0; a < 27; ++a) {
-          const int32_t n = h.cell_nodes[size_t(27 * c + a)];
-          int32_t s = n;
-          if (h.ntype[size_t(n)] == NODE_DIRICHLET) s = -1;
-          else if (h.ntype[size_t(n)] == NODE_HANGING) s = -(2 + h.hang_index[size_t(n)]), hh = true;
-          slots[size_t(27 * c + a)] = s;
-        }
-        clev[size_t(c)] = int8_t(h.clev[size_t(c)]);
-        (hh ? hang : reg).push_back(int32_t(c));
-      }
-      v.slots = ctx->upload(slots);
-      v.clev = ctx->upload(clev);
-      v.ntype = ctx->upload(h.ntype);
-      v.reg_cells = ctx->upload(reg);
-      v.n_reg_cells = int64_t(reg.size());
-      v.hang_cells = ctx->upload(hang);
-      v.n_hang_cells = int64_t(hang.size());
-      // operator partition into 4^3 blocks, then 2^3 blocks, then single cells
-      {
-        std::unordered_map<uint64_t, int32_t> at;
-        at.reserve(size_t(h.ncell));
-        auto code = [](int l, int64_t i, int64_t j, int64_t k) {
-          return (uint64_t(l) << 58) | (uint64_t(i) << 38) | (uint64_t(j) << 19) | uint64_t(k);
-        };
-        for (int64_t c = 0; c < h.ncell; ++c)
-          at.emplace(code(h.clev[size_t(c)], h.cijk[size_t(3 * c)], h.cijk[size_t(3 * c + 1)],
-                          h.cijk[size_t(3 * c + 2)]),
-                     int32_t(c));
-        std::vector<char> used(static_cast<size_t>(h.ncell), 0);
-        // A block keeps, per hanging lattice point, its masters as lattice
-        // points of the same block (a hanging node lies on the face shared with
-        // a coarser cell, whose face nodes are all on the block's lattice);
-        // blocks where that fails are left to the single-cell kernel.
-        struct Blocks {
-          std::vector<int32_t> slots, cells, hoff{0}, hent;
-          std::vector<double> hw;
-          std::vector<int32_t> pslots, phoff{0}, phent;   // leaf: Q1 pressure lattice
-          std::vector<double> phw;
-        };
-        const bool leaf = ell == L;
-        auto make_blocks = [&](int B, Blocks& out) {
-          const int E = 2 * B + 1, NC = B * B * B, P = E * E * E, NB = 64 / NC;
-          std::vector<int32_t> cs(static_cast<size_t>(NC)), bs(static_cast<size_t>(P));
-          std::unordered_map<int32_t, int32_t> at_node;
-          std::vector<int32_t> ent;
-          std::vector<double> wt;
-          for (int64_t c = 0; c < h.ncell; ++c) {
-            const int l = h.clev[size_t(c)];
-            const int64_t i = h.cijk[size_t(3 * c)], j = h.cijk[size_t(3 * c + 1)], k = h.cijk[size_t(3 * c + 2)];
-            if (used[size_t(c)] || i % B || j % B || k % B || (int64_t(1) << l) < B) continue;
-            bool ok = true;
-            for (int q = 0; q < NC && ok; ++q) {
-              auto it = at.find(code(l, i + q % B, j + (q / B) % B, k + q / (B * B)));
-              ok = it != at.end() && !used[size_t(it->second)];
-              if (ok) cs[size_t(q)] = it->second;
-            }
-            if (!ok) continue;
-            for (int q = 0; q < NC; ++q) {
-              const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
-              for (int a = 0; a < 27; ++a) {
-                const int p = (2 * qa + a % 3) + E * ((2 * qb + (a / 3) % 3) + E * (2 * qc + a / 9));
-                bs[size_t(p)] = slots[size_t(27 * int64_t(cs[size_t(q)]) + a)];
-              }
-            }
-            at_node.clear();
-            for (int p = 0; p < P; ++p)
-              if (bs[size_t(p)] >= 0) at_node[bs[size_t(p)]] = p;
-            ent.clear();
-            wt.clear();
-            const int32_t bl = int32_t((out.cells.size() / size_t(NC)) % size_t(NB));
-            for (int p = 0; p < P && ok; ++p) {
-              if (bs[size_t(p)] >= -1) continue;
-              const int64_t hr = -int64_t(bs[size_t(p)]) - 2;
-              for (int64_t q = h.hang.ptr[size_t(hr)]; q < h.hang.ptr[size_t(hr + 1)] && ok; ++q) {
-                auto it = at_node.find(h.hang.master[size_t(q)]);
-                ok = it != at_node.end();
-                if (ok) {
-                  ent.push_back(p | (it->second << 10) | (bl << 20));
-                  wt.push_back(h.hang.weight[size_t(q)]);
-                }
-              }
-            }
-            if (!ok) continue;
-            // leaf: the pressure lattice of the block, hanging masters on it as well
-            std::vector<int32_t> pb;
-            std::vector<int32_t> pent;
-            std::vector<double> pwt;
-            if (leaf) {
-              const int EP = B + 1, PP = EP * EP * EP;
-              pb.assign(size_t(PP), -1);
-              for (int q = 0; q < NC; ++q) {
-                const int qa = q % B, qb = (q / B) % B, qc = q / (B * B);
-                for (int a = 0; a < 8; ++a) {
-                  const int pp = (qa + a % 2) + EP * ((qb + (a / 2) % 2) + EP * (qc + a / 4));
-                  pb[size_t(pp)] = h.cell_pnodes[size_t(8 * int64_t(cs[size_t(q)]) + a)];
-                }
-              }
-              std::unordered_map<int32_t, int32_t> pat;
-              for (int pp = 0; pp < PP; ++pp)
-                if (h.ptype[size_t(pb[size_t(pp)])] != NODE_HANGING) pat[pb[size_t(pp)]] = pp;
-              for (int pp = 0; pp < PP && ok; ++pp) {
-                const int32_t nd = pb[size_t(pp)];
-                if (h.ptype[size_t(nd)] != NODE_HANGING) continue;
-                const int32_t hr = h.phang_index[size_t(nd)];
-                for (int64_t q = h.phang.ptr[size_t(hr)]; q < h.phang.ptr[size_t(hr) + 1] && ok; ++q) {
-                  auto it = pat.find(h.phang.master[size_t(q)]);
-                  ok = it != pat.end();
-                  if (ok) {
-                    pent.push_back(pp | (it->second << 10) | (bl << 20));
-                    pwt.push_back(h.phang.weight[size_t(q)]);
-                  }
-                }
-                pb[size_t(pp)] = -2;
-              }
-              if (!ok) continue;
-            }
-            for (int q = 0; q < NC; ++q) {
-              used[size_t(cs[size_t(q)])] = 1;
-              out.cells.push_back(cs[size_t(q)]);
-            }
-            if (leaf) {
-              out.pslots.insert(out.pslots.end(), pb.begin(), pb.end());
-              out.phent.insert(out.phent.end(), pent.begin(), pent.end());
-              out.phw.insert(out.phw.end(), pwt.begin(), pwt.end());
-              out.phoff.push_back(int32_t(out.phent.size()));
-            }
-            for (int p = 0; p < P; ++p) out.slots.push_back(bs[size_t(p)] < -1 ? -2 : bs[size_t(p)]);
-            out.hent.insert(out.hent.end(), ent.begin(), ent.end());
-            out.hw.insert(out.hw.end(), wt.begin(), wt.end());
-            out.hoff.push_back(int32_t(out.hent.size()));
-          }
-        };
-        Blocks b4, b2;
-        std::vector<int32_t> sreg, shang;
-        make_blocks(4, b4);
-        make_blocks(2, b2);
-        for (int64_t c = 0; c < h.ncell; ++c) {
-          if (used[size_t(c)]) continue;
-          bool hh = false;
-          for (int a = 0; a < 27; ++a) hh = hh || slots[size_t(27 * c + a)] < -1;
-          (hh ? shang : sreg).push_back(int32_t(c));
-        }
-        auto upload_blocks = [&](const Blocks& b, DevBlocks& d, int NC) {
-          d.slots = ctx->upload(b.slots);
-          d.cells = ctx->upload(b.cells);
-          d.n = int64_t(b.cells.size() / size_t(NC));
-          d.hoff = ctx->upload(b.hoff);
-          d.hent = ctx->upload(b.hent);
-          d.hw_d = ctx->upload(b.hw);
-          d.hw_f = ctx->upload(std::vector<float>(b.hw.begin(), b.hw.end()));
-          if (leaf) {
-            d.pslots = ctx->upload(b.pslots);
-            d.phoff = ctx->upload(b.phoff);
-            d.phent = ctx->upload(b.phent);
-            d.phw = ctx->upload(b.phw);
-          }
-        };
-        upload_blocks(b4, v.blk4, 64);
-        upload_blocks(b2, v.blk2, 8);
-        // face gather: every free face point of a block -> its slot, grouped by node
-        {
-          std::vector<std::pair<int32_t, int32_t>> nf;   // (node, slot)
-          auto faces = [&](const Blocks& b, int B, int64_t slot0) {
-            const int E = 2 * B + 1, P = E * E * E, NC = B * B * B;
-            const int64_t nb = int64_t(b.cells.size() / size_t(NC));
-            for (int64_t k = 0; k < nb; ++k)
-              for (int p = 0; p < P; ++p) {
-                const int px = p % E, py = (p / E) % E, pz = p / (E * E);
-                const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
-                const int32_t nd = b.slots[size_t(k * P + p)];
-                if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
-              }
-            return slot0 + nb * P;
-          };
-          const int64_t s2 = faces(b4, 4, 0);
-          const int64_t ns = faces(b2, 2, s2);
-          std::sort(nf.begin(), nf.end());
-          std::vector<int32_t> fnode, fptr{0}, fent;
-          for (size_t i = 0; i < nf.size(); ++i) {
-            if (i == 0 || nf[i].first != nf[i - 1].first) {
-              if (i) fptr.push_back(int32_t(fent.size()));
-              fnode.push_back(nf[i].first);
-            }
-            fent.push_back(nf[i].second);
-          }
-          if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
-          v.fslot_blk2 = s2;
-          v.n_face = int64_t(fnode.size());
-          if (v.n_face) {
-            v.face_node = ctx->upload(fnode);
-            v.face_ptr = ctx->upload(fptr);
-            v.face_ent = ctx->upload(fent);
-            v.fslot_f = ctx->dalloc<float>(size_t(3 * ns));
-            v.fslot_d = ctx->dalloc<double>(size_t(3 * ns));
-            if (!v.fslot_f || !v.fslot_d) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
-          }
-        }
-        // the same for the pressure mass blocks of the leaf ((B+1)^3 Q1 lattices)
-        if (leaf) {
-          std::vector<std::pair<int32_t, int32_t>> nf;
-          auto faces = [&](const Blocks& b, int B, int64_t slot0) {
-            const int E = B + 1, P = E * E * E, NC = B * B * B;
-            const int64_t nb = int64_t(b.cells.size() / size_t(NC));
-            for (int64_t k = 0; k < nb; ++k)
-              for (int p = 0; p < P; ++p) {
-                const int px = p % E, py = (p / E) % E, pz = p / (E * E);
-                const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
-                const int32_t nd = b.pslots[size_t(k * P + p)];
-                if (!inner && nd >= 0) nf.emplace_back(nd, int32_t(slot0 + k * P + p));
-              }
-            return slot0 + nb * P;
-          };
-          const int64_t s2 = faces(b4, 4, 0);
-          const int64_t ns = faces(b2, 2, s2);
-          std::sort(nf.begin(), nf.end());
-          std::vector<int32_t> fnode, fptr{0}, fent;
-          for (size_t i = 0; i < nf.size(); ++i) {
-            if (i && nf[i].first != nf[i - 1].first) fptr.push_back(int32_t(fent.size()));
-            if (i == 0 || nf[i].first != nf[i - 1].first) fnode.push_back(nf[i].first);
-            fent.push_back(nf[i].second);
-          }
-          if (!nf.empty()) fptr.push_back(int32_t(fent.size()));
-          v.pfslot_blk2 = s2;
-          v.n_pface = int64_t(fnode.size());
-          if (v.n_pface) {
-            v.pface_node = ctx->upload(fnode);
-            v.pface_ptr = ctx->upload(fptr);
-            v.pface_ent = ctx->upload(fent);
-            v.pfslot = ctx->dalloc<double>(size_t(ns));
-            if (!v.pfslot) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
-          }
-        }
-        v.single_reg = ctx->upload(sreg);
-        v.n_single_reg = int64_t(sreg.size());
-        v.single_hang = ctx->upload(shang);
-        v.n_single_hang = int64_t(shang.size());
-      }
-      v.hptr = ctx->upload(h.hang.ptr);
-      v.hmaster = ctx->upload(h.hang.master);
-      v.hw_d = ctx->upload(h.hang.weight);
-      std::vector<float> wf(h.hang.weight.begin(), h.hang.weight.end());
-      v.hw_f = ctx->upload(wf);
-      v.hnode = ctx->upload(h.hang.node);
-      v.nhang = int64_t(h.hang.count());
-    }
-    if (ell >= 2) {
-      d.P_ptr = ctx->upload(h.P_ptr);
-      d.P_col = ctx->upload(h.P_col);
-      d.P_w = ctx->upload(std::vector<float>(h.P_w.begin(), h.P_w.end()));
-      d.R_ptr = ctx->upload(h.R_ptr);
-      d.R_col = ctx->upload(h.R_col);
-      d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
-    }
-    if (h.uniform) {
-      const int64_t wf = brick_halo_words<float>(h.n_edge), wd = brick_halo_words<double>(h.n_edge);
-      if (wf) v.halo_f = ctx->dalloc<float>(size_t(wf));
-      if (wd) v.halo_d = ctx->dalloc<double>(size_t(wd));
-      if ((wf && !v.halo_f) || (wd && !v.halo_d)) return ctx->set(MFGMG_ERR_NOMEM, "device allocation failed");
-      // the zero pad after the slots is read by the halo kernel and never written
-      if (wf) HIPCHK(hipMemset(v.halo_f + (wf - 64), 0, 64 * sizeof(float)));
-      if (wd) HIPCHK(hipMemset(v.halo_d + (wd - 64), 0, 64 * sizeof(double)));
-    }
-    if (ell < L) d.mu_src = ctx->upload(h.mu_src);
-    d.mu_d = ctx->dalloc<double>(size_t(h.ncell));
-    d.mu_f = ctx->dalloc<float>(size_t(h.ncell));
-    v.mu_d = d.mu_d;
-    v.mu_f = d.mu_f;
-    d.minv_d = ctx->dalloc<double>(size_t(3 * h.nnode));
-    d.minv_f = ctx->dalloc<float>(size_t(3 * h.nnode));
-    for (int p = 0; p < 2; ++p)
-      for (int k = 0; k < 5; ++k) {
-        if (ell == L && k < 2) continue;   // top-level b, x come from the caller
-        d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
-                              : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
-      }
+    const int st = upload_level(ctx, m.level(ell), ctx->lv[size_t(ell)], ell == L, ell == L, ell >= 2, true);
+    if (st) return st;
   }
   // pressure on the leaf
   const Level& lf = m.leaf();
@@ -605,10 +614,14 @@ const double* minv_s_of<double>(const LevelDev& d) {
 // Chebyshev smoothing (Saad, Alg. 12.1) on [lambda/15, lambda], M^{-1} = minv
 template <typename T>
 void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t s) {
+  smooth_on<T>(ctx, ctx->lv[size_t(ell)], b, x, x_zero, s);
+}
+
+template <typename T>
+void smooth_on(mfgmg_ctx* ctx, LevelDev& d, const T* b, T* x, bool x_zero, hipStream_t s) {
   // Chebyshev iteration (Saad, Alg. 12.1) with the residual formed as b - A x
   // at each step (the same iterates as the residual recurrence in exact
   // arithmetic; r is never stored)
-  LevelDev& d = ctx->lv[size_t(ell)];
   const int64_t n = 3 * d.v.nnode;
   T* dd = static_cast<T*>(d.work[prec_index<T>()][3]);
   T* t = static_cast<T*>(d.work[prec_index<T>()][4]);
@@ -687,8 +700,13 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
 
 int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out, hipStream_t s, double* basis,
                    double* ritz) {
-  LevelDev& d = ctx->lv[size_t(ell)];
-  const Level& h = ctx->mesh->level(ell);
+  return lanczos_on(ctx, ctx->lv[size_t(ell)], ctx->mesh->level(ell), minv, lam_out, s, basis, ritz);
+}
+
+// the same on any level: d its device data, h its host mesh (start vector over
+// the free nodes of h by canonical key)
+int lanczos_on(mfgmg_ctx* ctx, LevelDev& d, const Level& h, const double* minv, double* lam_out, hipStream_t s,
+               double* basis, double* ritz) {
   const int64_t n = 3 * h.nnode;
   std::vector<double> r0(static_cast<size_t>(n));
   for (int64_t i = 0; i < h.nnode; ++i)
@@ -838,6 +856,15 @@ template void smooth<float>(mfgmg_ctx*, int, const float*, float*, bool, hipStre
 template void smooth<double>(mfgmg_ctx*, int, const double*, double*, bool, hipStream_t);
 template void vcycle<float>(mfgmg_ctx*, int, const float*, float*, hipStream_t);
 template void vcycle<double>(mfgmg_ctx*, int, const double*, double*, hipStream_t);
+template void smooth_on<float>(mfgmg_ctx*, LevelDev&, const float*, float*, bool, hipStream_t);
+template void smooth_on<double>(mfgmg_ctx*, LevelDev&, const double*, double*, bool, hipStream_t);
+
+// the preconditioner's V-cycle: local smoothing or global coarsening
+template <typename T>
+void vcycle_of(mfgmg_ctx* ctx, bool local, int L, const T* b, T* x, hipStream_t s) {
+  if (local) local_vcycle<T>(ctx, b, x, s);
+  else vcycle<T>(ctx, L, b, x, s);
+}
 
 }  // namespace detail
 }  // namespace mfgmg
@@ -1020,6 +1047,7 @@ int mfgmg_set_viscosity(mfgmg_ctx* ctx, const double* mu_qp, void* stream) {
   if (st) return st;
   st = pressure_setup(ctx, s);
   if (st) return st;
+  ctx->ls_mu_ready = false;   // the local levels take their viscosity on first use
   ctx->mu_ready = true;
   return MFGMG_OK;
 }
@@ -1230,6 +1258,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->block = MFGMG_BLOCK_TRIANGULAR;
   o->schur = MFGMG_SCHUR_CG;
   o->schur_degree = 8;
+  o->hierarchy = MFGMG_GLOBAL_COARSENING;
   return MFGMG_OK;
 }
 
@@ -1244,11 +1273,18 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       (o.vcycle_prec != MFGMG_FP32 && o.vcycle_prec != MFGMG_FP64) || o.krylov < MFGMG_FGMRES ||
       o.krylov > MFGMG_IDR || o.idr_s < 1 || o.idr_s > 8 || (o.block != MFGMG_BLOCK_TRIANGULAR &&
       o.block != MFGMG_BLOCK_DIAGONAL) || (o.schur != MFGMG_SCHUR_CG && o.schur != MFGMG_SCHUR_CHEB) ||
-      o.schur_degree < 1 || o.schur_degree > 64)
+      o.schur_degree < 1 || o.schur_degree > 64 ||
+      (o.hierarchy != MFGMG_GLOBAL_COARSENING && o.hierarchy != MFGMG_LOCAL_SMOOTHING))
     return ctx->set(MFGMG_ERR_INVALID, "bad solver options");
   if (o.krylov != MFGMG_FGMRES && o.schur != MFGMG_SCHUR_CHEB)
     return ctx->set(MFGMG_ERR_INVALID, "GMRES and IDR need the linear (Chebyshev) Schur approximation");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool local = o.hierarchy == MFGMG_LOCAL_SMOOTHING;
+  if (local) {
+    if (o.use_scaling) return ctx->set(MFGMG_ERR_INVALID, "the learned scaling applies to the global-coarsening levels");
+    const int st = local_setup(ctx, s);
+    if (st) return st;
+  }
   const auto t0 = std::chrono::steady_clock::now();
   struct ScalingGuard {   // V-cycles of this solve use the installed scalings iff requested
     mfgmg_ctx* c;
@@ -1367,8 +1403,8 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     hipStream_t cs = ctx->capture_stream;
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      if (fp64) vcycle<double>(ctx, L, tu, zfix, cs);
-      else vcycle<float>(ctx, L, bf, xf, cs);
+      if (fp64) vcycle_of<double>(ctx, local, L, tu, zfix, cs);
+      else vcycle_of<float>(ctx, local, L, bf, xf, cs);
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(cs, &g);
       if (e == hipSuccess) e = hipGraphInstantiate(&vexec, g, nullptr, nullptr, 0);
@@ -1390,12 +1426,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
         (void)hipGraphLaunch(vexec, s);
         launch_scale_copy(nu, 1.0, zfix, z, s);
       } else {
-        vcycle<double>(ctx, L, tu, z, s);
+        vcycle_of<double>(ctx, local, L, tu, z, s);
       }
     } else {
       launch_to_float(nu, tu, bf, s);
       if (vexec) (void)hipGraphLaunch(vexec, s);
-      else vcycle<float>(ctx, L, bf, xf, s);
+      else vcycle_of<float>(ctx, local, L, bf, xf, s);
       launch_to_double(nu, xf, z, s);
     }
     ++vcycles;

@@ -38,6 +38,18 @@ struct LevelDev {
 };
 
 
+// One level of the local-smoothing hierarchy above its uniform base.
+struct LocalDev {
+  LevelDev a;                       // refinement edge fixed: smoother operator, transfers from below, work
+  LevelDev k;                       // refinement edge free: interface terms (shares a's viscosity)
+  const uint8_t* kind = nullptr;    // per node: 0 inner, 1 domain boundary, 2 refinement edge
+  const int32_t* gc_cell = nullptr; // per cell: its cell in the global-coarsening level
+  const int32_t* copy_leaf = nullptr;
+  const int32_t* copy_node = nullptr;
+  int64_t ncopy = 0;
+  void* ext[2][2] = {{nullptr}};    // [prec][coarse correction z, K y_E]
+};
+
 }  // namespace mfgmg
 
 struct mfgmg_ctx {
@@ -64,6 +76,13 @@ struct mfgmg_ctx {
   bool use_scaling = false;     // V-cycles use the installed scalings
   std::vector<void*> scratch;   // learned-part work buffers (released with the context)
   hipStream_t capture_stream = nullptr;   // V-cycle graph capture (default priority)
+  // local-smoothing hierarchy (built on first use)
+  std::vector<mfgmg::LocalDev> ls;
+  bool ls_ready = false;                  // device data of the local levels
+  bool ls_mu_ready = false;               // their viscosity, diagonals, bounds
+  const int32_t* ls_base_leaf = nullptr;  // leaf free nodes whose finest level is the base
+  const int32_t* ls_base_node = nullptr;
+  int64_t ls_base_ncopy = 0;
 
   int set(int code, const std::string& msg) {
     err = msg;
@@ -95,9 +114,12 @@ namespace mfgmg {
 namespace detail {
 
 int upload_mesh(mfgmg_ctx* ctx);
+int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool top, bool transfers, bool work);
 double dot_sync(mfgmg_ctx* ctx, int64_t n, const double* a, const double* b, hipStream_t s);
 template <typename T>
 void smooth(mfgmg_ctx* ctx, int ell, const T* b, T* x, bool x_zero, hipStream_t s);
+template <typename T>
+void smooth_on(mfgmg_ctx* ctx, LevelDev& d, const T* b, T* x, bool x_zero, hipStream_t s);
 template <typename T>
 void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s);
 int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s);
@@ -106,6 +128,12 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s);
 // that eigenvalue (M-orthonormal Lanczos basis (-1)^k z_k / sqrt(r_k . z_k))
 int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam, hipStream_t s,
                    double* basis = nullptr, double* ritz = nullptr);
+int lanczos_on(mfgmg_ctx* ctx, LevelDev& d, const Level& h, const double* minv, double* lam, hipStream_t s,
+               double* basis = nullptr, double* ritz = nullptr);
+// local smoothing: device set-up (idempotent) and one V-cycle on leaf vectors
+int local_setup(mfgmg_ctx* ctx, hipStream_t s);
+template <typename T>
+void local_vcycle(mfgmg_ctx* ctx, const T* b, T* x, hipStream_t s);
 constexpr int kLanczosSteps = 12;
 double splitmix_pm1(uint64_t seed, uint64_t counter);
 int check_level(const mfgmg_ctx* ctx, int32_t level);

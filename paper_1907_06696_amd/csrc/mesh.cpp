@@ -284,6 +284,7 @@ std::string Mesh::finalize() {
   for (int ell = 1; ell <= L_; ++ell) build_level(ell);
   for (int ell = 2; ell <= L_; ++ell) build_transfer(ell);
   for (int ell = 1; ell < L_; ++ell) build_mu_restriction(ell);
+  build_local_smoothing();
   g_scratch = nullptr;
   // masters of hanging nodes must be free
   for (int ell = 1; ell <= L_; ++ell) {
@@ -646,6 +647,175 @@ void Mesh::build_transfer(int ell) {
     }
   }
   // transpose
+  fine.R_ptr.assign(size_t(coarse.nnode) + 1, 0);
+  for (int32_t c : fine.P_col) ++fine.R_ptr[size_t(c) + 1];
+  for (int64_t c = 0; c < coarse.nnode; ++c) fine.R_ptr[size_t(c) + 1] += fine.R_ptr[size_t(c)];
+  fine.R_col.resize(fine.P_col.size());
+  fine.R_w.resize(fine.P_col.size());
+  std::vector<int64_t> pos(fine.R_ptr.begin(), fine.R_ptr.end() - 1);
+  for (int64_t f = 0; f < fine.nnode; ++f)
+    for (int64_t q = fine.P_ptr[size_t(f)]; q < fine.P_ptr[size_t(f) + 1]; ++q) {
+      const int32_t c = fine.P_col[size_t(q)];
+      const int64_t d = pos[size_t(c)]++;
+      fine.R_col[size_t(d)] = int32_t(f);
+      fine.R_w[size_t(d)] = fine.P_w[size_t(q)];
+    }
+}
+
+// Local-smoothing levels: for every level finer than the finest uniform one,
+// the cells of exactly that level (taken from the global-coarsening mesh of
+// the level, in its Morton order), their Q2 nodes, the node kinds and the
+// refinement edge; the transfers from the level below; and, for every free
+// leaf node, the finest level whose cells hold it.
+void Mesh::build_local_smoothing() {
+  const int U = L_ + 1;
+  const int64_t S1 = (int64_t(1) << U) + 1;
+  int base = 0;
+  for (int ell = 1; ell <= L_; ++ell)
+    if (levels_[ell].uniform) base = ell;
+  ls_base_ = base;
+  ls_.assign(size_t(L_ + 1), LocalLevel{});
+  ls_base_leaf_.clear();
+  ls_base_node_.clear();
+  Scratch scratch;
+  scratch.node_map.resize(size_t(L_ + 1));
+  scratch.cell_map.resize(size_t(L_ + 1));
+  Scratch* saved = g_scratch;
+  g_scratch = &scratch;
+  for (int ell = base + 1; ell <= L_; ++ell) {
+    const Level& g = levels_[ell];
+    LocalLevel& t = ls_[size_t(ell)];
+    Level& m = t.mesh;
+    m.ell = ell;
+    m.uniform = false;
+    for (int64_t c = 0; c < g.ncell; ++c)
+      if (g.clev[size_t(c)] == ell) {
+        m.clev.push_back(ell);
+        for (int d = 0; d < 3; ++d) m.cijk.push_back(g.cijk[size_t(3 * c + d)]);
+        t.gc_cell.push_back(int32_t(c));
+      }
+    m.ncell = int64_t(m.clev.size());
+    m.min_cell_level = ell;
+    KeyMap& cmap = scratch.cell_map[size_t(ell)];
+    cmap = KeyMap(size_t(m.ncell));
+    for (int64_t c = 0; c < m.ncell; ++c)
+      cmap.insert(int64_t(cell_code(ell, m.cijk[3 * c], m.cijk[3 * c + 1], m.cijk[3 * c + 2])), int32_t(c));
+    build_nodes(m, false);   // same-level cells: no hanging nodes
+    // kinds; a node is on the refinement edge when a level-ell cell position
+    // touching it, inside the domain, holds no cell of the level
+    const int64_t size = int64_t(1) << (U - ell), n = int64_t(1) << ell;
+    t.kind.assign(size_t(m.nnode), 0);
+    for (int64_t id = 0; id < m.nnode; ++id) {
+      if (m.ntype[size_t(id)] == NODE_DIRICHLET) {
+        t.kind[size_t(id)] = 1;
+        continue;
+      }
+      const int64_t k = m.key[size_t(id)];
+      const int64_t P[3] = {k % S1, (k / S1) % S1, k / (S1 * S1)};
+      int64_t lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        const bool on = P[d] % size == 0;
+        hi[d] = P[d] / size;
+        lo[d] = on ? hi[d] - 1 : hi[d];
+      }
+      bool edge = false;
+      for (int64_t z = lo[2]; z <= hi[2] && !edge; ++z)
+        for (int64_t y = lo[1]; y <= hi[1] && !edge; ++y)
+          for (int64_t x = lo[0]; x <= hi[0] && !edge; ++x) {
+            if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) continue;
+            edge = cmap.find(int64_t(cell_code(ell, x, y, z))) < 0;
+          }
+      if (edge) {
+        t.kind[size_t(id)] = 2;
+        m.ntype[size_t(id)] = NODE_DIRICHLET;
+      }
+    }
+    int64_t nf = 0;
+    for (uint8_t ty : m.ntype) nf += ty == NODE_FREE;
+    m.nfree_nodes = nf;
+  }
+  for (int ell = base + 1; ell <= L_; ++ell) build_local_transfer(ell);
+  if (base < L_) {
+    const Level& leaf = levels_[L_];
+    for (int64_t i = 0; i < leaf.nnode; ++i) {
+      if (leaf.ntype[size_t(i)] != NODE_FREE) continue;
+      const int64_t k = leaf.key[size_t(i)];
+      bool done = false;
+      for (int ell = L_; ell > base && !done; --ell) {
+        const int32_t id = scratch.node_map[size_t(ell)].find(k);
+        if (id >= 0) {
+          ls_[size_t(ell)].copy_leaf.push_back(int32_t(i));
+          ls_[size_t(ell)].copy_node.push_back(id);
+          done = true;
+        }
+      }
+      if (!done) {
+        const int32_t id = find_node(levels_[base], nullptr, k, U);
+        if (id >= 0) {
+          ls_base_leaf_.push_back(int32_t(i));
+          ls_base_node_.push_back(id);
+        }
+      }
+    }
+  }
+  g_scratch = saved;
+}
+
+// P of local level ell from level ell - 1 (the uniform base level or the
+// local level below): the Q2 function of each refined level-(ell-1) cell at
+// its children's nodes; boundary rows empty, boundary columns dropped;
+// refinement-edge rows and columns kept.
+void Mesh::build_local_transfer(int ell) {
+  Level& fine = ls_[size_t(ell)].mesh;
+  const std::vector<uint8_t>& fkind = ls_[size_t(ell)].kind;
+  const bool cbase = ell - 1 == ls_base_;
+  const Level& coarse = cbase ? levels_[ell - 1] : ls_[size_t(ell - 1)].mesh;
+  auto coarse_boundary = [&](int32_t cn) {
+    return cbase ? coarse.ntype[size_t(cn)] == NODE_DIRICHLET : ls_[size_t(ell - 1)].kind[size_t(cn)] == 1;
+  };
+  const int U = L_ + 1;
+  const int64_t S1 = (int64_t(1) << U) + 1;
+  auto key_of = [&](int64_t X, int64_t Y, int64_t Z) { return X + S1 * (Y + S1 * Z); };
+  const KeyMap& fmap = g_scratch->node_map[size_t(ell)];
+  const KeyMap& fcells = g_scratch->cell_map[size_t(ell)];
+  double P1[5][3];
+  for (int a = 0; a < 5; ++a)
+    for (int i = 0; i < 3; ++i) P1[a][i] = q2_at_quarter(a, i);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(static_cast<size_t>(fine.nnode));
+  std::vector<uint8_t> seen(static_cast<size_t>(fine.nnode), 0);
+  for (int64_t c = 0; c < coarse.ncell; ++c) {
+    if (coarse.clev[size_t(c)] != ell - 1) continue;
+    const int64_t ci = coarse.cijk[size_t(3 * c)], cj = coarse.cijk[size_t(3 * c + 1)],
+                  ck = coarse.cijk[size_t(3 * c + 2)];
+    if (fcells.find(int64_t(cell_code(ell, 2 * ci, 2 * cj, 2 * ck))) < 0) continue;   // not refined
+    const int64_t size = int64_t(1) << (U - (ell - 1)), step = size / 4;
+    const int32_t* cn27 = &coarse.cell_nodes[size_t(27 * c)];
+    for (int z = 0; z < 5; ++z)
+      for (int y = 0; y < 5; ++y)
+        for (int x = 0; x < 5; ++x) {
+          const int32_t f = fmap.find(key_of(ci * size + x * step, cj * size + y * step, ck * size + z * step));
+          if (f < 0 || seen[size_t(f)]) continue;
+          seen[size_t(f)] = 1;
+          if (fkind[size_t(f)] == 1) continue;   // domain boundary: empty row
+          for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j)
+              for (int i = 0; i < 3; ++i) {
+                const double w = P1[x][i] * P1[y][j] * P1[z][k];
+                const int32_t cn = cn27[i + 3 * j + 9 * k];
+                if (w != 0.0 && !coarse_boundary(cn)) rows[size_t(f)].emplace_back(cn, w);
+              }
+        }
+  }
+  fine.P_ptr.assign(size_t(fine.nnode) + 1, 0);
+  fine.P_col.clear();
+  fine.P_w.clear();
+  for (int64_t f = 0; f < fine.nnode; ++f) {
+    for (const auto& e : rows[size_t(f)]) {
+      fine.P_col.push_back(e.first);
+      fine.P_w.push_back(e.second);
+    }
+    fine.P_ptr[size_t(f) + 1] = int64_t(fine.P_col.size());
+  }
   fine.R_ptr.assign(size_t(coarse.nnode) + 1, 0);
   for (int32_t c : fine.P_col) ++fine.R_ptr[size_t(c) + 1];
   for (int64_t c = 0; c < coarse.nnode; ++c) fine.R_ptr[size_t(c) + 1] += fine.R_ptr[size_t(c)];

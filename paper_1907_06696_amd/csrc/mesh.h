@@ -62,6 +62,20 @@ struct Level {
   Constraints phang;
 };
 
+// One level of the local-smoothing hierarchy: the cells of refinement level
+// exactly `ell` (a part of the domain once the leaf mesh is adaptive), no
+// hanging nodes.  In `mesh` the nodes on the refinement edge (on the boundary
+// of the part, inside the domain) are typed NODE_DIRICHLET: the level
+// operator of the smoother keeps them fixed.  P/R in `mesh` transfer from
+// the level below, with the refinement-edge rows kept.
+struct LocalLevel {
+  Level mesh;
+  std::vector<uint8_t> kind;        // per node: 0 inner, 1 domain boundary, 2 refinement edge
+  std::vector<int32_t> gc_cell;     // per cell: its index in the global-coarsening mesh of the level
+  std::vector<int32_t> copy_leaf;   // leaf free nodes whose finest level is this one ...
+  std::vector<int32_t> copy_node;   // ... and their node on this level
+};
+
 class Mesh {
  public:
   explicit Mesh(int base_level);
@@ -82,18 +96,32 @@ class Mesh {
   // physical Gauss points of the leaf cells [ncell][27][3]
   void leaf_quadrature_points(double* out) const;
 
+  // local-smoothing hierarchy: levels 1 .. local_base() are the uniform
+  // global-coarsening levels (every cell of the level exists), the finer
+  // ones local_level(ell); local_base() == L() for a uniform leaf mesh.
+  // local_base_copy_*: leaf free nodes whose finest level is local_base().
+  int local_base() const { return ls_base_; }
+  const LocalLevel& local_level(int ell) const { return ls_[size_t(ell)]; }
+  const std::vector<int32_t>& local_base_copy_leaf() const { return ls_base_leaf_; }
+  const std::vector<int32_t>& local_base_copy_node() const { return ls_base_node_; }
+
  private:
   void balance();
   void build_level(int ell);
   void build_nodes(Level& lv, bool q1);
   void build_transfer(int ell);
   void build_mu_restriction(int ell);
+  void build_local_smoothing();
+  void build_local_transfer(int ell);
 
   std::vector<int32_t> lev_;   // active cells
   std::vector<int32_t> ijk_;
   bool finalized_ = false;
   int L_ = 0;
   std::vector<Level> levels_;
+  int ls_base_ = 0;
+  std::vector<LocalLevel> ls_;
+  std::vector<int32_t> ls_base_leaf_, ls_base_node_;
 };
 
 // 1D Q2 Lagrange basis on {0, 1/2, 1} evaluated at t

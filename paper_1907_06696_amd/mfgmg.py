@@ -30,6 +30,7 @@ EXPORTS = [
     "mfgmg_prolongate", "mfgmg_restrict", "mfgmg_smooth", "mfgmg_coarse_solve",
     "mfgmg_assemble_rhs", "mfgmg_apply_div", "mfgmg_apply_grad", "mfgmg_apply_pmass",
     "mfgmg_default_opts", "mfgmg_solve_stokes",
+    "mfgmg_local_levels", "mfgmg_local_nodes", "mfgmg_local_transfer", "mfgmg_vcycle_local",
     "mfgmg_features", "mfgmg_fit_objective", "mfgmg_fit_targets", "mfgmg_set_scaling", "mfgmg_use_scaling",
     "mfgmg_vcycle_factor", "mfgmg_mlp_forward", "mfgmg_mlp_backward", "mfgmg_mlp_work_size", "mfgmg_mlp_adam",
     "mfgmg_mlp_train", "mfgmg_apply_mlp", "mfgmg_vmult_uniform_noalloc",
@@ -52,7 +53,7 @@ class SolveOpts(C.Structure):
                 ("vcycle_prec", C.c_int32), ("schur_rtol", C.c_double), ("schur_max_iter", C.c_int32),
                 ("use_scaling", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32),
                 ("krylov", C.c_int32), ("idr_s", C.c_int32), ("block", C.c_int32), ("schur", C.c_int32),
-                ("schur_degree", C.c_int32)]
+                ("schur_degree", C.c_int32), ("hierarchy", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -100,6 +101,10 @@ def load():
         "mfgmg_apply_pmass": [vp, vp, vp, vp],
         "mfgmg_default_opts": [C.POINTER(SolveOpts)],
         "mfgmg_solve_stokes": [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp],
+        "mfgmg_local_levels": [vp, C.POINTER(i32), vp, vp],
+        "mfgmg_local_nodes": [vp, i32, vp, vp],
+        "mfgmg_local_transfer": [vp, i32, C.POINTER(i64), vp, vp, vp],
+        "mfgmg_vcycle_local": [vp, i32, vp, vp, vp],
         "mfgmg_features": [vp, i32, vp, vp],
         "mfgmg_fit_objective": [vp, i32, vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), vp, vp],
         "mfgmg_fit_targets": [vp, i32, i32, C.c_double, vp, vp, vp],
@@ -399,7 +404,7 @@ class Solver:
         o = SolveOpts()
         self.lib.mfgmg_default_opts(C.byref(o))
         names = {"krylov": {"fgmres": 0, "gmres": 1, "idr": 2}, "block": {"triangular": 0, "diagonal": 1},
-                 "schur": {"cg": 0, "cheb": 1}}
+                 "schur": {"cg": 0, "cheb": 1}, "hierarchy": {"global": 0, "local": 1}}
         fields = {f for f, _ in SolveOpts._fields_}
         for k, v in opts.items():
             if k not in fields:
@@ -420,6 +425,42 @@ class Solver:
         if code != OK and not (code == ERR_NOCONV and not raise_on_noconv):
             self._check(code)
         return stats
+
+    # ---------------------------------------------------- local smoothing
+    def local_levels(self):
+        """(base, n_cells[l], n_nodes[l]) of the local-smoothing hierarchy."""
+        base = C.c_int32()
+        nc = np.zeros(MAX_LEVELS + 1, np.int64)
+        nn = np.zeros(MAX_LEVELS + 1, np.int64)
+        self._check(self.lib.mfgmg_local_levels(self.h, C.byref(base), _np_ptr(nc), _np_ptr(nn)))
+        return base.value, nc, nn
+
+    def local_nodes(self, level):
+        base, _, nn = self.local_levels()
+        if not base < int(level) <= self.info()["L"]:
+            raise ValueError(f"local level {level} outside {base + 1}..{self.info()['L']}")
+        keys = np.empty(int(nn[level]), np.int64)
+        kinds = np.empty(int(nn[level]), np.uint8)
+        self._check(self.lib.mfgmg_local_nodes(self.h, int(level), _np_ptr(keys), _np_ptr(kinds)))
+        return keys, kinds
+
+    def local_transfer(self, level):
+        base, _, nn = self.local_levels()
+        if not base < int(level) <= self.info()["L"]:
+            raise ValueError(f"local level {level} outside {base + 1}..{self.info()['L']}")
+        nnz = C.c_int64()
+        self._check(self.lib.mfgmg_local_transfer(self.h, int(level), C.byref(nnz), None, None, None))
+        ptr = np.empty(int(nn[level]) + 1, np.int64)
+        col = np.empty(nnz.value, np.int64)
+        w = np.empty(nnz.value, np.float64)
+        self._check(self.lib.mfgmg_local_transfer(self.h, int(level), C.byref(nnz), _np_ptr(ptr), _np_ptr(col),
+                                                  _np_ptr(w)))
+        return ptr, col, w
+
+    def vcycle_local(self, rhs, x, stream=None):
+        p, n = _prec_of(rhs), self._nu(self.info()["L"])
+        self._check(self.lib.mfgmg_vcycle_local(self.h, p, _dev_ptr(rhs, n, p, "vcycle rhs"),
+                                                _dev_ptr(x, n, p, "vcycle x"), stream or current_stream()))
 
     # ------------------------------------------------ learned smoother scaling
     def features(self, level, out=None, stream=None):
