@@ -54,8 +54,9 @@ def parse():
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
     p.add_argument("--max-iter", type=int, default=3000, help="FGMRES iteration cap of --solve-workload")
     p.add_argument("--variants", default=None,
-                   help="solves of --solve-workload, comma separated from fp64, fp32, fp32_learned, fp32_gmres, "
-                        "fp32_idr2, fp64_idr2, fp32_diag (default: all on adaptive32p2; on uniform128p1 all but "
+                   help="solves of --solve-workload, comma separated from fp64, fp32, fp32_learned, fp64_local, "
+                        "fp32_local, fp32_gmres, fp32_idr2, fp64_idr2, fp32_diag (default: all on adaptive32p2; "
+                        "on uniform128p1 all but "
                         "fp32_idr2, which stalls near 1e-5 there, and fp32_diag, which needs ~4x the iterations)")
     p.add_argument("--oracle-residual", action="store_true",
                    help="with --solve-workload: recompute every solve's FP64 residual with the oracle")
@@ -124,6 +125,8 @@ def measured_traffic(level, prec):
     return {"bytes": int(c[prec]["bytes_per_application"]), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
+# the local-smoothing hierarchy (level meshes of one refinement level, the
+# multigrid of Sec. 2.2.1's reference) with the FP64 and the FP32 V-cycle;
 # outer-solver variants of Sec. 3.4 (V-cycle precision, options): plain GMRES
 # and IDR(2) with the fixed Chebyshev Schur map (IDR also with the FP64
 # V-cycle: its short recurrences can stall on the FP32 one), FGMRES with the
@@ -131,6 +134,8 @@ def measured_traffic(level, prec):
 # vectors = FP64 block vectors the Krylov method keeps (FGMRES 2m + 1, GMRES
 # m + 2, IDR(s) 3s + 2, each plus b, x, r, w)
 SOLVER_VARIANTS = {
+    "fp64_local": ("fp64", dict(hierarchy="local")),
+    "fp32_local": ("fp32", dict(hierarchy="local")),
     "fp32_gmres": ("fp32", dict(krylov="gmres", schur="cheb")),
     "fp32_idr2": ("fp32", dict(krylov="idr", schur="cheb", idr_s=2)),
     "fp64_idr2": ("fp64", dict(krylov="idr", schur="cheb", idr_s=2)),
@@ -149,6 +154,7 @@ def krylov_vectors(kw, restart):
 
 def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50, keep=None,
                   variants=("fp64", "fp32", "fp32_learned", "fp32_gmres", "fp32_idr2", "fp64_idr2", "fp32_diag")):
+    # (on a uniform mesh the local-smoothing cycle is the global one: not repeated)
     """Stokes solve to 1e-8 (FP64 FGMRES): plain FP64 V-cycle, FP32 V-cycle,
     and FP32 V-cycle with the learned smoother scaling (installed behind its
     guard, estimated with the FP64 V-cycle; a failed learned solve is redone
@@ -550,7 +556,8 @@ def main():
         print("[bench] 64^3 solves done", file=sys.stderr, flush=True)
     s.close()
     if not args.no_solve and not args.no_adaptive:
-        out, keep, keys, cells, cen = solve_workload("adaptive32p2", ("fp64", "fp32", "fp32_learned"),
+        out, keep, keys, cells, cen = solve_workload("adaptive32p2", ("fp64", "fp32", "fp32_learned", "fp64_local",
+                                                                      "fp32_local"),
                                                      verbose=0, oracle_check=not args.no_cpu)
         result["adaptive32p2"] = out
         if keep is not None:

@@ -284,7 +284,6 @@ std::string Mesh::finalize() {
   for (int ell = 1; ell <= L_; ++ell) build_level(ell);
   for (int ell = 2; ell <= L_; ++ell) build_transfer(ell);
   for (int ell = 1; ell < L_; ++ell) build_mu_restriction(ell);
-  build_local_smoothing();
   g_scratch = nullptr;
   // masters of hanging nodes must be free
   for (int ell = 1; ell <= L_; ++ell) {
@@ -369,7 +368,7 @@ void Mesh::build_level(int ell) {
   if (ell == L_) build_nodes(lv, true);
 }
 
-void Mesh::build_nodes(Level& lv, bool q1) {
+void Mesh::build_nodes(Level& lv, bool q1) const {
   const int U = L_ + 1;
   const int64_t S = int64_t(1) << U;
   const int64_t S1 = S + 1;
@@ -667,7 +666,13 @@ void Mesh::build_transfer(int ell) {
 // the level, in its Morton order), their Q2 nodes, the node kinds and the
 // refinement edge; the transfers from the level below; and, for every free
 // leaf node, the finest level whose cells hold it.
-void Mesh::build_local_smoothing() {
+void Mesh::ensure_local() const {
+  if (ls_built_ || !finalized_) return;
+  build_local_smoothing();
+  ls_built_ = true;
+}
+
+void Mesh::build_local_smoothing() const {
   const int U = L_ + 1;
   const int64_t S1 = (int64_t(1) << U) + 1;
   int base = 0;
@@ -765,7 +770,7 @@ void Mesh::build_local_smoothing() {
 // local level below): the Q2 function of each refined level-(ell-1) cell at
 // its children's nodes; boundary rows empty, boundary columns dropped;
 // refinement-edge rows and columns kept.
-void Mesh::build_local_transfer(int ell) {
+void Mesh::build_local_transfer(int ell) const {
   Level& fine = ls_[size_t(ell)].mesh;
   const std::vector<uint8_t>& fkind = ls_[size_t(ell)].kind;
   const bool cbase = ell - 1 == ls_base_;

@@ -100,28 +100,44 @@ class Mesh {
   // global-coarsening levels (every cell of the level exists), the finer
   // ones local_level(ell); local_base() == L() for a uniform leaf mesh.
   // local_base_copy_*: leaf free nodes whose finest level is local_base().
-  int local_base() const { return ls_base_; }
-  const LocalLevel& local_level(int ell) const { return ls_[size_t(ell)]; }
-  const std::vector<int32_t>& local_base_copy_leaf() const { return ls_base_leaf_; }
-  const std::vector<int32_t>& local_base_copy_node() const { return ls_base_node_; }
+  // (built on first use)
+  int local_base() const {
+    ensure_local();
+    return ls_base_;
+  }
+  const LocalLevel& local_level(int ell) const {
+    ensure_local();
+    return ls_[size_t(ell)];
+  }
+  const std::vector<int32_t>& local_base_copy_leaf() const {
+    ensure_local();
+    return ls_base_leaf_;
+  }
+  const std::vector<int32_t>& local_base_copy_node() const {
+    ensure_local();
+    return ls_base_node_;
+  }
 
  private:
   void balance();
   void build_level(int ell);
-  void build_nodes(Level& lv, bool q1);
+  void build_nodes(Level& lv, bool q1) const;
   void build_transfer(int ell);
   void build_mu_restriction(int ell);
-  void build_local_smoothing();
-  void build_local_transfer(int ell);
+  void ensure_local() const;
+  void build_local_smoothing() const;
+  void build_local_transfer(int ell) const;
 
   std::vector<int32_t> lev_;   // active cells
   std::vector<int32_t> ijk_;
   bool finalized_ = false;
   int L_ = 0;
   std::vector<Level> levels_;
-  int ls_base_ = 0;
-  std::vector<LocalLevel> ls_;
-  std::vector<int32_t> ls_base_leaf_, ls_base_node_;
+  // local-smoothing levels, built from the finished global-coarsening levels
+  mutable bool ls_built_ = false;
+  mutable int ls_base_ = 0;
+  mutable std::vector<LocalLevel> ls_;
+  mutable std::vector<int32_t> ls_base_leaf_, ls_base_node_;
 };
 
 // 1D Q2 Lagrange basis on {0, 1/2, 1} evaluated at t

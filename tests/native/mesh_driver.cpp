@@ -55,5 +55,16 @@ int main() {
   std::printf("pressure npnode %ld nhang %zu\npkeys", long(lf.npnode), lf.phang.count());
   for (int64_t k : lf.pkey) std::printf(" %ld", long(k));
   std::printf("\n");
+  // local-smoothing levels: cells, nodes, refinement-edge nodes, transfer entries, copied leaf nodes
+  std::printf("local base %d", m.local_base());
+  size_t copied = m.local_base_copy_leaf().size();
+  for (int ell = m.local_base() + 1; ell <= m.L(); ++ell) {
+    const LocalLevel& t = m.local_level(ell);
+    long edge = 0;
+    for (uint8_t k : t.kind) edge += k == 2;
+    copied += t.copy_leaf.size();
+    std::printf(" | %d %ld %ld %ld %zu", ell, long(t.mesh.ncell), long(t.mesh.nnode), edge, t.mesh.P_col.size());
+  }
+  std::printf(" | copied %zu\n", copied);
   return 0;
 }

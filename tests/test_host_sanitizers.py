@@ -93,3 +93,13 @@ def test_mesh_layer_under_sanitizers_matches_oracle(driver, base, corners, times
     ph = out[pos].split()
     assert int(ph[2]) == H.leaf.npnode
     assert np.array_equal(np.sort(np.array(out[pos + 1].split()[1:], dtype=np.int64)), H.leaf.pkeys)
+    # local-smoothing levels (built under the sanitizers too): sizes against the oracle's
+    from oracle import local_smoothing as ols
+    G = ols.LocalSmoothingGMG(H, ops.level_viscosities(H, np.ones(H.leaf.ncell)))
+    parts = out[pos + 2].split("|")
+    base = int(parts[0].split()[2])
+    for part in parts[1:-1]:
+        ell, nc, nn, ne, _ = (int(v) for v in part.split())
+        assert ell > base and nc == G.T[ell].ncell and nn == G.T[ell].nnode and ne == G.edge[ell][::3].sum()
+    # every free leaf node copied once (a uniform leaf mesh has no local levels)
+    assert int(parts[-1].split()[1]) == (int(H.leaf.free.sum()) if base < H.L else 0)
