@@ -140,6 +140,10 @@ SOLVER_VARIANTS = {
     "fp32_idr2": ("fp32", dict(krylov="idr", schur="cheb", idr_s=2)),
     "fp64_idr2": ("fp64", dict(krylov="idr", schur="cheb", idr_s=2)),
     "fp32_diag": ("fp32", dict(block="diagonal")),
+    # the inner pressure-mass CG tolerance (1e-6 by default)
+    "fp32_schur1e-2": ("fp32", dict(schur_rtol=1e-2)),
+    "fp32_schur1e-3": ("fp32", dict(schur_rtol=1e-3)),
+    "fp32_schur1e-4": ("fp32", dict(schur_rtol=1e-4)),
 }
 
 
@@ -405,7 +409,8 @@ def main():
         variants = args.variants
         if variants is None:
             skip = ("fp32_idr2", "fp32_diag") if args.solve_workload == "uniform128p1" else ()
-            variants = ",".join(["fp64", "fp32", "fp32_learned"] + [v for v in SOLVER_VARIANTS if v not in skip])
+            variants = ",".join(["fp64", "fp32", "fp32_learned"] + [v for v in SOLVER_VARIANTS
+                                                                       if v not in skip and "schur" not in v])
         out, keep, keys, cells, centres = solve_workload(args.solve_workload, variants.split(","), args.max_iter,
                                                          oracle_check=args.oracle_residual)
         if args.oracle_residual:
