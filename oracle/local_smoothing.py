@@ -119,6 +119,7 @@ class LocalSmoothingGMG:
     onto parents, Sec. 2.3)."""
 
     def __init__(self, hier, mus, seed=mg.LAMBDA_SEED):
+        assert hier.bc == "dirichlet", "local smoothing is built for the Dirichlet condition"
         self.hier = hier
         self.L = hier.L
         self.T, self.K, self.A, self.P, self.minv, self.lam = {}, {}, {}, {}, {}, {}

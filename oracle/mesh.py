@@ -169,9 +169,22 @@ class LevelMesh:
       C          csr [nn, nn] node-level constraint matrix: x_full = C x;
                  identity on free nodes, interpolation weights on hanging
                  nodes (free masters only), zero rows on Dirichlet nodes.
+      bc         boundary condition of the velocity (Sec. 2, eq. stokes):
+                 "dirichlet": u = 0 on the boundary (every component of a
+                 boundary node is fixed; Dirichlet wins over hanging);
+                 "noflux": u . n = 0, read on the axis-aligned unit cube as
+                 "component c vanishes on the two faces normal to axis c"
+                 (edge and corner nodes fix two or three components); the
+                 tangential components stay free, their condition (zero
+                 tangential stress) is the natural one of the weak form.
+                 Boundary nodes are then free or hanging at node level, and
+                 the fixed components are removed per dof in ``Cu``.
+      fixed      [nn, 3] bool  components fixed by the boundary condition
     """
 
-    def __init__(self, lev, ijk, U, with_pressure=False):
+    def __init__(self, lev, ijk, U, with_pressure=False, bc="dirichlet"):
+        assert bc in ("dirichlet", "noflux"), bc
+        self.bc = bc
         self.lev = np.asarray(lev, dtype=np.int64)
         self.ijk = np.asarray(ijk, dtype=np.int64)
         self.U = int(U)
@@ -270,7 +283,13 @@ class LevelMesh:
         self.keys = np.unique(allk)
         self.cell_nodes = np.searchsorted(self.keys, allk)
         self.xyz = self.unkey(self.keys)
-        self.dirichlet = np.any((self.xyz == 0) | (self.xyz == self.S), axis=1)
+        on_bnd = (self.xyz == 0) | (self.xyz == self.S)            # [nn, 3] per axis
+        if self.bc == "dirichlet":
+            self.dirichlet = np.any(on_bnd, axis=1)
+            self.fixed = np.repeat(self.dirichlet[:, None], 3, axis=1)
+        else:
+            self.dirichlet = np.zeros(len(self.keys), dtype=bool)
+            self.fixed = on_bnd
         hmap = self._hanging(self.keys, Q2_OFF, Q2_HANG_CAND, 2,
                              lambda loc: fe.q2_basis(loc))
         self._hmap = hmap
@@ -306,10 +325,18 @@ class LevelMesh:
         return (3 * self.cell_nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(self.ncell, 81)
 
     def free_dofs_mask(self):
-        return np.repeat(self.free, 3)
+        return np.repeat(self.free, 3) & ~self.fixed.ravel()
 
     def Cu(self):
-        return sp.kron(self.C, sp.identity(3), format='csr')
+        """Dof-level constraint matrix: kron(C, I_3), and for "noflux" the rows
+        and columns of the components fixed by u . n = 0 zeroed (a hanging
+        node's component interpolates the same component of its masters, and
+        a master's fixed component carries zero)."""
+        Cu = sp.kron(self.C, sp.identity(3), format='csr')
+        if self.bc == "noflux":
+            D = sp.diags((~self.fixed.ravel()).astype(np.float64))
+            Cu = (D @ Cu @ D).tocsr()
+        return Cu
 
     def node_positions(self):
         return self.xyz.astype(np.float64) / self.S
@@ -321,20 +348,21 @@ class LevelMesh:
 class Hierarchy:
     """Leaf mesh plus its global-coarsening level meshes G_1 .. G_L."""
 
-    def __init__(self, lev, ijk):
+    def __init__(self, lev, ijk, bc="dirichlet"):
         lev, ijk = morton_sort(np.asarray(lev, dtype=np.int64), np.asarray(ijk, dtype=np.int64))
         self.L = int(lev.max())
         assert int(lev.min()) >= 1, "the coarsest level mesh is the 2x2x2 mesh"
         self.U = self.L + 1
+        self.bc = bc
         self.levels = {}
         for ell in range(1, self.L + 1):
             l2, c2 = level_cells(lev, ijk, ell)
-            self.levels[ell] = LevelMesh(l2, c2, self.U, with_pressure=(ell == self.L))
+            self.levels[ell] = LevelMesh(l2, c2, self.U, with_pressure=(ell == self.L), bc=bc)
         self.leaf = self.levels[self.L]
 
     @staticmethod
-    def uniform(L):
-        return Hierarchy(*uniform_leaves(L))
+    def uniform(L, bc="dirichlet"):
+        return Hierarchy(*uniform_leaves(L), bc=bc)
 
     def parent_map(self, ell):
         """For each cell of G_ell (ell >= 2): index in G_{ell-1} of the cell that

@@ -248,7 +248,9 @@ def prolongation(hier, ell, dirichlet=True):
     1/2, 3/4, 1, columns the coarse nodes 0, 1/2, 1); for a cell present on
     both levels the nodes coincide.  A fine node shared by several coarse cells
     gets the same value from each (the coarse function is continuous), so the
-    first one is kept.  Fine constrained rows are zeroed."""
+    first one is kept.  Fine constrained rows are zeroed; under the
+    no-normal-flux condition the fixed components of either level carry and
+    receive nothing (rows and columns of kron(., I_3) zeroed per dof)."""
     fine, coarse = hier.levels[ell], hier.levels[ell - 1]
     corg = coarse.cell_origin()
     csize = coarse.cell_size_units()
@@ -277,7 +279,13 @@ def prolongation(hier, ell, dirichlet=True):
         _, ffree, _ = fine.C_no_dirichlet()
         _, _, Cc = coarse.C_no_dirichlet()
     Pn = sp.diags(ffree.astype(np.float64)) @ I @ Cc
-    return sp.kron(Pn.tocsr(), sp.identity(3), format='csr')
+    P = sp.kron(Pn.tocsr(), sp.identity(3), format='csr')
+    if dirichlet and fine.bc == "noflux":
+        # the components fixed by u . n = 0 carry and receive nothing
+        Df = sp.diags((~fine.fixed.ravel()).astype(np.float64))
+        Dc = sp.diags((~coarse.fixed.ravel()).astype(np.float64))
+        P = (Df @ P @ Dc).tocsr()
+    return P
 
 
 def cell_code_of(mesh):
