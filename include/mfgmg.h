@@ -6,7 +6,9 @@
  * geometric multigrid for a Stokes problem on adaptive meshes with variable
  * viscosity" (arXiv 1907.06696).
  *   - problem: -div(2 mu eps(u)) + grad p = f, div u = 0, u = 0 on the boundary
- *     (Sec. 2, eq. stokes), Taylor-Hood Q2-Q1 (Sec. 2.1, eq. weak_form);
+ *     (Sec. 2, eq. stokes), Taylor-Hood Q2-Q1 (Sec. 2.1, eq. weak_form); also
+ *     div u = g (a pressure right-hand side) and the no-normal-flux condition
+ *     u . n = 0 (Sec. 2, the variants named after eq. stokes);
  *   - block system [A B^T; B 0] (Sec. 2.1, eq. stokes_linear_system);
  *   - FGMRES right-preconditioned by P = [A B^T; 0 -S] (Sec. 2.2,
  *     eq. stokes_precond), A^{-1} ~ one matrix-free GMG V-cycle with a degree-4
@@ -28,8 +30,9 @@
  *   - Nodes are identified across layouts by a canonical key: with U = L + 1,
  *     integer coordinates (X, Y, Z) in units of 2^-U, key = X + (S+1)(Y + (S+1)Z),
  *     S = 2^U.
- *   - Constrained dofs (Dirichlet boundary, hanging nodes) have identity rows:
- *     (A x)_i = x_i.  Hanging values are interpolated from their masters
+ *   - Constrained dofs (Dirichlet boundary, hanging nodes, and under
+ *     u . n = 0 the normal component on each boundary face) have identity
+ *     rows: (A x)_i = x_i.  Hanging values are interpolated from their masters
  *     (Lagrange basis on {0, 1/2, 1} / {0, 1}) when a solution is returned.
  *   - Pointers named *_dev are device pointers (e.g. torch CUDA tensors on the
  *     current device); *_host are host pointers.  The caller owns them; device
@@ -78,7 +81,11 @@ typedef struct {
   int32_t uniform[MFGMG_MAX_LEVELS + 1];    /* 1: all 8^l cells of level l */
   int64_t n_p;                              /* leaf Q1 nodes */
   int64_t n_p_hanging;                      /* hanging leaf Q1 nodes */
+  int32_t boundary;                         /* MFGMG_BC_DIRICHLET or MFGMG_BC_NOFLUX */
 } mfgmg_info_t;
+
+/* velocity boundary conditions */
+enum { MFGMG_BC_DIRICHLET = 0, MFGMG_BC_NOFLUX = 1 };
 
 /* ---------------------------------------------------------------- mesh setup
  * The mesh is the unit cube as an octree (abstract; Sec. 3.2 domain).  Host
@@ -87,6 +94,18 @@ typedef struct {
 /* Unit cube refined uniformly to 2^base_level cells per edge
  * (1 <= base_level <= MFGMG_MAX_LEVELS - 2).  *out receives a new context. */
 int mfgmg_create(int32_t base_level, mfgmg_ctx** out);
+
+/* Velocity boundary condition (Sec. 2, eq. stokes and the variants after it),
+ * before mfgmg_finalize_mesh:
+ *   MFGMG_BC_DIRICHLET (default): u = 0 on the boundary;
+ *   MFGMG_BC_NOFLUX: u . n = 0.  On the unit cube component c is fixed (zero)
+ *     on the two faces normal to axis c, at edge and corner nodes two or three
+ *     components; tangential components are unknowns whose condition (zero
+ *     tangential stress) is the natural one of the weak form.  Every level is
+ *     then stored as a general level (mfgmg_info uniform[] = 0) and the local
+ *     smoothing calls are not available (ERR_INVALID).
+ * Errors: ERR_INVALID for another value, ERR_STATE after finalize. */
+int mfgmg_set_boundary(mfgmg_ctx* ctx, int32_t bc);
 
 /* Refine the listed active cells `levels_up` times (each becomes 8^levels_up
  * cells), then restore 2:1 balance across faces, edges and vertices by
@@ -109,7 +128,10 @@ int mfgmg_cells(const mfgmg_ctx* ctx, int32_t level, int32_t* cells_host);
  * field 1: Q1 pressure nodes of the leaf ([n_p]; level must be L). */
 int mfgmg_support_points(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_t* keys_host);
 
-/* Node kinds of a level: 0 free, 1 Dirichlet, 2 hanging.  field as above. */
+/* Node kinds of a level: 0 free, 1 Dirichlet, 2 hanging.  field as above;
+ * field 2: per Q2 node of `level`, the constrained components as bits
+ * (bit c: dof 3*node + c has an identity row): 7 for Dirichlet and hanging
+ * nodes, the fixed components of a no-normal-flux boundary node, else 0. */
 int mfgmg_node_types(const mfgmg_ctx* ctx, int32_t level, int32_t field, uint8_t* types_host);
 
 /* Hanging-node constraints of a level as CSR over the hanging nodes, in the
@@ -121,7 +143,8 @@ int mfgmg_constraints(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_
 
 /* Node-level prolongation from level-1 to level (2 <= level <= L) as CSR
  * over fine nodes: ptr_host[n_nodes[level]+1], col_host[nnz] (coarse nodes),
- * weight_host[nnz].  The velocity prolongation applies it to each component.
+ * weight_host[nnz].  The velocity prolongation applies it to each component
+ * (under u . n = 0, with the fixed components of either level masked out).
  * Rows of constrained fine nodes are empty.  NULL arrays: *nnz only. */
 int mfgmg_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* ptr_host, int64_t* col_host,
                    double* weight_host);

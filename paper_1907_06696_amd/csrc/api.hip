@@ -217,12 +217,24 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
   v.nnode = h.nnode;
   v.uniform = h.uniform;
   v.n_edge = h.n_edge;
-  // constrained and hanging node lists
+  // constrained velocity dofs
   std::vector<int64_t> cons;
   for (int64_t i = 0; i < h.nnode; ++i)
-    if (h.ntype[size_t(i)] != NODE_FREE) cons.push_back(i);
-  v.cons_nodes = ctx->upload(cons);
+    for (int c = 0; c < 3; ++c)
+      if (!h.dof_free(i, c)) cons.push_back(3 * i + c);
+  v.cons_dofs = ctx->upload(cons);
   v.n_cons = int64_t(cons.size());
+  v.noflux = !h.fixmask.empty();
+  if (v.noflux && h.nnode > int64_t(kSlotNodeMask))
+    return ctx->set(MFGMG_ERR_MESH, "no-normal-flux levels are limited to 2^28 nodes");
+  // a free slot with the node's fixed components in its top bits (no-normal-
+  // flux levels; the slot itself otherwise)
+  auto encode = [&](std::vector<int32_t> sl) {
+    if (v.noflux)
+      for (int32_t& x : sl)
+        if (x >= 0) x |= int32_t(h.fixmask[size_t(x)]) << kSlotFixShift;
+    return sl;
+  };
   if (!h.uniform || leaf) {   // the leaf keeps cell tables for the pressure operators
     std::vector<int32_t> slots(static_cast<size_t>(27 * h.ncell));
     std::vector<int8_t> clev(static_cast<size_t>(h.ncell));
@@ -239,9 +251,13 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
       clev[size_t(c)] = int8_t(h.clev[size_t(c)]);
       (hh ? hang : reg).push_back(int32_t(c));
     }
-    v.slots = ctx->upload(slots);
+    v.slots = ctx->upload(encode(slots));
     v.clev = ctx->upload(clev);
-    v.ntype = ctx->upload(h.ntype);
+    {
+      std::vector<uint8_t> cm(static_cast<size_t>(h.nnode));
+      for (int64_t i = 0; i < h.nnode; ++i) cm[size_t(i)] = h.cmask(i);
+      v.cmask = ctx->upload(cm);
+    }
     v.reg_cells = ctx->upload(reg);
     v.n_reg_cells = int64_t(reg.size());
     v.hang_cells = ctx->upload(hang);
@@ -371,7 +387,7 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
         (hh ? shang : sreg).push_back(int32_t(c));
       }
       auto upload_blocks = [&](const Blocks& b, DevBlocks& d, int NC) {
-        d.slots = ctx->upload(b.slots);
+        d.slots = ctx->upload(encode(b.slots));
         d.cells = ctx->upload(b.cells);
         d.n = int64_t(b.cells.size() / size_t(NC));
         d.hoff = ctx->upload(b.hoff);
@@ -558,9 +574,10 @@ int upload_mesh(mfgmg_ctx* ctx) {
     const Level& c1 = m.level(1);
     std::vector<int32_t> fd;
     for (int64_t i = 0; i < c1.nnode; ++i)
-      if (c1.ntype[size_t(i)] == NODE_FREE)
-        for (int c = 0; c < 3; ++c) fd.push_back(int32_t(3 * i + c));
+      for (int c = 0; c < 3; ++c)
+        if (c1.dof_free(i, c)) fd.push_back(int32_t(3 * i + c));
     ctx->ncfree = int(fd.size());
+    if (ctx->ncfree > 375 || c1.nnode != 125) return ctx->set(MFGMG_ERR_MESH, "level 1 is not the 2x2x2 mesh");
     ctx->coarse_free = ctx->upload(fd);
     ctx->Ainv_d = ctx->dalloc<double>(size_t(ctx->ncfree) * ctx->ncfree);
     ctx->Ainv_f = ctx->dalloc<float>(size_t(ctx->ncfree) * ctx->ncfree);
@@ -637,7 +654,7 @@ void smooth_on(mfgmg_ctx* ctx, LevelDev& d, const T* b, T* x, bool x_zero, hipSt
   ChebPrep cp;
   if (prep) {
     cp.tn = t;
-    cp.ntype = d.v.uniform ? nullptr : d.v.ntype;
+    cp.cmask = d.v.uniform ? nullptr : d.v.cmask;
     cp.m = d.v.uniform ? 2 * d.v.n_edge + 1 : 0;
     cp.from_x = true;
   }
@@ -711,9 +728,7 @@ int lanczos_on(mfgmg_ctx* ctx, LevelDev& d, const Level& h, const double* minv, 
   std::vector<double> r0(static_cast<size_t>(n));
   for (int64_t i = 0; i < h.nnode; ++i)
     for (int c = 0; c < 3; ++c)
-      r0[size_t(3 * i + c)] = h.ntype[size_t(i)] == NODE_FREE
-                                  ? splitmix_pm1(12345, uint64_t(3 * h.key[size_t(i)] + c))
-                                  : 0.0;
+      r0[size_t(3 * i + c)] = h.dof_free(i, c) ? splitmix_pm1(12345, uint64_t(3 * h.key[size_t(i)] + c)) : 0.0;
   double* r = static_cast<double*>(d.work[1][2]);
   double* z = static_cast<double*>(d.work[1][3]);
   double* q = static_cast<double*>(d.work[1][4]);
@@ -780,8 +795,8 @@ int factor_coarse(mfgmg_ctx* ctx, hipStream_t s) {
   }
   std::vector<int32_t> fd;
   for (int64_t i = 0; i < c1.nnode; ++i)
-    if (c1.ntype[size_t(i)] == NODE_FREE)
-      for (int c = 0; c < 3; ++c) fd.push_back(int32_t(3 * i + c));
+    for (int c = 0; c < 3; ++c)
+      if (c1.dof_free(i, c)) fd.push_back(int32_t(3 * i + c));
   const int nf = int(fd.size());
   std::vector<double> Af(size_t(nf) * nf);
   for (int i = 0; i < nf; ++i)
@@ -892,6 +907,14 @@ int mfgmg_create(int32_t base_level, mfgmg_ctx** out) {
   return MFGMG_OK;
 }
 
+int mfgmg_set_boundary(mfgmg_ctx* ctx, int32_t bc) {
+  if (!ctx) return MFGMG_ERR_INVALID;
+  if (bc != MFGMG_BC_DIRICHLET && bc != MFGMG_BC_NOFLUX) return ctx->set(MFGMG_ERR_INVALID, "unknown boundary condition");
+  if (ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "mesh already finalized");
+  ctx->mesh->set_noflux(bc == MFGMG_BC_NOFLUX);
+  return MFGMG_OK;
+}
+
 int mfgmg_refine(mfgmg_ctx* ctx, const int32_t* cells, int64_t n, int32_t levels_up) {
   if (!ctx || (!cells && n > 0) || n < 0) return MFGMG_ERR_INVALID;
   if (ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "mesh already finalized");
@@ -927,12 +950,18 @@ int mfgmg_info(const mfgmg_ctx* ctx, mfgmg_info_t* out) {
     out->n_cells[l] = h.ncell;
     out->n_nodes[l] = h.nnode;
     out->n_u[l] = 3 * h.nnode;
-    out->n_free[l] = 3 * h.nfree_nodes;
+    int64_t nf = 0;
+    for (int64_t i = 0; i < h.nnode; ++i) {
+      const unsigned cm = h.cmask(i);
+      nf += 3 - int64_t((cm & 1) + ((cm >> 1) & 1) + ((cm >> 2) & 1));
+    }
+    out->n_free[l] = nf;
     out->n_hanging[l] = int64_t(h.hang.count());
     out->uniform[l] = h.uniform ? 1 : 0;
   }
   out->n_p = m.leaf().npnode;
   out->n_p_hanging = int64_t(m.leaf().phang.count());
+  out->boundary = m.noflux() ? MFGMG_BC_NOFLUX : MFGMG_BC_DIRICHLET;
   return MFGMG_OK;
 }
 
@@ -963,8 +992,12 @@ int mfgmg_support_points(const mfgmg_ctx* ctx, int32_t level, int32_t field, int
 int mfgmg_node_types(const mfgmg_ctx* ctx, int32_t level, int32_t field, uint8_t* types) {
   int st = check_level(ctx, level);
   if (st) return st;
-  if (!types || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
+  if (!types || field < 0 || field > 2 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
   const Level& h = ctx->mesh->level(level);
+  if (field == 2) {
+    for (int64_t i = 0; i < h.nnode; ++i) types[i] = h.cmask(i);
+    return MFGMG_OK;
+  }
   const auto& src = field == 0 ? h.ntype : h.ptype;
   std::memcpy(types, src.data(), src.size());
   return MFGMG_OK;
@@ -1282,6 +1315,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   const bool local = o.hierarchy == MFGMG_LOCAL_SMOOTHING;
   if (local) {
     if (o.use_scaling) return ctx->set(MFGMG_ERR_INVALID, "the learned scaling applies to the global-coarsening levels");
+    if (ctx->mesh->noflux()) return ctx->set(MFGMG_ERR_INVALID, "local smoothing is built for the Dirichlet condition");
     const int st = local_setup(ctx, s);
     if (st) return st;
   }

@@ -18,6 +18,8 @@ inline unsigned grid_for(int64_t n, int block = kBlock, int64_t cap = 1 << 20) {
 }
 
 // velocity slot of local node a of cell c: node >= 0 when free, < 0 otherwise
+// (on general levels a free slot also marks the components fixed by the
+// no-normal-flux condition: slot_node / slot_fixed)
 __device__ __forceinline__ int32_t lslot(const DevLevel& L, int64_t c, int a) {
   if (!L.uniform) return L.slots[27 * c + a];
   const int64_t n = L.n_edge, m = 2 * n + 1;
@@ -34,10 +36,12 @@ __global__ void k_scal_accum(DevLevel L, const double* __restrict__ y, double* _
     for (int a = 0; a < 27; ++a) {
       const int32_t s = lslot(L, c, a);
       if (s < 0) continue;
-      atomicAdd(&acc[3 * int64_t(s)], y0);
-      atomicAdd(&acc[3 * int64_t(s) + 1], y1);
-      atomicAdd(&acc[3 * int64_t(s) + 2], y2);
-      if (cnt) atomicAdd(&cnt[s], 1.0);
+      // a fixed component keeps s = 1 (its acc stays 0)
+      const int64_t b = 3 * int64_t(slot_node(s));
+      if (!slot_fixed(s, 0)) atomicAdd(&acc[b], y0);
+      if (!slot_fixed(s, 1)) atomicAdd(&acc[b + 1], y1);
+      if (!slot_fixed(s, 2)) atomicAdd(&acc[b + 2], y2);
+      if (cnt) atomicAdd(&cnt[slot_node(s)], 1.0);
     }
   }
 }
@@ -64,11 +68,11 @@ __global__ void k_scal_grad(DevLevel L, const double* __restrict__ sbar, const d
     for (int a = 0; a < 27; ++a) {
       const int32_t s = lslot(L, c, a);
       if (s < 0) continue;
-      const int64_t b = 3 * int64_t(s);
-      const double ic = 1.0 / cnt[s];
-      g0 += sbar[b] * sdof[b] * ic;
-      g1 += sbar[b + 1] * sdof[b + 1] * ic;
-      g2 += sbar[b + 2] * sdof[b + 2] * ic;
+      const int64_t b = 3 * int64_t(slot_node(s));
+      const double ic = 1.0 / cnt[slot_node(s)];
+      if (!slot_fixed(s, 0)) g0 += sbar[b] * sdof[b] * ic;
+      if (!slot_fixed(s, 1)) g1 += sbar[b + 1] * sdof[b + 1] * ic;
+      if (!slot_fixed(s, 2)) g2 += sbar[b + 2] * sdof[b + 2] * ic;
     }
     ybar[3 * c] = g0, ybar[3 * c + 1] = g1, ybar[3 * c + 2] = g2;
   }

@@ -104,7 +104,7 @@ struct Fit {
       for (int64_t i = 0; i < h.nnode; ++i)
         for (int q = 0; q < 3; ++q)
           hv[size_t(3 * i + q)] =
-              h.ntype[size_t(i)] == NODE_FREE ? splitmix_pm1(kFitSeed + k, uint64_t(3 * h.key[size_t(i)] + q)) : 0.0;
+              h.dof_free(i, q) ? splitmix_pm1(kFitSeed + k, uint64_t(3 * h.key[size_t(i)] + q)) : 0.0;
       (void)hipMemcpyAsync(es[k], hv.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
       (void)hipStreamSynchronize(s);   // hv is refilled for the next vector
     }
@@ -289,7 +289,7 @@ double vcycle_factor(mfgmg_ctx* ctx, hipStream_t s, int prec, int steps) {
   for (int64_t i = 0; i < h.nnode; ++i)
     for (int q = 0; q < 3; ++q)
       hv[size_t(3 * i + q)] =
-          h.ntype[size_t(i)] == NODE_FREE ? splitmix_pm1(kGuardSeed, uint64_t(3 * h.key[size_t(i)] + q)) : 0.0;
+          h.dof_free(i, q) ? splitmix_pm1(kGuardSeed, uint64_t(3 * h.key[size_t(i)] + q)) : 0.0;
   (void)hipMemcpyAsync(e, hv.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s);
   double rho = 0.0;
   for (int it = 0; it < steps; ++it) {

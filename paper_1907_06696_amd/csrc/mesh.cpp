@@ -308,7 +308,7 @@ void Mesh::build_level(int ell) {
       all_fine = false;
       break;
     }
-  if (all_fine) {
+  if (all_fine && !noflux_) {
     // uniform level mesh: every 8^ell cell of level ell, lexicographic
     const int64_t n = int64_t(1) << ell;
     lv.uniform = true;
@@ -434,12 +434,20 @@ void Mesh::build_nodes(Level& lv, bool q1) const {
   else
     lv.nnode = nn;
   types.assign(size_t(nn), NODE_FREE);
-  if (!q1)
+  if (!q1) {
+    // u = 0: boundary nodes are Dirichlet nodes; u . n = 0: component c of a
+    // node on a face normal to axis c is fixed, the node stays free (or
+    // hanging, below)
+    if (noflux_) lv.fixmask.assign(size_t(nn), 0);
+    else lv.fixmask.clear();
     for (int64_t id = 0; id < nn; ++id) {
       const int64_t k = keys[size_t(id)];
       const int64_t X = k % S1, Y = (k / S1) % S1, Z = k / (S1 * S1);
-      if (X == 0 || Y == 0 || Z == 0 || X == S || Y == S || Z == S) types[size_t(id)] = NODE_DIRICHLET;
+      const bool bx = X == 0 || X == S, by = Y == 0 || Y == S, bz = Z == 0 || Z == S;
+      if (noflux_) lv.fixmask[size_t(id)] = uint8_t((bx ? 1 : 0) | (by ? 2 : 0) | (bz ? 4 : 0));
+      else if (bx || by || bz) types[size_t(id)] = NODE_DIRICHLET;
     }
+  }
 
   // cells adjacent to finer cells: the parents of finer cells touch them
   std::vector<uint8_t> coarse_adj(size_t(lv.ncell), 0);

@@ -35,9 +35,19 @@ struct Level {
   std::vector<int64_t> key;         // canonical key per node
   std::vector<int32_t> cell_nodes;  // [27*ncell]
   std::vector<uint8_t> ntype;       // NodeType per node
+  // no-normal-flux meshes only (empty otherwise): per node, bit c set when
+  // component c is fixed by u . n = 0 (the node lies on a face normal to
+  // axis c); such boundary nodes are NODE_FREE or NODE_HANGING
+  std::vector<uint8_t> fixmask;
   std::vector<int32_t> hang_index;  // per node: row in `hang` or -1
   Constraints hang;
   int64_t nfree_nodes = 0;
+  // per node: bit c set when velocity dof (node, c) is constrained (all three
+  // for Dirichlet and hanging nodes, the fixed ones of a free boundary node)
+  uint8_t cmask(int64_t i) const {
+    return ntype[size_t(i)] != NODE_FREE ? uint8_t(7) : (fixmask.empty() ? uint8_t(0) : fixmask[size_t(i)]);
+  }
+  bool dof_free(int64_t i, int c) const { return !((cmask(i) >> c) & 1); }
 
   // prolongation from level ell-1 (node level, applied per component);
   // rows = nodes of this level (constrained rows empty)
@@ -79,6 +89,11 @@ struct LocalLevel {
 class Mesh {
  public:
   explicit Mesh(int base_level);
+  // velocity boundary condition (before finalize): u = 0 (default) or the
+  // no-normal-flux condition u . n = 0.  Under the latter every level mesh
+  // is built by the general path (no uniform lattice levels).
+  void set_noflux(bool on) { noflux_ = on; }
+  bool noflux() const { return noflux_; }
   // refine the listed active cells `times` levels, then 2:1 balance
   // returns "" on success or an error message
   std::string refine(const int32_t* cells, int64_t n, int times);
@@ -131,6 +146,7 @@ class Mesh {
   std::vector<int32_t> lev_;   // active cells
   std::vector<int32_t> ijk_;
   bool finalized_ = false;
+  bool noflux_ = false;
   int L_ = 0;
   std::vector<Level> levels_;
   // local-smoothing levels, built from the finished global-coarsening levels

@@ -7,6 +7,17 @@
 
 namespace mfgmg {
 
+// Velocity slots (cell tables and block lattices) hold node >= 0 for a free
+// node, -1 for a Dirichlet node, -(2+h) for hanging row h (-2 in blocks).  A
+// free node's slot carries in bits 28..30 the components fixed by the
+// no-normal-flux condition (bit 28 + c: component c), zero under u = 0;
+// node indices stay below 2^28.
+constexpr int kSlotFixShift = 28;
+constexpr int32_t kSlotNodeMask = (int32_t(1) << kSlotFixShift) - 1;
+__host__ __device__ __forceinline__ int32_t slot_node(int32_t s) { return s & kSlotNodeMask; }
+// for a free slot: true when component c is fixed
+__host__ __device__ __forceinline__ bool slot_fixed(int32_t s, int c) { return (s >> (kSlotFixShift + c)) & 1; }
+
 // Blocks of B^3 same-level cells of a non-uniform level: node-box slots
 // [(2B+1)^3] per block (x fastest; node >= 0 free, -1 Dirichlet, -2
 // hanging), cell indices [B^3], and the hanging points' masters as lattice
@@ -37,7 +48,10 @@ struct DevLevel {
   // general (non-uniform) levels
   const int32_t* slots = nullptr;   // [27*ncell]: node >= 0 free, -1 Dirichlet, -(2+h) hanging row h
   const int8_t* clev = nullptr;     // [ncell]
-  const uint8_t* ntype = nullptr;   // [nnode]
+  // [nnode]: bit c set when dof (node, c) is constrained (Dirichlet and
+  // hanging nodes: all three; fixed components of no-normal-flux nodes)
+  const uint8_t* cmask = nullptr;
+  bool noflux = false;              // u . n = 0 on the boundary (general levels only)
   const int64_t* hptr = nullptr;    // hanging CSR
   const int32_t* hmaster = nullptr;
   const float* hw_f = nullptr;
@@ -53,7 +67,7 @@ struct DevLevel {
   int64_t n_single_reg = 0;
   const int32_t* single_hang = nullptr;
   int64_t n_single_hang = 0;
-  const int64_t* cons_nodes = nullptr;  // constrained nodes (Dirichlet + hanging)
+  const int64_t* cons_dofs = nullptr;   // constrained velocity dofs (3 node + c)
   int64_t n_cons = 0;
   const int64_t* hnode = nullptr;       // node of each hanging row
   int64_t nhang = 0;
@@ -117,11 +131,12 @@ void launch_cheb_step(int64_t n, const T* t, const T* minv, T* r, T* d, T* x, do
 // With p.tn set, the smoother's updates (launch_chebx_*) also prepare the
 // output of the next operator call on a level whose operator starts with an
 // initialisation kernel: tn = (constrained ? src : 0), src the new x (from_x)
-// or the new d; that call is then launch_vmult_prepared.  ntype: the level's
-// node types (general levels), else null and m = 2n + 1 (uniform levels).
+// or the new d; that call is then launch_vmult_prepared.  cmask: the level's
+// constrained-component masks (general levels), else null and m = 2n + 1
+// (uniform levels).
 struct ChebPrep {
   void* tn = nullptr;
-  const uint8_t* ntype = nullptr;
+  const uint8_t* cmask = nullptr;
   int64_t m = 0;
   bool from_x = false;
 };
@@ -143,14 +158,17 @@ bool vmult_has_init(const DevLevel& L);
 template <typename T>
 void launch_vmult_prepared(const DevLevel& L, const T* x, T* y, hipStream_t s);
 
-// transfers (node-level CSR, 3 components)
+// transfers (node-level CSR, 3 components).  cm_fine / cm_coarse (may be
+// null): constrained-component masks of the two levels; a masked component
+// neither carries nor receives anything (no-normal-flux levels, where the
+// node-level rows do not express the per-component condition)
 template <typename T>
 void launch_prolong(int64_t nfine, const int64_t* ptr, const int32_t* col, const float* w, const T* coarse, T* fine,
-                    bool add, hipStream_t s);
+                    bool add, hipStream_t s, const uint8_t* cm_fine = nullptr, const uint8_t* cm_coarse = nullptr);
 // coarse = R (b - t) (t may be null: coarse = R b)
 template <typename T>
 void launch_restrict(int64_t ncoarse, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
-                     T* coarse, hipStream_t s);
+                     T* coarse, hipStream_t s, const uint8_t* cm_fine = nullptr, const uint8_t* cm_coarse = nullptr);
 
 // level-aware transfers: structured kernels between two uniform levels,
 // the CSR kernels otherwise

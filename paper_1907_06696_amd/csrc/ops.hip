@@ -76,13 +76,13 @@ __global__ __launch_bounds__(256) void k_init_out_uniform(int64_t n, const T* __
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_init_out_general(int64_t nn, const uint8_t* __restrict__ ntype,
+__global__ __launch_bounds__(256) void k_init_out_general(int64_t nn, const uint8_t* __restrict__ cmask,
                                                           const T* __restrict__ x, T* __restrict__ y) {
   for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
-    const bool b = ntype[v] != 0;
-    y[3 * v] = b ? x[3 * v] : T(0);
-    y[3 * v + 1] = b ? x[3 * v + 1] : T(0);
-    y[3 * v + 2] = b ? x[3 * v + 2] : T(0);
+    const unsigned b = cmask[v];
+    y[3 * v] = (b & 1) ? x[3 * v] : T(0);
+    y[3 * v + 1] = (b & 2) ? x[3 * v + 1] : T(0);
+    y[3 * v + 2] = (b & 4) ? x[3 * v + 2] : T(0);
   }
 }
 
@@ -203,24 +203,30 @@ struct BrickShape<double> {
 // components, exchanged through LDS.  The single cells are few, so the kernel
 // is latency-bound; this cuts each thread's chain of dependent loads,
 // arithmetic and atomics to about a third.
+// (cm: the level's constrained-component masks on no-normal-flux levels,
+// where a master's fixed component carries zero; null otherwise)
 template <typename T>
 __device__ __forceinline__ T gather1(int32_t s, int comp, const T* __restrict__ x, const int64_t* __restrict__ hptr,
-                                     const int32_t* __restrict__ hm, const T* __restrict__ hw) {
-  if (s >= 0) return x[3 * int64_t(s) + comp];
+                                     const int32_t* __restrict__ hm, const T* __restrict__ hw,
+                                     const uint8_t* __restrict__ cm) {
+  if (s >= 0) return slot_fixed(s, comp) ? T(0) : x[3 * int64_t(slot_node(s)) + comp];
   if (s == -1) return T(0);
   const int64_t h = -int64_t(s) - 2;
   T v = T(0);
-  for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) v += hw[q] * x[3 * int64_t(hm[q]) + comp];
+  for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q)
+    if (!cm || !((cm[hm[q]] >> comp) & 1)) v += hw[q] * x[3 * int64_t(hm[q]) + comp];
   return v;
 }
 template <typename T>
 __device__ __forceinline__ void scatter1(int32_t s, int comp, T v, T* __restrict__ y, const int64_t* __restrict__ hptr,
-                                         const int32_t* __restrict__ hm, const T* __restrict__ hw) {
+                                         const int32_t* __restrict__ hm, const T* __restrict__ hw,
+                                         const uint8_t* __restrict__ cm) {
   if (s >= 0) {
-    atomic_add(&y[3 * int64_t(s) + comp], v);
+    if (!slot_fixed(s, comp)) atomic_add(&y[3 * int64_t(slot_node(s)) + comp], v);
   } else if (s < -1) {
     const int64_t h = -int64_t(s) - 2;
-    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) atomic_add(&y[3 * int64_t(hm[q]) + comp], hw[q] * v);
+    for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q)
+      if (!cm || !((cm[hm[q]] >> comp) & 1)) atomic_add(&y[3 * int64_t(hm[q]) + comp], hw[q] * v);
   }
 }
 template <typename T, bool HANG>
@@ -229,7 +235,8 @@ __global__ __launch_bounds__(192) void k_vmult_general3(const int32_t* __restric
                                                         const int8_t* __restrict__ clev, const T* __restrict__ mu,
                                                         const int64_t* __restrict__ hptr,
                                                         const int32_t* __restrict__ hm, const T* __restrict__ hw,
-                                                        const T* __restrict__ x, T* __restrict__ y) {
+                                                        const uint8_t* __restrict__ cm, const T* __restrict__ x,
+                                                        T* __restrict__ y) {
   __shared__ T wsh[3][27][64];
   const int lane = threadIdx.x & 63;
   const int comp = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -242,9 +249,9 @@ __global__ __launch_bounds__(192) void k_vmult_general3(const int32_t* __restric
   for (int a = 0; a < 27; ++a) {
     sl[a] = slots[27 * c + a];
     if constexpr (HANG)
-      w[a] = gather1<T>(sl[a], comp, x, hptr, hm, hw);
+      w[a] = gather1<T>(sl[a], comp, x, hptr, hm, hw, cm);
     else
-      w[a] = sl[a] >= 0 ? x[3 * int64_t(sl[a]) + comp] : T(0);
+      w[a] = sl[a] >= 0 && !slot_fixed(sl[a], comp) ? x[3 * int64_t(slot_node(sl[a])) + comp] : T(0);
   }
   cellop::interp_all(w);
 #pragma unroll
@@ -264,9 +271,9 @@ __global__ __launch_bounds__(192) void k_vmult_general3(const int32_t* __restric
 #pragma unroll
   for (int a = 0; a < 27; ++a) {
     if constexpr (HANG)
-      scatter1<T>(sl[a], comp, w[a], y, hptr, hm, hw);
-    else if (sl[a] >= 0)
-      atomic_add(&y[3 * int64_t(sl[a]) + comp], w[a]);
+      scatter1<T>(sl[a], comp, w[a], y, hptr, hm, hw, cm);
+    else if (sl[a] >= 0 && !slot_fixed(sl[a], comp))
+      atomic_add(&y[3 * int64_t(slot_node(sl[a])) + comp], w[a]);
   }
 }
 
@@ -321,8 +328,9 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
   };
   const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
   // staging: every slot load, then every value load, issued before use;
-  // points of missing blocks, Dirichlet and hanging points store zero.  The
-  // slots stay in registers for the write-back.
+  // points of missing blocks, Dirichlet and hanging points (and components
+  // fixed by the no-normal-flux condition) store zero.  The slots stay in
+  // registers for the write-back.
   int32_t sl[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -333,7 +341,7 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     T v[KP][3];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int64_t i = 3 * int64_t(sl[k] >= 0 ? sl[k] : 0);
+      const int64_t i = 3 * int64_t(sl[k] >= 0 ? slot_node(sl[k]) : 0);
       v[k][0] = x[i], v[k][1] = x[i + 1], v[k][2] = x[i + 2];
     }
 #pragma unroll
@@ -342,9 +350,9 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
       if (pa < NB * P) {
         const int o = lds_of(pa / P, pa % P);
         const bool f = sl[k] >= 0;
-        buf[o] = f ? v[k][0] : T(0);
-        buf[o + P] = f ? v[k][1] : T(0);
-        buf[o + 2 * P] = f ? v[k][2] : T(0);
+        buf[o] = f && !slot_fixed(sl[k], 0) ? v[k][0] : T(0);
+        buf[o + P] = f && !slot_fixed(sl[k], 1) ? v[k][1] : T(0);
+        buf[o + 2 * P] = f && !slot_fixed(sl[k], 2) ? v[k][2] : T(0);
       }
     }
   }
@@ -410,16 +418,19 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
   __syncthreads();
   // write-back of the free points: inside the block stored (added when
   // accumulating); on its faces, where other cells contribute too, to the
-  // block's slots, summed into y by the face gather (no atomics)
+  // block's slots, summed into y by the face gather (no atomics).  Fixed
+  // components (on the domain boundary, so never inside a block) send zero.
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (sl[k] < 0) continue;
     const int pa = lane + 64 * k, p = pa % P;
     const int o = lds_of(pa / P, p);
-    const T v0 = buf[o], v1 = buf[o + P], v2 = buf[o + 2 * P];
+    const T v0 = slot_fixed(sl[k], 0) ? T(0) : buf[o];
+    const T v1 = slot_fixed(sl[k], 1) ? T(0) : buf[o + P];
+    const T v2 = slot_fixed(sl[k], 2) ? T(0) : buf[o + 2 * P];
     const int px = p % E, py = (p / E) % E, pz = p / (E * E);
     const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
-    T* yp = y + 3 * int64_t(sl[k]);
+    T* yp = y + 3 * int64_t(slot_node(sl[k]));
     if (inner && ACC) {
       yp[0] += v0, yp[1] += v1, yp[2] += v2;
     } else if (inner) {
@@ -470,7 +481,7 @@ __global__ __launch_bounds__(kCellBlock) void k_diag_regular(const int32_t* __re
   for (int a = 0; a < 27; ++a) {
     const int32_t sl = slots[27 * c + a];
     if (sl < 0) continue;
-    for (int cc = 0; cc < 3; ++cc) atomicAdd(&d[3 * int64_t(sl) + cc], s * c_khat_diag[3 * a + cc]);
+    for (int cc = 0; cc < 3; ++cc) atomicAdd(&d[3 * int64_t(slot_node(sl)) + cc], s * c_khat_diag[3 * a + cc]);
   }
 }
 
@@ -494,7 +505,7 @@ __global__ __launch_bounds__(64) void k_diag_hanging(const int32_t* __restrict__
     for (int a = 0; a < 27; ++a) {
       const int32_t s = slots[27 * c + a];
       if (s >= 0) {
-        t_a[k] = a, t_m[k] = s, t_w[k] = 1.0, ++k;
+        t_a[k] = a, t_m[k] = slot_node(s), t_w[k] = 1.0, ++k;
       } else if (s < -1) {
         const int64_t h = -int64_t(s) - 2;
         for (int64_t q = hptr[h]; q < hptr[h + 1] && k < 256; ++q) t_a[k] = a, t_m[k] = hm[q], t_w[k] = hw[q], ++k;
@@ -545,12 +556,12 @@ __global__ void k_invert_diag_uniform(int64_t n, const double* __restrict__ d, d
   }
 }
 
-__global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ ntype, const double* __restrict__ d,
+__global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ cmask, const double* __restrict__ d,
                                       double* __restrict__ md, float* __restrict__ mf) {
   for (int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; v < nn; v += int64_t(gridDim.x) * blockDim.x) {
-    const bool b = ntype[v] != 0;
+    const unsigned b = cmask[v];
     for (int c = 0; c < 3; ++c) {
-      const double r = b ? 1.0 : 1.0 / d[3 * v + c];
+      const double r = ((b >> c) & 1) ? 1.0 : 1.0 / d[3 * v + c];
       md[3 * v + c] = r;
       mf[3 * v + c] = float(r);
     }
@@ -561,26 +572,26 @@ __global__ void k_invert_diag_general(int64_t nn, const uint8_t* __restrict__ nt
 // The smoother's Chebyshev updates (k_chebx_*) can also prepare the output of
 // the next operator call on levels whose operator otherwise starts with an
 // initialisation kernel (k_init_out_*): tn = (constrained dof ? src : 0), src
-// being the new d, or the new x when from_x.  Constrained: ntype != 0 on
-// general levels (ntype given), a boundary node of the m^3 lattice on uniform
-// ones.  tn may be t itself (each entry is read before it is written, by the
+// being the new d, or the new x when from_x.  Constrained: the dof's bit of
+// cmask on general levels (cmask given), a boundary node of the m^3 lattice on
+// uniform ones.  tn may be t itself (each entry is read before it is written, by the
 // same thread; t and tn are therefore not restrict).
 template <typename T>
 struct OutPrep {
   T* tn;
-  const uint8_t* ntype;
+  const uint8_t* cmask;
   int64_t m;
   int from_x;
 };
-__device__ __forceinline__ bool constrained_dof(int64_t i, const uint8_t* ntype, int64_t m) {
+__device__ __forceinline__ bool constrained_dof(int64_t i, const uint8_t* cmask, int64_t m) {
   const int64_t v = i / 3;
-  if (ntype) return ntype[v] != 0;
+  if (cmask) return (cmask[v] >> (i - 3 * v)) & 1;
   const int64_t X = v % m, Y = (v / m) % m, Z = v / (m * m);
   return X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1;
 }
 template <typename T>
 __device__ __forceinline__ void out_prep(const OutPrep<T>& o, int64_t i, T di, T xi) {
-  if (o.tn) o.tn[i] = constrained_dof(i, o.ntype, o.m) ? (o.from_x ? xi : di) : T(0);
+  if (o.tn) o.tn[i] = constrained_dof(i, o.cmask, o.m) ? (o.from_x ? xi : di) : T(0);
 }
 
 template <typename T>
@@ -671,10 +682,14 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// (cmf, cmc: constrained-component masks of the fine and coarse level, or
+// null: a masked coarse component carries nothing, a masked fine component
+// receives nothing)
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_prolong(int64_t nf, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                    const T* __restrict__ xc, T* __restrict__ xf, bool add) {
+                                                    const T* __restrict__ xc, T* __restrict__ xf, bool add,
+                                                    const uint8_t* __restrict__ cmf, const uint8_t* __restrict__ cmc) {
   const int sub = int(threadIdx.x) % G;
   for (int64_t f = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / G; f < nf;
        f += int64_t(gridDim.x) * (blockDim.x / G)) {
@@ -682,11 +697,24 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int64_t nf, const int64_t* _
     for (int64_t q = ptr[f] + sub; q < ptr[f + 1]; q += G) {
       const int64_t cc = 3 * int64_t(col[q]);
       const T ww = T(w[q]);
-      a0 += ww * xc[cc];
-      a1 += ww * xc[cc + 1];
-      a2 += ww * xc[cc + 2];
+      if (cmc) {
+        const unsigned m = cmc[col[q]];
+        a0 += (m & 1) ? T(0) : ww * xc[cc];
+        a1 += (m & 2) ? T(0) : ww * xc[cc + 1];
+        a2 += (m & 4) ? T(0) : ww * xc[cc + 2];
+      } else {
+        a0 += ww * xc[cc];
+        a1 += ww * xc[cc + 1];
+        a2 += ww * xc[cc + 2];
+      }
     }
     a0 = group_sum<G>(a0), a1 = group_sum<G>(a1), a2 = group_sum<G>(a2);
+    if (cmf) {
+      const unsigned m = cmf[f];
+      if (m & 1) a0 = T(0);
+      if (m & 2) a1 = T(0);
+      if (m & 4) a2 = T(0);
+    }
     if (sub == 0) {
       if (add) {
         xf[3 * f] += a0;
@@ -705,7 +733,8 @@ template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int64_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ col, const float* __restrict__ w,
                                                      const T* __restrict__ b, const T* __restrict__ t,
-                                                     T* __restrict__ xc) {
+                                                     T* __restrict__ xc, const uint8_t* __restrict__ cmf,
+                                                     const uint8_t* __restrict__ cmc) {
   const int sub = int(threadIdx.x) % G;
   for (int64_t c = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / G; c < nc;
        c += int64_t(gridDim.x) * (blockDim.x / G)) {
@@ -713,17 +742,29 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int64_t* 
     for (int64_t q = ptr[c] + sub; q < ptr[c + 1]; q += G) {
       const int64_t ff = 3 * int64_t(col[q]);
       const T ww = T(w[q]);
+      T r0, r1, r2;
       if (t) {
-        a0 += ww * (b[ff] - t[ff]);
-        a1 += ww * (b[ff + 1] - t[ff + 1]);
-        a2 += ww * (b[ff + 2] - t[ff + 2]);
+        r0 = b[ff] - t[ff], r1 = b[ff + 1] - t[ff + 1], r2 = b[ff + 2] - t[ff + 2];
       } else {
-        a0 += ww * b[ff];
-        a1 += ww * b[ff + 1];
-        a2 += ww * b[ff + 2];
+        r0 = b[ff], r1 = b[ff + 1], r2 = b[ff + 2];
       }
+      if (cmf) {
+        const unsigned m = cmf[col[q]];
+        if (m & 1) r0 = T(0);
+        if (m & 2) r1 = T(0);
+        if (m & 4) r2 = T(0);
+      }
+      a0 += ww * r0;
+      a1 += ww * r1;
+      a2 += ww * r2;
     }
     a0 = group_sum<G>(a0), a1 = group_sum<G>(a1), a2 = group_sum<G>(a2);
+    if (cmc) {
+      const unsigned m = cmc[c];
+      if (m & 1) a0 = T(0);
+      if (m & 2) a1 = T(0);
+      if (m & 4) a2 = T(0);
+    }
     if (sub == 0) {
       xc[3 * c] = a0;
       xc[3 * c + 1] = a1;
@@ -880,10 +921,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict_z(int nc, const T* __restri
 }
 
 // ------------------------------------------------------------- coarse
+// the level-1 mesh (2^3 cells) has 125 Q2 nodes: at most 375 free dofs (81
+// under u = 0, 225 under u . n = 0)
+constexpr int kCoarseMaxFree = 375;
 template <typename T>
 __global__ __launch_bounds__(128) void k_coarse(const T* __restrict__ Ainv, const int32_t* __restrict__ fd,
                                                 int nfree, int n, const T* __restrict__ b, T* __restrict__ x) {
-  __shared__ T bs[128];
+  __shared__ T bs[kCoarseMaxFree];
   for (int i = threadIdx.x; i < nfree; i += blockDim.x) bs[i] = b[fd[i]];
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = b[i];
   __syncthreads();
@@ -1087,21 +1131,28 @@ __device__ __forceinline__ void pscatter(const DevPressure& P, int32_t s, double
   for (int64_t q = P.hptr[h]; q < P.hptr[h + 1]; ++q) atomicAdd(&p[P.hmaster[q]], P.hw[q] * v);
 }
 
+// a hanging node's master component that the no-normal-flux condition fixes
+__device__ __forceinline__ bool master_fixed(const DevLevel& L, int32_t m, int comp) {
+  return L.noflux && ((L.cmask[m] >> comp) & 1);
+}
+
 __device__ __forceinline__ double vgather1(const DevLevel& L, int32_t s, int comp, const double* u) {
-  if (s >= 0) return u[3 * int64_t(s) + comp];
+  if (s >= 0) return slot_fixed(s, comp) ? 0.0 : u[3 * int64_t(slot_node(s)) + comp];
   if (s == -1) return 0.0;
   const int64_t h = -int64_t(s) - 2;
   double v = 0.0;
-  for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q) v += L.hw_d[q] * u[3 * int64_t(L.hmaster[q]) + comp];
+  for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q)
+    if (!master_fixed(L, L.hmaster[q], comp)) v += L.hw_d[q] * u[3 * int64_t(L.hmaster[q]) + comp];
   return v;
 }
 
 __device__ __forceinline__ void vscatter1(const DevLevel& L, int32_t s, int comp, double v, double* u) {
   if (s >= 0) {
-    atomicAdd(&u[3 * int64_t(s) + comp], v);
+    if (!slot_fixed(s, comp)) atomicAdd(&u[3 * int64_t(slot_node(s)) + comp], v);
   } else if (s < -1) {
     const int64_t h = -int64_t(s) - 2;
-    for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q) atomicAdd(&u[3 * int64_t(L.hmaster[q]) + comp], L.hw_d[q] * v);
+    for (int64_t q = L.hptr[h]; q < L.hptr[h + 1]; ++q)
+      if (!master_fixed(L, L.hmaster[q], comp)) atomicAdd(&u[3 * int64_t(L.hmaster[q]) + comp], L.hw_d[q] * v);
   }
 }
 
@@ -1240,10 +1291,13 @@ __global__ __launch_bounds__(64) void k_grad_blocks(DevBlocks blk, DevLevel L, D
     if (sl[k] < 0) continue;
     const int pa = lane + 64 * k, q = pa % PP;
     const int o = lds_of(pa / PP, q);
-    const double v0 = buf[o], v1 = buf[o + PP], v2 = buf[o + 2 * PP];
+    // components fixed by the no-normal-flux condition receive nothing
+    const double v0 = slot_fixed(sl[k], 0) ? 0.0 : buf[o];
+    const double v1 = slot_fixed(sl[k], 1) ? 0.0 : buf[o + PP];
+    const double v2 = slot_fixed(sl[k], 2) ? 0.0 : buf[o + 2 * PP];
     const int px = q % E, py = (q / E) % E, pz = q / (E * E);
     const bool inner = px > 0 && px < E - 1 && py > 0 && py < E - 1 && pz > 0 && pz < E - 1;
-    double* yp = uo + 3 * int64_t(sl[k]);
+    double* yp = uo + 3 * int64_t(slot_node(sl[k]));
     if (inner) {
       yp[0] += v0, yp[1] += v1, yp[2] += v2;
     } else {   // shared face point: the block's slot, added by the face gather
@@ -1475,7 +1529,7 @@ __global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, De
     double v[KP][3];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int64_t i = 3 * int64_t(sl[k] >= 0 ? sl[k] : 0);
+      const int64_t i = 3 * int64_t(sl[k] >= 0 ? slot_node(sl[k]) : 0);
       v[k][0] = u[i], v[k][1] = u[i + 1], v[k][2] = u[i + 2];
     }
 #pragma unroll
@@ -1484,9 +1538,9 @@ __global__ __launch_bounds__(64) void k_div_blocks(DevBlocks blk, DevLevel L, De
       if (pa < NB * PP) {
         const int o = lds_of(pa / PP, pa % PP);
         const bool f = sl[k] >= 0;
-        buf[o] = f ? v[k][0] : 0.0;
-        buf[o + PP] = f ? v[k][1] : 0.0;
-        buf[o + 2 * PP] = f ? v[k][2] : 0.0;
+        buf[o] = f && !slot_fixed(sl[k], 0) ? v[k][0] : 0.0;
+        buf[o + PP] = f && !slot_fixed(sl[k], 1) ? v[k][1] : 0.0;
+        buf[o + 2 * PP] = f && !slot_fixed(sl[k], 2) ? v[k][2] : 0.0;
       }
     }
   }
@@ -1632,13 +1686,19 @@ __global__ void k_p_identity(int64_t nh, const int64_t* __restrict__ nodes, cons
     pout[nodes[i]] = pin[nodes[i]];
 }
 
+// (cm: constrained-component masks on no-normal-flux levels, else null: a
+// master's fixed component carries zero)
 __global__ void k_distribute_u(int64_t nh, const int64_t* __restrict__ nodes, const int64_t* __restrict__ hptr,
-                               const int32_t* __restrict__ hm, const double* __restrict__ hw, double* __restrict__ u) {
+                               const int32_t* __restrict__ hm, const double* __restrict__ hw,
+                               const uint8_t* __restrict__ cm, double* __restrict__ u) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nh; i += int64_t(gridDim.x) * blockDim.x) {
     double v0 = 0, v1 = 0, v2 = 0;
     for (int64_t q = hptr[i]; q < hptr[i + 1]; ++q) {
       const int64_t m = 3 * int64_t(hm[q]);
-      v0 += hw[q] * u[m], v1 += hw[q] * u[m + 1], v2 += hw[q] * u[m + 2];
+      const unsigned f = cm ? cm[hm[q]] : 0u;
+      v0 += (f & 1) ? 0.0 : hw[q] * u[m];
+      v1 += (f & 2) ? 0.0 : hw[q] * u[m + 1];
+      v2 += (f & 4) ? 0.0 : hw[q] * u[m + 2];
     }
     const int64_t n = 3 * nodes[i];
     u[n] = v0, u[n + 1] = v1, u[n + 2] = v2;
@@ -1654,11 +1714,9 @@ __global__ void k_distribute_p(int64_t nh, const int64_t* __restrict__ nodes, co
   }
 }
 
-__global__ void k_zero_nodes(int64_t n, const int64_t* __restrict__ nodes, double* __restrict__ u) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t v = 3 * nodes[i];
-    u[v] = 0, u[v + 1] = 0, u[v + 2] = 0;
-  }
+__global__ void k_zero_dofs(int64_t n, const int64_t* __restrict__ dofs, double* __restrict__ u) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    u[dofs[i]] = 0;
 }
 
 __global__ __launch_bounds__(kCellBlock) void k_rhs(DevLevel L, const double* __restrict__ f,
@@ -1747,7 +1805,7 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
     }
     return;
   }
-  if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, x, y);
+  if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.cmask, x, y);
   T* fs = face_slots<T>(L);
   if (L.blk4.n) {
     if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
@@ -1761,10 +1819,11 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
   }
   if (L.n_single_reg)
     k_vmult_general3<T, false><<<unsigned((L.n_single_reg + 63) / 64), 192, 0, s>>>(
-        L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, x, y);
+        L.single_reg, L.n_single_reg, L.slots, L.clev, mu_of<T>(L), nullptr, nullptr, nullptr, nullptr, x, y);
   if (L.n_single_hang)
     k_vmult_general3<T, true><<<unsigned((L.n_single_hang + 63) / 64), 192, 0, s>>>(
-        L.single_hang, L.n_single_hang, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L), x, y);
+        L.single_hang, L.n_single_hang, L.slots, L.clev, mu_of<T>(L), L.hptr, L.hmaster, hw_of<T>(L),
+        L.noflux ? L.cmask : nullptr, x, y);
   if (L.n_face)
     k_face_gather<T><<<grid_for(L.n_face), kBlock, 0, s>>>(L.n_face, L.face_node, L.face_ptr, L.face_ent, fs, y);
 }
@@ -1805,12 +1864,12 @@ void launch_invert_diag(const DevLevel& L, const double* d, double* md, float* m
   if (L.uniform)
     k_invert_diag_uniform<<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, d, md, mf);
   else
-    k_invert_diag_general<<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.ntype, d, md, mf);
+    k_invert_diag_general<<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.cmask, d, md, mf);
 }
 
 template <typename T>
 OutPrep<T> out_prep_of(const ChebPrep& p) {
-  OutPrep<T> o{static_cast<T*>(p.tn), p.ntype, p.m, p.from_x ? 1 : 0};
+  OutPrep<T> o{static_cast<T*>(p.tn), p.cmask, p.m, p.from_x ? 1 : 0};
   return o;
 }
 template <typename T>
@@ -1853,25 +1912,27 @@ MFGMG_INST_CHEB(double)
 
 template <typename T>
 void launch_prolong(int64_t nf, const int64_t* ptr, const int32_t* col, const float* w, const T* xc, T* xf, bool add,
-                    hipStream_t s) {
-  k_prolong<T, kProlongLanes><<<grid_for(nf * kProlongLanes), kBlock, 0, s>>>(nf, ptr, col, w, xc, xf, add);
+                    hipStream_t s, const uint8_t* cmf, const uint8_t* cmc) {
+  k_prolong<T, kProlongLanes><<<grid_for(nf * kProlongLanes), kBlock, 0, s>>>(nf, ptr, col, w, xc, xf, add, cmf, cmc);
 }
 template <typename T>
 void launch_restrict(int64_t nc, const int64_t* ptr, const int32_t* col, const float* w, const T* b, const T* t,
-                     T* xc, hipStream_t s) {
-  k_restrict<T, kRestrictLanes><<<grid_for(nc * kRestrictLanes), kBlock, 0, s>>>(nc, ptr, col, w, b, t, xc);
+                     T* xc, hipStream_t s, const uint8_t* cmf, const uint8_t* cmc) {
+  k_restrict<T, kRestrictLanes><<<grid_for(nc * kRestrictLanes), kBlock, 0, s>>>(nc, ptr, col, w, b, t, xc, cmf,
+                                                                                  cmc);
 }
 template void launch_prolong<float>(int64_t, const int64_t*, const int32_t*, const float*, const float*, float*, bool,
-                                    hipStream_t);
+                                    hipStream_t, const uint8_t*, const uint8_t*);
 template void launch_prolong<double>(int64_t, const int64_t*, const int32_t*, const float*, const double*, double*,
-                                     bool, hipStream_t);
+                                     bool, hipStream_t, const uint8_t*, const uint8_t*);
 template void launch_restrict<float>(int64_t, const int64_t*, const int32_t*, const float*, const float*,
-                                     const float*, float*, hipStream_t);
+                                     const float*, float*, hipStream_t, const uint8_t*, const uint8_t*);
 template void launch_restrict<double>(int64_t, const int64_t*, const int32_t*, const float*, const double*,
-                                      const double*, double*, hipStream_t);
+                                      const double*, double*, hipStream_t, const uint8_t*, const uint8_t*);
 
 template <typename T>
 void launch_coarse(const T* Ainv, const int32_t* fd, int nfree, int n, const T* b, T* x, hipStream_t s) {
+  if (nfree > kCoarseMaxFree) return;   // cannot happen: the caller checks the coarse mesh
   k_coarse<T><<<1, 128, 0, s>>>(Ainv, fd, nfree, n, b, x);
 }
 template void launch_coarse<float>(const float*, const int32_t*, int, int, const float*, float*, hipStream_t);
@@ -2175,13 +2236,15 @@ void launch_p_identity(const DevPressure& P, const double* pin, double* pout, hi
   if (P.nh) k_p_identity<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, pin, pout);
 }
 void launch_distribute_u(const DevLevel& L, double* u, hipStream_t s) {
-  if (L.nhang) k_distribute_u<<<grid_for(L.nhang), kBlock, 0, s>>>(L.nhang, L.hnode, L.hptr, L.hmaster, L.hw_d, u);
+  if (L.nhang)
+    k_distribute_u<<<grid_for(L.nhang), kBlock, 0, s>>>(L.nhang, L.hnode, L.hptr, L.hmaster, L.hw_d,
+                                                        L.noflux ? L.cmask : nullptr, u);
 }
 void launch_distribute_p(const DevPressure& P, double* p, hipStream_t s) {
   if (P.nh) k_distribute_p<<<grid_for(P.nh), kBlock, 0, s>>>(P.nh, P.hang_nodes, P.hptr, P.hmaster, P.hw, p);
 }
 void launch_zero_constrained(const DevLevel& L, double* u, hipStream_t s) {
-  if (L.n_cons) k_zero_nodes<<<grid_for(L.n_cons), kBlock, 0, s>>>(L.n_cons, L.cons_nodes, u);
+  if (L.n_cons) k_zero_dofs<<<grid_for(L.n_cons), kBlock, 0, s>>>(L.n_cons, L.cons_dofs, u);
 }
 void launch_rhs(const DevLevel& L, const double* f, double* b, hipStream_t s) {
   k_fill<<<grid_for(3 * L.nnode), kBlock, 0, s>>>(3 * L.nnode, 0.0, b);
@@ -2205,8 +2268,11 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
     k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
+  // no-normal-flux levels: the fixed components are masked on both sides
+  const uint8_t* cmf = F.noflux ? F.cmask : nullptr;
+  const uint8_t* cmc = F.noflux ? Cc.cmask : nullptr;
   k_prolong<T, kProlongLanes><<<grid_for(F.nnode * kProlongLanes), kBlock, 0, s>>>(F.nnode, ptr, col, w, xc, xf,
-                                                                                    add);
+                                                                                    add, cmf, cmc);
 }
 
 template <typename T>
@@ -2221,8 +2287,10 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
     k_restrict_z<T><<<grid_for(mc * mc * mc), kBlock, 0, s>>>(nc, s2, xc);
     return;
   }
+  const uint8_t* cmf = F.noflux ? F.cmask : nullptr;
+  const uint8_t* cmc = F.noflux ? Cc.cmask : nullptr;
   k_restrict<T, kRestrictLanes><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(Cc.nnode, ptr, col, w, b,
-                                                                                        t, xc);
+                                                                                        t, xc, cmf, cmc);
 }
 
 #define MFGMG_INST_TRANSFER(T)                                                                                \

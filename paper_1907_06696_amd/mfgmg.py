@@ -34,10 +34,14 @@ EXPORTS = [
     "mfgmg_features", "mfgmg_fit_objective", "mfgmg_fit_targets", "mfgmg_set_scaling", "mfgmg_use_scaling",
     "mfgmg_vcycle_factor", "mfgmg_mlp_forward", "mfgmg_mlp_backward", "mfgmg_mlp_work_size", "mfgmg_mlp_adam",
     "mfgmg_mlp_train", "mfgmg_apply_mlp", "mfgmg_vmult_uniform_noalloc",
-    "mfgmg_last_error", "mfgmg_destroy",
+    "mfgmg_last_error", "mfgmg_destroy", "mfgmg_set_boundary",
 ]
 N_PARAMS = 6147
 MLP_CACHE = 131
+
+
+BC_DIRICHLET, BC_NOFLUX = 0, 1
+BOUNDARY = {"dirichlet": BC_DIRICHLET, "noflux": BC_NOFLUX}
 
 
 class Info(C.Structure):
@@ -45,7 +49,7 @@ class Info(C.Structure):
                 ("n_cells", C.c_int64 * (MAX_LEVELS + 1)), ("n_nodes", C.c_int64 * (MAX_LEVELS + 1)),
                 ("n_u", C.c_int64 * (MAX_LEVELS + 1)), ("n_free", C.c_int64 * (MAX_LEVELS + 1)),
                 ("n_hanging", C.c_int64 * (MAX_LEVELS + 1)), ("uniform", C.c_int32 * (MAX_LEVELS + 1)),
-                ("n_p", C.c_int64), ("n_p_hanging", C.c_int64)]
+                ("n_p", C.c_int64), ("n_p_hanging", C.c_int64), ("boundary", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -77,6 +81,7 @@ def load():
         "mfgmg_create": [i32, C.POINTER(vp)],
         "mfgmg_refine": [vp, vp, i64, i32],
         "mfgmg_finalize_mesh": [vp],
+        "mfgmg_set_boundary": [vp, i32],
         "mfgmg_info": [vp, C.POINTER(Info)],
         "mfgmg_cells": [vp, i32, vp],
         "mfgmg_support_points": [vp, i32, i32, vp],
@@ -233,6 +238,13 @@ class Solver:
             pass
 
     # ---------------------------------------------------------------- mesh
+    def set_boundary(self, bc):
+        """Velocity boundary condition before finalize_mesh: "dirichlet"
+        (u = 0, the default) or "noflux" (u . n = 0)."""
+        if bc not in BOUNDARY:
+            raise ValueError(f"unknown boundary condition {bc!r} (expected one of {sorted(BOUNDARY)})")
+        self._check(self.lib.mfgmg_set_boundary(self.h, BOUNDARY[bc]))
+
     def refine(self, cells, levels_up):
         cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 4)
         self._check(self.lib.mfgmg_refine(self.h, _np_ptr(cells), len(cells), int(levels_up)))
@@ -255,6 +267,7 @@ class Solver:
                 "n_hanging": [int(inf.n_hanging[l]) for l in range(L + 1)],
                 "uniform": [bool(inf.uniform[l]) for l in range(L + 1)],
                 "n_p": int(inf.n_p), "n_p_hanging": int(inf.n_p_hanging),
+                "boundary": "noflux" if inf.boundary == BC_NOFLUX else "dirichlet",
             }
         return self._info
 
@@ -272,7 +285,10 @@ class Solver:
         return out
 
     def node_types(self, level, field=0):
-        n = self.info()["n_nodes"][level] if field == 0 else self.info()["n_p"]
+        """field 0: Q2 node kinds (0 free, 1 Dirichlet, 2 hanging); 1: leaf Q1
+        node kinds; 2: per Q2 node, the constrained velocity components as
+        bits (bit c: dof 3 node + c)."""
+        n = self.info()["n_nodes"][level] if field in (0, 2) else self.info()["n_p"]
         out = np.empty(n, dtype=np.uint8)
         self._check(self.lib.mfgmg_node_types(self.h, level, field, _np_ptr(out)))
         return out

@@ -11,8 +11,11 @@ class Case:
     """Library solver + oracle hierarchy for one mesh and one sinker field."""
 
     def __init__(self, base, corners=(), times=1, sinkers=4, dr=1e3, seed=1, refine_cells=None,
-                 build_oracle=True):
+                 build_oracle=True, bc="dirichlet"):
         self.s = mfgmg.Solver(base)
+        self.bc = bc
+        if bc != "dirichlet":
+            self.s.set_boundary(bc)
         lev, ijk = omesh.uniform_leaves(base)
         cells = None
         if refine_cells is not None:
@@ -35,7 +38,7 @@ class Case:
         self.f_qp_lib = inputs.sinker_force(qp.reshape(-1, 3), self.centres).reshape(-1, 27, 3)
         self.H = None
         if build_oracle:
-            self.H = omesh.Hierarchy(lev, ijk)
+            self.H = omesh.Hierarchy(lev, ijk, bc=bc)
             lf = self.H.leaf
             X = ops.gauss_points_of_cells(lf).reshape(-1, 3)
             self.mu_qp_or = inputs.sinker_mu(X, self.centres, dr).reshape(-1, 27)

@@ -12,7 +12,13 @@ smaller than the largest rows, are held to the same relative accuracy.
 
 The 32^3 case runs the uniform-level kernels used at full size (the brick
 operator with its halo pass, its accumulating form, the structured
-transfers) inside vmult, vmult_add, the smoother and the V-cycle."""
+transfers) inside vmult, vmult_add, the smoother and the V-cycle.
+
+The noflux cases run every check under u . n = 0 (Sec. 2, eq. stokes and
+the variants after it): all levels general, per-component constraints on the
+boundary, hanging nodes on the boundary faces (noflux2+1, noflux3+2); inputs
+carry nonzero values on the fixed components, which the operators must
+ignore."""
 import numpy as np
 import pytest
 
@@ -54,6 +60,11 @@ CASES = {
     "adaptive2+2": dict(base=2, corners=((0, 1, 0),), times=2, dr=1e6),
     "adaptive3+2": dict(base=3, corners=((2, 5, 3), (0, 0, 0), (7, 7, 7)), times=2, dr=1e4, sinkers=6, seed=5),
     "uniform5": dict(base=5, dr=1e4, sinkers=8, seed=2),
+    "noflux2": dict(base=2, bc="noflux"),
+    "noflux2+1": dict(base=2, corners=((0, 1, 0),), times=1, dr=1e4, bc="noflux"),
+    "noflux3+2": dict(base=3, corners=((0, 0, 0), (7, 3, 2), (4, 4, 4)), times=2, dr=1e6, sinkers=6, seed=5,
+                      bc="noflux"),
+    "noflux4": dict(base=4, dr=1e4, sinkers=5, seed=9, bc="noflux"),
 }
 
 
@@ -62,7 +73,7 @@ def case(request):
     _need_gpu()
     c = Case(**CASES[request.param])
     print(f"\n[case {request.param}] L={c.L} cells={c.info['n_cells'][c.L]} n_u={c.info['n_u'][c.L]} "
-          f"hanging={c.info['n_hanging'][c.L]}", flush=True)
+          f"hanging={c.info['n_hanging'][c.L]} bc={c.bc}", flush=True)
     c.s.set_viscosity(c.mu_qp_lib)
     c.gmg = omg.GMG(c.H, c.mus)
     yield c
@@ -226,7 +237,8 @@ def test_pressure_operators_and_rhs(case):
     pu, pp = case.dof_perm(L), case.pnode_perm()
     B = ops.assemble_B(lf)
     Mp = ops.assemble_Mp(lf, case.mus[L])
-    u = inputs.uniform_vector(nu, 51) * lf.free_dofs_mask()
+    # nonzero on the constrained entries too: B ignores them (B = C_p^T B_full C_u)
+    u = inputs.uniform_vector(nu, 51)
     p = inputs.uniform_vector(npp, 52) * lf.pfree
     out_p = torch.empty(npp, dtype=torch.float64, device=DEV)
     case.s.apply_div(to_dev(u[pu]), out_p)

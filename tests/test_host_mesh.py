@@ -30,9 +30,11 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name)
 
 
-def _pair(base, corners=(), times=1):
+def _pair(base, corners=(), times=1, bc="dirichlet"):
     """(library solver, oracle hierarchy) for the same mesh."""
     s = mfgmg.Solver(base)
+    if bc != "dirichlet":
+        s.set_boundary(bc)
     lev, ijk = omesh.uniform_leaves(base)
     if corners:
         cells = np.array([[base, *c] for c in corners], dtype=np.int32)
@@ -43,10 +45,11 @@ def _pair(base, corners=(), times=1):
         lev, ijk = omesh.refine(lev, ijk, mask, times)
         lev, ijk = omesh.balance(lev, ijk)
     s.finalize_mesh()
-    return s, omesh.Hierarchy(lev, ijk)
+    return s, omesh.Hierarchy(lev, ijk, bc=bc)
 
 
 CASES = [(2, (), 1), (3, (), 1), (2, ((1, 1, 1),), 1), (2, ((0, 1, 0),), 2), (3, ((2, 5, 3), (0, 0, 0)), 2)]
+BCS = ["dirichlet", "noflux"]
 
 
 def _constraint_dict(keys, node, ptr, master, w):
@@ -65,11 +68,14 @@ def _oracle_constraints(keys, hanging, Cmat):
     return out
 
 
+@pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("base,corners,times", CASES)
-def test_mesh_nodes_constraints_match_oracle(base, corners, times):
-    s, H = _pair(base, corners, times)
+def test_mesh_nodes_constraints_match_oracle(base, corners, times, bc):
+    s, H = _pair(base, corners, times, bc)
     inf = s.info()
-    assert inf["L"] == H.L and inf["U"] == H.U
+    assert inf["L"] == H.L and inf["U"] == H.U and inf["boundary"] == bc
+    if bc == "noflux":
+        assert not any(inf["uniform"])
     for ell in range(1, H.L + 1):
         om = H.levels[ell]
         keys = s.support_points(ell)
@@ -84,7 +90,11 @@ def test_mesh_nodes_constraints_match_oracle(base, corners, times):
         pos = np.searchsorted(om.keys, keys)
         ot = np.where(om.dirichlet, 1, np.where(om.hanging, 2, 0))[pos]
         assert np.array_equal(t, ot)
-        assert inf["n_free"][ell] == 3 * int(om.free.sum())
+        assert inf["n_free"][ell] == int(om.free_dofs_mask().sum())
+        # constrained components per node (bit c: dof 3 node + c)
+        cm = s.node_types(ell, 2)
+        ocm = ((~om.free_dofs_mask()).reshape(-1, 3) * np.array([1, 2, 4])).sum(axis=1)[pos]
+        assert np.array_equal(cm, ocm)
         # hanging constraints
         cs = s.constraints(ell)
         assert _constraint_dict(keys, *cs) == _oracle_constraints(om.keys, om.hanging, om.C)
@@ -98,9 +108,10 @@ def test_mesh_nodes_constraints_match_oracle(base, corners, times):
     s.close()
 
 
+@pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("base,corners,times", CASES)
-def test_transfers_match_oracle(base, corners, times):
-    s, H = _pair(base, corners, times)
+def test_transfers_match_oracle(base, corners, times, bc):
+    s, H = _pair(base, corners, times, bc)
     for ell in range(2, H.L + 1):
         ptr, col, w = s.transfer(ell)
         fk, ck = s.support_points(ell), s.support_points(ell - 1)
@@ -109,7 +120,10 @@ def test_transfers_match_oracle(base, corners, times):
         # map library numbering to the oracle's (sorted keys)
         Pl = sp.csr_matrix((w, (np.searchsorted(f.keys, fk)[rows], np.searchsorted(c.keys, ck)[col])),
                            shape=(f.nnode, c.nnode))
-        Po = ops.prolongation(H, ell)[0::3, 0::3]
+        # node level: with u = 0 the component-0 block of the oracle's P; with
+        # u . n = 0 the per-dof masks are applied on the device, the node-level
+        # CSR is the transfer without boundary condition
+        Po = ops.prolongation(H, ell, dirichlet=(bc == "dirichlet"))[0::3, 0::3]
         assert abs(Pl - Po).max() < 1e-15
     s.close()
 
@@ -139,3 +153,29 @@ def test_quadrature_points_and_rejects():
     with pytest.raises(mfgmg.MFGMGError):
         mfgmg.Solver(0)
     t.close()
+
+
+def test_boundary_condition_calls():
+    """u . n = 0 is chosen before finalize (ERR_STATE after, ERR_INVALID for an
+    unknown value); its levels are all general; the local-smoothing hierarchy,
+    built for u = 0, is refused."""
+    s = mfgmg.Solver(2)
+    assert s.lib.mfgmg_set_boundary(s.h, 7) == mfgmg.ERR_INVALID
+    with pytest.raises(ValueError):
+        s.set_boundary("slip")
+    s.set_boundary("noflux")
+    s.set_boundary("dirichlet")
+    s.set_boundary("noflux")
+    s.refine(np.array([[2, 0, 1, 0]], dtype=np.int32), 1)
+    s.finalize_mesh()
+    inf = s.info()
+    assert inf["boundary"] == "noflux" and not any(inf["uniform"][1:])
+    assert s.lib.mfgmg_set_boundary(s.h, mfgmg.BC_DIRICHLET) == mfgmg.ERR_STATE
+    with pytest.raises(mfgmg.MFGMGError) as e:
+        s.local_levels()
+    assert e.value.code == mfgmg.ERR_INVALID
+    s.close()
+    d = mfgmg.Solver(2)
+    d.finalize_mesh()
+    assert d.info()["boundary"] == "dirichlet" and all(d.info()["uniform"][1:])
+    d.close()
