@@ -232,7 +232,8 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length (50) */
   int32_t max_iter;       /* total outer iterations (1000) */
   int32_t vcycle_prec;    /* MFGMG_FP32 or MFGMG_FP64 */
-  double schur_rtol;      /* inner pressure-mass CG tolerance (1e-6) */
+  double schur_rtol;      /* inner pressure-mass CG tolerance (1e-2: the
+                             1-5 inner iterations of Sec. 2.2.2) */
   int32_t schur_max_iter; /* (200) */
   int32_t use_scaling;    /* 1: use the installed smoother scaling */
   int32_t verbose;        /* > 0: every `verbose` outer iterations print the

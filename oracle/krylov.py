@@ -299,12 +299,14 @@ class StokesProblem:
         return self.K @ x
 
     def precondition(self, r, a_inv=None, s_inv=None, block="triangular", schur="cg", schur_degree=8,
-                     schur_rtol=1e-6, schur_maxit=200):
+                     schur_rtol=1e-2, schur_maxit=200):
         """z = P^{-1} r: z_p = -S_hat^{-1} r_p, z_u = A_hat^{-1}(r_u - B^T z_p)
         (block "triangular", eq. stokes_precond) or A_hat^{-1} r_u (block
         "diagonal", eq. stokes_precond_diag).  S_hat^{-1}: Jacobi CG ("cg", to
         schur_rtol or at most schur_maxit iterations) or the fixed Chebyshev
-        iteration ("cheb") on M_p."""
+        iteration ("cheb") on M_p.  The default tolerance 1e-2 is the reading
+        of Sec. 2.2.2, which states the count (1-5 CG iterations) rather than a
+        tolerance."""
         ru, rp = r[:self.nu], r[self.nu:]
         if s_inv is not None:
             zp_pos = s_inv(rp)

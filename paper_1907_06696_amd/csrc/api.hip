@@ -1281,7 +1281,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->restart = 50;
   o->max_iter = 1000;
   o->vcycle_prec = MFGMG_FP32;
-  o->schur_rtol = 1e-6;
+  o->schur_rtol = 1e-2;   // Sec. 2.2.2: the inner CG converges in 1-5 iterations
   o->schur_max_iter = 200;
   o->use_scaling = 0;
   o->verbose = 0;

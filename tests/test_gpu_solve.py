@@ -302,8 +302,8 @@ def test_solver_variants_match_oracle(name):
 
 
 def test_capped_inner_cg_matches_oracle():
-    """Inner CG stopped by its iteration cap (3 steps, far from its 1e-6
-    tolerance) on a uniform leaf (two-kernel iterations with the direction
+    """Inner CG stopped by its iteration cap (3 steps, far from a 1e-6
+    tolerance set for this test) on a uniform leaf (two-kernel iterations with the direction
     update fused into M_p p) and on an adaptive leaf (the block kernels): every
     preconditioner application runs exactly 3 CG steps on both sides, but the
     first, whose pressure residual is zero (no divergence right-hand side) and
@@ -315,7 +315,7 @@ def test_capped_inner_cg_matches_oracle():
         L = c.L
         nu, npp = c.info["n_u"][L], c.info["n_p"]
         prob = krylov.StokesProblem(c.H, ops.harmonic_cell_viscosity(c.mu_qp_or), c.f_qp_or, gmg_kwargs={})
-        x_or, st_or = prob.solve(rtol=1e-8, restart=50, maxit=600, schur_maxit=3)
+        x_or, st_or = prob.solve(rtol=1e-8, restart=50, maxit=600, schur_rtol=1e-6, schur_maxit=3)
         assert prob.inner_cg_its[0] == 0 and all(it == 3 for it in prob.inner_cg_its[1:])
         xd = prob.solve_direct()
         # both stop at residual 1e-8; the error that leaves depends on the
@@ -326,7 +326,7 @@ def test_capped_inner_cg_matches_oracle():
         c.s.assemble_rhs(c.f_qp_lib, rhs)
         u = torch.empty(nu, dtype=torch.float64, device=DEV)
         p = torch.empty(npp, dtype=torch.float64, device=DEV)
-        st = c.s.solve_stokes(rhs, u, p, vcycle_prec="fp64", max_iter=600, schur_max_iter=3)
+        st = c.s.solve_stokes(rhs, u, p, vcycle_prec="fp64", max_iter=600, schur_rtol=1e-6, schur_max_iter=3)
         torch.cuda.synchronize()
         x = np.zeros(nu + npp)
         x[pu] = u.cpu().numpy()
@@ -361,8 +361,10 @@ def test_gmres_needs_the_linear_schur_map():
 
 def test_nonzero_divergence_manufactured():
     """div u = g through the pressure right-hand side (rhs_p): b = K [u*; p*]
-    built on the CPU from a discrete u*, p*, solved on the device; the
-    solution recovers (u*, p*) to the residual times the condition number."""
+    built on the CPU from a discrete u*, p*, solved on the device to 1e-11;
+    the solution recovers (u*, p*) to the residual times the condition number
+    (on the adaptive case the oracle's own FGMRES leaves 1.2e-5 at 1e-11 and
+    1.2e-4 at 1e-10, mostly in the pressure)."""
     for kw in (dict(base=2, sinkers=3, dr=1e2, seed=4),
                dict(base=3, corners=((2, 5, 3), (0, 0, 0)), times=1, sinkers=4, dr=1e3, seed=7)):
         c = Case(**kw)
@@ -385,7 +387,7 @@ def test_nonzero_divergence_manufactured():
         for prec in ("fp64", "fp32"):
             u = torch.empty(nu, dtype=torch.float64, device=DEV)
             p = torch.empty(npp, dtype=torch.float64, device=DEV)
-            st = c.s.solve_stokes(rhs_u, u, p, rhs_p=rhs_p, vcycle_prec=prec, rtol=1e-10, max_iter=600)
+            st = c.s.solve_stokes(rhs_u, u, p, rhs_p=rhs_p, vcycle_prec=prec, rtol=1e-11, max_iter=600)
             torch.cuda.synchronize()
             x = np.zeros(nu + npp)
             x[pu] = u.cpu().numpy()
@@ -394,5 +396,5 @@ def test_nonzero_divergence_manufactured():
             x[nu:] *= lf.pfree
             res, err = prob.residual(x), np.linalg.norm(x - xs) / np.linalg.norm(xs)
             print(f"  div u = g {prec}: its={st['iterations']} res={res:.2e} err={err:.2e}", flush=True)
-            assert st["converged"] == 1 and res <= 2e-10 and err <= 1e-4, (prec, res, err)
+            assert st["converged"] == 1 and res <= 2e-11 and err <= 1e-4, (prec, res, err)
         c.close()
