@@ -26,6 +26,9 @@ viscosity", arXiv 1907.06696):
                     OOPSLA 2014), used for start vectors the method draws.
 * ``learned``    -- MLP smoother scaling (not part of the paper; the learned
                     extension of the smoother).
+* ``local_smoothing`` -- the local-smoothing level hierarchy and V-cycle.
+* ``q3q2``       -- the Q3-Q2 pair (k = 2 of Sec. 2.1) on uniform meshes:
+                    element, operators, transfers, GMG and the Stokes solve.
 
 Where the paper is silent the oracle takes the readings listed in the design
 notes (basis, quadrature, constraint weights, Chebyshev interval, ...); each
