@@ -82,6 +82,7 @@ typedef struct {
   int64_t n_p;                              /* leaf Q1 nodes */
   int64_t n_p_hanging;                      /* hanging leaf Q1 nodes */
   int32_t boundary;                         /* MFGMG_BC_DIRICHLET or MFGMG_BC_NOFLUX */
+  int32_t element_k;                        /* 1: Q2-Q1, 2: Q3-Q2 (mfgmg_set_element) */
 } mfgmg_info_t;
 
 /* velocity boundary conditions */
@@ -106,6 +107,25 @@ int mfgmg_create(int32_t base_level, mfgmg_ctx** out);
  *     smoothing calls are not available (ERR_INVALID).
  * Errors: ERR_INVALID for another value, ERR_STATE after finalize. */
 int mfgmg_set_boundary(mfgmg_ctx* ctx, int32_t bc);
+
+/* Taylor-Hood pair [Q_{k+1}]^3 x Q_k (Sec. 2.1), before mfgmg_finalize_mesh:
+ * k = 1: Q2-Q1 (default, every call of this header);
+ * k = 2: Q3-Q2 on uniform meshes (no mfgmg_refine) with u = 0.  Support points
+ *   are the Gauss-Lobatto points of each direction, 4 Gauss points per
+ *   direction integrate the forms.  A level of n = 2^l cells per edge stores
+ *   its Q3 nodes X + m (Y + m Z), m = 3n + 1 (cell (i, j, k), local node (a, b,
+ *   c): X = 3i + a, ...), and the leaf its Q2 pressure nodes on the (2n + 1)^3
+ *   lattice; these lattice indices are the keys mfgmg_support_points returns.
+ *   Viscosity and body force are given at the 64 Gauss points of each leaf
+ *   cell (mfgmg_leaf_quadrature_points: [n_cells][64][3]); node kinds,
+ *   transfers, vmult, vmult_add, the diagonal, smoother, transfers, coarse
+ *   solve, V-cycle, right-hand side, B, B^T, M_p and mfgmg_solve_stokes (FGMRES
+ *   with the CG Schur solve, either block preconditioner) work as for k = 1;
+ *   the Chebyshev Schur map (its interval is the Q1 one), the local smoothing
+ *   and the learned scaling return ERR_INVALID.
+ * Errors: ERR_INVALID for another k; ERR_STATE after finalize; ERR_MESH from
+ * finalize for k = 2 on a refined mesh or with MFGMG_BC_NOFLUX. */
+int mfgmg_set_element(mfgmg_ctx* ctx, int32_t k);
 
 /* Refine the listed active cells `levels_up` times (each becomes 8^levels_up
  * cells), then restore 2:1 balance across faces, edges and vertices by

@@ -20,9 +20,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-munsafe-fp-atomics",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-Wall", "-Wno-unused-function"]
-SOURCES = [("mesh.cpp", False), ("ops.hip", True), ("api.hip", True), ("learned.hip", True), ("learned_api.hip", True),
-           ("noalloc.hip", True),
-           ("local_api.hip", True)]
+SOURCES = [("mesh.cpp", False), ("q3.cpp", False), ("ops.hip", True), ("api.hip", True), ("learned.hip", True),
+           ("learned_api.hip", True), ("noalloc.hip", True), ("local_api.hip", True), ("q3_ops.hip", True)]
 
 
 def _run(cmd):

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include "q3.h"
+
 #include "../../include/mfgmg.h"
 #include "ctx.h"
 #include "mesh.h"
@@ -523,6 +525,55 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
   return MFGMG_OK;
 }
 
+// Device data of a Q3-Q2 lattice level: constrained-component masks and
+// list, transfers (node-level CSR with FP64 weights), viscosity, inverse
+// diagonal and work vectors; the Q3 kernels compute node indices from the
+// lattice, so no cell tables are needed.
+int upload_q3_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool top, const double* kdiag) {
+  DevLevel& v = d.v;
+  v.ell = h.ell;
+  v.ncell = h.ncell;
+  v.nnode = h.nnode;
+  v.uniform = false;
+  v.q3 = true;
+  v.n_edge = h.n_edge;
+  v.q3_kdiag = kdiag;
+  std::vector<int64_t> cons;
+  std::vector<uint8_t> cm(static_cast<size_t>(h.nnode));
+  for (int64_t i = 0; i < h.nnode; ++i) {
+    cm[size_t(i)] = h.cmask(i);
+    for (int c = 0; c < 3; ++c)
+      if (!h.dof_free(i, c)) cons.push_back(3 * i + c);
+  }
+  v.cmask = ctx->upload(cm);
+  v.cons_dofs = ctx->upload(cons);
+  v.n_cons = int64_t(cons.size());
+  if (h.ell >= 2) {
+    d.P_ptr = ctx->upload(h.P_ptr);
+    d.P_col = ctx->upload(h.P_col);
+    d.P_w = ctx->upload(std::vector<float>(h.P_w.begin(), h.P_w.end()));
+    d.R_ptr = ctx->upload(h.R_ptr);
+    d.R_col = ctx->upload(h.R_col);
+    d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
+    v.q3_Pw = ctx->upload(h.P_w);
+    v.q3_Rw = ctx->upload(h.R_w);
+  }
+  if (!h.mu_src.empty()) d.mu_src = ctx->upload(h.mu_src);
+  d.mu_d = ctx->dalloc<double>(size_t(h.ncell));
+  d.mu_f = ctx->dalloc<float>(size_t(h.ncell));
+  v.mu_d = d.mu_d;
+  v.mu_f = d.mu_f;
+  d.minv_d = ctx->dalloc<double>(size_t(3 * h.nnode));
+  d.minv_f = ctx->dalloc<float>(size_t(3 * h.nnode));
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 5; ++k) {
+      if (top && k < 2) continue;
+      d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
+                            : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
+    }
+  return MFGMG_OK;
+}
+
 int upload_mesh(mfgmg_ctx* ctx) {
   if (ctx->dev_ready) return MFGMG_OK;
   HIPCHK(hipGetDevice(&ctx->device));
@@ -534,13 +585,33 @@ int upload_mesh(mfgmg_ctx* ctx) {
   for (int i = 0; i < 81; ++i) kd[i] = E.K[i * 81 + i];
   set_element_constants(kd, E.B, E.M);
   ctx->khat_d = ctx->upload(std::vector<double>(E.K, E.K + 81 * 81));
-  for (int ell = 1; ell <= L; ++ell) {
-    const int st = upload_level(ctx, m.level(ell), ctx->lv[size_t(ell)], ell == L, ell == L, ell >= 2, true);
-    if (st) return st;
+  if (m.velocity_degree() == 3) {
+    // Q3-Q2: lattice levels, the pressure on the leaf's Q2 lattice (no constraints)
+    const Q3Element& Q = q3_element();
+    double N[16], D[16], P2[12], M2[9], kd[192];
+    for (int q = 0; q < 4; ++q)
+      for (int a = 0; a < 4; ++a) N[4 * q + a] = Q.N[q][a], D[4 * q + a] = Q.D[q][a];
+    for (int q = 0; q < 4; ++q)
+      for (int i = 0; i < 3; ++i) P2[3 * q + i] = Q.P2[q][i];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M2[3 * i + j] = Q.M2[i][j];
+    for (int i = 0; i < 192; ++i) kd[i] = Q.K[size_t(i) * 192 + i];
+    set_q3_constants(N, D, Q.wg, P2, M2);
+    const double* kdiag = ctx->upload(std::vector<double>(kd, kd + 192));
+    for (int ell = 1; ell <= L; ++ell) {
+      const int st = upload_q3_level(ctx, m.vlevel(ell), ctx->lv[size_t(ell)], ell == L, kdiag);
+      if (st) return st;
+    }
+    ctx->pres.np = m.vleaf().npnode;
+  } else {
+    for (int ell = 1; ell <= L; ++ell) {
+      const int st = upload_level(ctx, m.level(ell), ctx->lv[size_t(ell)], ell == L, ell == L, ell >= 2, true);
+      if (st) return st;
+    }
   }
   // pressure on the leaf
-  const Level& lf = m.leaf();
-  {
+  const Level& lf = m.vleaf();
+  if (m.velocity_degree() == 2) {
     std::vector<int32_t> ps(static_cast<size_t>(8 * lf.ncell));
     for (int64_t c = 0; c < lf.ncell; ++c)
       for (int i = 0; i < 8; ++i) {
@@ -571,13 +642,13 @@ int upload_mesh(mfgmg_ctx* ctx) {
   }
   // coarse level: free dofs of level 1
   {
-    const Level& c1 = m.level(1);
+    const Level& c1 = m.vlevel(1);
     std::vector<int32_t> fd;
     for (int64_t i = 0; i < c1.nnode; ++i)
       for (int c = 0; c < 3; ++c)
         if (c1.dof_free(i, c)) fd.push_back(int32_t(3 * i + c));
     ctx->ncfree = int(fd.size());
-    if (ctx->ncfree > 375 || c1.nnode != 125) return ctx->set(MFGMG_ERR_MESH, "level 1 is not the 2x2x2 mesh");
+    if (ctx->ncfree > 375 || c1.ncell != 8) return ctx->set(MFGMG_ERR_MESH, "level 1 is not the 2x2x2 mesh");
     ctx->coarse_free = ctx->upload(fd);
     ctx->Ainv_d = ctx->dalloc<double>(size_t(ctx->ncfree) * ctx->ncfree);
     ctx->Ainv_f = ctx->dalloc<float>(size_t(ctx->ncfree) * ctx->ncfree);
@@ -717,7 +788,7 @@ int estimate_lambda(mfgmg_ctx* ctx, int ell, hipStream_t s) {
 
 int lanczos_lambda(mfgmg_ctx* ctx, int ell, const double* minv, double* lam_out, hipStream_t s, double* basis,
                    double* ritz) {
-  return lanczos_on(ctx, ctx->lv[size_t(ell)], ctx->mesh->level(ell), minv, lam_out, s, basis, ritz);
+  return lanczos_on(ctx, ctx->lv[size_t(ell)], ctx->mesh->vlevel(ell), minv, lam_out, s, basis, ritz);
 }
 
 // the same on any level: d its device data, h its host mesh (start vector over
@@ -775,14 +846,29 @@ int lanczos_on(mfgmg_ctx* ctx, LevelDev& d, const Level& h, const double* minv, 
 }
 
 int factor_coarse(mfgmg_ctx* ctx, hipStream_t s) {
-  const Level& c1 = ctx->mesh->level(1);
+  const Level& c1 = ctx->mesh->vlevel(1);
   std::vector<double> mu(static_cast<size_t>(c1.ncell));
   HIPCHK(hipMemcpyAsync(mu.data(), ctx->lv[1].mu_d, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const Element& E = element();
   const int64_t n = 3 * c1.nnode;
   std::vector<double> A(size_t(n * n), 0.0);
-  for (int64_t c = 0; c < c1.ncell; ++c) {
+  if (ctx->mesh->velocity_degree() == 3) {
+    // Q3 level 1 (2 x 2 x 2 cells, 7^3 lattice nodes): mu_K h K_hat per cell
+    const Q3Element& Q = q3_element();
+    const int64_t m = 3 * c1.n_edge + 1;
+    for (int64_t c = 0; c < c1.ncell; ++c) {
+      const double sc = mu[size_t(c)] / double(c1.n_edge);
+      const int64_t ci = c % c1.n_edge, cj = (c / c1.n_edge) % c1.n_edge, ck = c / (c1.n_edge * c1.n_edge);
+      int64_t nd[64];
+      for (int a = 0; a < 64; ++a)
+        nd[a] = (3 * ci + a % 4) + m * ((3 * cj + (a / 4) % 4) + m * (3 * ck + a / 16));
+      for (int a = 0; a < 192; ++a)
+        for (int b = 0; b < 192; ++b)
+          A[size_t((3 * nd[a / 3] + a % 3) * n + 3 * nd[b / 3] + b % 3)] += sc * Q.K[size_t(a) * 192 + b];
+    }
+  }
+  for (int64_t c = 0; c < (ctx->mesh->velocity_degree() == 3 ? 0 : c1.ncell); ++c) {
     const double sc = mu[size_t(c)] * std::ldexp(1.0, -c1.clev[size_t(c)]);
     for (int a = 0; a < 27; ++a)
       for (int b = 0; b < 27; ++b)
@@ -811,6 +897,34 @@ int factor_coarse(mfgmg_ctx* ctx, hipStream_t s) {
 
 // Jacobi preconditioner of M_p and the zero-mean weights (host, from leaf mu)
 int pressure_setup(mfgmg_ctx* ctx, hipStream_t s) {
+  if (ctx->mesh->velocity_degree() == 3) {
+    // Q2 pressure on the (2n+1)^3 lattice: Jacobi from diag(M_p) (device),
+    // mean weights int psi_j = h^3 (row sums of the 1D Q2 mass: 1/6, 2/3, 1/6)
+    const Level& lf = ctx->mesh->vleaf();
+    const DevLevel& v = ctx->lv[size_t(ctx->mesh->L())].v;
+    const int64_t n = lf.n_edge, mp = 2 * n + 1;
+    launch_fill(lf.npnode, 0.0, ctx->pmass_minv, s);
+    launch_pmass_diag_q2(v, ctx->pmass_minv, s);
+    std::vector<double> dg(static_cast<size_t>(lf.npnode));
+    HIPCHK(hipMemcpyAsync(dg.data(), ctx->pmass_minv, dg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (double& x : dg) x = 1.0 / x;
+    const double h3 = 1.0 / double(n * n * n), rs[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    std::vector<double> mw(static_cast<size_t>(lf.npnode), 0.0);
+    for (int64_t c = 0; c < lf.ncell; ++c) {
+      const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+      for (int a = 0; a < 27; ++a)
+        mw[size_t((2 * i + a % 3) + mp * ((2 * j + (a / 3) % 3) + mp * (2 * k + a / 9)))] +=
+            h3 * rs[a % 3] * rs[(a / 3) % 3] * rs[a / 9];
+    }
+    double tot = 0.0;
+    for (double x : mw) tot += x;
+    ctx->pmean_total = tot;
+    HIPCHK(hipMemcpyAsync(ctx->pmass_minv, dg.data(), dg.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->pmean_w, mw.data(), mw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MFGMG_OK;
+  }
   const Level& lf = ctx->mesh->leaf();
   const Element& E = element();
   std::vector<double> mu(static_cast<size_t>(lf.ncell));
@@ -907,6 +1021,14 @@ int mfgmg_create(int32_t base_level, mfgmg_ctx** out) {
   return MFGMG_OK;
 }
 
+int mfgmg_set_element(mfgmg_ctx* ctx, int32_t k) {
+  if (!ctx) return MFGMG_ERR_INVALID;
+  if (k != 1 && k != 2) return ctx->set(MFGMG_ERR_INVALID, "element: k = 1 (Q2-Q1) or k = 2 (Q3-Q2)");
+  if (ctx->mesh->finalized()) return ctx->set(MFGMG_ERR_STATE, "mesh already finalized");
+  ctx->mesh->set_velocity_degree(k + 1);
+  return MFGMG_OK;
+}
+
 int mfgmg_set_boundary(mfgmg_ctx* ctx, int32_t bc) {
   if (!ctx) return MFGMG_ERR_INVALID;
   if (bc != MFGMG_BC_DIRICHLET && bc != MFGMG_BC_NOFLUX) return ctx->set(MFGMG_ERR_INVALID, "unknown boundary condition");
@@ -946,7 +1068,7 @@ int mfgmg_info(const mfgmg_ctx* ctx, mfgmg_info_t* out) {
   out->n_levels = m.L();
   out->unit_exponent = m.U();
   for (int l = 1; l <= m.L(); ++l) {
-    const Level& h = m.level(l);
+    const Level& h = m.vlevel(l);
     out->n_cells[l] = h.ncell;
     out->n_nodes[l] = h.nnode;
     out->n_u[l] = 3 * h.nnode;
@@ -959,8 +1081,9 @@ int mfgmg_info(const mfgmg_ctx* ctx, mfgmg_info_t* out) {
     out->n_hanging[l] = int64_t(h.hang.count());
     out->uniform[l] = h.uniform ? 1 : 0;
   }
-  out->n_p = m.leaf().npnode;
-  out->n_p_hanging = int64_t(m.leaf().phang.count());
+  out->n_p = m.vleaf().npnode;
+  out->n_p_hanging = int64_t(m.vleaf().phang.count());
+  out->element_k = m.velocity_degree() - 1;
   out->boundary = m.noflux() ? MFGMG_BC_NOFLUX : MFGMG_BC_DIRICHLET;
   return MFGMG_OK;
 }
@@ -983,7 +1106,7 @@ int mfgmg_support_points(const mfgmg_ctx* ctx, int32_t level, int32_t field, int
   int st = check_level(ctx, level);
   if (st) return st;
   if (!keys || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
-  const Level& h = ctx->mesh->level(level);
+  const Level& h = ctx->mesh->vlevel(level);
   const auto& src = field == 0 ? h.key : h.pkey;
   std::memcpy(keys, src.data(), src.size() * sizeof(int64_t));
   return MFGMG_OK;
@@ -993,7 +1116,7 @@ int mfgmg_node_types(const mfgmg_ctx* ctx, int32_t level, int32_t field, uint8_t
   int st = check_level(ctx, level);
   if (st) return st;
   if (!types || field < 0 || field > 2 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
-  const Level& h = ctx->mesh->level(level);
+  const Level& h = ctx->mesh->vlevel(level);
   if (field == 2) {
     for (int64_t i = 0; i < h.nnode; ++i) types[i] = h.cmask(i);
     return MFGMG_OK;
@@ -1008,7 +1131,7 @@ int mfgmg_constraints(const mfgmg_ctx* ctx, int32_t level, int32_t field, int64_
   int st = check_level(ctx, level);
   if (st) return st;
   if (!nh || !nnz || field < 0 || field > 1 || (field == 1 && level != ctx->mesh->L())) return MFGMG_ERR_INVALID;
-  const Level& h = ctx->mesh->level(level);
+  const Level& h = ctx->mesh->vlevel(level);
   const Constraints& cs = field == 0 ? h.hang : h.phang;
   *nh = int64_t(cs.count());
   *nnz = int64_t(cs.master.size());
@@ -1024,7 +1147,7 @@ int mfgmg_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* p
   int st = check_level(ctx, level);
   if (st) return st;
   if (level < 2 || !nnz) return MFGMG_ERR_INVALID;
-  const Level& h = ctx->mesh->level(level);
+  const Level& h = ctx->mesh->vlevel(level);
   *nnz = int64_t(h.P_col.size());
   if (ptr && col && w) {
     for (size_t i = 0; i < h.P_ptr.size(); ++i) ptr[i] = h.P_ptr[i];
@@ -1046,21 +1169,23 @@ int mfgmg_set_viscosity(mfgmg_ctx* ctx, const double* mu_qp, void* stream) {
   const Mesh& m = *ctx->mesh;
   const int L = m.L();
   const int64_t nl = m.leaf().ncell;
-  for (int64_t i = 0; i < 27 * nl; ++i)
+  const int nq = m.quad_points(), nq3 = nq * nq * nq;
+  for (int64_t i = 0; i < nq3 * nl; ++i)
     if (!(mu_qp[i] > 0) || !std::isfinite(mu_qp[i]))
       return ctx->set(MFGMG_ERR_INVALID, "viscosity must be positive and finite");
   int st = upload_mesh(ctx);
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* mq = nullptr;
-  HIPCHK(hipMalloc(&mq, size_t(27 * nl) * sizeof(double)));
-  HIPCHK(hipMemcpyAsync(mq, mu_qp, size_t(27 * nl) * sizeof(double), hipMemcpyHostToDevice, s));
-  launch_harmonic_mu(nl, mq, ctx->lv[size_t(L)].mu_d, s);
+  HIPCHK(hipMalloc(&mq, size_t(nq3 * nl) * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(mq, mu_qp, size_t(nq3 * nl) * sizeof(double), hipMemcpyHostToDevice, s));
+  if (nq == 4) launch_harmonic_mu64(nl, mq, ctx->lv[size_t(L)].mu_d, s);
+  else launch_harmonic_mu(nl, mq, ctx->lv[size_t(L)].mu_d, s);
   for (int ell = L - 1; ell >= 1; --ell)
     launch_restrict_mu(ctx->lv[size_t(ell)].v.ncell, ctx->lv[size_t(ell)].mu_src, ctx->lv[size_t(ell + 1)].mu_d,
                        ctx->lv[size_t(ell)].mu_d, s);
   double* dtmp = nullptr;
-  HIPCHK(hipMalloc(&dtmp, size_t(3 * m.leaf().nnode) * sizeof(double) + 64));
+  HIPCHK(hipMalloc(&dtmp, size_t(3 * m.vleaf().nnode) * sizeof(double) + 64));
   for (int ell = 1; ell <= L; ++ell) {
     LevelDev& d = ctx->lv[size_t(ell)];
     launch_to_float(d.v.ncell, d.mu_d, d.mu_f, s);
@@ -1238,7 +1363,8 @@ int mfgmg_assemble_rhs(mfgmg_ctx* ctx, const double* f_qp, double* rhs_u, void* 
   if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevLevel& v = ctx->lv[size_t(ctx->mesh->L())].v;
-  const size_t nf = size_t(81 * v.ncell);
+  const int nq = ctx->mesh->quad_points();
+  const size_t nf = size_t(3 * nq * nq * nq) * size_t(v.ncell);
   double* fd = nullptr;
   HIPCHK(hipMalloc(&fd, nf * sizeof(double)));
   HIPCHK(hipMemcpyAsync(fd, f_qp, nf * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1313,9 +1439,14 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     return ctx->set(MFGMG_ERR_INVALID, "GMRES and IDR need the linear (Chebyshev) Schur approximation");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool local = o.hierarchy == MFGMG_LOCAL_SMOOTHING;
+  if (o.use_scaling && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
+  if (o.schur == MFGMG_SCHUR_CHEB && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the Chebyshev Schur map takes the Q1 pressure interval");
   if (local) {
     if (o.use_scaling) return ctx->set(MFGMG_ERR_INVALID, "the learned scaling applies to the global-coarsening levels");
-    if (ctx->mesh->noflux()) return ctx->set(MFGMG_ERR_INVALID, "local smoothing is built for the Dirichlet condition");
+    if (ctx->mesh->noflux() || ctx->mesh->velocity_degree() != 2)
+      return ctx->set(MFGMG_ERR_INVALID, "local smoothing is built for Q2-Q1 with the Dirichlet condition");
     const int st = local_setup(ctx, s);
     if (st) return st;
   }
@@ -1502,7 +1633,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     double* hres = ctx->host_res;
     {
       // shadow space: keyed SplitMix64 columns, then Gram-Schmidt
-      const Level& h = ctx->mesh->level(L);
+      const Level& h = ctx->mesh->vlevel(L);
       std::vector<double> q(static_cast<size_t>(n));
       for (int i = 0; i < ss; ++i) {
         const uint64_t seed = uint64_t(4711 + i);

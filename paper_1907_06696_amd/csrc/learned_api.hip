@@ -316,6 +316,8 @@ double vcycle_factor(mfgmg_ctx* ctx, hipStream_t s, int prec, int steps) {
 extern "C" {
 
 int mfgmg_features(mfgmg_ctx* ctx, int32_t level, float* feat, void* stream) {
+  if (ctx && ctx->mesh && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
   int st = check_ready(ctx, level, false);
   if (st) return st;
   if (!feat) return MFGMG_ERR_INVALID;
@@ -378,6 +380,8 @@ int mfgmg_features(mfgmg_ctx* ctx, int32_t level, float* feat, void* stream) {
 
 int mfgmg_fit_objective(mfgmg_ctx* ctx, int32_t level, const float* y, double lam_fixed, double* J, double* lam_out,
                         float* grad, void* stream) {
+  if (ctx && ctx->mesh && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
   int st = check_ready(ctx, level, true);
   if (st) return st;
   if (!y || !J) return MFGMG_ERR_INVALID;
@@ -402,6 +406,8 @@ int mfgmg_fit_objective(mfgmg_ctx* ctx, int32_t level, const float* y, double la
 
 int mfgmg_fit_targets(mfgmg_ctx* ctx, int32_t level, int32_t steps, double lr, float* y_out, double* J_hist,
                       void* stream) {
+  if (ctx && ctx->mesh && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
   int st = check_ready(ctx, level, true);
   if (st) return st;
   if (!y_out || steps < 0 || !(lr > 0)) return MFGMG_ERR_INVALID;
@@ -441,6 +447,8 @@ int mfgmg_fit_targets(mfgmg_ctx* ctx, int32_t level, int32_t steps, double lr, f
 }
 
 int mfgmg_set_scaling(mfgmg_ctx* ctx, int32_t level, const float* y, void* stream) {
+  if (ctx && ctx->mesh && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
   int st = check_ready(ctx, level, true);
   if (st) return st;
   LevelDev& L = ctx->lv[size_t(level)];
@@ -579,6 +587,8 @@ int mfgmg_mlp_train(float* w, const float* feats, const float* targets, int64_t 
 }
 
 int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w, int32_t guard, int32_t* used, double* factors, void* stream) {
+  if (ctx && ctx->mesh && ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "the learned scaling is built for Q2-Q1");
   if (!ctx || !w || guard < MFGMG_GUARD_NONE || guard > MFGMG_GUARD_FP32) return MFGMG_ERR_INVALID;
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -285,7 +285,8 @@ extern "C" {
 int mfgmg_local_levels(const mfgmg_ctx* ctx, int32_t* base, int64_t* n_cells, int64_t* n_nodes) {
   if (!ctx || !base || !n_cells || !n_nodes) return MFGMG_ERR_INVALID;
   if (!ctx->mesh || !ctx->mesh->finalized()) return MFGMG_ERR_STATE;
-  if (ctx->mesh->noflux()) return MFGMG_ERR_INVALID;   // local smoothing: Dirichlet condition only
+  // local smoothing: Q2-Q1 with u = 0 only
+  if (ctx->mesh->noflux() || ctx->mesh->velocity_degree() != 2) return MFGMG_ERR_INVALID;
   const Mesh& m = *ctx->mesh;
   *base = m.local_base();
   for (int ell = 0; ell <= MFGMG_MAX_LEVELS; ++ell) n_cells[ell] = n_nodes[ell] = 0;
@@ -300,7 +301,8 @@ int mfgmg_local_levels(const mfgmg_ctx* ctx, int32_t* base, int64_t* n_cells, in
 int mfgmg_local_nodes(const mfgmg_ctx* ctx, int32_t level, int64_t* keys, uint8_t* kinds) {
   if (!ctx || !keys || !kinds) return MFGMG_ERR_INVALID;
   if (!ctx->mesh || !ctx->mesh->finalized()) return MFGMG_ERR_STATE;
-  if (ctx->mesh->noflux()) return MFGMG_ERR_INVALID;   // local smoothing: Dirichlet condition only
+  // local smoothing: Q2-Q1 with u = 0 only
+  if (ctx->mesh->noflux() || ctx->mesh->velocity_degree() != 2) return MFGMG_ERR_INVALID;
   const Mesh& m = *ctx->mesh;
   if (level <= m.local_base() || level > m.L()) return MFGMG_ERR_INVALID;
   const LocalLevel& h = m.local_level(level);
@@ -311,7 +313,8 @@ int mfgmg_local_nodes(const mfgmg_ctx* ctx, int32_t level, int64_t* keys, uint8_
 int mfgmg_local_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* ptr, int64_t* col, double* w) {
   if (!ctx || !nnz) return MFGMG_ERR_INVALID;
   if (!ctx->mesh || !ctx->mesh->finalized()) return MFGMG_ERR_STATE;
-  if (ctx->mesh->noflux()) return MFGMG_ERR_INVALID;   // local smoothing: Dirichlet condition only
+  // local smoothing: Q2-Q1 with u = 0 only
+  if (ctx->mesh->noflux() || ctx->mesh->velocity_degree() != 2) return MFGMG_ERR_INVALID;
   const Mesh& m = *ctx->mesh;
   if (level <= m.local_base() || level > m.L()) return MFGMG_ERR_INVALID;
   const Level& h = m.local_level(level).mesh;
@@ -326,7 +329,8 @@ int mfgmg_local_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int6
 int mfgmg_vcycle_local(mfgmg_ctx* ctx, mfgmg_prec prec, const void* rhs, void* x, void* stream) {
   if (!ctx || !rhs || !x || rhs == x || (prec != MFGMG_FP32 && prec != MFGMG_FP64)) return MFGMG_ERR_INVALID;
   if (!ctx->mu_ready) return ctx->set(MFGMG_ERR_STATE, "set_viscosity first");
-  if (ctx->mesh->noflux()) return ctx->set(MFGMG_ERR_INVALID, "local smoothing is built for the Dirichlet condition");
+  if (ctx->mesh->noflux() || ctx->mesh->velocity_degree() != 2)
+    return ctx->set(MFGMG_ERR_INVALID, "local smoothing is built for Q2-Q1 with the Dirichlet condition");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int st = local_setup(ctx, s);
   if (st) return st;

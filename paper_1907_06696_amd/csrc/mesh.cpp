@@ -13,6 +13,8 @@
 //    stokes), and Dirichlet wins over hanging.
 #include "mesh.h"
 
+#include "q3.h"
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -285,6 +287,13 @@ std::string Mesh::finalize() {
   for (int ell = 2; ell <= L_; ++ell) build_transfer(ell);
   for (int ell = 1; ell < L_; ++ell) build_mu_restriction(ell);
   g_scratch = nullptr;
+  if (vdeg_ == 3) {
+    if (noflux_) return "the Q3-Q2 pair is built for u = 0 on the boundary";
+    for (int ell = 1; ell <= L_; ++ell)
+      if (!levels_[ell].uniform) return "the Q3-Q2 pair is built for uniform meshes";
+    q3_.assign(size_t(L_ + 1), Level{});
+    for (int ell = 1; ell <= L_; ++ell) build_q3_level(levels_[ell], ell == L_, q3_[size_t(ell)]);
+  }
   // masters of hanging nodes must be free
   for (int ell = 1; ell <= L_; ++ell) {
     const Level& lv = levels_[ell];
@@ -866,15 +875,21 @@ void Mesh::build_mu_restriction(int ell) {
 
 void Mesh::leaf_quadrature_points(double* out) const {
   const Level& lv = leaf();
-  const double g = 0.5 * std::sqrt(3.0 / 5.0);
-  const double xi[3] = {0.5 - g, 0.5, 0.5 + g};
+  const int nq = quad_points(), nq3 = nq * nq * nq;
+  double xi[4];
+  if (nq == 3) {
+    const double g = 0.5 * std::sqrt(3.0 / 5.0);
+    xi[0] = 0.5 - g, xi[1] = 0.5, xi[2] = 0.5 + g;
+  } else {
+    for (int q = 0; q < 4; ++q) xi[q] = q3_element().xg[q];
+  }
   for (int64_t c = 0; c < lv.ncell; ++c) {
     const double h = std::ldexp(1.0, -lv.clev[c]);
     const double ox = lv.cijk[3 * c] * h, oy = lv.cijk[3 * c + 1] * h, oz = lv.cijk[3 * c + 2] * h;
-    for (int z = 0; z < 3; ++z)
-      for (int y = 0; y < 3; ++y)
-        for (int x = 0; x < 3; ++x) {
-          double* p = out + 3 * (27 * c + x + 3 * y + 9 * z);
+    for (int z = 0; z < nq; ++z)
+      for (int y = 0; y < nq; ++y)
+        for (int x = 0; x < nq; ++x) {
+          double* p = out + 3 * (nq3 * c + x + nq * y + nq * nq * z);
           p[0] = ox + xi[x] * h;
           p[1] = oy + xi[y] * h;
           p[2] = oz + xi[z] * h;

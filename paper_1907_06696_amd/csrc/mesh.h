@@ -94,6 +94,16 @@ class Mesh {
   // is built by the general path (no uniform lattice levels).
   void set_noflux(bool on) { noflux_ = on; }
   bool noflux() const { return noflux_; }
+  // velocity element (before finalize): 2 for Q2-Q1 (default), 3 for Q3-Q2
+  // (k = 2 of Sec. 2.1; uniform meshes with u = 0 only).  The cell meshes
+  // (level(ell)) are the same; vlevel(ell) holds the velocity nodes, the
+  // transfers and, on the leaf, the pressure nodes of the chosen pair.
+  void set_velocity_degree(int p) { vdeg_ = p; }
+  int velocity_degree() const { return vdeg_; }
+  const Level& vlevel(int ell) const { return vdeg_ == 3 ? q3_[size_t(ell)] : levels_[size_t(ell)]; }
+  const Level& vleaf() const { return vlevel(L_); }
+  // Gauss points per direction of the velocity element
+  int quad_points() const { return vdeg_ == 3 ? 4 : 3; }
   // refine the listed active cells `times` levels, then 2:1 balance
   // returns "" on success or an error message
   std::string refine(const int32_t* cells, int64_t n, int times);
@@ -108,7 +118,7 @@ class Mesh {
   const Level& leaf() const { return levels_[L_]; }
   int64_t n_active() const { return int64_t(lev_.size()); }
 
-  // physical Gauss points of the leaf cells [ncell][27][3]
+  // physical Gauss points of the leaf cells [ncell][q^3][3], q = quad_points()
   void leaf_quadrature_points(double* out) const;
 
   // local-smoothing hierarchy: levels 1 .. local_base() are the uniform
@@ -147,6 +157,8 @@ class Mesh {
   std::vector<int32_t> ijk_;
   bool finalized_ = false;
   bool noflux_ = false;
+  int vdeg_ = 2;
+  std::vector<Level> q3_;   // Q3-Q2 lattice levels (velocity degree 3)
   int L_ = 0;
   std::vector<Level> levels_;
   // local-smoothing levels, built from the finished global-coarsening levels

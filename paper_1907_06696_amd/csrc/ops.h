@@ -52,6 +52,13 @@ struct DevLevel {
   // hanging nodes: all three; fixed components of no-normal-flux nodes)
   const uint8_t* cmask = nullptr;
   bool noflux = false;              // u . n = 0 on the boundary (general levels only)
+  // Q3-Q2 lattice levels (k = 2): the Q3 kernels, FP64 transfer weights of
+  // the prolongation from the level below (CSR of the LevelDev) and of its
+  // transpose, the diagonal of the unit element matrix [192]
+  bool q3 = false;
+  const double* q3_Pw = nullptr;
+  const double* q3_Rw = nullptr;
+  const double* q3_kdiag = nullptr;
   const int64_t* hptr = nullptr;    // hanging CSR
   const int32_t* hmaster = nullptr;
   const float* hw_f = nullptr;
@@ -269,5 +276,21 @@ void launch_rhs(const DevLevel& L, const double* f_qp, double* b, hipStream_t s)
 
 // upload element constants (K_hat diagonal, B_hat, M_hat) to constant memory
 void set_element_constants(const double* khat_diag81, const double* bhat8x81, const double* mhat8x8);
+
+// Q3-Q2 lattice levels (q3_ops.hip): 1D tables N [4x4], D [4x4], Gauss
+// weights [4], P2 [4x3], Q2 mass M2 [3x3]; operator cells (y += cell terms on
+// free dofs; the caller initialises y), diagonal, harmonic viscosity over 4^3
+// Gauss points, right-hand side (b zeroed by the caller) and the Q2 pressure
+// side on the leaf (B u, B^T p added; M_p p added; diag(M_p) added)
+void set_q3_constants(const double* N, const double* D, const double* w, const double* P2, const double* M2);
+template <typename T>
+void launch_vmult_q3_cells(const DevLevel& L, const T* x, T* y, hipStream_t s);
+void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s);
+void launch_harmonic_mu64(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s);
+void launch_rhs_q3(const DevLevel& L, const double* f_qp, double* b, hipStream_t s);
+void launch_div_q3(const DevLevel& L, const double* u, double* p_out, hipStream_t s);
+void launch_grad_q3(const DevLevel& L, const double* p, double* u_out, hipStream_t s);
+void launch_pmass_q2(const DevLevel& L, const double* p, double* p_out, hipStream_t s, const double* gate = nullptr);
+void launch_pmass_diag_q2(const DevLevel& L, double* dg, hipStream_t s);
 
 }  // namespace mfgmg

@@ -685,9 +685,9 @@ __device__ __forceinline__ T group_sum(T v) {
 // (cmf, cmc: constrained-component masks of the fine and coarse level, or
 // null: a masked coarse component carries nothing, a masked fine component
 // receives nothing)
-template <typename T, int G>
+template <typename T, int G, typename W = float>
 __global__ __launch_bounds__(kBlock) void k_prolong(int64_t nf, const int64_t* __restrict__ ptr,
-                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                    const int32_t* __restrict__ col, const W* __restrict__ w,
                                                     const T* __restrict__ xc, T* __restrict__ xf, bool add,
                                                     const uint8_t* __restrict__ cmf, const uint8_t* __restrict__ cmc) {
   const int sub = int(threadIdx.x) % G;
@@ -729,9 +729,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int64_t nf, const int64_t* _
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, typename W = float>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int64_t* __restrict__ ptr,
-                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const int32_t* __restrict__ col, const W* __restrict__ w,
                                                      const T* __restrict__ b, const T* __restrict__ t,
                                                      T* __restrict__ xc, const uint8_t* __restrict__ cmf,
                                                      const uint8_t* __restrict__ cmc) {
@@ -1806,6 +1806,10 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
     return;
   }
   if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.cmask, x, y);
+  if (L.q3) {
+    launch_vmult_q3_cells<T>(L, x, y, s);
+    return;
+  }
   T* fs = face_slots<T>(L);
   if (L.blk4.n) {
     if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
@@ -1848,6 +1852,10 @@ template void launch_vmult<float>(const DevLevel&, const float*, float*, hipStre
 template void launch_vmult<double>(const DevLevel&, const double*, double*, hipStream_t, bool);
 
 void launch_diag(const DevLevel& L, const double* khat, double* d, hipStream_t s) {
+  if (L.q3) {
+    launch_diag_q3(L, L.q3_kdiag, d, s);
+    return;
+  }
   if (L.uniform) {
     k_diag_uniform<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L.n_edge, L.mu_d, d);
     return;
@@ -2006,7 +2014,9 @@ void launch_mul(int64_t n, const double* a, const double* b, double* y, hipStrea
 
 void launch_div(const DevLevel& L, const DevPressure& P, const double* u, double* po, hipStream_t s) {
   k_fill<<<grid_for(P.np), kBlock, 0, s>>>(P.np, 0.0, po);
-  if (L.blk4.n || L.blk2.n) {
+  if (L.q3) {
+    launch_div_q3(L, u, po, s);
+  } else if (L.blk4.n || L.blk2.n) {
     if (L.blk4.n) k_div_blocks<4><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L, P, u, po);
     if (L.blk2.n) k_div_blocks<2><<<unsigned((L.blk2.n + 7) / 8), 64, 0, s>>>(L.blk2, L, P, u, po);
     for (auto lst : {std::make_pair(L.single_reg, L.n_single_reg), std::make_pair(L.single_hang, L.n_single_hang)})
@@ -2028,7 +2038,9 @@ void launch_grad_from(const DevLevel& L, const DevPressure& P, const double* p, 
   launch_grad_add(L, P, p, uo, s);
 }
 void launch_grad_add(const DevLevel& L, const DevPressure& P, const double* p, double* uo, hipStream_t s) {
-  if (L.uniform) {
+  if (L.q3) {
+    launch_grad_q3(L, p, uo, s);
+  } else if (L.uniform) {
     k_grad_uniform<false><<<grad_uniform_tiles(L.n_edge), kGradTX * kGradTY * kGradTZ, 0, s>>>(L.n_edge, P, p,
                                                                                                nullptr, uo);
   } else if (L.blk4.n || L.blk2.n) {
@@ -2056,7 +2068,9 @@ void launch_pmass(const DevLevel& L, const DevPressure& P, const double* p, doub
 }
 void launch_pmass_add(const DevLevel& L, const DevPressure& P, const double* p, double* po, hipStream_t s,
                       const double* gate) {
-  if (L.uniform && P.plat) {
+  if (L.q3) {
+    launch_pmass_q2(L, p, po, s, gate);
+  } else if (L.uniform && P.plat) {
     k_pmass_uniform<<<pmass_uniform_tiles(L.n_edge), kPmTX * kPmTY * kPmTZ, 0, s>>>(L.n_edge, P, L.mu_d, p, po, gate);
   } else if ((L.blk4.n && L.blk4.pslots) || (L.blk2.n && L.blk2.pslots)) {
     double* fs = L.pfslot;
@@ -2248,6 +2262,10 @@ void launch_zero_constrained(const DevLevel& L, double* u, hipStream_t s) {
 }
 void launch_rhs(const DevLevel& L, const double* f, double* b, hipStream_t s) {
   k_fill<<<grid_for(3 * L.nnode), kBlock, 0, s>>>(3 * L.nnode, 0.0, b);
+  if (L.q3) {
+    launch_rhs_q3(L, f, b, s);
+    return;
+  }
   k_rhs<<<unsigned((L.ncell + kCellBlock - 1) / kCellBlock), kCellBlock, 0, s>>>(L, f, b);
 }
 
@@ -2268,6 +2286,11 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
     k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
+  if (F.q3) {   // Q3 lattice levels: the CSR with its FP64 weights (not dyadic)
+    k_prolong<T, kProlongLanes, double><<<grid_for(F.nnode * kProlongLanes), kBlock, 0, s>>>(
+        F.nnode, ptr, col, F.q3_Pw, xc, xf, add, nullptr, nullptr);
+    return;
+  }
   // no-normal-flux levels: the fixed components are masked on both sides
   const uint8_t* cmf = F.noflux ? F.cmask : nullptr;
   const uint8_t* cmc = F.noflux ? Cc.cmask : nullptr;
@@ -2280,6 +2303,11 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
                            const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s) {
   // (the passes index nodes with 32-bit integers: levels up to 512^3 cells)
   const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
+  if (F.q3) {
+    k_restrict<T, kRestrictLanes, double><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(
+        Cc.nnode, ptr, col, F.q3_Rw, b, t, xc, nullptr, nullptr);
+    return;
+  }
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge && mc * mf * mf < (int64_t(1) << 31)) {
     const int nc = int(Cc.n_edge);
     k_restrict_x<T><<<grid_for(mc * mf * mf), kBlock, 0, s>>>(nc, b, t, s1);

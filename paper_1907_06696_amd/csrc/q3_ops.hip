@@ -1,0 +1,355 @@
+// Device kernels of the Q3-Q2 pair (k = 2 of Sec. 2.1) on uniform lattice
+// levels (see q3.h for the numbering).
+//
+// One wavefront per cell: lane l = x + 4 y + 16 z stands for the tensor
+// point (x, y, z) of the cell's 4 x 4 x 4 nodes and, after interpolation, of
+// its 4 x 4 x 4 Gauss points.  A one-dimensional 4 x 4 contraction along an
+// axis is four cross-lane reads (ds_bpermute through __shfl) and four fused
+// multiply-adds per lane, so the sum-factorised operator keeps one value per
+// lane and component and needs no LDS allocation or barrier:
+//   interpolate u to the Gauss points (3 axes x 3 components),
+//   differentiate there with the Gauss-collocation derivative (9 sweeps),
+//   F_cd = mu h w_q (d_d u_c + d_c u_d),
+//   y_c = N^T N^T N^T sum_d D_d^T F_cd (9 + 9 transposed sweeps),
+// then each lane adds its node's three results (atomics: a node is shared by
+// up to 8 cells).  Constrained (boundary) nodes are read as zero and receive
+// nothing; the caller initialises y (identity rows) beforehand.
+#include <hip/hip_runtime.h>
+
+#include "ops.h"
+
+namespace mfgmg {
+
+namespace {
+
+__constant__ double c_q3N[16];    // N[q][a] = L_a(xg_q)
+__constant__ double c_q3D[16];    // D[q][r] = l_r'(xg_q)
+__constant__ double c_q3W[4];     // Gauss weights on [0, 1]
+__constant__ double c_q3P[12];    // P2[q][i]: Q2 pressure basis at the Gauss points
+__constant__ double c_q3M2[9];    // 1D Q2 mass
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t n, int block = kBlock, int64_t cap = 1 << 20) {
+  int64_t g = (n + block - 1) / block;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+// out(.., q, ..) = sum_a c[a] v(.., a, ..) along axis AX, c the lane's row
+template <int AX, typename T>
+__device__ __forceinline__ T sweep(T v, int lane, const T (&c)[4]) {
+  constexpr int S = 1 << (2 * AX);
+  const int base = lane - ((lane >> (2 * AX)) & 3) * S;
+  T out = c[0] * __shfl(v, base);
+  out += c[1] * __shfl(v, base + S);
+  out += c[2] * __shfl(v, base + 2 * S);
+  out += c[3] * __shfl(v, base + 3 * S);
+  return out;
+}
+
+// the lane's row of a 4 x 4 matrix along axis AX (row = lane coordinate), and
+// its column (transposed sweep)
+template <int AX, typename T>
+__device__ __forceinline__ void row_of(const double* M, int lane, T (&c)[4]) {
+  const int q = (lane >> (2 * AX)) & 3;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) c[a] = T(M[4 * q + a]);
+}
+template <int AX, typename T>
+__device__ __forceinline__ void col_of(const double* M, int lane, T (&c)[4]) {
+  const int a = (lane >> (2 * AX)) & 3;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = T(M[4 * q + a]);
+}
+
+struct Q3Cell {
+  int64_t node;
+  bool bnd;
+  __device__ Q3Cell(int64_t n, int64_t c, int lane) {
+    const int64_t m = 3 * n + 1;
+    const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+    const int64_t X = 3 * i + (lane & 3), Y = 3 * j + ((lane >> 2) & 3), Z = 3 * k + (lane >> 4);
+    node = X + m * (Y + m * Z);
+    bnd = X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vmult_q3(int64_t n, const T* __restrict__ mu, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const bool live = cell < n * n * n;
+  const int64_t c = live ? cell : 0;   // a dead wave works on cell 0 and writes nothing
+  const Q3Cell qc(n, c, lane);
+  T u[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) u[k] = qc.bnd ? T(0) : x[3 * qc.node + k];
+  T Nx[4], Ny[4], Nz[4];
+  row_of<0>(c_q3N, lane, Nx), row_of<1>(c_q3N, lane, Ny), row_of<2>(c_q3N, lane, Nz);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) u[k] = sweep<2>(sweep<1>(sweep<0>(u[k], lane, Nx), lane, Ny), lane, Nz);
+  T Dx[4], Dy[4], Dz[4];
+  row_of<0>(c_q3D, lane, Dx), row_of<1>(c_q3D, lane, Dy), row_of<2>(c_q3D, lane, Dz);
+  T g[3][3];   // g[c][d] = d_d u_c at the lane's Gauss point
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g[k][0] = sweep<0>(u[k], lane, Dx);
+    g[k][1] = sweep<1>(u[k], lane, Dy);
+    g[k][2] = sweep<2>(u[k], lane, Dz);
+  }
+  const T wq = T(c_q3W[lane & 3] * c_q3W[(lane >> 2) & 3] * c_q3W[lane >> 4]);
+  const T coef = mu[c] / T(n) * wq;
+  T F[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) F[a][b] = coef * (g[a][b] + g[b][a]);
+  col_of<0>(c_q3D, lane, Dx), col_of<1>(c_q3D, lane, Dy), col_of<2>(c_q3D, lane, Dz);
+  col_of<0>(c_q3N, lane, Nx), col_of<1>(c_q3N, lane, Ny), col_of<2>(c_q3N, lane, Nz);
+  T out[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T t = sweep<0>(F[k][0], lane, Dx) + sweep<1>(F[k][1], lane, Dy) + sweep<2>(F[k][2], lane, Dz);
+    out[k] = sweep<2>(sweep<1>(sweep<0>(t, lane, Nx), lane, Ny), lane, Nz);
+  }
+  if (!live || qc.bnd) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) atomicAdd(&y[3 * qc.node + k], out[k]);
+}
+
+// diagonal: d[3 node + c] += mu h K_hat[(a, c), (a, c)] over the cells (one thread per cell)
+__global__ __launch_bounds__(kBlock) void k_diag_q3(int64_t n, const double* __restrict__ mu,
+                                                    const double* __restrict__ kdiag, double* __restrict__ d) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= n * n * n) return;
+  const double s = mu[c] / double(n);
+  for (int a = 0; a < 64; ++a) {
+    const Q3Cell qc(n, c, a);
+    if (qc.bnd) continue;
+    for (int k = 0; k < 3; ++k) atomicAdd(&d[3 * qc.node + k], s * kdiag[3 * a + k]);
+  }
+}
+
+// mu_K = sum w_q / sum (w_q / mu_q) over the 4^3 Gauss points
+__global__ void k_harmonic64(int64_t ncell, const double* __restrict__ mq, double* __restrict__ mu) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < ncell; c += int64_t(gridDim.x) * blockDim.x) {
+    double sw = 0.0, s = 0.0;
+    for (int q = 0; q < 64; ++q) {
+      const double w = c_q3W[q & 3] * c_q3W[(q >> 2) & 3] * c_q3W[q >> 4];
+      sw += w;
+      s += w / mq[64 * c + q];
+    }
+    mu[c] = sw / s;
+  }
+}
+
+// b += D F, F_e[(a, c)] = h^3 sum_q w_q phi_a(xi_q) f_c(x_q); f [ncell][64][3]
+__global__ __launch_bounds__(256) void k_rhs_q3(int64_t n, const double* __restrict__ f, double* __restrict__ b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const bool live = cell < n * n * n;
+  const int64_t c = live ? cell : 0;
+  const Q3Cell qc(n, c, lane);
+  const double h = 1.0 / double(n);
+  const double wq = c_q3W[lane & 3] * c_q3W[(lane >> 2) & 3] * c_q3W[lane >> 4] * h * h * h;
+  double Nx[4], Ny[4], Nz[4];
+  col_of<0>(c_q3N, lane, Nx), col_of<1>(c_q3N, lane, Ny), col_of<2>(c_q3N, lane, Nz);
+  double out[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double v = wq * f[(64 * c + lane) * 3 + k];
+    out[k] = sweep<2>(sweep<1>(sweep<0>(v, lane, Nx), lane, Ny), lane, Nz);
+  }
+  if (!live || qc.bnd) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) atomicAdd(&b[3 * qc.node + k], out[k]);
+}
+
+// ---------------------------------------------------------- Q2 pressure
+// The pressure side of the pair on the leaf: B u (-int psi_i div u), B^T p
+// and the mu^{-1}-weighted Q2 mass matrix, with psi on the (2n + 1)^3 lattice.
+// Lanes hold Gauss points as above; a pressure node (i, j, k) of the cell
+// (3 x 3 x 3) is taken by lane i + 4 j + 16 k (lanes with a coordinate 3 idle
+// in the contraction to and from the Q2 basis, whose matrix P2 is 4 x 3).
+
+// out(.., q, ..) = sum_i P2[q][i] v(.., i, ..) (i < 3)
+template <int AX>
+__device__ __forceinline__ double sweep_p(double v, int lane) {
+  constexpr int S = 1 << (2 * AX);
+  const int q = (lane >> (2 * AX)) & 3;
+  const int base = lane - q * S;
+  return c_q3P[3 * q] * __shfl(v, base) + c_q3P[3 * q + 1] * __shfl(v, base + S) +
+         c_q3P[3 * q + 2] * __shfl(v, base + 2 * S);
+}
+// out(.., i, ..) = sum_q P2[q][i] v(.., q, ..) (i < 3; lanes with i = 3 get 0)
+template <int AX>
+__device__ __forceinline__ double sweep_pt(double v, int lane) {
+  constexpr int S = 1 << (2 * AX);
+  const int i = (lane >> (2 * AX)) & 3;
+  const int base = lane - i * S;
+  const int ii = i < 3 ? i : 0;
+  double o = c_q3P[ii] * __shfl(v, base) + c_q3P[3 + ii] * __shfl(v, base + S) +
+             c_q3P[6 + ii] * __shfl(v, base + 2 * S) + c_q3P[9 + ii] * __shfl(v, base + 3 * S);
+  return i < 3 ? o : 0.0;
+}
+
+struct Q2PCell {
+  int64_t pnode;
+  bool used;   // lane is a pressure node of the cell (coordinates < 3)
+  __device__ Q2PCell(int64_t n, int64_t c, int lane) {
+    const int64_t mp = 2 * n + 1;
+    const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+    const int a = lane & 3, b = (lane >> 2) & 3, cc = lane >> 4;
+    used = a < 3 && b < 3 && cc < 3;
+    pnode = used ? (2 * i + a) + mp * ((2 * j + b) + mp * (2 * k + cc)) : 0;
+  }
+};
+
+// p_out += B u (accumulated with atomics; p_out zeroed by the caller)
+__global__ __launch_bounds__(256) void k_div_q3(int64_t n, const double* __restrict__ u, double* __restrict__ po) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const bool live = cell < n * n * n;
+  const int64_t c = live ? cell : 0;
+  const Q3Cell qc(n, c, lane);
+  double Nx[4], Ny[4], Nz[4], Dx[4], Dy[4], Dz[4];
+  row_of<0>(c_q3N, lane, Nx), row_of<1>(c_q3N, lane, Ny), row_of<2>(c_q3N, lane, Nz);
+  row_of<0>(c_q3D, lane, Dx), row_of<1>(c_q3D, lane, Dy), row_of<2>(c_q3D, lane, Dz);
+  double div = 0.0;
+  {
+    double v = qc.bnd ? 0.0 : u[3 * qc.node];
+    div += sweep<0>(sweep<2>(sweep<1>(sweep<0>(v, lane, Nx), lane, Ny), lane, Nz), lane, Dx);
+    v = qc.bnd ? 0.0 : u[3 * qc.node + 1];
+    div += sweep<1>(sweep<2>(sweep<1>(sweep<0>(v, lane, Nx), lane, Ny), lane, Nz), lane, Dy);
+    v = qc.bnd ? 0.0 : u[3 * qc.node + 2];
+    div += sweep<2>(sweep<2>(sweep<1>(sweep<0>(v, lane, Nx), lane, Ny), lane, Nz), lane, Dz);
+  }
+  const double h = 1.0 / double(n);
+  const double wq = c_q3W[lane & 3] * c_q3W[(lane >> 2) & 3] * c_q3W[lane >> 4];
+  // -int psi_i div u dx = -h^2 sum_q w_q psi_i(xi_q) (div_xi u)(xi_q)
+  const double r = sweep_pt<2>(sweep_pt<1>(sweep_pt<0>(-h * h * wq * div, lane), lane), lane);
+  const Q2PCell pc(n, c, lane);
+  if (live && pc.used) atomicAdd(&po[pc.pnode], r);
+}
+
+// u_out += B^T p on the free velocity dofs (-h^2 sum_q w_q p(xi_q) d_c phi_a(xi_q))
+__global__ __launch_bounds__(256) void k_grad_q3(int64_t n, const double* __restrict__ p, double* __restrict__ uo) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const bool live = cell < n * n * n;
+  const int64_t c = live ? cell : 0;
+  const Q2PCell pc(n, c, lane);
+  double pv = pc.used ? p[pc.pnode] : 0.0;
+  pv = sweep_p<2>(sweep_p<1>(sweep_p<0>(pv, lane), lane), lane);
+  const double h = 1.0 / double(n);
+  const double wq = c_q3W[lane & 3] * c_q3W[(lane >> 2) & 3] * c_q3W[lane >> 4];
+  const double f = -h * h * wq * pv;
+  double Nx[4], Ny[4], Nz[4], Dx[4], Dy[4], Dz[4];
+  col_of<0>(c_q3N, lane, Nx), col_of<1>(c_q3N, lane, Ny), col_of<2>(c_q3N, lane, Nz);
+  col_of<0>(c_q3D, lane, Dx), col_of<1>(c_q3D, lane, Dy), col_of<2>(c_q3D, lane, Dz);
+  double out[3];
+  out[0] = sweep<2>(sweep<1>(sweep<0>(sweep<0>(f, lane, Dx), lane, Nx), lane, Ny), lane, Nz);
+  out[1] = sweep<2>(sweep<1>(sweep<0>(sweep<1>(f, lane, Dy), lane, Nx), lane, Ny), lane, Nz);
+  out[2] = sweep<2>(sweep<1>(sweep<0>(sweep<2>(f, lane, Dz), lane, Nx), lane, Ny), lane, Nz);
+  const Q3Cell qc(n, c, lane);
+  if (!live || qc.bnd) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) atomicAdd(&uo[3 * qc.node + k], out[k]);
+}
+
+// p_out += M_p p (mu^{-1}-weighted Q2 mass, h^3 / mu_K M2 x M2 x M2), one
+// thread per cell; skipped when *gate != 0 (the CG's convergence flag)
+__global__ __launch_bounds__(kBlock) void k_pmass_q2(int64_t n, const double* __restrict__ mu,
+                                                     const double* __restrict__ p, double* __restrict__ po,
+                                                     const double* __restrict__ gate) {
+  if (gate && *gate != 0.0) return;
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= n * n * n) return;
+  const int64_t mp = 2 * n + 1;
+  const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+  const int64_t base = 2 * i + mp * (2 * j + mp * 2 * k);
+  double v[27];
+  for (int a = 0; a < 27; ++a) v[a] = p[base + (a % 3) + mp * ((a / 3) % 3 + mp * (a / 9))];
+  // contraction with M2 along x, then y, then z
+  double t[27];
+  for (int a = 0; a < 27; ++a) {
+    const int x = a % 3, r = a - x;
+    t[a] = c_q3M2[3 * x] * v[r] + c_q3M2[3 * x + 1] * v[r + 1] + c_q3M2[3 * x + 2] * v[r + 2];
+  }
+  for (int a = 0; a < 27; ++a) {
+    const int y = (a / 3) % 3, r = a - 3 * y;
+    v[a] = c_q3M2[3 * y] * t[r] + c_q3M2[3 * y + 1] * t[r + 3] + c_q3M2[3 * y + 2] * t[r + 6];
+  }
+  const double s = 1.0 / (double(n) * double(n) * double(n) * mu[c]);
+  for (int a = 0; a < 27; ++a) {
+    const int z = a / 9, r = a - 9 * z;
+    const double o = c_q3M2[3 * z] * v[r] + c_q3M2[3 * z + 1] * v[r + 9] + c_q3M2[3 * z + 2] * v[r + 18];
+    atomicAdd(&po[base + (a % 3) + mp * ((a / 3) % 3 + mp * (a / 9))], s * o);
+  }
+}
+
+// diag(M_p) by the same cell sums (one thread per cell)
+__global__ __launch_bounds__(kBlock) void k_pmass_diag_q2(int64_t n, const double* __restrict__ mu,
+                                                          double* __restrict__ dg) {
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= n * n * n) return;
+  const int64_t mp = 2 * n + 1;
+  const int64_t i = c % n, j = (c / n) % n, k = c / (n * n);
+  const int64_t base = 2 * i + mp * (2 * j + mp * 2 * k);
+  const double s = 1.0 / (double(n) * double(n) * double(n) * mu[c]);
+  for (int a = 0; a < 27; ++a) {
+    const int x = a % 3, y = (a / 3) % 3, z = a / 9;
+    atomicAdd(&dg[base + x + mp * (y + mp * z)], s * c_q3M2[4 * x] * c_q3M2[4 * y] * c_q3M2[4 * z]);
+  }
+}
+
+}  // namespace
+
+void set_q3_constants(const double* N, const double* D, const double* w, const double* P2, const double* M2) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_q3N), N, 16 * sizeof(double));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_q3D), D, 16 * sizeof(double));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_q3W), w, 4 * sizeof(double));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_q3P), P2, 12 * sizeof(double));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_q3M2), M2, 9 * sizeof(double));
+}
+
+template <typename T>
+void launch_vmult_q3_cells(const DevLevel& L, const T* x, T* y, hipStream_t s) {
+  const int64_t nc = L.ncell;
+  k_vmult_q3<T><<<unsigned((nc + 3) / 4), 256, 0, s>>>(L.n_edge, mu_of<T>(L), x, y);
+}
+template void launch_vmult_q3_cells<float>(const DevLevel&, const float*, float*, hipStream_t);
+template void launch_vmult_q3_cells<double>(const DevLevel&, const double*, double*, hipStream_t);
+
+void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s) {
+  k_diag_q3<<<grid_for(L.ncell), kBlock, 0, s>>>(L.n_edge, L.mu_d, kdiag, d);
+}
+
+void launch_harmonic_mu64(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s) {
+  k_harmonic64<<<grid_for(ncell), kBlock, 0, s>>>(ncell, mu_qp, mu);
+}
+
+void launch_rhs_q3(const DevLevel& L, const double* f, double* b, hipStream_t s) {
+  k_rhs_q3<<<unsigned((L.ncell + 3) / 4), 256, 0, s>>>(L.n_edge, f, b);
+}
+
+void launch_div_q3(const DevLevel& L, const double* u, double* po, hipStream_t s) {
+  k_div_q3<<<unsigned((L.ncell + 3) / 4), 256, 0, s>>>(L.n_edge, u, po);
+}
+
+void launch_grad_q3(const DevLevel& L, const double* p, double* uo, hipStream_t s) {
+  k_grad_q3<<<unsigned((L.ncell + 3) / 4), 256, 0, s>>>(L.n_edge, p, uo);
+}
+
+void launch_pmass_q2(const DevLevel& L, const double* p, double* po, hipStream_t s, const double* gate) {
+  k_pmass_q2<<<grid_for(L.ncell), kBlock, 0, s>>>(L.n_edge, L.mu_d, p, po, gate);
+}
+
+void launch_pmass_diag_q2(const DevLevel& L, double* dg, hipStream_t s) {
+  k_pmass_diag_q2<<<grid_for(L.ncell), kBlock, 0, s>>>(L.n_edge, L.mu_d, dg);
+}
+
+}  // namespace mfgmg

@@ -34,7 +34,7 @@ EXPORTS = [
     "mfgmg_features", "mfgmg_fit_objective", "mfgmg_fit_targets", "mfgmg_set_scaling", "mfgmg_use_scaling",
     "mfgmg_vcycle_factor", "mfgmg_mlp_forward", "mfgmg_mlp_backward", "mfgmg_mlp_work_size", "mfgmg_mlp_adam",
     "mfgmg_mlp_train", "mfgmg_apply_mlp", "mfgmg_vmult_uniform_noalloc",
-    "mfgmg_last_error", "mfgmg_destroy", "mfgmg_set_boundary",
+    "mfgmg_last_error", "mfgmg_destroy", "mfgmg_set_boundary", "mfgmg_set_element",
 ]
 N_PARAMS = 6147
 MLP_CACHE = 131
@@ -49,7 +49,7 @@ class Info(C.Structure):
                 ("n_cells", C.c_int64 * (MAX_LEVELS + 1)), ("n_nodes", C.c_int64 * (MAX_LEVELS + 1)),
                 ("n_u", C.c_int64 * (MAX_LEVELS + 1)), ("n_free", C.c_int64 * (MAX_LEVELS + 1)),
                 ("n_hanging", C.c_int64 * (MAX_LEVELS + 1)), ("uniform", C.c_int32 * (MAX_LEVELS + 1)),
-                ("n_p", C.c_int64), ("n_p_hanging", C.c_int64), ("boundary", C.c_int32)]
+                ("n_p", C.c_int64), ("n_p_hanging", C.c_int64), ("boundary", C.c_int32), ("element_k", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -82,6 +82,7 @@ def load():
         "mfgmg_refine": [vp, vp, i64, i32],
         "mfgmg_finalize_mesh": [vp],
         "mfgmg_set_boundary": [vp, i32],
+        "mfgmg_set_element": [vp, i32],
         "mfgmg_info": [vp, C.POINTER(Info)],
         "mfgmg_cells": [vp, i32, vp],
         "mfgmg_support_points": [vp, i32, i32, vp],
@@ -245,6 +246,11 @@ class Solver:
             raise ValueError(f"unknown boundary condition {bc!r} (expected one of {sorted(BOUNDARY)})")
         self._check(self.lib.mfgmg_set_boundary(self.h, BOUNDARY[bc]))
 
+    def set_element(self, k):
+        """Taylor-Hood pair before finalize_mesh: k = 1 (Q2-Q1, the default)
+        or k = 2 (Q3-Q2; uniform meshes with u = 0)."""
+        self._check(self.lib.mfgmg_set_element(self.h, int(k)))
+
     def refine(self, cells, levels_up):
         cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 4)
         self._check(self.lib.mfgmg_refine(self.h, _np_ptr(cells), len(cells), int(levels_up)))
@@ -268,6 +274,7 @@ class Solver:
                 "uniform": [bool(inf.uniform[l]) for l in range(L + 1)],
                 "n_p": int(inf.n_p), "n_p_hanging": int(inf.n_p_hanging),
                 "boundary": "noflux" if inf.boundary == BC_NOFLUX else "dirichlet",
+                "element_k": int(inf.element_k),
             }
         return self._info
 
@@ -314,9 +321,13 @@ class Solver:
         self._check(self.lib.mfgmg_transfer(self.h, level, C.byref(nnz), _np_ptr(ptr), _np_ptr(col), _np_ptr(w)))
         return ptr, col, w
 
+    def quad_points_per_cell(self):
+        """Gauss points per leaf cell: 27 for Q2-Q1, 64 for Q3-Q2."""
+        return 64 if self.info()["element_k"] == 2 else 27
+
     def leaf_quadrature_points(self):
         L = self.info()["L"]
-        out = np.empty((self.info()["n_cells"][L], 27, 3), dtype=np.float64)
+        out = np.empty((self.info()["n_cells"][L], self.quad_points_per_cell(), 3), dtype=np.float64)
         self._check(self.lib.mfgmg_leaf_quadrature_points(self.h, _np_ptr(out)))
         return out
 
@@ -324,8 +335,9 @@ class Solver:
     def set_viscosity(self, mu_qp, stream=None):
         mu_qp = np.ascontiguousarray(mu_qp, dtype=np.float64)
         L = self.info()["L"]
-        if mu_qp.size != 27 * self.info()["n_cells"][L]:
-            raise ValueError("mu_qp must have 27 values per leaf cell")
+        nq = self.quad_points_per_cell()
+        if mu_qp.size != nq * self.info()["n_cells"][L]:
+            raise ValueError(f"mu_qp must have {nq} values per leaf cell")
         self._check(self.lib.mfgmg_set_viscosity(self.h, _np_ptr(mu_qp), stream or current_stream()))
 
     def cell_viscosity(self, level):
@@ -396,7 +408,7 @@ class Solver:
 
     def assemble_rhs(self, f_qp, rhs, stream=None):
         L = self.info()["L"]
-        f_qp = _host_f64(f_qp, 27 * 3 * self.info()["n_cells"][L], "f_qp")
+        f_qp = _host_f64(f_qp, self.quad_points_per_cell() * 3 * self.info()["n_cells"][L], "f_qp")
         self._check(self.lib.mfgmg_assemble_rhs(self.h, _np_ptr(f_qp), _dev_ptr(rhs, self._nu(L), FP64, "rhs"),
                                                 stream or current_stream()))
 

@@ -1,0 +1,226 @@
+"""Device parity of the Q3-Q2 pair (k = 2 of Sec. 2.1) against the CPU oracle
+(``oracle/q3q2.py``), on uniform meshes of 4^3 and 8^3 cells with
+sinker viscosity; both sides number nodes on the same lattice, so vectors
+compare entry by entry without a permutation.
+
+Tolerances as for Q2-Q1: operator FP64 1e-12, FP32 1e-5 (relative 2-norm;
+row by row against (|D K D| + I)|x| with the ROW64 / ROW32 factors of the
+Q2-Q1 tests), smoother FP64 1e-12 / FP32 1e-5, V-cycle FP64 1e-11 / FP32 1e-4,
+transfers 1e-14, B, B^T, M_p and the right-hand side 1e-12, lambda 1e-9; the
+Stokes solve reaches an FP64 residual <= 1e-8 recomputed by the oracle's
+assembled block system and matches its direct solve."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import multigrid as omg, q3q2
+from paper_1907_06696_amd import inputs, mfgmg
+from tests.parity_cases import rel_err, row_err
+from tests.test_gpu_parity import ROW32, ROW64
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CASES = {"q3_4": dict(L=2, sinkers=4, dr=1e2, seed=1), "q3_8": dict(L=3, sinkers=6, dr=1e4, seed=5)}
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+class Q3Case:
+    def __init__(self, L, sinkers, dr, seed):
+        self.L = L
+        self.s = mfgmg.Solver(L)
+        self.s.set_element(2)
+        self.s.finalize_mesh()
+        self.info = self.s.info()
+        cen = inputs.sinker_centres(sinkers, seed)
+        qp = self.s.leaf_quadrature_points().reshape(-1, 3)
+        self.mu_qp = inputs.sinker_mu(qp, cen, dr).reshape(-1, 64)
+        self.f_qp = inputs.sinker_force(qp, cen).reshape(-1, 64, 3)
+        self.mu_leaf = q3q2.harmonic_cell_viscosity(self.mu_qp)
+        self.gmg = q3q2.GMG(L, self.mu_leaf)
+        self.s.set_viscosity(self.mu_qp)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Q3Case(**CASES[request.param])
+    print(f"\n[q3 case {request.param}] L={c.L} n_u={c.info['n_u'][c.L]} n_p={c.info['n_p']}", flush=True)
+    yield c
+    c.s.close()
+
+
+def abs_bound(mesh, mu, x):
+    """(|D K D| + (I - D)) |x| with K the sum over cells of mu_K h |K_hat|."""
+    kabs = np.abs(q3q2.khat())
+    dofs = mesh.cell_dofs()
+    f = mesh.free_dofs_mask()
+    xa = np.abs(x) * f
+    loc = xa[dofs] @ kabs.T * (np.asarray(mu) * mesh.h)[:, None]
+    y = np.bincount(dofs.ravel(), weights=loc.ravel(), minlength=mesh.n_u)
+    return y * f + np.where(f, 0.0, np.abs(x))
+
+
+def test_cell_viscosity(case):
+    for ell in range(1, case.L + 1):
+        ref = case.gmg.mu[ell]
+        assert np.abs(case.s.cell_viscosity(ell) - ref).max() <= 1e-13 * ref.max()
+
+
+def test_vmult_fp64_fp32(case):
+    for ell in range(1, case.L + 1):
+        n = case.info["n_u"][ell]
+        A, mesh, mu = case.gmg.A[ell], case.gmg.mesh[ell], case.gmg.mu[ell]
+        x = inputs.uniform_vector(n, 100 + ell)
+        y = torch.empty(n, dtype=torch.float64, device=DEV)
+        case.s.vmult(ell, to_dev(x), y)
+        ref = A @ x
+        yh = to_host(y)
+        e64, r64 = rel_err(yh, ref), row_err(yh, ref, abs_bound(mesh, mu, x))
+        x32 = x.astype(np.float32)
+        y32 = torch.empty(n, dtype=torch.float32, device=DEV)
+        case.s.vmult(ell, to_dev(x32, torch.float32), y32)
+        ref32 = A @ x32.astype(np.float64)
+        yh32 = to_host(y32)
+        e32, r32 = rel_err(yh32, ref32), row_err(yh32, ref32, abs_bound(mesh, mu, x32.astype(np.float64)))
+        print(f"[q3 vmult] level {ell}: FP64 rel {e64:.2e} row {r64:.2e}; FP32 rel {e32:.2e} row {r32:.2e}",
+              flush=True)
+        assert e64 <= 1e-12 and r64 <= ROW64, (ell, e64, r64)
+        assert e32 <= 1e-5 and r32 <= ROW32, (ell, e32, r32)
+
+
+def test_vmult_add(case):
+    ell = case.L
+    n = case.info["n_u"][ell]
+    free = case.gmg.free[ell]
+    x = inputs.uniform_vector(n, 300)
+    y0 = inputs.uniform_vector(n, 400)
+    y = to_dev(y0)
+    case.s.vmult_add(ell, to_dev(x), y)
+    ref = y0 + np.where(free, case.gmg.A[ell] @ x, 0.0)
+    yh = to_host(y)
+    assert rel_err(yh, ref) <= 1e-12
+    assert np.array_equal(yh[~free], y0[~free])
+
+
+def test_inverse_diagonal_and_lambda(case):
+    for ell in range(1, case.L + 1):
+        n = case.info["n_u"][ell]
+        d = torch.empty(n, dtype=torch.float64, device=DEV)
+        case.s.inverse_diagonal(ell, d)
+        ref = case.gmg.minv[ell]
+        assert np.abs(to_host(d) - ref).max() <= 1e-12 * np.abs(ref).max()
+        if ell >= 2:
+            lam = case.s.smoother_lambda(ell)
+            assert abs(lam - case.gmg.lam[ell]) <= 1e-9 * case.gmg.lam[ell], (ell, lam, case.gmg.lam[ell])
+
+
+def test_transfers(case):
+    for ell in range(2, case.L + 1):
+        nf, nc = case.info["n_u"][ell], case.info["n_u"][ell - 1]
+        P = case.gmg.P[ell]
+        xc = inputs.uniform_vector(nc, 11 + ell)
+        xf = torch.empty(nf, dtype=torch.float64, device=DEV)
+        case.s.prolongate(ell, to_dev(xc), xf)
+        assert rel_err(to_host(xf), P @ xc) <= 1e-14
+        rf = inputs.uniform_vector(nf, 21 + ell)
+        rc = torch.empty(nc, dtype=torch.float64, device=DEV)
+        case.s.restrict(ell, to_dev(rf), rc)
+        assert rel_err(to_host(rc), P.T @ rf) <= 1e-14
+
+
+def test_smoother_coarse_vcycle(case):
+    ell = case.L
+    n = case.info["n_u"][ell]
+    free = case.gmg.free[ell]
+    A = case.gmg.A[ell]
+    for dt, npt, tol in ((torch.float64, np.float64, 1e-12), (torch.float32, np.float32, 1e-5)):
+        b = (inputs.uniform_vector(n, 31) * free).astype(npt).astype(np.float64)
+        x0 = (inputs.uniform_vector(n, 32) * free).astype(npt).astype(np.float64)
+        for zero in (True, False):
+            ref = omg.chebyshev(lambda v: A @ v, case.gmg.minv[ell], b, None if zero else x0, case.gmg.lam[ell],
+                                x_is_zero=zero)
+            x = to_dev(x0, dt)
+            case.s.smooth(ell, to_dev(b, dt), x, x_is_zero=zero)
+            e = rel_err(to_host(x), ref)
+            print(f"[q3 smooth] {dt} from {'zero' if zero else 'x0'}: rel {e:.2e}", flush=True)
+            assert e <= tol, (dt, zero, e)
+    n1 = case.info["n_u"][1]
+    b1 = inputs.uniform_vector(n1, 33) * case.gmg.free[1]
+    x1 = torch.empty(n1, dtype=torch.float64, device=DEV)
+    case.s.coarse_solve(to_dev(b1), x1)
+    assert rel_err(to_host(x1), case.gmg.coarse_solve(b1)) <= 1e-12
+    b = inputs.uniform_vector(n, 41) * free
+    ref = case.gmg.vcycle(b)
+    x = torch.empty(n, dtype=torch.float64, device=DEV)
+    case.s.vcycle(to_dev(b), x)
+    e64 = rel_err(to_host(x), ref)
+    x32 = torch.empty(n, dtype=torch.float32, device=DEV)
+    case.s.vcycle(to_dev(b, torch.float32), x32)
+    e32 = rel_err(to_host(x32), ref)
+    print(f"[q3 vcycle] L {ell}: FP64 rel {e64:.2e}, FP32 rel {e32:.2e}", flush=True)
+    assert e64 <= 1e-11 and e32 <= 1e-4, (e64, e32)
+
+
+def test_pressure_operators_and_rhs(case):
+    mesh = case.gmg.mesh[case.L]
+    nu, npp = case.info["n_u"][case.L], case.info["n_p"]
+    B = q3q2.assemble_B(mesh)
+    Mp = q3q2.assemble_Mp(mesh, case.mu_leaf)
+    u = inputs.uniform_vector(nu, 51)
+    p = inputs.uniform_vector(npp, 52)
+    out_p = torch.empty(npp, dtype=torch.float64, device=DEV)
+    case.s.apply_div(to_dev(u), out_p)
+    assert rel_err(to_host(out_p), B @ u) <= 1e-12
+    out_u = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.apply_grad(to_dev(p), out_u)
+    assert rel_err(to_host(out_u), B.T @ p) <= 1e-12
+    case.s.apply_pmass(to_dev(p), out_p)
+    assert rel_err(to_host(out_p), Mp @ p) <= 1e-12
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.assemble_rhs(case.f_qp, rhs)
+    assert rel_err(to_host(rhs), q3q2.assemble_rhs(mesh, case.f_qp)) <= 1e-12
+
+
+def test_solve_matches_oracle(case):
+    prob = q3q2.StokesProblem(case.L, case.mu_leaf, case.f_qp, with_gmg=False)
+    xd = prob.solve_direct()
+    nu, npp = case.info["n_u"][case.L], case.info["n_p"]
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    case.s.assemble_rhs(case.f_qp, rhs)
+    for prec in ("fp64", "fp32"):
+        u = torch.empty(nu, dtype=torch.float64, device=DEV)
+        p = torch.empty(npp, dtype=torch.float64, device=DEV)
+        st = case.s.solve_stokes(rhs, u, p, vcycle_prec=prec, rtol=1e-10)
+        x = np.concatenate([to_host(u) * case.gmg.free[case.L], to_host(p)])
+        res, err = prob.residual(x), np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"[q3 solve] L {case.L} {prec}: its={st['iterations']} inner={st['inner_cg_iterations']} "
+              f"res={res:.2e} err={err:.2e}", flush=True)
+        assert st["converged"] == 1 and res <= 1.5e-10 and err <= 1e-5, (prec, res, err)
+
+
+def test_q2q1_only_calls_refused():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = Q3Case(L=2, sinkers=2, dr=1e2, seed=3)
+    nu, npp = c.info["n_u"][2], c.info["n_p"]
+    rhs = torch.zeros(nu, dtype=torch.float64, device=DEV)
+    u = torch.empty_like(rhs)
+    p = torch.empty(npp, dtype=torch.float64, device=DEV)
+    with pytest.raises(mfgmg.MFGMGError) as e:
+        c.s.solve_stokes(rhs, u, p, krylov="gmres", schur="cheb")
+    assert e.value.code == mfgmg.ERR_INVALID
+    with pytest.raises(mfgmg.MFGMGError) as e:
+        c.s.features(2)
+    assert e.value.code == mfgmg.ERR_INVALID
+    c.s.close()
