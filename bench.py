@@ -39,6 +39,12 @@ PEAK_HBM_GBS = 8000.0
 # counting an FMA as 2 flops): 810 (interpolation) + 972 (gradients) + 297
 # (stress) + 1215 (transposed gradients) + 729 (transposed interpolation)
 FLOP_PER_CELL = 4023
+# The Q3-Q2 operator (k = 2) per cell: 36 one-dimensional contractions of 64
+# values with 4 terms each (9 interpolation, 9 derivative, 9 transposed
+# derivative, 9 transposed interpolation sweeps; 4 multiplies + 3 adds),
+# 768 for the symmetric stress (6 sums, 6 scalings per point) and 384 for
+# summing the three transposed derivatives of each component
+Q3_FLOP_PER_CELL = 36 * 64 * 7 + 768 + 384
 
 
 def parse():
@@ -49,6 +55,9 @@ def parse():
     p.add_argument("--no-solve", action="store_true", help="skip every Stokes solve")
     p.add_argument("--no-adaptive", action="store_true", help="skip the adaptive 32^3 + 2 solves")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (oracle timing and residual checks)")
+    p.add_argument("--no-q3", action="store_true", help="skip the Q3-Q2 (k = 2) section")
+    p.add_argument("--q3-level", type=int, default=5, help="Q3-Q2 section: 2^level cells per edge (default 5: 32^3)")
+    p.add_argument("--q3-only", action="store_true", help="run the Q3-Q2 section alone (for profiling)")
     p.add_argument("--level", type=int, default=6, help="cells per edge = 2^level (default 6: 64^3)")
     p.add_argument("--solve-workload", choices=["adaptive32p2", "uniform128p1"], default=None,
                    help="instead of the operator benchmark, compare the Stokes solves on this workload")
@@ -143,6 +152,78 @@ SOLVER_VARIANTS = {
     # the inner pressure-mass CG to 1e-6 instead of the default 1e-2
     "fp32_schur1e-6": ("fp32", dict(schur_rtol=1e-6)),
 }
+
+
+def q3_section(level, centres, dr, timed, solves=True):
+    """The Q3-Q2 pair (k = 2 of Sec. 2.1) on the same sinker field (8
+    sinkers, DR 1e4): operator throughput, FP64 and FP32, on rotating vector
+    pairs larger than the last-level cache (one mfgmg_vmult: the output
+    initialisation and the wavefront-per-cell kernel), V-cycles, and the
+    Stokes solves to 1e-8 with the FP64 and the FP32 V-cycle (FGMRES(50))."""
+    import torch
+    from paper_1907_06696_amd import inputs, mfgmg
+    t0 = time.perf_counter()
+    s = mfgmg.Solver(level)
+    s.set_element(2)
+    s.finalize_mesh()
+    info = s.info()
+    L = info["L"]
+    n, ncell = info["n_u"][L], info["n_cells"][L]
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    s.set_viscosity(inputs.sinker_mu(qp, centres, dr).reshape(-1, 64))
+    torch.cuda.synchronize()
+    out = {"workload": f"sinker {1 << level}^3 uniform Q3-Q2, 8 sinkers, DR 1e4", "cells": ncell,
+           "velocity_dofs": n, "pressure_dofs": info["n_p"], "setup_s": round(time.perf_counter() - t0, 2)}
+    print(f"[q3] {out['workload']}: {n} velocity dofs, setup {out['setup_s']} s", file=sys.stderr, flush=True)
+    reps = 20
+    flops = Q3_FLOP_PER_CELL * ncell
+    ops = {}
+    first = {}
+    for prec, dt, word, peak in (("f64", torch.float64, 8, PEAK_FP64_TFLOPS), ("f32", torch.float32, 4,
+                                                                                PEAK_FP32_TFLOPS)):
+        npairs = max(2, int(np.ceil(320e6 / (2 * word * n))))
+        xs = [torch.tensor(inputs.uniform_vector(n, 42 + i), dtype=dt, device="cuda") for i in range(npairs)]
+        ys = [torch.empty_like(x) for x in xs]
+        k = [0]
+
+        def step():
+            for r in range(reps):
+                i = (k[0] + r) % npairs
+                s.vmult(L, xs[i], ys[i])
+            k[0] += reps
+        t = timed(step, 5, 1) / (5 * reps)
+        ach = flops / t / 1e12
+        ops[prec] = {"gdofs": round(n / t / 1e9, 3), "call_us": round(t * 1e6, 2), "pairs": npairs,
+                     "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                     "flop_per_launch": flops, "alg_bytes_per_launch": 2 * word * n + word * ncell,
+                     "hbm_frac_algorithmic": round((2 * word * n + word * ncell) / t / 1e9 / PEAK_HBM_GBS, 4)}
+        first[prec] = xs[0]
+        del ys
+    ops["kernel"] = "k_init_out_general + k_vmult_q3 (one mfgmg_vmult)"
+    out["operator"] = ops
+    vc = {}
+    for name, key in (("fp32", "f32"), ("fp64", "f64")):
+        xx = first[key]
+        yy = torch.empty_like(xx)
+        vc[name] = round(timed(lambda: s.vcycle(xx, yy), 10, 2) / 10 * 1e3, 3)
+    out["vcycle_ms"] = vc
+    print(f"[q3] operator {json.dumps({p: ops[p]['gdofs'] for p in ('f64', 'f32')})} GDoF/s, "
+          f"V-cycle {vc} ms", file=sys.stderr, flush=True)
+    if solves:
+        rhs = torch.empty(n, dtype=torch.float64, device="cuda")
+        s.assemble_rhs(inputs.sinker_force(qp, centres).reshape(-1, 64, 3), rhs)
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        p = torch.empty(info["n_p"], dtype=torch.float64, device="cuda")
+        sol = {}
+        for prec in ("fp64", "fp32"):
+            st = s.solve_stokes(rhs, u, p, vcycle_prec=prec, raise_on_noconv=False, max_iter=3000)
+            sol[prec] = {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
+                         "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
+                         "converged": bool(st["converged"])}
+        out["stokes_solve_1e-8"] = sol
+        print(f"[q3] solves {json.dumps(sol)}", file=sys.stderr, flush=True)
+    s.close()
+    return out
 
 
 def krylov_vectors(kw, restart):
@@ -383,7 +464,7 @@ def summarize_trace(path, top=14):
     groups = {}
     for r in csv.DictReader(open(path)):
         name = r["Kernel_Name"] or "(unnamed)"
-        name = name.replace("void ", "").split("(")[0].replace("mfgmg::", "").replace("(anonymous namespace)::", "")
+        name = name.replace("void ", "").replace("(anonymous namespace)::", "").replace("mfgmg::", "").split("(")[0]
         grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
         g = groups.setdefault((name, grid), {"d": [], "vgpr": r["VGPR_Count"], "agpr": r["Accum_VGPR_Count"],
                                              "lds": r["LDS_Block_Size"]})
@@ -435,6 +516,23 @@ def main():
     centres = inputs.sinker_centres(cfg["sinkers"], cfg["centre_seed"])
     dr = cfg["dr"]
 
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    if args.q3_only:
+        print(json.dumps({"q3q2": q3_section(args.q3_level, centres, dr, timed, solves=not args.no_solve)}),
+              flush=True)
+        return
+
     t_setup = time.perf_counter()
     s = mfgmg.Solver(level)
     s.finalize_mesh()
@@ -458,18 +556,6 @@ def main():
         counter_probe(s, L, pairs)
         s.close()
         return
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3
 
     def op_step(prec, rotate, add=False):
         xs, ys = pairs[prec]
@@ -573,6 +659,8 @@ def main():
             checks["adaptive32p2"] = (lev, ijk, cen, acfg["dr"], keys, keep)
         print("[bench] adaptive 32^3+2 solves done", file=sys.stderr, flush=True)
 
+    if not args.no_q3:
+        result["q3q2"] = q3_section(args.q3_level, centres, dr, timed, solves=not args.no_solve)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(level, centres, dr, checks)
     print(json.dumps(result), flush=True)

@@ -28,18 +28,18 @@ def driver(tmp_path_factory):
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("asan") / "mesh_driver")
     cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=all", os.path.join(CSRC, "mesh.cpp"),
+           "-fno-sanitize-recover=all", os.path.join(CSRC, "mesh.cpp"), os.path.join(CSRC, "q3.cpp"),
            os.path.join(ROOT, "tests", "native", "mesh_driver.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     return exe
 
 
-def _run(exe, base, corners, times):
+def _run(exe, base, corners, times, mode="dirichlet"):
     cells = [f"{base} {c[0]} {c[1]} {c[2]}" for c in corners]
     inp = f"{base} {times} {len(cells)}\n" + "\n".join(cells) + "\n"
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    r = subprocess.run([exe], input=inp, capture_output=True, text=True, env=env, timeout=300)
+    r = subprocess.run([exe, mode], input=inp, capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0 and "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
     return r.stdout.splitlines()
 
@@ -103,3 +103,59 @@ def test_mesh_layer_under_sanitizers_matches_oracle(driver, base, corners, times
         assert ell > base and nc == G.T[ell].ncell and nn == G.T[ell].nnode and ne == G.edge[ell][::3].sum()
     # every free leaf node copied once (a uniform leaf mesh has no local levels)
     assert int(parts[-1].split()[1]) == (int(H.leaf.free.sum()) if base < H.L else 0)
+
+
+@pytest.mark.parametrize("base,corners,times", CASES[2:5])
+def test_noflux_mesh_layer_under_sanitizers(driver, base, corners, times):
+    """u . n = 0: node kinds, fixed-component masks, hanging rows and the
+    node-level transfers (no boundary rows dropped) against the oracle."""
+    out = _run(driver, base, corners, times, "noflux")
+    lev, ijk = omesh.uniform_leaves(base)
+    mask = np.zeros(len(lev), bool)
+    for c in corners:
+        mask |= np.all(ijk == list(c), axis=1)
+    H = omesh.Hierarchy(*omesh.balance(*omesh.refine(lev, ijk, mask, times)), bc="noflux")
+    assert out[0] == f"L {H.L}"
+    pos = 1
+    for ell in range(1, H.L + 1):
+        om = H.levels[ell]
+        keys = np.array(out[pos + 1].split()[1:], dtype=np.int64)
+        order = np.argsort(keys)
+        assert np.array_equal(keys[order], om.keys)
+        types = np.array(out[pos + 2].split()[1:], dtype=np.int64)[order]
+        assert np.array_equal(types, np.where(om.hanging, 2, 0))
+        fix = np.array(out[pos + 5].split()[1:], dtype=np.int64)[order]
+        assert np.array_equal(fix, (om.fixed * np.array([1, 2, 4])).sum(axis=1))
+        if ell >= 2:
+            Pn = sp.lil_matrix((om.nnode, H.levels[ell - 1].nnode))
+            for tok in out[pos + 4].split()[1:]:
+                a, b, w = tok.split(":")
+                Pn[np.searchsorted(om.keys, keys[int(a)]), np.searchsorted(H.levels[ell - 1].keys, ckeys[int(b)])] \
+                    = float(w)
+            assert abs(Pn.tocsr() - ops.prolongation(H, ell, dirichlet=False)[::3, ::3]).max() <= 1e-14
+        ckeys = keys
+        pos += 6
+
+
+@pytest.mark.parametrize("base", [1, 2, 3])
+def test_q3_levels_under_sanitizers(driver, base):
+    """Q3-Q2 lattice levels: node counts and kinds, transfers against the oracle."""
+    from oracle import q3q2
+    out = _run(driver, base, (), 1, "q3")
+    assert out[0] == f"L {base}"
+    pos = 1
+    for ell in range(1, base + 1):
+        om = q3q2.UniformMesh(ell)
+        head = out[pos].split()
+        assert int(head[5]) == om.nnode and int(head[7]) == 0
+        assert np.array_equal(np.array(out[pos + 1].split()[1:], dtype=np.int64), np.arange(om.nnode))
+        assert np.array_equal(np.array(out[pos + 2].split()[1:], dtype=np.int64), np.where(om.dirichlet, 1, 0))
+        if ell >= 2:
+            Pn = sp.lil_matrix((om.nnode, q3q2.UniformMesh(ell - 1).nnode))
+            for tok in out[pos + 4].split()[1:]:
+                a, b, w = tok.split(":")
+                Pn[int(a), int(b)] = float(w)
+            Pref = q3q2.prolongation(q3q2.UniformMesh(ell - 1), om)[::3, ::3]
+            assert abs(Pn.tocsr() - Pref).max() <= 1e-14
+        pos += 5
+    assert int(out[pos].split()[2]) == (2 ** (base + 1) + 1) ** 3
