@@ -4,16 +4,24 @@
 // One wavefront per cell: lane l = x + 4 y + 16 z stands for the tensor
 // point (x, y, z) of the cell's 4 x 4 x 4 nodes and, after interpolation, of
 // its 4 x 4 x 4 Gauss points.  A one-dimensional 4 x 4 contraction along an
-// axis is four cross-lane reads (ds_bpermute through __shfl) and four fused
-// multiply-adds per lane, so the sum-factorised operator keeps one value per
-// lane and component and needs no LDS allocation or barrier:
+// axis is four reads of other lanes and four multiply-adds per lane, so the
+// sum-factorised operator keeps one value per lane and component:
 //   interpolate u to the Gauss points (3 axes x 3 components),
 //   differentiate there with the Gauss-collocation derivative (9 sweeps),
 //   F_cd = mu h w_q (d_d u_c + d_c u_d),
-//   y_c = N^T N^T N^T sum_d D_d^T F_cd (9 + 9 transposed sweeps),
-// then each lane adds its node's three results (atomics: a node is shared by
-// up to 8 cells).  Constrained (boundary) nodes are read as zero and receive
-// nothing; the caller initialises y (identity rows) beforehand.
+//   y_c = N^T N^T N^T sum_d D_d^T F_cd (9 + 9 transposed sweeps).
+// In the operator the x and y contractions read the other lanes through DPP
+// (quad broadcast along x, row rotation by 4, 8, 12 lanes along y: VALU
+// operand modifiers, no LDS traffic) and the z contraction, across rows,
+// through __shfl (ds_bpermute); the other kernels use __shfl throughout.
+// The operator's results are summed over a 2 x 2 x 2 block of cells (one
+// workgroup, a wavefront per cell): each wavefront stores its 3 x 64 results
+// in its own LDS slot, and each thread of the write-back sums the (up to 8)
+// slot entries of one block lattice point and component and adds them into
+// y: the points inside the block, which no other block touches, with a plain
+// read-add-write, those on its faces with atomics (218 of 343 points instead
+// of 8 x 64 cell nodes).  Constrained (boundary) nodes are read as zero and
+// receive nothing; the caller initialises y (identity rows) beforehand.
 #include <hip/hip_runtime.h>
 
 #include "ops.h"
@@ -64,6 +72,59 @@ __device__ __forceinline__ void col_of(const double* M, int lane, T (&c)[4]) {
   for (int q = 0; q < 4; ++q) c[q] = T(M[4 * q + a]);
 }
 
+// DPP move of a 32-bit value (CTRL: quad_perm / row_ror encodings of GFX9)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i<CTRL>(int(b & 0xffffffffLL)), hi = dpp_i<CTRL>(int(b >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+constexpr int kQuadBcast[4] = {0x00, 0x55, 0xAA, 0xFF};   // quad_perm: every lane of a quad reads lane a
+constexpr int kRowRor[4] = {0, 0x124, 0x128, 0x12C};      // row_ror by 0, 4, 8, 12 lanes
+
+// x contraction: c[a] the lane's coefficient of quad lane a (row_of / col_of)
+template <typename T>
+__device__ __forceinline__ T sweep_x(T v, const T (&c)[4]) {
+  return c[0] * dpp<kQuadBcast[0]>(v) + c[1] * dpp<kQuadBcast[1]>(v) + c[2] * dpp<kQuadBcast[2]>(v) +
+         c[3] * dpp<kQuadBcast[3]>(v);
+}
+// y contraction: r[k] the lane's coefficient of the value that the rotation by
+// 4k lanes brings (the coefficient of that value's y coordinate)
+template <typename T>
+__device__ __forceinline__ T sweep_y(T v, const T (&r)[4]) {
+  return r[0] * v + r[1] * dpp<kRowRor[1]>(v) + r[2] * dpp<kRowRor[2]>(v) + r[3] * dpp<kRowRor[3]>(v);
+}
+// y coordinate (lane bits 2-3) of the lane each rotation reads
+__device__ __forceinline__ void rot_sources(int lane, int (&src)[4]) {
+  const int yv = (lane >> 2) & 3;
+  src[0] = yv;
+  src[1] = dpp_i<kRowRor[1]>(yv);
+  src[2] = dpp_i<kRowRor[2]>(yv);
+  src[3] = dpp_i<kRowRor[3]>(yv);
+}
+// coefficients of a y contraction in rotation order: row (out(q) = sum_a M[q][a] v(a))
+// or column (out(a) = sum_q M[q][a] v(q)) of M for the lane's y coordinate
+template <typename T>
+__device__ __forceinline__ void rot_row(const double* M, int lane, const int (&src)[4], T (&r)[4]) {
+  const int q = (lane >> 2) & 3;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = T(M[4 * q + src[k]]);
+}
+template <typename T>
+__device__ __forceinline__ void rot_col(const double* M, int lane, const int (&src)[4], T (&r)[4]) {
+  const int a = (lane >> 2) & 3;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = T(M[4 * src[k] + a]);
+}
+
 struct Q3Cell {
   int64_t node;
   bool bnd;
@@ -76,28 +137,37 @@ struct Q3Cell {
   }
 };
 
+constexpr int kQ3B = 2;                         // cells per block edge
+constexpr int kQ3E = 3 * kQ3B + 1;              // lattice points per block edge
+constexpr int kQ3P = kQ3E * kQ3E * kQ3E;        // lattice points per block
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_vmult_q3(int64_t n, const T* __restrict__ mu, const T* __restrict__ x,
-                                                  T* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int64_t cell = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const bool live = cell < n * n * n;
-  const int64_t c = live ? cell : 0;   // a dead wave works on cell 0 and writes nothing
+__global__ __launch_bounds__(64 * kQ3B * kQ3B * kQ3B) void k_vmult_q3(int64_t n, const T* __restrict__ mu,
+                                                                     const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int NW = kQ3B * kQ3B * kQ3B;
+  __shared__ T slot[NW][3][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t nb = n / kQ3B;
+  const int64_t bx = blockIdx.x % nb, by = (blockIdx.x / nb) % nb, bz = blockIdx.x / (nb * nb);
+  const int cx = w % kQ3B, cy = (w / kQ3B) % kQ3B, cz = w / (kQ3B * kQ3B);
+  const int64_t c = (bx * kQ3B + cx) + n * ((by * kQ3B + cy) + n * (bz * kQ3B + cz));
   const Q3Cell qc(n, c, lane);
   T u[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) u[k] = qc.bnd ? T(0) : x[3 * qc.node + k];
+  int src[4];
+  rot_sources(lane, src);
   T Nx[4], Ny[4], Nz[4];
-  row_of<0>(c_q3N, lane, Nx), row_of<1>(c_q3N, lane, Ny), row_of<2>(c_q3N, lane, Nz);
+  row_of<0>(c_q3N, lane, Nx), rot_row(c_q3N, lane, src, Ny), row_of<2>(c_q3N, lane, Nz);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) u[k] = sweep<2>(sweep<1>(sweep<0>(u[k], lane, Nx), lane, Ny), lane, Nz);
+  for (int k = 0; k < 3; ++k) u[k] = sweep<2>(sweep_y(sweep_x(u[k], Nx), Ny), lane, Nz);
   T Dx[4], Dy[4], Dz[4];
-  row_of<0>(c_q3D, lane, Dx), row_of<1>(c_q3D, lane, Dy), row_of<2>(c_q3D, lane, Dz);
+  row_of<0>(c_q3D, lane, Dx), rot_row(c_q3D, lane, src, Dy), row_of<2>(c_q3D, lane, Dz);
   T g[3][3];   // g[c][d] = d_d u_c at the lane's Gauss point
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    g[k][0] = sweep<0>(u[k], lane, Dx);
-    g[k][1] = sweep<1>(u[k], lane, Dy);
+    g[k][0] = sweep_x(u[k], Dx);
+    g[k][1] = sweep_y(u[k], Dy);
     g[k][2] = sweep<2>(u[k], lane, Dz);
   }
   const T wq = T(c_q3W[lane & 3] * c_q3W[(lane >> 2) & 3] * c_q3W[lane >> 4]);
@@ -107,17 +177,43 @@ __global__ __launch_bounds__(256) void k_vmult_q3(int64_t n, const T* __restrict
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) F[a][b] = coef * (g[a][b] + g[b][a]);
-  col_of<0>(c_q3D, lane, Dx), col_of<1>(c_q3D, lane, Dy), col_of<2>(c_q3D, lane, Dz);
-  col_of<0>(c_q3N, lane, Nx), col_of<1>(c_q3N, lane, Ny), col_of<2>(c_q3N, lane, Nz);
-  T out[3];
+  col_of<0>(c_q3D, lane, Dx), rot_col(c_q3D, lane, src, Dy), col_of<2>(c_q3D, lane, Dz);
+  col_of<0>(c_q3N, lane, Nx), rot_col(c_q3N, lane, src, Ny), col_of<2>(c_q3N, lane, Nz);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T t = sweep<0>(F[k][0], lane, Dx) + sweep<1>(F[k][1], lane, Dy) + sweep<2>(F[k][2], lane, Dz);
-    out[k] = sweep<2>(sweep<1>(sweep<0>(t, lane, Nx), lane, Ny), lane, Nz);
+    // every lane takes part in the cross-lane reads; boundary lanes drop the result after
+    const T t = sweep_x(F[k][0], Dx) + sweep_y(F[k][1], Dy) + sweep<2>(F[k][2], lane, Dz);
+    const T o = sweep<2>(sweep_y(sweep_x(t, Nx), Ny), lane, Nz);
+    slot[w][k][lane] = qc.bnd ? T(0) : o;
   }
-  if (!live || qc.bnd) return;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) atomicAdd(&y[3 * qc.node + k], out[k]);
+  __syncthreads();
+  // write-back: point p of the block lattice gathers, per axis, the cells
+  // (0 or 1) whose local coordinate p - 3 cell lies in 0..3
+  const int64_t m = 3 * n + 1;
+  for (int e = threadIdx.x; e < 3 * kQ3P; e += blockDim.x) {
+    const int p = e / 3, k = e - 3 * p;
+    const int px = p % kQ3E, py = (p / kQ3E) % kQ3E, pz = p / (kQ3E * kQ3E);
+    const int64_t X = 3 * kQ3B * bx + px, Y = 3 * kQ3B * by + py, Z = 3 * kQ3B * bz + pz;
+    if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) continue;
+    T v = T(0);
+    for (int ccz = 0; ccz < kQ3B; ++ccz) {
+      const int lz = pz - 3 * ccz;
+      if (lz < 0 || lz > 3) continue;
+      for (int ccy = 0; ccy < kQ3B; ++ccy) {
+        const int ly = py - 3 * ccy;
+        if (ly < 0 || ly > 3) continue;
+        for (int ccx = 0; ccx < kQ3B; ++ccx) {
+          const int lx = px - 3 * ccx;
+          if (lx < 0 || lx > 3) continue;
+          v += slot[ccx + kQ3B * (ccy + kQ3B * ccz)][k][lx + 4 * ly + 16 * lz];
+        }
+      }
+    }
+    T* dst = &y[3 * (X + m * (Y + m * Z)) + k];
+    const bool inner = px > 0 && px < kQ3E - 1 && py > 0 && py < kQ3E - 1 && pz > 0 && pz < kQ3E - 1;
+    if (inner) *dst += v;
+    else atomicAdd(dst, v);
+  }
 }
 
 // diagonal: d[3 node + c] += mu h K_hat[(a, c), (a, c)] over the cells (one thread per cell)
@@ -318,8 +414,9 @@ void set_q3_constants(const double* N, const double* D, const double* w, const d
 
 template <typename T>
 void launch_vmult_q3_cells(const DevLevel& L, const T* x, T* y, hipStream_t s) {
-  const int64_t nc = L.ncell;
-  k_vmult_q3<T><<<unsigned((nc + 3) / 4), 256, 0, s>>>(L.n_edge, mu_of<T>(L), x, y);
+  // uniform levels have n = 2^l >= 2 cells per edge: whole 2 x 2 x 2 blocks
+  const int64_t nb = L.n_edge / kQ3B;
+  k_vmult_q3<T><<<unsigned(nb * nb * nb), 64 * kQ3B * kQ3B * kQ3B, 0, s>>>(L.n_edge, mu_of<T>(L), x, y);
 }
 template void launch_vmult_q3_cells<float>(const DevLevel&, const float*, float*, hipStream_t);
 template void launch_vmult_q3_cells<double>(const DevLevel&, const double*, double*, hipStream_t);

@@ -224,3 +224,61 @@ def test_q2q1_only_calls_refused():
         c.s.features(2)
     assert e.value.code == mfgmg.ERR_INVALID
     c.s.close()
+
+
+def test_vmult_sampled_rows_at_bench_size():
+    """The 32^3 leaf the bench times (2,738,019 dofs), FP64 and FP32, in the
+    launch configuration the bench uses: 3,000 sampled rows (free and
+    constrained) against the oracle's rows built cell by cell from its
+    element matrix (FP32: on the rounded input), held to the row-scaled
+    bounds."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L = 5
+    s = mfgmg.Solver(L)
+    s.set_element(2)
+    s.finalize_mesh()
+    cen = inputs.sinker_centres(8, 2)
+    qp = s.leaf_quadrature_points().reshape(-1, 3)
+    mu_qp = inputs.sinker_mu(qp, cen, 1e4).reshape(-1, 64)
+    s.set_viscosity(mu_qp)
+    mesh = q3q2.UniformMesh(L)
+    mu = q3q2.harmonic_cell_viscosity(mu_qp)
+    n, m, nc = mesh.n_u, mesh.m, mesh.n
+    f = mesh.free_dofs_mask()
+    K = q3q2.khat()
+    rows = np.random.default_rng(7).choice(n, 3000, replace=False)
+
+    def reference(xin):
+        ref, bound = np.empty(len(rows)), np.empty(len(rows))
+        xf = xin * f
+        for r, i in enumerate(rows):
+            node, comp = divmod(int(i), 3)
+            if not f[i]:
+                ref[r], bound[r] = xin[i], abs(xin[i])
+                continue
+            X = (node % m, (node // m) % m, node // (m * m))
+            cand = [sorted({min(v // 3, nc - 1), max(v - 1, 0) // 3}) for v in X]
+            acc = accb = 0.0
+            for ci in cand[0]:
+                for cj in cand[1]:
+                    for ck in cand[2]:
+                        a = (X[0] - 3 * ci) + 4 * (X[1] - 3 * cj) + 16 * (X[2] - 3 * ck)
+                        c = ci + nc * (cj + nc * ck)
+                        row = K[3 * a + comp] * mu[c] / nc
+                        loc = (3 * mesh.cell_nodes[c][:, None] + np.arange(3)[None, :]).ravel()
+                        acc += row @ xf[loc]
+                        accb += np.abs(row) @ np.abs(xf[loc])
+            ref[r], bound[r] = acc, accb
+        return ref, bound
+
+    x = inputs.uniform_vector(n, 42)
+    for dt, npt, rowtol in ((torch.float64, np.float64, ROW64), (torch.float32, np.float32, ROW32)):
+        xin = x.astype(npt).astype(np.float64)
+        ref, bound = reference(xin)
+        y = torch.empty(n, dtype=dt, device=DEV)
+        s.vmult(L, to_dev(xin, dt), y)
+        err = row_err(to_host(y)[rows], ref, bound)
+        print(f"[q3 sampled rows 32^3] {dt}: row {err:.2e}", flush=True)
+        assert err <= rowtol, (dt, err)
+    s.close()
