@@ -548,6 +548,8 @@ int upload_q3_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool top, const
   v.cmask = ctx->upload(cm);
   v.cons_dofs = ctx->upload(cons);
   v.n_cons = int64_t(cons.size());
+  v.q3_halo_f = ctx->dalloc<float>(size_t(q3_halo_words(h.n_edge)));
+  v.q3_halo_d = ctx->dalloc<double>(size_t(q3_halo_words(h.n_edge)));
   if (h.ell >= 2) {
     d.P_ptr = ctx->upload(h.P_ptr);
     d.P_col = ctx->upload(h.P_col);

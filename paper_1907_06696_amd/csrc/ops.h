@@ -56,6 +56,8 @@ struct DevLevel {
   // the prolongation from the level below (CSR of the LevelDev) and of its
   // transpose, the diagonal of the unit element matrix [192]
   bool q3 = false;
+  float* q3_halo_f = nullptr;       // operator halo slots (q3_halo_words entries)
+  double* q3_halo_d = nullptr;
   const double* q3_Pw = nullptr;
   const double* q3_Rw = nullptr;
   const double* q3_kdiag = nullptr;
@@ -157,7 +159,8 @@ template <typename T>
 void launch_chebx_step(int64_t n, const T* b, const T* t, const T* minv, T* d, T* x, double alpha, double beta,
                        hipStream_t s, const ChebPrep& p = ChebPrep());
 // true when launch_vmult<T> on L starts with an output initialisation kernel
-// (every level but the uniform ones the brick kernel takes)
+// (every level but the uniform ones the brick kernel takes and the Q3 lattice
+// levels)
 template <typename T>
 bool vmult_has_init(const DevLevel& L);
 // y = A x like launch_vmult (init), for a y already holding x on the
@@ -278,13 +281,16 @@ void launch_rhs(const DevLevel& L, const double* f_qp, double* b, hipStream_t s)
 void set_element_constants(const double* khat_diag81, const double* bhat8x81, const double* mhat8x8);
 
 // Q3-Q2 lattice levels (q3_ops.hip): 1D tables N [4x4], D [4x4], Gauss
-// weights [4], P2 [4x3], Q2 mass M2 [3x3]; operator cells (y += cell terms on
-// free dofs; the caller initialises y), diagonal, harmonic viscosity over 4^3
+// weights [4], P2 [4x3], Q2 mass M2 [3x3]; operator, diagonal, harmonic viscosity over 4^3
 // Gauss points, right-hand side (b zeroed by the caller) and the Q2 pressure
-// side on the leaf (B u, B^T p added; M_p p added; diag(M_p) added)
+// side on the leaf (B u, B^T p added; M_p p added; diag(M_p) added).  The
+// operator writes every entry of y (identity rows on constrained dofs), or
+// adds the cell terms to the free entries when accumulating.
 void set_q3_constants(const double* N, const double* D, const double* w, const double* P2, const double* M2);
 template <typename T>
-void launch_vmult_q3_cells(const DevLevel& L, const T* x, T* y, hipStream_t s);
+void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipStream_t s);
+// entries of a Q3 level's operator halo buffer (n cells per edge)
+int64_t q3_halo_words(int64_t n);
 void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s);
 void launch_harmonic_mu64(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s);
 void launch_rhs_q3(const DevLevel& L, const double* f_qp, double* b, hipStream_t s);

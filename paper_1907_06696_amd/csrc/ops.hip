@@ -1805,11 +1805,11 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
     }
     return;
   }
-  if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.cmask, x, y);
-  if (L.q3) {
-    launch_vmult_q3_cells<T>(L, x, y, s);
+  if (L.q3) {   // owner-computes: no initialisation kernel (vmult_has_init is false)
+    launch_vmult_q3<T>(L, x, y, !init, s);
     return;
   }
+  if (init && !prepared) k_init_out_general<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.nnode, L.cmask, x, y);
   T* fs = face_slots<T>(L);
   if (L.blk4.n) {
     if (init) k_vmult_blocks<T, 4, false><<<unsigned(L.blk4.n), 64, 0, s>>>(L.blk4, L.clev, mu_of<T>(L), x, y, fs);
@@ -1842,7 +1842,7 @@ void launch_vmult_prepared(const DevLevel& L, const T* x, T* y, hipStream_t s) {
 }
 template <typename T>
 bool vmult_has_init(const DevLevel& L) {
-  return !(L.uniform && brick_halo<T>(L) && brick_fits<T>(L.n_edge));
+  return !L.q3 && !(L.uniform && brick_halo<T>(L) && brick_fits<T>(L.n_edge));
 }
 template void launch_vmult_prepared<float>(const DevLevel&, const float*, float*, hipStream_t);
 template void launch_vmult_prepared<double>(const DevLevel&, const double*, double*, hipStream_t);

@@ -17,11 +17,16 @@
 // The operator's results are summed over a 2 x 2 x 2 block of cells (one
 // workgroup, a wavefront per cell): each wavefront stores its 3 x 64 results
 // in its own LDS slot, and each thread of the write-back sums the (up to 8)
-// slot entries of one block lattice point and component and adds them into
-// y: the points inside the block, which no other block touches, with a plain
-// read-add-write, those on its faces with atomics (218 of 343 points instead
-// of 8 x 64 cell nodes).  Constrained (boundary) nodes are read as zero and
-// receive nothing; the caller initialises y (identity rows) beforehand.
+// slot entries of one block lattice point and component.  Owner computes, as
+// in the Q2 brick kernel: a lattice point belongs to the block whose
+// half-open box [6b, 6b + 6) holds it (the last block along an axis also owns
+// the closing plane); the block writes the points it owns (y = its sum, or
+// y = x on constrained points: identity rows; accumulating, y += its sum on
+// free points) and stores the sums of the 127 points of its high faces, owned
+// by upper neighbours, in its halo slot; a second kernel adds, for every
+// point on a block's low face, the neighbours' slot values.  No atomics and
+// no separate initialisation of y.  Constrained (boundary) nodes are read as
+// zero.
 #include <hip/hip_runtime.h>
 
 #include "ops.h"
@@ -140,10 +145,21 @@ struct Q3Cell {
 constexpr int kQ3B = 2;                         // cells per block edge
 constexpr int kQ3E = 3 * kQ3B + 1;              // lattice points per block edge
 constexpr int kQ3P = kQ3E * kQ3E * kQ3E;        // lattice points per block
+constexpr int kQ3H = kQ3P - (kQ3E - 1) * (kQ3E - 1) * (kQ3E - 1);   // high-face points per block (127)
 
-template <typename T>
+// index of a high-face point of the block lattice in the block's halo slot
+// (p_x = 6: the 7 x 7 plane; else p_y = 6: 6 x 7; else p_z = 6: 6 x 6)
+__device__ __forceinline__ int q3_halo_index(int px, int py, int pz) {
+  constexpr int L = kQ3E - 1;
+  if (px == L) return py + kQ3E * pz;
+  if (py == L) return kQ3E * kQ3E + px + L * pz;
+  return kQ3E * kQ3E + L * kQ3E + px + L * py;
+}
+
+template <typename T, bool ACC>
 __global__ __launch_bounds__(64 * kQ3B * kQ3B * kQ3B) void k_vmult_q3(int64_t n, const T* __restrict__ mu,
-                                                                     const T* __restrict__ x, T* __restrict__ y) {
+                                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                                     T* __restrict__ halo) {
   constexpr int NW = kQ3B * kQ3B * kQ3B;
   __shared__ T slot[NW][3][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -194,7 +210,13 @@ __global__ __launch_bounds__(64 * kQ3B * kQ3B * kQ3B) void k_vmult_q3(int64_t n,
     const int p = e / 3, k = e - 3 * p;
     const int px = p % kQ3E, py = (p / kQ3E) % kQ3E, pz = p / (kQ3E * kQ3E);
     const int64_t X = 3 * kQ3B * bx + px, Y = 3 * kQ3B * by + py, Z = 3 * kQ3B * bz + pz;
-    if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) continue;
+    const bool own = (px < kQ3E - 1 || bx == nb - 1) && (py < kQ3E - 1 || by == nb - 1) &&
+                     (pz < kQ3E - 1 || bz == nb - 1);
+    const int64_t d = 3 * (X + m * (Y + m * Z)) + k;
+    if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) {
+      if (!ACC && own) y[d] = x[d];   // identity row (every constrained point has one owner)
+      continue;
+    }
     T v = T(0);
     for (int ccz = 0; ccz < kQ3B; ++ccz) {
       const int lz = pz - 3 * ccz;
@@ -209,11 +231,35 @@ __global__ __launch_bounds__(64 * kQ3B * kQ3B * kQ3B) void k_vmult_q3(int64_t n,
         }
       }
     }
-    T* dst = &y[3 * (X + m * (Y + m * Z)) + k];
-    const bool inner = px > 0 && px < kQ3E - 1 && py > 0 && py < kQ3E - 1 && pz > 0 && pz < kQ3E - 1;
-    if (inner) *dst += v;
-    else atomicAdd(dst, v);
+    if (own) y[d] = ACC ? y[d] + v : v;
+    else halo[(int64_t(blockIdx.x) * kQ3H + q3_halo_index(px, py, pz)) * 3 + k] = v;
   }
+}
+
+// Adds the halo values of its lower neighbour blocks into every free lattice
+// point that lies on a block's low face (one thread per point, 3 components).
+template <typename T>
+__global__ __launch_bounds__(256) void k_q3_halo_add(int64_t n, const T* __restrict__ halo, T* __restrict__ y) {
+  const int64_t nb = n / kQ3B, m = 3 * n + 1, L = 3 * kQ3B;
+  // points with a coordinate on an inner block plane (a multiple of 6 in 6 .. m - 7)
+  const int64_t node = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (node >= m * m * m) return;
+  const int64_t X = node % m, Y = (node / m) % m, Z = node / (m * m);
+  if (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1) return;
+  const bool fx = X % L == 0, fy = Y % L == 0, fz = Z % L == 0;
+  if (!fx && !fy && !fz) return;
+  const int64_t ox = X / L < nb ? X / L : nb - 1, oy = Y / L < nb ? Y / L : nb - 1, oz = Z / L < nb ? Z / L : nb - 1;
+  const int px = int(X - L * ox), py = int(Y - L * oy), pz = int(Z - L * oz);
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+  for (int sv = 1; sv < 8; ++sv) {
+    const int sx = sv & 1, sy = (sv >> 1) & 1, sz = sv >> 2;
+    if ((sx && !fx) || (sy && !fy) || (sz && !fz)) continue;
+    const int64_t nbk = (ox - sx) + nb * ((oy - sy) + nb * (oz - sz));
+    const T* h = halo + (nbk * kQ3H + q3_halo_index(px + int(L) * sx, py + int(L) * sy, pz + int(L) * sz)) * 3;
+    a0 += h[0], a1 += h[1], a2 += h[2];
+  }
+  T* yp = y + 3 * node;
+  yp[0] += a0, yp[1] += a1, yp[2] += a2;
 }
 
 // diagonal: d[3 node + c] += mu h K_hat[(a, c), (a, c)] over the cells (one thread per cell)
@@ -413,13 +459,34 @@ void set_q3_constants(const double* N, const double* D, const double* w, const d
 }
 
 template <typename T>
-void launch_vmult_q3_cells(const DevLevel& L, const T* x, T* y, hipStream_t s) {
-  // uniform levels have n = 2^l >= 2 cells per edge: whole 2 x 2 x 2 blocks
-  const int64_t nb = L.n_edge / kQ3B;
-  k_vmult_q3<T><<<unsigned(nb * nb * nb), 64 * kQ3B * kQ3B * kQ3B, 0, s>>>(L.n_edge, mu_of<T>(L), x, y);
+T* q3_halo(const DevLevel& L);
+template <>
+float* q3_halo<float>(const DevLevel& L) {
+  return L.q3_halo_f;
 }
-template void launch_vmult_q3_cells<float>(const DevLevel&, const float*, float*, hipStream_t);
-template void launch_vmult_q3_cells<double>(const DevLevel&, const double*, double*, hipStream_t);
+template <>
+double* q3_halo<double>(const DevLevel& L) {
+  return L.q3_halo_d;
+}
+
+int64_t q3_halo_words(int64_t n) {
+  const int64_t nb = n / kQ3B;
+  return nb * nb * nb * kQ3H * 3;
+}
+
+template <typename T>
+void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipStream_t s) {
+  // uniform levels have n = 2^l >= 2 cells per edge: whole 2 x 2 x 2 blocks
+  const int64_t n = L.n_edge, nb = n / kQ3B, m = 3 * n + 1;
+  T* halo = q3_halo<T>(L);
+  if (accumulate)
+    k_vmult_q3<T, true><<<unsigned(nb * nb * nb), 64 * kQ3B * kQ3B * kQ3B, 0, s>>>(n, mu_of<T>(L), x, y, halo);
+  else
+    k_vmult_q3<T, false><<<unsigned(nb * nb * nb), 64 * kQ3B * kQ3B * kQ3B, 0, s>>>(n, mu_of<T>(L), x, y, halo);
+  if (nb > 1) k_q3_halo_add<T><<<grid_for(m * m * m, 256, int64_t(1) << 30), 256, 0, s>>>(n, halo, y);
+}
+template void launch_vmult_q3<float>(const DevLevel&, const float*, float*, bool, hipStream_t);
+template void launch_vmult_q3<double>(const DevLevel&, const double*, double*, bool, hipStream_t);
 
 void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s) {
   k_diag_q3<<<grid_for(L.ncell), kBlock, 0, s>>>(L.n_edge, L.mu_d, kdiag, d);
