@@ -199,7 +199,7 @@ def q3_section(level, centres, dr, timed, solves=True):
                      "hbm_frac_algorithmic": round((2 * word * n + word * ncell) / t / 1e9 / PEAK_HBM_GBS, 4)}
         first[prec] = xs[0]
         del ys
-    ops["kernel"] = "k_init_out_general + k_vmult_q3 (one mfgmg_vmult)"
+    ops["kernel"] = "k_vmult_q3 + k_q3_halo_add (one mfgmg_vmult)"
     out["operator"] = ops
     vc = {}
     for name, key in (("fp32", "f32"), ("fp64", "f64")):

@@ -559,6 +559,25 @@ int upload_q3_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool top, const
     d.R_w = ctx->upload(std::vector<float>(h.R_w.begin(), h.R_w.end()));
     v.q3_Pw = ctx->upload(h.P_w);
     v.q3_Rw = ctx->upload(h.R_w);
+    // the 1D factor and its transpose (CSR over coarse coordinates)
+    const int64_t mf = 3 * h.n_edge + 1, mc = 3 * (h.n_edge / 2) + 1;
+    std::vector<int32_t> rptr(size_t(mc + 1), 0), rcol;
+    std::vector<double> rw;
+    std::vector<std::vector<std::pair<int32_t, double>>> cols(static_cast<size_t>(mc));
+    for (int64_t X = 0; X < mf; ++X)
+      for (int j = 0; j < 4; ++j) {
+        const double w = h.p1_w[size_t(4 * X + j)];
+        if (w != 0.0) cols[size_t(h.p1_c0[size_t(X)] + j)].emplace_back(int32_t(X), w);
+      }
+    for (int64_t C = 0; C < mc; ++C) {
+      for (const auto& e : cols[size_t(C)]) rcol.push_back(e.first), rw.push_back(e.second);
+      rptr[size_t(C + 1)] = int32_t(rcol.size());
+    }
+    v.q3_pc0 = ctx->upload(h.p1_c0);
+    v.q3_pw = ctx->upload(h.p1_w);
+    v.q3_rptr = ctx->upload(rptr);
+    v.q3_rcol = ctx->upload(rcol);
+    v.q3_rw = ctx->upload(rw);
   }
   if (!h.mu_src.empty()) d.mu_src = ctx->upload(h.mu_src);
   d.mu_d = ctx->dalloc<double>(size_t(h.ncell));
@@ -573,6 +592,11 @@ int upload_q3_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool top, const
       d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
                             : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
     }
+  // the transfers' scratch: the smoother's r and d, dead while a transfer runs
+  v.q3_s1_f = static_cast<float*>(d.work[0][2]);
+  v.q3_s2_f = static_cast<float*>(d.work[0][3]);
+  v.q3_s1_d = static_cast<double*>(d.work[1][2]);
+  v.q3_s2_d = static_cast<double*>(d.work[1][3]);
   return MFGMG_OK;
 }
 

@@ -54,6 +54,10 @@ struct Level {
   std::vector<int64_t> P_ptr;
   std::vector<int32_t> P_col;
   std::vector<double> P_w;
+  // Q3 lattice levels (ell >= 2): the 1D factor of the prolongation, fine
+  // lattice coordinate X -> coarse coordinates p1_c0[X] + j, weights p1_w[4X + j]
+  std::vector<int32_t> p1_c0;
+  std::vector<double> p1_w;
   // transpose (rows = nodes of level ell-1)
   std::vector<int64_t> R_ptr;
   std::vector<int32_t> R_col;

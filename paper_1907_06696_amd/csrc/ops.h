@@ -60,6 +60,18 @@ struct DevLevel {
   double* q3_halo_d = nullptr;
   const double* q3_Pw = nullptr;
   const double* q3_Rw = nullptr;
+  // separable transfers from the level below: the 1D factor (fine coordinate
+  // -> 4 coarse coordinates from q3_pc0, weights q3_pw) and its transpose as
+  // CSR over coarse coordinates; two scratch vectors of this level's size
+  const int32_t* q3_pc0 = nullptr;
+  const double* q3_pw = nullptr;
+  const int32_t* q3_rptr = nullptr;
+  const int32_t* q3_rcol = nullptr;
+  const double* q3_rw = nullptr;
+  float* q3_s1_f = nullptr;
+  float* q3_s2_f = nullptr;
+  double* q3_s1_d = nullptr;
+  double* q3_s2_d = nullptr;
   const double* q3_kdiag = nullptr;
   const int64_t* hptr = nullptr;    // hanging CSR
   const int32_t* hmaster = nullptr;
@@ -291,6 +303,12 @@ template <typename T>
 void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipStream_t s);
 // entries of a Q3 level's operator halo buffer (n cells per edge)
 int64_t q3_halo_words(int64_t n);
+// separable transfers between a Q3 lattice level F and the level below
+// (three one-axis passes through F's scratch vectors); t may be null
+template <typename T>
+void launch_prolong_q3(const DevLevel& F, const T* xc, T* xf, bool add, hipStream_t s);
+template <typename T>
+void launch_restrict_q3(const DevLevel& F, const T* b, const T* t, T* xc, hipStream_t s);
 void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s);
 void launch_harmonic_mu64(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s);
 void launch_rhs_q3(const DevLevel& L, const double* f_qp, double* b, hipStream_t s);

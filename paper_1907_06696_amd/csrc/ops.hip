@@ -2280,13 +2280,28 @@ void set_element_constants(const double* kd, const double* bh, const double* mh)
 namespace mfgmg {
 
 template <typename T>
+bool q3_has_scratch(const DevLevel& F);
+template <>
+bool q3_has_scratch<float>(const DevLevel& F) {
+  return F.q3_s1_f && F.q3_s2_f;
+}
+template <>
+bool q3_has_scratch<double>(const DevLevel& F) {
+  return F.q3_s1_d && F.q3_s2_d;
+}
+
+template <typename T>
 void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
                           const float* w, const T* xc, T* xf, bool add, hipStream_t s) {
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
     k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
-  if (F.q3) {   // Q3 lattice levels: the CSR with its FP64 weights (not dyadic)
+  if (F.q3 && F.q3_pc0 && q3_has_scratch<T>(F)) {
+    launch_prolong_q3<T>(F, xc, xf, add, s);
+    return;
+  }
+  if (F.q3) {   // Q3 lattice levels without scratch: the CSR with its FP64 weights (not dyadic)
     k_prolong<T, kProlongLanes, double><<<grid_for(F.nnode * kProlongLanes), kBlock, 0, s>>>(
         F.nnode, ptr, col, F.q3_Pw, xc, xf, add, nullptr, nullptr);
     return;
@@ -2303,6 +2318,10 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
                            const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s) {
   // (the passes index nodes with 32-bit integers: levels up to 512^3 cells)
   const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
+  if (F.q3 && F.q3_pc0 && q3_has_scratch<T>(F)) {
+    launch_restrict_q3<T>(F, b, t, xc, s);
+    return;
+  }
   if (F.q3) {
     k_restrict<T, kRestrictLanes, double><<<grid_for(Cc.nnode * kRestrictLanes), kBlock, 0, s>>>(
         Cc.nnode, ptr, col, F.q3_Rw, b, t, xc, nullptr, nullptr);

@@ -139,6 +139,8 @@ void build_q3_level(const Level& cells, bool leaf, Level& lv) {
       c0[size_t(X)] = 3 * kc;
       for (int a = 0; a < 4; ++a) w1[size_t(4 * X + a)] = lagrange(E.gll, 4, a, t);
     }
+    lv.p1_c0.assign(c0.begin(), c0.end());
+    lv.p1_w = w1;
     lv.P_ptr.assign(size_t(lv.nnode) + 1, 0);
     for (int64_t Z = 0; Z < m; ++Z)
       for (int64_t Y = 0; Y < m; ++Y)

@@ -262,6 +262,109 @@ __global__ __launch_bounds__(256) void k_q3_halo_add(int64_t n, const T* __restr
   yp[0] += a0, yp[1] += a1, yp[2] += a2;
 }
 
+// ---------------------------------------------------------- transfers
+// Between two Q3 lattice levels the prolongation is the tensor product of one
+// 1D matrix P1 [m_f x m_c] (coarse Q3 functions at the fine lattice points,
+// at most 4 entries per row), with the boundary nodes of both levels masked:
+// P = D_f (P1 x P1 x P1) D_c, R = P^T.  Each runs as three one-axis passes
+// (one thread per output node, 3 components) through two scratch vectors.
+// dims: the output's extent along x, y, z; the input has `nin` points along
+// axis AX and the output's extents elsewhere.
+template <int AX>
+__device__ __forceinline__ void pass_coords(int64_t e, int64_t d0, int64_t d1, int64_t (&i)[3]) {
+  i[0] = e % d0;
+  i[1] = (e / d0) % d1;
+  i[2] = e / (d0 * d1);
+}
+template <int AX>
+__device__ __forceinline__ int64_t pass_index(const int64_t (&i)[3], int64_t a, int64_t d0, int64_t d1, int64_t nin) {
+  // node index in the input array (extent nin along AX) with coordinate a along AX
+  const int64_t e0 = AX == 0 ? nin : d0, e1 = AX == 1 ? nin : d1;
+  const int64_t c0 = AX == 0 ? a : i[0], c1 = AX == 1 ? a : i[1], c2 = AX == 2 ? a : i[2];
+  return c0 + e0 * (c1 + e1 * c2);
+}
+
+// prolongation pass: out(.., X, ..) = sum_j w[4X + j] in(.., c0[X] + j, ..).
+// FIRST: the input is the coarse vector, read as 0 on coarse boundary nodes;
+// LAST: the output is the fine vector, 0 (or untouched when adding) on fine
+// boundary nodes
+template <typename T, int AX, bool FIRST, bool LAST>
+__global__ __launch_bounds__(256) void k_q3_prolong_pass(int64_t d0, int64_t d1, int64_t d2, int64_t nin,
+                                                         const int32_t* __restrict__ c0, const double* __restrict__ w,
+                                                         const T* __restrict__ in, T* __restrict__ out, bool add) {
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= d0 * d1 * d2) return;
+  int64_t i[3];
+  pass_coords<AX>(e, d0, d1, i);
+  if (LAST) {
+    const int64_t mf = d0;
+    const bool bnd = i[0] == 0 || i[1] == 0 || i[2] == 0 || i[0] == mf - 1 || i[1] == mf - 1 || i[2] == mf - 1;
+    if (bnd) {
+      if (!add) out[3 * e] = out[3 * e + 1] = out[3 * e + 2] = T(0);
+      return;
+    }
+  }
+  const int64_t X = i[AX];
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t a = c0[X] + j;
+    const T wj = T(w[4 * X + j]);
+    if (FIRST) {   // coarse boundary: the other two coordinates are coarse as well here
+      const int64_t o1 = AX == 0 ? i[1] : i[0], o2 = AX == 2 ? i[1] : i[2];
+      if (a == 0 || a == nin - 1 || o1 == 0 || o1 == nin - 1 || o2 == 0 || o2 == nin - 1) continue;
+    }
+    const T* v = in + 3 * pass_index<AX>(i, a, d0, d1, nin);
+    a0 += wj * v[0], a1 += wj * v[1], a2 += wj * v[2];
+  }
+  T* o = out + 3 * e;
+  if (LAST && add) {
+    o[0] += a0, o[1] += a1, o[2] += a2;
+  } else {
+    o[0] = a0, o[1] = a1, o[2] = a2;
+  }
+}
+
+// restriction pass: out(.., C, ..) = sum over the fine points X of column C of
+// P1 (CSR rptr/rcol/rw) of w in(.., X, ..).  FIRST: in = b - t (t may be
+// null), read as 0 on fine boundary nodes; LAST: 0 on coarse boundary nodes
+template <typename T, int AX, bool FIRST, bool LAST>
+__global__ __launch_bounds__(256) void k_q3_restrict_pass(int64_t d0, int64_t d1, int64_t d2, int64_t nin,
+                                                          const int32_t* __restrict__ rptr,
+                                                          const int32_t* __restrict__ rcol,
+                                                          const double* __restrict__ rw, const T* __restrict__ in,
+                                                          const T* __restrict__ t, T* __restrict__ out) {
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= d0 * d1 * d2) return;
+  int64_t i[3];
+  pass_coords<AX>(e, d0, d1, i);
+  T* o = out + 3 * e;
+  if (LAST) {
+    const int64_t mc = d0;
+    if (i[0] == 0 || i[1] == 0 || i[2] == 0 || i[0] == mc - 1 || i[1] == mc - 1 || i[2] == mc - 1) {
+      o[0] = o[1] = o[2] = T(0);
+      return;
+    }
+  }
+  const int64_t C = i[AX];
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+  for (int32_t q = rptr[C]; q < rptr[C + 1]; ++q) {
+    const int64_t a = rcol[q];
+    if (FIRST) {   // fine boundary: the other two coordinates are fine as well here
+      const int64_t o1 = AX == 0 ? i[1] : i[0], o2 = AX == 2 ? i[1] : i[2];
+      if (a == 0 || a == nin - 1 || o1 == 0 || o1 == nin - 1 || o2 == 0 || o2 == nin - 1) continue;
+    }
+    const int64_t idx = 3 * pass_index<AX>(i, a, d0, d1, nin);
+    const T wq = T(rw[q]);
+    if (FIRST && t) {
+      a0 += wq * (in[idx] - t[idx]), a1 += wq * (in[idx + 1] - t[idx + 1]), a2 += wq * (in[idx + 2] - t[idx + 2]);
+    } else {
+      a0 += wq * in[idx], a1 += wq * in[idx + 1], a2 += wq * in[idx + 2];
+    }
+  }
+  o[0] = a0, o[1] = a1, o[2] = a2;
+}
+
 // diagonal: d[3 node + c] += mu h K_hat[(a, c), (a, c)] over the cells (one thread per cell)
 __global__ __launch_bounds__(kBlock) void k_diag_q3(int64_t n, const double* __restrict__ mu,
                                                     const double* __restrict__ kdiag, double* __restrict__ d) {
@@ -487,6 +590,47 @@ void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipSt
 }
 template void launch_vmult_q3<float>(const DevLevel&, const float*, float*, bool, hipStream_t);
 template void launch_vmult_q3<double>(const DevLevel&, const double*, double*, bool, hipStream_t);
+
+template <typename T>
+T* q3_scratch(const DevLevel& L, int k);
+template <>
+float* q3_scratch<float>(const DevLevel& L, int k) {
+  return k ? L.q3_s2_f : L.q3_s1_f;
+}
+template <>
+double* q3_scratch<double>(const DevLevel& L, int k) {
+  return k ? L.q3_s2_d : L.q3_s1_d;
+}
+
+// fine level F (m_f = 3n + 1), coarse m_c = 3 n / 2 + 1: x, then y, then z
+template <typename T>
+void launch_prolong_q3(const DevLevel& F, const T* xc, T* xf, bool add, hipStream_t s) {
+  const int64_t mf = 3 * F.n_edge + 1, mc = 3 * (F.n_edge / 2) + 1;
+  T* t1 = q3_scratch<T>(F, 0);
+  T* t2 = q3_scratch<T>(F, 1);
+  k_q3_prolong_pass<T, 0, true, false><<<grid_for(mf * mc * mc, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mf, mc, mc, mc, F.q3_pc0, F.q3_pw, xc, t1, false);
+  k_q3_prolong_pass<T, 1, false, false><<<grid_for(mf * mf * mc, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mf, mf, mc, mc, F.q3_pc0, F.q3_pw, t1, t2, false);
+  k_q3_prolong_pass<T, 2, false, true><<<grid_for(mf * mf * mf, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mf, mf, mf, mc, F.q3_pc0, F.q3_pw, t2, xf, add);
+}
+template <typename T>
+void launch_restrict_q3(const DevLevel& F, const T* b, const T* t, T* xc, hipStream_t s) {
+  const int64_t mf = 3 * F.n_edge + 1, mc = 3 * (F.n_edge / 2) + 1;
+  T* s1 = q3_scratch<T>(F, 0);
+  T* s2 = q3_scratch<T>(F, 1);
+  k_q3_restrict_pass<T, 0, true, false><<<grid_for(mc * mf * mf, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mc, mf, mf, mf, F.q3_rptr, F.q3_rcol, F.q3_rw, b, t, s1);
+  k_q3_restrict_pass<T, 1, false, false><<<grid_for(mc * mc * mf, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mc, mc, mf, mf, F.q3_rptr, F.q3_rcol, F.q3_rw, s1, nullptr, s2);
+  k_q3_restrict_pass<T, 2, false, true><<<grid_for(mc * mc * mc, 256, int64_t(1) << 30), 256, 0, s>>>(
+      mc, mc, mc, mf, F.q3_rptr, F.q3_rcol, F.q3_rw, s2, nullptr, xc);
+}
+template void launch_prolong_q3<float>(const DevLevel&, const float*, float*, bool, hipStream_t);
+template void launch_prolong_q3<double>(const DevLevel&, const double*, double*, bool, hipStream_t);
+template void launch_restrict_q3<float>(const DevLevel&, const float*, const float*, float*, hipStream_t);
+template void launch_restrict_q3<double>(const DevLevel&, const double*, const double*, double*, hipStream_t);
 
 void launch_diag_q3(const DevLevel& L, const double* kdiag, double* d, hipStream_t s) {
   k_diag_q3<<<grid_for(L.ncell), kBlock, 0, s>>>(L.n_edge, L.mu_d, kdiag, d);
