@@ -137,12 +137,31 @@ __device__ __forceinline__ void component_pass(T (&W)[3][27], T mu_h, T* buf, in
   }
 }
 
-template <typename T, int BX, int BY, int BZ, bool ACC, bool ROWS>
-__global__ __launch_bounds__(BX * BY * BZ, ROWS ? 3 : 1) void k_vmult_brick(int n, const T* __restrict__ mu, const T* __restrict__ x,
-                                                              T* __restrict__ y, T* __restrict__ halo) {
+// How a thread forms its cell's 81 results: all from all 81 inputs at once
+// (kAll), one output component at a time from all 81 Gauss-point values
+// (kRows), or one input component at a time, 27 inputs beside the 81 results
+// (kInputs).  They differ in registers: kRows and kInputs fit more waves per
+// SIMD (three in FP32, two in FP64) than kAll.
+enum CellMode { kAll = 0, kRows = 1, kInputs = 2 };
+
+template <int MODE>
+constexpr int brick_waves_per_simd() {
+  return MODE == kRows ? 3 : MODE == kInputs ? 2 : 1;
+}
+// LDS row pitch of the node box: 24 keeps a wavefront's 8x4 cells on distinct
+// banks; 20 (two banks shared by half a row) lets four FP64 workgroups of
+// 8x4x4 cells share a CU's LDS
+template <int MODE>
+constexpr int brick_row_pitch() {
+  return MODE == kInputs ? 20 : 24;
+}
+
+template <typename T, int BX, int BY, int BZ, bool ACC, int MODE>
+__global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_vmult_brick(
+    int n, const T* __restrict__ mu, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ halo) {
   constexpr int NT = BX * BY * BZ, NW = NT / 64;
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;
-  constexpr int RX = 24, PL = RX * NY, CS = PL * NZ;
+  constexpr int RX = brick_row_pitch<MODE>(), PL = RX * NY, CS = PL * NZ;
   constexpr int ROW = 3 * NX;
   static_assert(ROW <= 64, "row");
   constexpr int NR = NY * NZ, RPW = (NR + NW - 1) / NW;
@@ -194,29 +213,54 @@ __global__ __launch_bounds__(BX * BY * BZ, ROWS ? 3 : 1) void k_vmult_brick(int 
   });
   __syncthreads();
   const int cx = t % BX, cy = (t / BX) % BY, cz = t / (BX * BY);
-  T U[3][27];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) U[q][a + 3 * bb + 9 * c] = buf[q * CS + off];
-      }
-  __syncthreads();
-  {
+  const int64_t cell = (int64_t(bx) * BX + cx) + int64_t(n) * ((int64_t(by) * BY + cy) + int64_t(n) * (int64_t(bz) * BZ + cz));
+  auto zero_box = [&]() {
     constexpr int NV = (3 * CS * int(sizeof(T))) / 16;
     float4* b4 = reinterpret_cast<float4*>(buf);
     for (int e = t; e < NV; e += NT) b4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int e = NV * 16 / int(sizeof(T)) + t; e < 3 * CS; e += NT) buf[e] = T(0);
-  }
-  const int64_t cell = (int64_t(bx) * BX + cx) + int64_t(n) * ((int64_t(by) * BY + cy) + int64_t(n) * (int64_t(bz) * BZ + cz));
-  const T mu_h = mu[cell] / T(n);
-  if constexpr (!ROWS) {
-    cellop::apply_cell<T>(U, mu_h);
+  };
+  T U[3][27];
+  T mu_h;
+  if constexpr (MODE == kInputs) {
+    mu_h = mu[cell] / T(n);
+    cellop::apply_cell_by_input<T>(
+        [&](int q, T(&V)[27]) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX +
+                                split_index<BX>(2 * cx + a);
+                V[a + 3 * bb + 9 * c] = buf[q * CS + off];
+              }
+        },
+        U, mu_h);
     __syncthreads();
+    zero_box();
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) U[q][a + 3 * bb + 9 * c] = buf[q * CS + off];
+        }
+    __syncthreads();
+    zero_box();
+    mu_h = mu[cell] / T(n);
+  }
+  if constexpr (MODE != kRows) {
+    if constexpr (MODE == kAll) {
+      cellop::apply_cell<T>(U, mu_h);
+      __syncthreads();
+    }
     {
       // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
       // class the map (cell, local node) -> node is injective, so read-add-write is race free;

@@ -193,6 +193,111 @@ __device__ __forceinline__ void apply_cell_row(const T (&W)[3][27], T (&Y)[27], 
 #undef MFGMG_QPR
 }
 
+// transposed derivative along direction D at Gauss point (qx, qy, qz): adds
+// f * gD[q_D][p] to the collocation values y of the line through the point
+template <int D, int qx, int qy, int qz, typename T>
+__device__ __forceinline__ void line_deriv_t(T f, T* y) {
+  constexpr int q = qx + 3 * qy + 9 * qz;
+  if constexpr (D == 0) deriv_t<qx>(f, y[q - qx], y[q - qx + 1], y[q - qx + 2]);
+  else if constexpr (D == 1) deriv_t<qy>(f, y[q - 3 * qy], y[q - 3 * qy + 3], y[q - 3 * qy + 6]);
+  else deriv_t<qz>(f, y[q - 9 * qz], y[q - 9 * qz + 9], y[q - 9 * qz + 18]);
+}
+
+// The terms of one Gauss point that involve input component D only.  With
+// g_e = d_e u_D, u_D enters F_DD as 2 cq g_D and F_De = F_eD (e != D) as
+// cq g_e; row D of F is contracted with the derivative in every direction,
+// row e != D only in direction D.  Summed over D these are the terms of
+// quad_point, added in another order.
+template <int D, int qx, int qy, int qz, typename T>
+__device__ __forceinline__ void quad_point_input(const T (&V)[27], T (&Y)[3][27]) {
+  constexpr double w = (qx == 1 ? kW1 : kW0) * (qy == 1 ? kW1 : kW0) * (qz == 1 ? kW1 : kW0);
+  const T g0 = line_deriv<0, qx, qy, qz>(V);
+  const T g1 = line_deriv<1, qx, qy, qz>(V);
+  const T g2 = line_deriv<2, qx, qy, qz>(V);
+  const T f0 = T(D == 0 ? 2.0 * w : w) * g0;
+  const T f1 = T(D == 1 ? 2.0 * w : w) * g1;
+  const T f2 = T(D == 2 ? 2.0 * w : w) * g2;
+  line_deriv_t<0, qx, qy, qz>(f0, Y[D]);
+  line_deriv_t<1, qx, qy, qz>(f1, Y[D]);
+  line_deriv_t<2, qx, qy, qz>(f2, Y[D]);
+  if constexpr (D != 0) line_deriv_t<D, qx, qy, qz>(f0, Y[0]);
+  if constexpr (D != 1) line_deriv_t<D, qx, qy, qz>(f1, Y[1]);
+  if constexpr (D != 2) line_deriv_t<D, qx, qy, qz>(f2, Y[2]);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void pin_all(T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
+}
+template <typename T, int N, int M>
+__device__ __forceinline__ void pin_all(T (&v)[N][M]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) pin_all(v[i]);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void input_pass(const T (&V)[27], T (&Y)[3][27]) {
+#define MFGMG_QPI(x, y, z) quad_point_input<D, x, y, z>(V, Y);
+  MFGMG_QPI(0, 0, 0) MFGMG_QPI(1, 0, 0) MFGMG_QPI(2, 0, 0)
+  MFGMG_QPI(0, 1, 0) MFGMG_QPI(1, 1, 0) MFGMG_QPI(2, 1, 0)
+  MFGMG_QPI(0, 2, 0) MFGMG_QPI(1, 2, 0) MFGMG_QPI(2, 2, 0)
+  MFGMG_QPI(0, 0, 1) MFGMG_QPI(1, 0, 1) MFGMG_QPI(2, 0, 1)
+  MFGMG_QPI(0, 1, 1) MFGMG_QPI(1, 1, 1) MFGMG_QPI(2, 1, 1)
+  MFGMG_QPI(0, 2, 1) MFGMG_QPI(1, 2, 1) MFGMG_QPI(2, 2, 1)
+  MFGMG_QPI(0, 0, 2) MFGMG_QPI(1, 0, 2) MFGMG_QPI(2, 0, 2)
+  MFGMG_QPI(0, 1, 2) MFGMG_QPI(1, 1, 2) MFGMG_QPI(2, 1, 2)
+  MFGMG_QPI(0, 2, 2) MFGMG_QPI(1, 2, 2) MFGMG_QPI(2, 2, 2)
+#undef MFGMG_QPI
+}
+
+// The cell operator one input component at a time: get(D, V) fetches the 27
+// nodal values of component D, which are interpolated and whose terms are
+// added into all three result components before the next component is
+// fetched, so only 27 inputs live beside the 81 results.  Y: the cell's
+// output contributions y_(a,c) on return.  coef = mu * h.
+template <typename T, typename Get>
+__device__ __forceinline__ void apply_cell_by_input(const Get& get, T (&Y)[3][27], T mu_h) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 27; ++a) Y[c][a] = T(0);
+  const T coef = mu_h * T(kInvG2);
+  {
+    T V[27];
+    get(0, V);
+    interp_all(V);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) V[a] *= coef;
+    pin_all(V);
+    input_pass<0>(V, Y);
+  }
+  asm volatile("" ::: "memory");   // the next component's loads stay below
+  {
+    T V[27];
+    pin_all(Y);
+    get(1, V);
+    interp_all(V);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) V[a] *= coef;
+    pin_all(V);
+    input_pass<1>(V, Y);
+  }
+  asm volatile("" ::: "memory");
+  {
+    T V[27];
+    pin_all(Y);
+    get(2, V);
+    interp_all(V);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) V[a] *= coef;
+    pin_all(V);
+    input_pass<2>(V, Y);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) interp_all_t(Y[c]);
+}
+
 // U[c][a]: nodal values of component c at local node a (x fastest) on input,
 // the cell's output contributions y_(a,c) on return.  coef = mu * h.
 template <typename T>

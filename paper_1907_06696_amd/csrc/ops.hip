@@ -186,12 +186,12 @@ struct BrickShape;
 template <>
 struct BrickShape<float> {
   static constexpr int BX = 8, BY = 8, BZ = 4;
-  static constexpr bool ROWS = true;    // one output component at a time
+  static constexpr int MODE = brick::kRows;     // one output component at a time
 };
 template <>
 struct BrickShape<double> {
   static constexpr int BX = 8, BY = 4, BZ = 4;
-  static constexpr bool ROWS = false;   // all three output components at once
+  static constexpr int MODE = brick::kInputs;   // one input component at a time
 };
 
 // The single cells of a non-uniform level (those in no block): the cell
@@ -1793,10 +1793,10 @@ void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, b
       // owner computes: no output initialisation, no atomics
       const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
       if (init)
-        brick::k_vmult_brick<T, BX, BY, BZ, false, BrickShape<T>::ROWS><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+        brick::k_vmult_brick<T, BX, BY, BZ, false, BrickShape<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
             int(n), mu_of<T>(L), x, y, halo);
       else
-        brick::k_vmult_brick<T, BX, BY, BZ, true, BrickShape<T>::ROWS><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+        brick::k_vmult_brick<T, BX, BY, BZ, true, BrickShape<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
             int(n), mu_of<T>(L), x, y, halo);
       brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
     } else {
