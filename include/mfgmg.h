@@ -449,7 +449,7 @@ int mfgmg_apply_mlp(mfgmg_ctx* ctx, const float* w_dev, int32_t guard, int32_t* 
  * of 1/(2n), all in the precision `prec`; boundary nodes are Dirichlet
  * (identity rows: dst = src there).  Identical results to mfgmg_vmult on the
  * leaf of a uniform context with the same cell viscosities.  Work memory:
- * the library's static device array (75.6 MB per GPU, held until the process
+ * the library's static device array (71.4 MB per GPU, held until the process
  * ends); no allocation, no host synchronisation.  Calls on one GPU share that
  * array: calls whose work overlaps in time (other streams or threads) race.
  * Errors: ERR_INVALID for n_edge above 64 (the array's limit) or other than

@@ -83,6 +83,18 @@ constexpr int64_t halo_words() {
   return halo_box_words<BX, BY, BZ>() + 2 * halo_plane_words<BX, BY, BZ>();
 }
 
+// Brick shape of a uniform level with n cells per edge (n a multiple of 8):
+// 8 x BY x 4 cells with BY = 8 from 64 cells per edge up and 4 below, so that
+// a 32^3 level still has 256 bricks for the 256 CUs
+constexpr int brick_by(int64_t n) {
+  return n >= 64 ? 8 : 4;
+}
+// entries of the halo buffer of that level: one slot per brick plus a pad of 64 zeros
+constexpr int64_t halo_buffer_words(int64_t n) {
+  return brick_by(n) == 8 ? (n / 8) * (n / 8) * (n / 4) * halo_words<8, 8, 4>() + 64
+                          : (n / 8) * (n / 4) * (n / 4) * halo_words<8, 4, 4>() + 64;
+}
+
 // An empty asm that the compiler must assume reads and changes v: values
 // computed from v cannot move above it.  Arithmetic otherwise moves freely
 // across block barriers, and computing a later component's gradients early

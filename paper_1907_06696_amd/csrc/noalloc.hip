@@ -7,7 +7,7 @@
 // plus a zero pad that the halo kernel reads in place of slots that do not
 // apply.  Here those slots live in one file-scope device array, `scratch`,
 // sized for the largest mesh this entry point takes (64^3 cells, FP64:
-// 2048 bricks of 8x4x4 cells, 75.6 MB), instead of a buffer the library
+// 1024 bricks of 8x8x4 cells), instead of a buffer the library
 // allocates per context.  Each GPU the library runs on holds its own copy of
 // the array until the process ends; its device address is looked up once
 // per device (hipGetSymbolAddress) and only that address is passed to kernels.
@@ -37,10 +37,11 @@ using namespace mfgmg;
 using detail::g_last_error;
 
 constexpr int kMaxEdge = 64;   // largest mesh: 64^3 cells
-// halo words of the brick shapes used by the operator (FP32 8x8x4, FP64 8x4x4 cells)
-constexpr int64_t kWordsF32 = int64_t(kMaxEdge / 8) * (kMaxEdge / 8) * (kMaxEdge / 4) * brick::halo_words<8, 8, 4>() + 64;
-constexpr int64_t kWordsF64 = int64_t(kMaxEdge / 8) * (kMaxEdge / 4) * (kMaxEdge / 4) * brick::halo_words<8, 4, 4>() + 64;
-constexpr int64_t kScratchBytes = (kWordsF64 * 8 > kWordsF32 * 4) ? kWordsF64 * 8 : kWordsF32 * 4;
+// halo words of the brick shapes the operator uses on the supported edges
+constexpr int64_t kMaxWords = brick::halo_buffer_words(32) > brick::halo_buffer_words(kMaxEdge)
+                                  ? brick::halo_buffer_words(32)
+                                  : brick::halo_buffer_words(kMaxEdge);
+constexpr int64_t kScratchBytes = kMaxWords * 8;   // FP64 words
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -105,12 +106,20 @@ extern "C" int mfgmg_vmult_uniform_noalloc(int32_t n_edge, mfgmg_prec prec, cons
   v.nnode = (2 * n + 1) * (2 * n + 1) * (2 * n + 1);
   if (prec == MFGMG_FP64) {
     const int64_t words = brick_halo_words<double>(n);
+    if (words <= 64 || words * int64_t(sizeof(double)) > kScratchBytes) {
+      g_last_error = "halo slots exceed the scratch array";
+      return MFGMG_ERR_INVALID;
+    }
     v.mu_d = static_cast<const double*>(mu);
     v.halo_d = static_cast<double*>(base);
     launch_fill(64, 0.0, v.halo_d + (words - 64), s);
     launch_vmult<double>(v, static_cast<const double*>(src), static_cast<double*>(dst), s, true);
   } else {
     const int64_t words = brick_halo_words<float>(n);
+    if (words <= 64 || words * int64_t(sizeof(float)) > kScratchBytes) {
+      g_last_error = "halo slots exceed the scratch array";
+      return MFGMG_ERR_INVALID;
+    }
     v.mu_f = static_cast<const float*>(mu);
     v.halo_f = static_cast<float*>(base);
     launch_fill_f(64, 0.0f, v.halo_f + (words - 64), s);

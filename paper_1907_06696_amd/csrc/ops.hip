@@ -181,16 +181,16 @@ double* face_slots<double>(const DevLevel& L) {
   return L.fslot_d;
 }
 
+// How the brick kernel forms a cell's results (the shape of a level's bricks
+// is brick::brick_by of its edge)
 template <typename T>
-struct BrickShape;
+struct BrickMode;
 template <>
-struct BrickShape<float> {
-  static constexpr int BX = 8, BY = 8, BZ = 4;
+struct BrickMode<float> {
   static constexpr int MODE = brick::kRows;     // one output component at a time
 };
 template <>
-struct BrickShape<double> {
-  static constexpr int BX = 8, BY = 4, BZ = 4;
+struct BrickMode<double> {
   static constexpr int MODE = brick::kInputs;   // one input component at a time
 };
 
@@ -1769,36 +1769,40 @@ template <typename T>
 bool brick_fits(int64_t n) {
   // below 32 cells per edge there are too few bricks to fill the chip and a
   // brick's latency dominates: the cell-parallel kernel is faster there
-  return n % BrickShape<T>::BX == 0 && n % BrickShape<T>::BY == 0 && n % BrickShape<T>::BZ == 0 && n <= 256 &&
-         n >= kBrickMinEdge;
+  return n % 8 == 0 && n <= 256 && n >= kBrickMinEdge;
 }
 
 template <typename T>
 int64_t brick_halo_words(int64_t n) {
-  constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
   if (!brick_fits<T>(n)) return 0;
-  return (n / BX) * (n / BY) * (n / BZ) * brick::halo_words<BX, BY, BZ>() + 64;   // slots + zero pad
+  return brick::halo_buffer_words(n);   // slots + zero pad
 }
 template int64_t brick_halo_words<float>(int64_t);
 template int64_t brick_halo_words<double>(int64_t);
 
 namespace {
+// owner computes: no output initialisation, no atomics
+template <typename T, int BX, int BY, int BZ>
+void launch_brick(const DevLevel& L, const T* x, T* y, T* halo, bool init, hipStream_t s) {
+  const int64_t n = L.n_edge;
+  const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
+  if (init)
+    brick::k_vmult_brick<T, BX, BY, BZ, false, BrickMode<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+        int(n), mu_of<T>(L), x, y, halo);
+  else
+    brick::k_vmult_brick<T, BX, BY, BZ, true, BrickMode<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+        int(n), mu_of<T>(L), x, y, halo);
+  brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
+}
+
 template <typename T>
 void vmult_impl(const DevLevel& L, const T* x, T* y, hipStream_t s, bool init, bool prepared) {
   if (L.uniform) {
-    constexpr int BX = BrickShape<T>::BX, BY = BrickShape<T>::BY, BZ = BrickShape<T>::BZ;
     const int64_t n = L.n_edge;
     T* halo = brick_halo<T>(L);
     if (halo && brick_fits<T>(n)) {
-      // owner computes: no output initialisation, no atomics
-      const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
-      if (init)
-        brick::k_vmult_brick<T, BX, BY, BZ, false, BrickShape<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
-            int(n), mu_of<T>(L), x, y, halo);
-      else
-        brick::k_vmult_brick<T, BX, BY, BZ, true, BrickShape<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
-            int(n), mu_of<T>(L), x, y, halo);
-      brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
+      if (brick::brick_by(n) == 8) launch_brick<T, 8, 8, 4>(L, x, y, halo, init, s);
+      else launch_brick<T, 8, 4, 4>(L, x, y, halo, init, s);
     } else {
       if (init && !prepared) k_init_out_uniform<T><<<grid_for(L.nnode), kBlock, 0, s>>>(L.n_edge, x, y);
       k_vmult_uniform3<T><<<unsigned((L.ncell + 63) / 64), 192, 0, s>>>(n, mu_of<T>(L), x, y);
