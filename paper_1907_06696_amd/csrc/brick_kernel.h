@@ -322,15 +322,22 @@ __global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_
     component_pass<2, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
   }
   const bool x_own = lx < NX - 1 || bx == nbx - 1;
-  // lanes of the x planes shared with a neighbour brick: the packed pass below
-  // (FP32; the FP64 kernel, at one wave per SIMD, measured faster without it)
-  constexpr bool PACK = sizeof(T) == 4;
-  const bool x_plane = PACK && ((lx == 0 && bx > 0) || (lx == NX - 1 && bx < nbx - 1));
-  T* hslot = halo + int64_t(b) * halo_words<BX, BY, BZ>() + lane;
+  // Lanes of the x planes shared with a neighbour brick.  In the box layout of
+  // the halo slot every such value would sit on a cache line of its own, so
+  // they go to two packed planes ([NZ][NY][3]): the high plane's
+  // contributions for the right neighbour, and the low plane's own (owned)
+  // values, which the halo kernel completes and stores (accumulating, it
+  // adds y).  The choice is a per-lane store address in the row loop below.
+  const bool x_low = lx == 0 && bx > 0, x_high = lx == NX - 1 && bx < nbx - 1;
+  T* slot = halo + int64_t(b) * halo_words<BX, BY, BZ>();
+  T* plane = slot + halo_box_words<BX, BY, BZ>() + (x_high ? halo_plane_words<BX, BY, BZ>() : 0) + comp;
+  T* hslot = slot + lane;
   // Owned nodes are stored (added to the old value when accumulating; x on
   // Dirichlet nodes, identity rows, otherwise), the high-face nodes of the
-  // upper neighbours go to the halo slot.  Accumulating, every old value is
-  // read before the first store, so their latency is paid once.
+  // upper neighbours go to the halo slot, the shared x planes of owned rows
+  // to the packed planes (Dirichlet rows of the low plane: identity rows,
+  // stored).  Accumulating, every old value is read before the first store,
+  // so their latency is paid once.
   with_wave<NW>(__builtin_amdgcn_readfirstlane(t >> 6), [&](auto wc) {
     constexpr int W = decltype(wc)::value;
     T old[ACC ? RPW : 1];
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_
         }
       }
     }
-    if (lane_ok && !x_plane) {
+    if (lane_ok) {
 #pragma unroll
       for (int k = 0; k < RPW; ++k) {
         const int r = W + NW * k, ly = r % NY, lz = r / NY;
@@ -355,7 +362,9 @@ __global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_
           const bool row_own = (ly < NY - 1 || last_y) && (lz < NZ - 1 || last_z);
           const uint32_t off = box_off + uint32_t(ly) * row_stride + uint32_t(lz) * plane_stride + lane_off;
           const T val = buf[lds_lane + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX];
-          if (row_own && x_own) {
+          if (row_own && (x_high || (x_low && !rdir))) {
+            plane[(lz * NY + ly) * 3] = val;
+          } else if (row_own && x_own) {
             T out;
             if constexpr (ACC) {
               out = (rdir || xdir) ? old[k] : old[k] + val;
@@ -371,41 +380,6 @@ __global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_
       }
     }
   });
-  // The x planes shared with a neighbour, one (side, row, component) per
-  // thread.  Rows of the high y or z face belong to an upper neighbour: box
-  // slot, as above.  Otherwise the high plane's contributions go to the
-  // packed high plane, the low plane's (owned) values to the packed low plane,
-  // which the halo kernel completes and stores (accumulating, it adds y);
-  // Dirichlet rows of the low plane are identity rows.
-  if constexpr (PACK) {
-    constexpr int NP = NR * 3;
-    T* slot = halo + int64_t(b) * halo_words<BX, BY, BZ>();
-    T* plane_lo = slot + halo_box_words<BX, BY, BZ>();
-    T* plane_hi = plane_lo + halo_plane_words<BX, BY, BZ>();
-    for (int e = t; e < 2 * NP; e += NT) {
-      const int side = e >= NP ? 1 : 0, rc = e - side * NP;
-      const int row = rc / 3, c = rc - 3 * row;
-      const int ly = row % NY, lz = row / NY;
-      if (side ? bx == nbx - 1 : bx == 0) continue;   // domain boundary plane: written above
-      const int lxs = side ? NX - 1 : 0;
-      const T val = buf[c * CS + split_index<BZ>(lz) * PL + split_index<BY>(ly) * RX + split_index<BX>(lxs)];
-      const bool row_own = (ly < NY - 1 || last_y) && (lz < NZ - 1 || last_z);
-      if (!row_own) {
-        slot[(lz * NY + ly) * ROW + 3 * lxs + c] = val;
-      } else if (side) {
-        plane_hi[rc] = val;
-      } else {
-        const bool rdir = (ly == 0 && first_y) || (ly == NY - 1 && last_y) || (lz == 0 && first_z) ||
-                          (lz == NZ - 1 && last_z);
-        if (!rdir) {
-          plane_lo[rc] = val;
-        } else if (!ACC) {
-          const int64_t node3 = 3 * (int64_t(X0) + int64_t(m) * (Y0 + ly + int64_t(m) * (Z0 + lz))) + c;
-          y[node3] = x[node3];
-        }
-      }
-    }
-  }
 }
 
 // Adds the halo values of a node's lower neighbour bricks into the node, for
@@ -413,7 +387,7 @@ __global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_
 // brick; its low-face nodes are enumerated as the z-face (lz = 0), then the
 // y-face without it, then the x-face without both, thread t taking
 // component t mod 3 of node t / 3 (consecutive threads, consecutive words).
-// FP32: a low x-plane node of a brick that is not the first along x holds its
+// A low x-plane node of a brick that is not the first along x holds its
 // own value in the brick's packed low plane (y is then written without being
 // read, unless accumulating), and its x neighbour's contribution in that
 // neighbour's packed high plane.
@@ -460,18 +434,17 @@ __global__ __launch_bounds__(256) void k_brick_halo_add(int n, bool accumulate, 
     const bool live = t < total && !(X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1);
     const bool lowx = live && lx == 0 && bx > 0, lowy = live && ly == 0 && by > 0, lowz = live && lz == 0 && bz > 0;
     constexpr int64_t HB = halo_box_words<BX, BY, BZ>(), HP = halo_plane_words<BX, BY, BZ>();
-    constexpr bool PACK = sizeof(T) == 4;
 #pragma unroll
     for (int s = 1; s < 8; ++s) {
       const int sx = s & 1, sy = (s >> 1) & 1, sz = s >> 2;
       const bool use = !((sx && !lowx) || (sy && !lowy) || (sz && !lowz));
       const int64_t nb = (bx - sx) + int64_t(nbx) * ((by - sy) + int64_t(nby) * (bz - sz));
       const int qx = sx ? 2 * BX : lx, qy = sy ? 2 * BY : ly, qz = sz ? 2 * BZ : lz;
-      const T* src = PACK && s == 1 ? halo + nb * halo_words<BX, BY, BZ>() + HB + HP + (int64_t(lz) * NY + ly) * 3 + comp
+      const T* src = s == 1 ? halo + nb * halo_words<BX, BY, BZ>() + HB + HP + (int64_t(lz) * NY + ly) * 3 + comp
                             : halo + nb * halo_words<BX, BY, BZ>() + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp;
       acc[k] += *(use ? src : zero);
     }
-    const bool packed = PACK && lx == 0 && bx > 0;
+    const bool packed = lx == 0 && bx > 0;
     const T* own = halo + int64_t(b) * halo_words<BX, BY, BZ>() + HB + (int64_t(lz) * NY + ly) * 3 + comp;
     acc[k] += *(live && packed ? own : zero);
     const int64_t d = 3 * (X + int64_t(m) * (Y + int64_t(m) * Z)) + comp;
