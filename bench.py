@@ -591,7 +591,8 @@ def main():
         alg_bytes = 2 * word * n + word * ncell        # read x, write y, cell viscosity
         ach = flops / call / 1e12
         tr = measured_traffic(level, prec)
-        tname = "double, 8, 4, 4" if prec == "f64" else "float, 8, 8, 4"
+        # brick shape of the level (8 x 8 x 4 cells from 64 per edge up, 8 x 4 x 4 below)
+        tname = f"{'double' if prec == 'f64' else 'float'}, 8, {8 if (1 << level) >= 64 else 4}, 4"
         out = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                "frac": round(ach / peak, 4), "traffic": tr["bytes"] if tr else None,
                "kernel": f"k_vmult_brick<{tname}> + k_brick_halo_add<{tname}> (one mfgmg_vmult)",
