@@ -631,7 +631,16 @@ int upload_mesh(mfgmg_ctx* ctx) {
     ctx->pres.np = m.vleaf().npnode;
   } else {
     for (int ell = 1; ell <= L; ++ell) {
-      const int st = upload_level(ctx, m.level(ell), ctx->lv[size_t(ell)], ell == L, ell == L, ell >= 2, true);
+      // between two uniform lattice levels the transfers run from the
+      // lattice alone (k_prolong_uniform, k_restrict_x/y/z) unless the
+      // restriction passes' 32-bit node indices overflow: no tables there
+      bool csr = ell >= 2;
+      if (csr && m.transfer_deferred(ell)) {
+        const int64_t nc = m.level(ell - 1).n_edge, mc = 2 * nc + 1, mf = 4 * nc + 1;
+        csr = mc * mf * mf >= (int64_t(1) << 31);
+      }
+      const Level& h = csr ? m.level_transfer(ell) : m.level(ell);
+      const int st = upload_level(ctx, h, ctx->lv[size_t(ell)], ell == L, ell == L, csr, true);
       if (st) return st;
     }
   }
@@ -1173,7 +1182,7 @@ int mfgmg_transfer(const mfgmg_ctx* ctx, int32_t level, int64_t* nnz, int64_t* p
   int st = check_level(ctx, level);
   if (st) return st;
   if (level < 2 || !nnz) return MFGMG_ERR_INVALID;
-  const Level& h = ctx->mesh->vlevel(level);
+  const Level& h = ctx->mesh->velocity_degree() == 3 ? ctx->mesh->vlevel(level) : ctx->mesh->level_transfer(level);
   *nnz = int64_t(h.P_col.size());
   if (ptr && col && w) {
     for (size_t i = 0; i < h.P_ptr.size(); ++i) ptr[i] = h.P_ptr[i];

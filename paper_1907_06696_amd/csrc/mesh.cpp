@@ -284,7 +284,12 @@ std::string Mesh::finalize() {
   scratch.cell_map.resize(size_t(L_ + 1));
   g_scratch = &scratch;
   for (int ell = 1; ell <= L_; ++ell) build_level(ell);
-  for (int ell = 2; ell <= L_; ++ell) build_transfer(ell);
+  transfer_built_.assign(size_t(L_ + 1), 0);
+  for (int ell = 2; ell <= L_; ++ell)
+    if (!transfer_deferred(ell)) {
+      build_transfer(ell);
+      transfer_built_[size_t(ell)] = 1;
+    }
   for (int ell = 1; ell < L_; ++ell) build_mu_restriction(ell);
   g_scratch = nullptr;
   if (vdeg_ == 3) {
@@ -555,6 +560,21 @@ static int32_t find_node(const Level& lv, const KeyMap* map, int64_t key, int U)
   return map->find(key);
 }
 
+bool Mesh::transfer_deferred(int ell) const {
+  return ell >= 2 && ell <= L_ && levels_[size_t(ell)].uniform && levels_[size_t(ell - 1)].uniform;
+}
+
+const Level& Mesh::level_transfer(int ell) const {
+  if (finalized_ && ell >= 2 && ell <= L_ && !transfer_built_[size_t(ell)]) {
+    // uniform pair: build_transfer needs no set-up maps
+    const_cast<Mesh*>(this)->build_transfer(ell);
+    transfer_built_[size_t(ell)] = 1;
+  }
+  return levels_[size_t(ell)];
+}
+
+// Uniform fine levels (uniform coarse level too) use neither set-up map, so
+// this also runs after finalize.
 void Mesh::build_transfer(int ell) {
   Level& fine = levels_[ell];
   const Level& coarse = levels_[ell - 1];
@@ -562,7 +582,7 @@ void Mesh::build_transfer(int ell) {
   const int64_t S1 = (int64_t(1) << U) + 1;
   auto key_of = [&](int64_t X, int64_t Y, int64_t Z) { return X + S1 * (Y + S1 * Z); };
   const KeyMap* fmap = fine.uniform ? nullptr : &g_scratch->node_map[size_t(ell)];
-  const KeyMap& fcells = g_scratch->cell_map[size_t(ell)];
+  const KeyMap* fcells = fine.uniform ? nullptr : &g_scratch->cell_map[size_t(ell)];
   double P1[5][3];
   for (int a = 0; a < 5; ++a)
     for (int i = 0; i < 3; ++i) P1[a][i] = q2_at_quarter(a, i);
@@ -576,9 +596,25 @@ void Mesh::build_transfer(int ell) {
   vals.reserve(size_t(fine.nnode) * 8);
   int32_t rc[96];
   double rw[96];
-  auto emit = [&](int32_t f, const int32_t* cn27, const double* w27) {
+  auto emit = [&](int32_t f, const int32_t* cn27, const double* w27, bool cell_hangs) {
     // w27: weights of the 27 coarse local nodes at fine node f
     int nr = 0;
+    if (!cell_hangs) {
+      // the 27 nodes of a cell are distinct, so without hanging nodes no
+      // column repeats: the entries in local-node order, as the search below
+      // would give them
+      row_start[size_t(f)] = int64_t(cols.size());
+      int len = 0;
+      for (int s = 0; s < 27; ++s) {
+        const double w = w27[s];
+        if (w == 0.0 || coarse.ntype[size_t(cn27[s])] != NODE_FREE) continue;
+        cols.push_back(cn27[s]);
+        vals.push_back(w);
+        ++len;
+      }
+      row_len[size_t(f)] = len;
+      return;
+    }
     auto add = [&](int32_t col, double w) {
       for (int q = 0; q < nr; ++q)
         if (rc[q] == col) {
@@ -620,16 +656,41 @@ void Mesh::build_transfer(int ell) {
     const int64_t ox = int64_t(coarse.cijk[3 * c]) * size, oy = int64_t(coarse.cijk[3 * c + 1]) * size,
                   oz = int64_t(coarse.cijk[3 * c + 2]) * size;
     const int32_t* cn27 = &coarse.cell_nodes[size_t(27 * c)];
+    // (every cell of a uniform fine level is a child of a coarse cell)
     const bool refined = (l == ell - 1) &&
-                         fcells.find(int64_t(cell_code(ell, 2 * int64_t(coarse.cijk[3 * c]),
-                                                       2 * int64_t(coarse.cijk[3 * c + 1]),
-                                                       2 * int64_t(coarse.cijk[3 * c + 2])))) >= 0;
+                         (fine.uniform || fcells->find(int64_t(cell_code(ell, 2 * int64_t(coarse.cijk[3 * c]),
+                                                                         2 * int64_t(coarse.cijk[3 * c + 1]),
+                                                                         2 * int64_t(coarse.cijk[3 * c + 2])))) >= 0);
     const int lat = refined ? 5 : 3;
     const int64_t step = refined ? size / 4 : size / 2;
+    bool cell_hangs = false;
+    for (int q = 0; q < 27; ++q) cell_hangs = cell_hangs || coarse.ntype[size_t(cn27[q])] == NODE_HANGING;
+    // fine nodes of the cell's lattice: from the fine cells that cover it (the
+    // cell itself, or its 8 children), one cell lookup instead of a node
+    // lookup per lattice point on non-uniform fine levels
+    int32_t fl[125];
+    if (!fine.uniform) {
+      const int64_t ci = coarse.cijk[3 * c], cj = coarse.cijk[3 * c + 1], ck = coarse.cijk[3 * c + 2];
+      for (int q = 0; q < lat * lat * lat; ++q) fl[q] = -1;
+      const int nch = refined ? 2 : 1;
+      for (int hz = 0; hz < nch; ++hz)
+        for (int hy = 0; hy < nch; ++hy)
+          for (int hx = 0; hx < nch; ++hx) {
+            const int32_t fc = refined ? fcells->find(int64_t(cell_code(ell, 2 * ci + hx, 2 * cj + hy, 2 * ck + hz)))
+                                       : fcells->find(int64_t(cell_code(l, ci, cj, ck)));
+            if (fc < 0) continue;   // cannot happen for a valid hierarchy
+            const int32_t* fn27 = &fine.cell_nodes[size_t(27 * int64_t(fc))];
+            for (int k = 0; k < 3; ++k)
+              for (int j = 0; j < 3; ++j)
+                for (int i = 0; i < 3; ++i)
+                  fl[(2 * hx + i) + lat * ((2 * hy + j) + lat * (2 * hz + k))] = fn27[i + 3 * j + 9 * k];
+          }
+    }
     for (int z = 0; z < lat; ++z)
       for (int y = 0; y < lat; ++y)
         for (int x = 0; x < lat; ++x) {
-          const int32_t f = find_node(fine, fmap, key_of(ox + x * step, oy + y * step, oz + z * step), U);
+          const int32_t f = fine.uniform ? find_node(fine, fmap, key_of(ox + x * step, oy + y * step, oz + z * step), U)
+                                         : fl[x + lat * (y + lat * z)];
           if (f < 0) continue;   // cannot happen for a valid hierarchy
           if (seen[size_t(f)]) continue;
           seen[size_t(f)] = 1;
@@ -648,7 +709,7 @@ void Mesh::build_transfer(int ell) {
                   w = (x == i && y == j && z == k) ? 1.0 : 0.0;
                 w27[i + 3 * j + 9 * k] = w;
               }
-          emit(f, cn27, w27);
+          emit(f, cn27, w27, cell_hangs);
         }
   }
   fine.P_ptr.assign(size_t(fine.nnode) + 1, 0);

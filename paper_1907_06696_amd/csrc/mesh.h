@@ -119,6 +119,13 @@ class Mesh {
   int64_t S() const { return int64_t(1) << (L_ + 1); }
   const Level& level(int ell) const { return levels_[ell]; }
   Level& level(int ell) { return levels_[ell]; }
+  // Transfers between two uniform lattice levels are applied on the device
+  // from their lattice structure alone, so their node-level tables (P_*,
+  // R_* of level ell) are built on first use: transfer_deferred(ell) tells
+  // whether level ell's tables are such, level_transfer(ell) builds them if
+  // needed and returns level(ell).
+  bool transfer_deferred(int ell) const;
+  const Level& level_transfer(int ell) const;
   const Level& leaf() const { return levels_[L_]; }
   int64_t n_active() const { return int64_t(lev_.size()); }
 
@@ -167,6 +174,7 @@ class Mesh {
   std::vector<Level> levels_;
   // local-smoothing levels, built from the finished global-coarsening levels
   mutable bool ls_built_ = false;
+  mutable std::vector<uint8_t> transfer_built_;
   mutable int ls_base_ = 0;
   mutable std::vector<LocalLevel> ls_;
   mutable std::vector<int32_t> ls_base_leaf_, ls_base_node_;

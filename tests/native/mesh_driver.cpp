@@ -41,7 +41,7 @@ int main(int argc, char** argv) {
   }
   std::printf("L %d\n", m.L());
   for (int ell = 1; ell <= m.L(); ++ell) {
-    const Level& lv = m.vlevel(ell);
+    const Level& lv = mode == "q3" ? m.vlevel(ell) : m.level_transfer(ell);
     std::printf("level %d ncell %ld nnode %ld nhang %zu\n", ell, long(lv.ncell), long(lv.nnode), lv.hang.count());
     std::printf("keys");
     for (int64_t k : lv.key) std::printf(" %ld", long(k));
