@@ -65,8 +65,7 @@ def parse():
     p.add_argument("--variants", default=None,
                    help="solves of --solve-workload, comma separated from fp64, fp32, fp32_learned, fp64_local, "
                         "fp32_local, fp32_gmres, fp32_idr2, fp64_idr2, fp32_diag (default: all on adaptive32p2; "
-                        "on uniform128p1 all but "
-                        "fp32_idr2, which stalls near 1e-5 there, and fp32_diag, which needs ~4x the iterations)")
+                        "on uniform128p1 all but fp32_diag, which needs ~4x the iterations)")
     p.add_argument("--oracle-residual", action="store_true",
                    help="with --solve-workload: recompute every solve's FP64 residual with the oracle")
     p.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -261,9 +260,12 @@ def solve_compare(s, qp, centres, max_iter=3000, verbose=0, restart=50, keep=Non
                             max_iter=max_iter, verbose=verbose, restart=restart, **kw)
         if keep is not None:
             keep[name] = (u.cpu().numpy(), p.cpu().numpy())
-        return {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
-                "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
-                "converged": bool(st["converged"]), "vectors": krylov_vectors(kw, restart)}
+        rec = {"seconds": round(st["seconds"], 3), "iterations": st["iterations"],
+               "rel_residual": st["rel_residual"], "inner_cg": st["inner_cg_iterations"],
+               "converged": bool(st["converged"]), "vectors": krylov_vectors(kw, restart)}
+        if st["fp64_from"] >= 0:   # a stalled FP32 IDR run went on with the FP64 V-cycle
+            rec["fp64_from_iteration"] = st["fp64_from"]
+        return rec
 
     out = {"restart": restart}
     if "fp64" in variants:
@@ -491,7 +493,7 @@ def main():
     if args.solve_workload:
         variants = args.variants
         if variants is None:
-            skip = ("fp32_idr2", "fp32_diag") if args.solve_workload == "uniform128p1" else ()
+            skip = ("fp32_diag",) if args.solve_workload == "uniform128p1" else ()
             variants = ",".join(["fp64", "fp32", "fp32_learned"] + [v for v in SOLVER_VARIANTS
                                                                        if v not in skip and "schur" not in v])
         out, keep, keys, cells, centres = solve_workload(args.solve_workload, variants.split(","), args.max_iter,

@@ -299,6 +299,9 @@ typedef struct {
   double rel_residual;   /* ||b - K x|| / ||b||, recomputed in FP64 at the end */
   double seconds;        /* wall time of the solve */
   int32_t converged;
+  int32_t fp64_from;     /* IDR with the FP32 V-cycle: the iteration from which
+                            the stalled solve went on with the FP64 V-cycle,
+                            restarted from its best iterate; -1 otherwise */
 } mfgmg_solve_stats;
 
 /* Fill opts with the defaults above. */

@@ -1516,8 +1516,12 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   double* yv = ctx->dalloc<double>(size_t(std::max(m + 1, 16)));
   const bool fp64 = o.vcycle_prec == MFGMG_FP64;
   double* zfix = (o.use_graph && fp64) ? ctx->dalloc<double>(size_t(nu)) : nullptr;   // graph's fixed output
+  // IDR(s) with the FP32 V-cycle restarts from its best iterate (below)
+  const bool idr_restarts = idr && !fp64;
+  double* xbest = idr_restarts ? ctx->dalloc<double>(size_t(n)) : nullptr;
   std::vector<void*> mine = {V, Z, b, x, r, w, tu, bf, xf, cg, yv};
   if (o.use_graph && fp64) mine.push_back(zfix);
+  if (idr_restarts) mine.push_back(xbest);
   auto release = [&]() {
     for (void* p : mine) {
       auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
@@ -1538,6 +1542,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   double* cp2 = cg + 5 * np;
   int64_t inner_total = 0;
   int vcycles = 0;
+  int fp64_from = -1;
 
   auto apply_K = [&](const double* in, double* out) {
     launch_vmult<double>(lv, in, out, s);
@@ -1617,12 +1622,14 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
   }
   // z = P^{-1} v: z_p = -S^{-1} v_p, z_u = V(v_u - B^T z_p) (block
   // triangular) or V(v_u) (block diagonal)
+  // (IDR switches an FP32 V-cycle to FP64 where it stalls, below)
+  bool pre64 = fp64;
   auto precondition = [&](const double* v, double* z) {
     schur(v + nu);
     if (o.block == MFGMG_BLOCK_TRIANGULAR) launch_grad_from(lv, P, cx, v, tu, s);
     else (void)hipMemcpyAsync(tu, v, size_t(nu) * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (fp64) {
-      if (vexec) {
+    if (pre64) {
+      if (vexec && fp64) {
         (void)hipGraphLaunch(vexec, s);
         launch_scale_copy(nu, 1.0, zfix, z, s);
       } else {
@@ -1694,6 +1701,35 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     constexpr double kKappa = 0.7;
     bool done = rn <= o.rtol * bn;
     int printed = 0;
+    // With the FP32 V-cycle the preconditioner is linear only up to FP32
+    // rounding, which IDR's short recurrences (unlike flexible GMRES) do not
+    // tolerate at high viscosity contrast: at 128^3+1 cells and contrast 1e6
+    // the true residual levels off near 1e-5, and restarting IDR from its
+    // best iterate does not move that floor.  So where an FP32 run stalls --
+    // the recursive residual exceeds 10x its best (not in the first 50
+    // iterations, whose residual may grow before it falls), 200 iterations
+    // bring no new best, or it meets the tolerance but the true residual does
+    // not -- the solve restarts from its best iterate with the true residual
+    // (fresh G, U and M, the same shadow space) and the FP64 V-cycle; after
+    // that it restarts (twice at most) only where the recursion meets the
+    // tolerance and the true residual does not.  Runs that start with the
+    // FP64 V-cycle never restart.
+    constexpr int kMaxRestarts = 3, kStall = 200, kGrace = 50;
+    constexpr double kGrowth = 10.0;
+    int restarts = 0, best_it = 0, start_it = 0;
+    double best = rn;
+    bool restart_now = false;
+    if (idr_restarts) HIPCHK(hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    auto track = [&]() {
+      if (!idr_restarts || pre64) return;
+      if (rn < best) {
+        best = rn;
+        best_it = its;
+        (void)hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      } else if ((rn > kGrowth * best && its - start_it >= kGrace) || its - best_it >= kStall) {
+        restart_now = true;
+      }
+    };
     auto progress = [&]() {
       if (o.verbose > 0 && its / o.verbose > printed) {
         printed = its / o.verbose;
@@ -1702,6 +1738,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
         std::fflush(stderr);
       }
     };
+    for (;;) {
     while (!done && !bad && its < o.max_iter) {
       launch_mdot(n, ss, Q, n, r, ctx->red_part, res, s);   // f = Q^T r
       (void)hipMemcpyAsync(hres, res, size_t(ss) * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1745,7 +1782,8 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
         rn = std::sqrt(dot_sync(ctx, n, r, r, s));
         progress();
         if (!std::isfinite(rn)) bad = true;
-        if (bad || rn <= o.rtol * bn || its >= o.max_iter) {
+        if (!bad) track();
+        if (bad || rn <= o.rtol * bn || its >= o.max_iter || restart_now) {
           done = true;
           break;
         }
@@ -1768,7 +1806,41 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       rn = std::sqrt(dot_sync(ctx, n, r, r, s));
       progress();
       if (!std::isfinite(rn)) bad = true;
-      done = rn <= o.rtol * bn;
+      if (!bad) track();
+      done = rn <= o.rtol * bn || restart_now;
+    }
+    if (!idr_restarts || bad || its >= o.max_iter || restarts >= kMaxRestarts) break;
+    if (!restart_now) {   // met the tolerance by the recursion: the true residual decides
+      apply_K(x, w);
+      launch_axpby(n, 1.0, b, -1.0, w, s);
+      if (std::sqrt(dot_sync(ctx, n, w, w, s)) <= o.rtol * bn) break;
+    }
+    // restart with the FP64 V-cycle: a stall from the best iterate, a
+    // tolerance gap from the current one
+    if (!pre64) fp64_from = its;
+    pre64 = true;
+    if (restart_now) HIPCHK(hipMemcpyAsync(x, xbest, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    apply_K(x, r);
+    launch_axpby(n, 1.0, b, -1.0, r, s);
+    rn = std::sqrt(dot_sync(ctx, n, r, r, s));
+    if (!std::isfinite(rn)) {
+      bad = true;
+      break;
+    }
+    launch_fill(2 * int64_t(ss) * n, 0.0, G, s);
+    std::fill(M.begin(), M.end(), 0.0);
+    for (int i = 0; i < ss; ++i) Mij(i, i) = 1.0;
+    om = 1.0;
+    best = rn;
+    best_it = its;
+    start_it = its;
+    restart_now = false;
+    ++restarts;
+    done = rn <= o.rtol * bn;
+    if (o.verbose > 0) {
+      std::fprintf(stderr, "[mfgmg] idr(%d) restart at it %d from residual %.3e, FP64 V-cycle\n", ss, its, rn / bn);
+      std::fflush(stderr);
+    }
     }
     apply_K(x, r);   // the true residual decides
     launch_axpby(n, 1.0, b, -1.0, r, s);
@@ -1891,6 +1963,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     stats->rel_residual = bn > 0 ? beta / bn : 0.0;
     stats->seconds = secs;
     stats->converged = conv ? 1 : 0;
+    stats->fp64_from = fp64_from;
   }
   if (!conv) return ctx->set(MFGMG_ERR_NOCONV, bad ? "NaN or Inf in the solve" : "tolerance not reached");
   return MFGMG_OK;

@@ -62,7 +62,8 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("vcycles", C.c_int32), ("inner_cg_iterations", C.c_int64),
-                ("rel_residual", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32),
+                ("fp64_from", C.c_int32)]
 
 
 _lib = None
