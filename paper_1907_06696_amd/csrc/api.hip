@@ -1706,9 +1706,10 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     // tolerate at high viscosity contrast: at 128^3+1 cells and contrast 1e6
     // the true residual levels off near 1e-5, and restarting IDR from its
     // best iterate does not move that floor.  So where an FP32 run stalls --
-    // the recursive residual exceeds 10x its best (not in the first 50
-    // iterations, whose residual may grow before it falls), 200 iterations
-    // bring no new best, or it meets the tolerance but the true residual does
+    // while its best residual is still above 100x the tolerance, the
+    // recursive residual exceeds 10x that best (not in the first 50
+    // iterations, whose residual may grow before it falls) or 200 iterations
+    // bring no new best; or it meets the tolerance but the true residual does
     // not -- the solve restarts from its best iterate with the true residual
     // (fresh G, U and M, the same shadow space) and the FP64 V-cycle; after
     // that it restarts (twice at most) only where the recursion meets the
@@ -1726,7 +1727,8 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
         best = rn;
         best_it = its;
         (void)hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s);
-      } else if ((rn > kGrowth * best && its - start_it >= kGrace) || its - best_it >= kStall) {
+      } else if (best > 100.0 * o.rtol * bn &&
+                 ((rn > kGrowth * best && its - start_it >= kGrace) || its - best_it >= kStall)) {
         restart_now = true;
       }
     };
