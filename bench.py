@@ -613,6 +613,25 @@ def main():
         out = torch.empty_like(xx)
         tv = timed(lambda: s.vcycle(xx, out), 10, 2)
         vc[name] = tv / 10 * 1e3
+    # the same V-cycle captured once as a graph and replayed (as the solves
+    # run it: no host launch per kernel); every replay checked against the
+    # eager V-cycle
+    vcg = {}
+    for name, xx in (("fp32", pairs["f32"][0][0]), ("fp64", pairs["f64"][0][0])):
+        ref = torch.empty_like(xx)
+        out = torch.empty_like(xx)
+        s.vcycle(xx, ref)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.vcycle(xx, out)
+        tv = timed(g.replay, 10, 2)
+        err = float((out - ref).norm() / ref.norm())
+        tol = 1e-5 if name == "fp32" else 1e-12
+        if not err <= tol:
+            raise RuntimeError(f"graph-replayed {name} V-cycle differs from the eager one ({err:.2e})")
+        vcg[name] = round(tv / 10 * 1e3, 3)
+        del g
 
     result = {
         "metric": "Q2 viscous vmult GDoF/s",
@@ -636,6 +655,7 @@ def main():
             "frac_unpacked_peak": round(flops / times[("f32", "cold")] / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 4),
             "unpacked_peak": PEAK_FP32_UNPACKED_TFLOPS}),
         "vcycle_ms": {k: round(v, 3) for k, v in vc.items()},
+        "vcycle_graph_ms": vcg,
         "setup_s": {"mesh": round(t_mesh, 2), "assemble": round(t_assemble, 2)},
     }
     print(f"[bench] operator done: {json.dumps(result['vmult_gdofs'])}", file=sys.stderr, flush=True)
