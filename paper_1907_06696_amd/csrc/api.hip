@@ -1706,30 +1706,34 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     // tolerate at high viscosity contrast: at 128^3+1 cells and contrast 1e6
     // the true residual levels off near 1e-5, and restarting IDR from its
     // best iterate does not move that floor.  So where an FP32 run stalls --
-    // while its best residual is still above 100x the tolerance, the
-    // recursive residual exceeds 10x that best (not in the first 50
-    // iterations, whose residual may grow before it falls) or 200 iterations
-    // bring no new best; or it meets the tolerance but the true residual does
+    // while its best residual is still above 100x the tolerance, 200
+    // iterations fail to halve that best, or the recursive residual exceeds
+    // 100x it (not in the first 50 iterations, whose residual may grow
+    // before it falls); or it meets the tolerance but the true residual does
     // not -- the solve restarts from its best iterate with the true residual
     // (fresh G, U and M, the same shadow space) and the FP64 V-cycle; after
     // that it restarts (twice at most) only where the recursion meets the
     // tolerance and the true residual does not.  Runs that start with the
     // FP64 V-cycle never restart.
-    constexpr int kMaxRestarts = 3, kStall = 200, kGrace = 50;
-    constexpr double kGrowth = 10.0;
-    int restarts = 0, best_it = 0, start_it = 0;
-    double best = rn;
+    constexpr int kMaxRestarts = 3, kWindow = 200, kGrace = 50;
+    constexpr double kGrowth = 100.0;
+    int restarts = 0, start_it = 0, win_it = 0;
+    double best = rn, win_best = rn;
     bool restart_now = false;
     if (idr_restarts) HIPCHK(hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
     auto track = [&]() {
       if (!idr_restarts || pre64) return;
       if (rn < best) {
         best = rn;
-        best_it = its;
         (void)hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s);
-      } else if (best > 100.0 * o.rtol * bn &&
-                 ((rn > kGrowth * best && its - start_it >= kGrace) || its - best_it >= kStall)) {
+      }
+      if (best <= 100.0 * o.rtol * bn) return;
+      if (rn > kGrowth * best && its - start_it >= kGrace) {
         restart_now = true;
+      } else if (its - win_it >= kWindow) {
+        if (best > 0.5 * win_best) restart_now = true;
+        win_it = its;
+        win_best = best;
       }
     };
     auto progress = [&]() {
@@ -1834,7 +1838,8 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
     for (int i = 0; i < ss; ++i) Mij(i, i) = 1.0;
     om = 1.0;
     best = rn;
-    best_it = its;
+    win_best = rn;
+    win_it = its;
     start_it = its;
     restart_now = false;
     ++restarts;
