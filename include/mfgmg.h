@@ -284,6 +284,10 @@ typedef struct {
                              refinement level exactly l, smoothed with the
                              refinement edge fixed (mfgmg_vcycle_local)
                              (MFGMG_GLOBAL_COARSENING) */
+  int32_t idr_fp64_from;  /* IDR with the FP32 V-cycle: go on with the FP64
+                             V-cycle from this iteration at the latest (from
+                             the best iterate, with the true residual, as
+                             where the run stalls); 0: only where it stalls (0) */
 } mfgmg_solve_opts;
 
 enum { MFGMG_FGMRES = 0, MFGMG_GMRES = 1, MFGMG_IDR = 2 };

@@ -1453,6 +1453,7 @@ int mfgmg_default_opts(mfgmg_solve_opts* o) {
   o->schur = MFGMG_SCHUR_CG;
   o->schur_degree = 8;
   o->hierarchy = MFGMG_GLOBAL_COARSENING;
+  o->idr_fp64_from = 0;
   return MFGMG_OK;
 }
 
@@ -1468,7 +1469,7 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       o.krylov > MFGMG_IDR || o.idr_s < 1 || o.idr_s > 8 || (o.block != MFGMG_BLOCK_TRIANGULAR &&
       o.block != MFGMG_BLOCK_DIAGONAL) || (o.schur != MFGMG_SCHUR_CG && o.schur != MFGMG_SCHUR_CHEB) ||
       o.schur_degree < 1 || o.schur_degree > 64 ||
-      (o.hierarchy != MFGMG_GLOBAL_COARSENING && o.hierarchy != MFGMG_LOCAL_SMOOTHING))
+      (o.hierarchy != MFGMG_GLOBAL_COARSENING && o.hierarchy != MFGMG_LOCAL_SMOOTHING) || o.idr_fp64_from < 0)
     return ctx->set(MFGMG_ERR_INVALID, "bad solver options");
   if (o.krylov != MFGMG_FGMRES && o.schur != MFGMG_SCHUR_CHEB)
     return ctx->set(MFGMG_ERR_INVALID, "GMRES and IDR need the linear (Chebyshev) Schur approximation");
@@ -1726,6 +1727,10 @@ int mfgmg_solve_stokes(mfgmg_ctx* ctx, const double* rhs_u, const double* rhs_p,
       if (rn < best) {
         best = rn;
         (void)hipMemcpyAsync(xbest, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s);
+      }
+      if (o.idr_fp64_from > 0 && its >= o.idr_fp64_from) {
+        restart_now = true;
+        return;
       }
       if (best <= 100.0 * o.rtol * bn) return;
       if (rn > kGrowth * best && its - start_it >= kGrace) {

@@ -57,7 +57,7 @@ class SolveOpts(C.Structure):
                 ("vcycle_prec", C.c_int32), ("schur_rtol", C.c_double), ("schur_max_iter", C.c_int32),
                 ("use_scaling", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32),
                 ("krylov", C.c_int32), ("idr_s", C.c_int32), ("block", C.c_int32), ("schur", C.c_int32),
-                ("schur_degree", C.c_int32), ("hierarchy", C.c_int32)]
+                ("schur_degree", C.c_int32), ("hierarchy", C.c_int32), ("idr_fp64_from", C.c_int32)]
 
 
 class SolveStats(C.Structure):

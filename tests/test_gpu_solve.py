@@ -304,6 +304,41 @@ def test_solver_variants_match_oracle(name):
         c.close()
 
 
+def test_idr_fp32_goes_on_in_fp64():
+    """IDR(2) with the FP32 V-cycle taken on with the FP64 V-cycle (forced
+    from iteration 10 here; the library does so where an FP32 run stalls):
+    the restart from the best iterate with the true residual still converges
+    to the oracle's direct solution; FP64 runs ignore the option."""
+    c = Case(base=3, corners=((2, 5, 3), (0, 0, 0)), times=1, sinkers=4, dr=1e3, seed=7)
+    c.s.set_viscosity(c.mu_qp_lib)
+    L = c.L
+    nu, npp = c.info["n_u"][L], c.info["n_p"]
+    prob = krylov.StokesProblem(c.H, ops.harmonic_cell_viscosity(c.mu_qp_or), c.f_qp_or, gmg_kwargs={})
+    xd = prob.solve_direct()
+    pu, pp = c.dof_perm(L), c.pnode_perm()
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    c.s.assemble_rhs(c.f_qp_lib, rhs)
+    for prec, switch in (("fp32", True), ("fp64", False)):
+        u = torch.empty(nu, dtype=torch.float64, device=DEV)
+        p = torch.empty(npp, dtype=torch.float64, device=DEV)
+        st = c.s.solve_stokes(rhs, u, p, vcycle_prec=prec, max_iter=600, krylov="idr", schur="cheb", idr_s=2,
+                              idr_fp64_from=10)
+        x = np.zeros(nu + npp)
+        x[pu] = u.cpu().numpy()
+        x[nu + pp] = p.cpu().numpy()
+        x[:nu] *= c.H.leaf.free_dofs_mask()
+        x[nu:] *= c.H.leaf.pfree
+        res = prob.residual(x)
+        err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"  idr {prec}: its={st['iterations']} fp64_from={st['fp64_from']} res={res:.2e} err={err:.2e}")
+        assert st["converged"] == 1 and res <= 1.5e-8 and err <= 1e-5, (prec, res, err)
+        if switch:
+            assert 10 <= st["fp64_from"] <= 12, st["fp64_from"]
+        else:
+            assert st["fp64_from"] == -1
+    c.close()
+
+
 def test_capped_inner_cg_matches_oracle():
     """Inner CG stopped by its iteration cap (3 steps, far from a 1e-6
     tolerance set for this test) on a uniform leaf (two-kernel iterations with the direction
