@@ -522,6 +522,11 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
       d.work[p][k] = p == 0 ? static_cast<void*>(ctx->dalloc<float>(size_t(3 * h.nnode)))
                             : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
     }
+  // the separable transfers' scratch: the smoother's r and d
+  v.tr_s1_f = static_cast<float*>(d.work[0][2]);
+  v.tr_s2_f = static_cast<float*>(d.work[0][3]);
+  v.tr_s1_d = static_cast<double*>(d.work[1][2]);
+  v.tr_s2_d = static_cast<double*>(d.work[1][3]);
   return MFGMG_OK;
 }
 
@@ -593,10 +598,10 @@ int upload_q3_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool top, const
                             : static_cast<void*>(ctx->dalloc<double>(size_t(3 * h.nnode)));
     }
   // the transfers' scratch: the smoother's r and d, dead while a transfer runs
-  v.q3_s1_f = static_cast<float*>(d.work[0][2]);
-  v.q3_s2_f = static_cast<float*>(d.work[0][3]);
-  v.q3_s1_d = static_cast<double*>(d.work[1][2]);
-  v.q3_s2_d = static_cast<double*>(d.work[1][3]);
+  v.tr_s1_f = static_cast<float*>(d.work[0][2]);
+  v.tr_s2_f = static_cast<float*>(d.work[0][3]);
+  v.tr_s1_d = static_cast<double*>(d.work[1][2]);
+  v.tr_s2_d = static_cast<double*>(d.work[1][3]);
   return MFGMG_OK;
 }
 

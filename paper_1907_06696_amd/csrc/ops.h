@@ -62,16 +62,18 @@ struct DevLevel {
   const double* q3_Rw = nullptr;
   // separable transfers from the level below: the 1D factor (fine coordinate
   // -> 4 coarse coordinates from q3_pc0, weights q3_pw) and its transpose as
-  // CSR over coarse coordinates; two scratch vectors of this level's size
+  // CSR over coarse coordinates
   const int32_t* q3_pc0 = nullptr;
   const double* q3_pw = nullptr;
   const int32_t* q3_rptr = nullptr;
   const int32_t* q3_rcol = nullptr;
   const double* q3_rw = nullptr;
-  float* q3_s1_f = nullptr;
-  float* q3_s2_f = nullptr;
-  double* q3_s1_d = nullptr;
-  double* q3_s2_d = nullptr;
+  // two scratch vectors of this level's size for the separable transfers
+  // from the level below (the smoother's r and d, free while a transfer runs)
+  float* tr_s1_f = nullptr;
+  float* tr_s2_f = nullptr;
+  double* tr_s1_d = nullptr;
+  double* tr_s2_d = nullptr;
   const double* q3_kdiag = nullptr;
   const int64_t* hptr = nullptr;    // hanging CSR
   const int32_t* hmaster = nullptr;
@@ -301,6 +303,18 @@ void set_element_constants(const double* khat_diag81, const double* bhat8x81, co
 void set_q3_constants(const double* N, const double* D, const double* w, const double* P2, const double* M2);
 template <typename T>
 void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipStream_t s);
+// scratch vector k (0 or 1) of level L's separable transfers, precision T
+template <typename T>
+inline T* tr_scratch(const DevLevel& L, int k);
+template <>
+inline float* tr_scratch<float>(const DevLevel& L, int k) {
+  return k ? L.tr_s2_f : L.tr_s1_f;
+}
+template <>
+inline double* tr_scratch<double>(const DevLevel& L, int k) {
+  return k ? L.tr_s2_d : L.tr_s1_d;
+}
+
 // entries of a Q3 level's operator halo buffer (n cells per edge)
 int64_t q3_halo_words(int64_t n);
 // separable transfers between a Q3 lattice level F and the level below

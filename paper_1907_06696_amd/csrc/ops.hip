@@ -2284,14 +2284,14 @@ void set_element_constants(const double* kd, const double* bh, const double* mh)
 namespace mfgmg {
 
 template <typename T>
-bool q3_has_scratch(const DevLevel& F);
+bool tr_has_scratch(const DevLevel& F);
 template <>
-bool q3_has_scratch<float>(const DevLevel& F) {
-  return F.q3_s1_f && F.q3_s2_f;
+bool tr_has_scratch<float>(const DevLevel& F) {
+  return F.tr_s1_f && F.tr_s2_f;
 }
 template <>
-bool q3_has_scratch<double>(const DevLevel& F) {
-  return F.q3_s1_d && F.q3_s2_d;
+bool tr_has_scratch<double>(const DevLevel& F) {
+  return F.tr_s1_d && F.tr_s2_d;
 }
 
 template <typename T>
@@ -2301,7 +2301,7 @@ void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* 
     k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
-  if (F.q3 && F.q3_pc0 && q3_has_scratch<T>(F)) {
+  if (F.q3 && F.q3_pc0 && tr_has_scratch<T>(F)) {
     launch_prolong_q3<T>(F, xc, xf, add, s);
     return;
   }
@@ -2322,7 +2322,7 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
                            const float* w, const T* b, const T* t, T* xc, T* s1, T* s2, hipStream_t s) {
   // (the passes index nodes with 32-bit integers: levels up to 512^3 cells)
   const int64_t mc = 2 * Cc.n_edge + 1, mf = 4 * Cc.n_edge + 1;
-  if (F.q3 && F.q3_pc0 && q3_has_scratch<T>(F)) {
+  if (F.q3 && F.q3_pc0 && tr_has_scratch<T>(F)) {
     launch_restrict_q3<T>(F, b, t, xc, s);
     return;
   }

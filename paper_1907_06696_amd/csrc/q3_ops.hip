@@ -591,23 +591,12 @@ void launch_vmult_q3(const DevLevel& L, const T* x, T* y, bool accumulate, hipSt
 template void launch_vmult_q3<float>(const DevLevel&, const float*, float*, bool, hipStream_t);
 template void launch_vmult_q3<double>(const DevLevel&, const double*, double*, bool, hipStream_t);
 
-template <typename T>
-T* q3_scratch(const DevLevel& L, int k);
-template <>
-float* q3_scratch<float>(const DevLevel& L, int k) {
-  return k ? L.q3_s2_f : L.q3_s1_f;
-}
-template <>
-double* q3_scratch<double>(const DevLevel& L, int k) {
-  return k ? L.q3_s2_d : L.q3_s1_d;
-}
-
 // fine level F (m_f = 3n + 1), coarse m_c = 3 n / 2 + 1: x, then y, then z
 template <typename T>
 void launch_prolong_q3(const DevLevel& F, const T* xc, T* xf, bool add, hipStream_t s) {
   const int64_t mf = 3 * F.n_edge + 1, mc = 3 * (F.n_edge / 2) + 1;
-  T* t1 = q3_scratch<T>(F, 0);
-  T* t2 = q3_scratch<T>(F, 1);
+  T* t1 = tr_scratch<T>(F, 0);
+  T* t2 = tr_scratch<T>(F, 1);
   k_q3_prolong_pass<T, 0, true, false><<<grid_for(mf * mc * mc, 256, int64_t(1) << 30), 256, 0, s>>>(
       mf, mc, mc, mc, F.q3_pc0, F.q3_pw, xc, t1, false);
   k_q3_prolong_pass<T, 1, false, false><<<grid_for(mf * mf * mc, 256, int64_t(1) << 30), 256, 0, s>>>(
@@ -618,8 +607,8 @@ void launch_prolong_q3(const DevLevel& F, const T* xc, T* xf, bool add, hipStrea
 template <typename T>
 void launch_restrict_q3(const DevLevel& F, const T* b, const T* t, T* xc, hipStream_t s) {
   const int64_t mf = 3 * F.n_edge + 1, mc = 3 * (F.n_edge / 2) + 1;
-  T* s1 = q3_scratch<T>(F, 0);
-  T* s2 = q3_scratch<T>(F, 1);
+  T* s1 = tr_scratch<T>(F, 0);
+  T* s2 = tr_scratch<T>(F, 1);
   k_q3_restrict_pass<T, 0, true, false><<<grid_for(mc * mf * mf, 256, int64_t(1) << 30), 256, 0, s>>>(
       mc, mf, mf, mf, F.q3_rptr, F.q3_rcol, F.q3_rw, b, t, s1);
   k_q3_restrict_pass<T, 1, false, false><<<grid_for(mc * mc * mf, 256, int64_t(1) << 30), 256, 0, s>>>(
