@@ -152,24 +152,25 @@ __device__ __forceinline__ void component_pass(T (&W)[3][27], T mu_h, T* buf, in
 // How a thread forms its cell's 81 results: all from all 81 inputs at once
 // (kAll), one output component at a time from all 81 Gauss-point values
 // (kRows), or one input component at a time, 27 inputs beside the 81 results
-// (kInputs).  They differ in registers: kRows and kInputs fit more waves per
-// SIMD (three in FP32, two in FP64) than kAll.
+// (kInputs).  They differ in registers: kRows fits three waves per SIMD in
+// FP32 (152 VGPRs), kInputs four in FP32 (128; three when accumulating, whose
+// old values need more) and two in FP64 (254), kAll fewer.
 enum CellMode { kAll = 0, kRows = 1, kInputs = 2 };
 
-template <int MODE>
+template <typename T, int MODE, bool ACC>
 constexpr int brick_waves_per_simd() {
-  return MODE == kRows ? 3 : MODE == kInputs ? 2 : 1;
+  return MODE == kRows ? 3 : MODE == kInputs ? (sizeof(T) == 4 ? (ACC ? 3 : 4) : 2) : 1;
 }
 // LDS row pitch of the node box: 24 keeps a wavefront's 8x4 cells on distinct
-// banks; 20 (two banks shared by half a row) lets four FP64 workgroups of
-// 8x4x4 cells share a CU's LDS
+// banks; 20 (two banks shared by half a row) lets two FP64 workgroups of 8x8x4
+// cells, or four FP32 ones, share a CU's LDS
 template <int MODE>
 constexpr int brick_row_pitch() {
   return MODE == kInputs ? 20 : 24;
 }
 
 template <typename T, int BX, int BY, int BZ, bool ACC, int MODE>
-__global__ __launch_bounds__(BX * BY * BZ, brick_waves_per_simd<MODE>()) void k_vmult_brick(
+__global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, MODE, ACC>())) void k_vmult_brick(
     int n, const T* __restrict__ mu, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ halo) {
   constexpr int NT = BX * BY * BZ, NW = NT / 64;
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;

@@ -187,7 +187,7 @@ template <typename T>
 struct BrickMode;
 template <>
 struct BrickMode<float> {
-  static constexpr int MODE = brick::kRows;     // one output component at a time
+  static constexpr int MODE = brick::kInputs;   // one input component at a time
 };
 template <>
 struct BrickMode<double> {
