@@ -95,86 +95,25 @@ constexpr int64_t halo_buffer_words(int64_t n) {
                           : (n / 8) * (n / 4) * (n / 4) * halo_words<8, 4, 4>() + 64;
 }
 
-// An empty asm that the compiler must assume reads and changes v: values
-// computed from v cannot move above it.  Arithmetic otherwise moves freely
-// across block barriers, and computing a later component's gradients early
-// keeps them live beside the current component's results.
-template <typename T>
-__device__ __forceinline__ void pin(T& v) {
-  asm volatile("" : "+v"(v));
-}
-
-// Output component C of the cell operator from the Gauss-point values W
-// (all three components), transformed back to the nodes and added into
-// component C of the zeroed LDS box with the class-ordered scheme of the
-// kernel below.  Ends with a block barrier.
-template <int C, int BX, int BY, int BZ, int CS, int PL, int RX, typename T>
-__device__ __forceinline__ void component_pass(T (&W)[3][27], T mu_h, T* buf, int cx, int cy, int cz) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int a = 0; a < 27; ++a) pin(W[c][a]);
-  T Y[27];
-  cellop::apply_cell_row<C>(W, Y, mu_h);
-  cellop::interp_all_t(Y);
-  T* bc = buf + C * CS;
-#pragma unroll
-  for (int cc = 0; cc < 2; ++cc) {
-#pragma unroll
-    for (int ab = 0; ab < 4; ++ab) {
-      const int ac = ab & 1, bcl = ab >> 1;
-      T tmp[2][2][2];
-#pragma unroll
-      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-#pragma unroll
-        for (int bb = bcl ? 2 : 0; bb < (bcl ? 3 : 2); ++bb)
-#pragma unroll
-          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-            tmp[c & 1][bb & 1][a & 1] = bc[off];
-          }
-#pragma unroll
-      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-#pragma unroll
-        for (int bb = bcl ? 2 : 0; bb < (bcl ? 3 : 2); ++bb)
-#pragma unroll
-          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-            bc[off] = tmp[c & 1][bb & 1][a & 1] + Y[a + 3 * bb + 9 * c];
-          }
-      __builtin_amdgcn_s_waitcnt(0xc07f);
-      asm volatile("" ::: "memory");
-    }
-    __syncthreads();
-  }
-}
-
-// How a thread forms its cell's 81 results: all from all 81 inputs at once
-// (kAll), one output component at a time from all 81 Gauss-point values
-// (kRows), or one input component at a time, 27 inputs beside the 81 results
-// (kInputs).  They differ in registers: kRows fits three waves per SIMD in
-// FP32 (152 VGPRs), kInputs four in FP32 (128; three when accumulating, whose
-// old values need more) and two in FP64 (254), kAll fewer.
-enum CellMode { kAll = 0, kRows = 1, kInputs = 2 };
-
-template <typename T, int MODE, bool ACC>
+// A thread forms its cell's 81 results one input component at a time
+// (cellop::apply_cell_by_input): 27 inputs live beside the 81 results, 128
+// VGPRs in FP32 (four waves per SIMD; three when accumulating, whose old
+// values need more) and 254 in FP64 (two waves per SIMD).
+template <typename T, bool ACC>
 constexpr int brick_waves_per_simd() {
-  return MODE == kRows ? 3 : MODE == kInputs ? (sizeof(T) == 4 ? (ACC ? 3 : 4) : 2) : 1;
+  return sizeof(T) == 4 ? (ACC ? 3 : 4) : 2;
 }
-// LDS row pitch of the node box: 24 keeps a wavefront's 8x4 cells on distinct
-// banks; 20 (two banks shared by half a row) lets two FP64 workgroups of 8x8x4
-// cells, or four FP32 ones, share a CU's LDS
-template <int MODE>
-constexpr int brick_row_pitch() {
-  return MODE == kInputs ? 20 : 24;
-}
+// LDS row pitch of the node box (doubles or floats per row of 2 BX + 1
+// nodes): 20 lets two FP64 workgroups of 8x8x4 cells, or four FP32 ones,
+// share a CU's LDS, with half a row's accesses on shared banks
+constexpr int kBrickRowPitch = 20;
 
-template <typename T, int BX, int BY, int BZ, bool ACC, int MODE>
-__global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, MODE, ACC>())) void k_vmult_brick(
+template <typename T, int BX, int BY, int BZ, bool ACC>
+__global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, ACC>())) void k_vmult_brick(
     int n, const T* __restrict__ mu, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ halo) {
   constexpr int NT = BX * BY * BZ, NW = NT / 64;
   constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1;
-  constexpr int RX = brick_row_pitch<MODE>(), PL = RX * NY, CS = PL * NZ;
+  constexpr int RX = kBrickRowPitch, PL = RX * NY, CS = PL * NZ;
   constexpr int ROW = 3 * NX;
   static_assert(ROW <= 64, "row");
   constexpr int NR = NY * NZ, RPW = (NR + NW - 1) / NW;
@@ -233,94 +172,61 @@ __global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, MODE, ACC>()
     for (int e = t; e < NV; e += NT) b4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int e = NV * 16 / int(sizeof(T)) + t; e < 3 * CS; e += NT) buf[e] = T(0);
   };
+  // the cell's results, one input component at a time from the box; then
+  // the box is zeroed and takes the sums
   T U[3][27];
-  T mu_h;
-  if constexpr (MODE == kInputs) {
-    mu_h = mu[cell] / T(n);
-    cellop::apply_cell_by_input<T>(
-        [&](int q, T(&V)[27]) {
+  const T mu_h = mu[cell] / T(n);
+  cellop::apply_cell_by_input<T>(
+      [&](int q, T(&V)[27]) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
+          for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX +
-                                split_index<BX>(2 * cx + a);
-                V[a + 3 * bb + 9 * c] = buf[q * CS + off];
-              }
-        },
-        U, mu_h);
-    __syncthreads();
-    zero_box();
-    __syncthreads();
-  } else {
+            for (int a = 0; a < 3; ++a) {
+              const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX +
+                              split_index<BX>(2 * cx + a);
+              V[a + 3 * bb + 9 * c] = buf[q * CS + off];
+            }
+      },
+      U, mu_h);
+  __syncthreads();
+  zero_box();
+  __syncthreads();
+  // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
+  // class the map (cell, local node) -> node is injective, so read-add-write is race free;
+  // c classes are separated by a block barrier (they couple waves), a/b classes by an
+  // in-order LDS wait (they couple lanes of one wave).
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+  for (int cc = 0; cc < 2; ++cc) {
 #pragma unroll
-      for (int bb = 0; bb < 3; ++bb)
+    for (int ab = 0; ab < 4; ++ab) {
+      const int ac = ab & 1, bc = ab >> 1;
+      T tmp[3][2][2][2];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
 #pragma unroll
-          for (int q = 0; q < 3; ++q) U[q][a + 3 * bb + 9 * c] = buf[q * CS + off];
-        }
-    __syncthreads();
-    zero_box();
-    mu_h = mu[cell] / T(n);
-  }
-  if constexpr (MODE != kRows) {
-    if constexpr (MODE == kAll) {
-      cellop::apply_cell<T>(U, mu_h);
-      __syncthreads();
+        for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+#pragma unroll
+          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) tmp[q][c & 1][bb & 1][a & 1] = buf[q * CS + off];
+          }
+#pragma unroll
+      for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
+#pragma unroll
+        for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
+#pragma unroll
+          for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
+            const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) buf[q * CS + off] = tmp[q][c & 1][bb & 1][a & 1] + U[q][a + 3 * bb + 9 * c];
+          }
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      asm volatile("" ::: "memory");
     }
-    {
-      // phases: local nodes grouped by class (a in {0,1} | {2}) x (b ...) x (c ...); within a
-      // class the map (cell, local node) -> node is injective, so read-add-write is race free;
-      // c classes are separated by a block barrier (they couple waves), a/b classes by an
-      // in-order LDS wait (they couple lanes of one wave).
-  #pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-  #pragma unroll
-        for (int ab = 0; ab < 4; ++ab) {
-          const int ac = ab & 1, bc = ab >> 1;
-          T tmp[3][2][2][2];
-  #pragma unroll
-          for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-  #pragma unroll
-            for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
-  #pragma unroll
-              for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-  #pragma unroll
-                for (int q = 0; q < 3; ++q) tmp[q][c & 1][bb & 1][a & 1] = buf[q * CS + off];
-              }
-  #pragma unroll
-          for (int c = cc ? 2 : 0; c < (cc ? 3 : 2); ++c)
-  #pragma unroll
-            for (int bb = bc ? 2 : 0; bb < (bc ? 3 : 2); ++bb)
-  #pragma unroll
-              for (int a = ac ? 2 : 0; a < (ac ? 3 : 2); ++a) {
-                const int off = split_index<BZ>(2 * cz + c) * PL + split_index<BY>(2 * cy + bb) * RX + split_index<BX>(2 * cx + a);
-  #pragma unroll
-                for (int q = 0; q < 3; ++q) buf[q * CS + off] = tmp[q][c & 1][bb & 1][a & 1] + U[q][a + 3 * bb + 9 * c];
-              }
-          __builtin_amdgcn_s_waitcnt(0xc07f);
-          asm volatile("" ::: "memory");
-        }
-        __syncthreads();
-      }
-    }
-  } else {
-    // one output component at a time: the 81 Gauss-point values stay in
-    // registers, the 27 results of component C are formed, transformed back
-    // and added into the box before the next component's
-#pragma unroll
-    for (int c = 0; c < 3; ++c) cellop::interp_all(U[c]);
     __syncthreads();
-    component_pass<0, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
-    component_pass<1, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
-    component_pass<2, BX, BY, BZ, CS, PL, RX>(U, mu_h, buf, cx, cy, cz);
   }
   const bool x_own = lx < NX - 1 || bx == nbx - 1;
   // Lanes of the x planes shared with a neighbour brick.  In the box layout of

@@ -181,19 +181,6 @@ double* face_slots<double>(const DevLevel& L) {
   return L.fslot_d;
 }
 
-// How the brick kernel forms a cell's results (the shape of a level's bricks
-// is brick::brick_by of its edge)
-template <typename T>
-struct BrickMode;
-template <>
-struct BrickMode<float> {
-  static constexpr int MODE = brick::kInputs;   // one input component at a time
-};
-template <>
-struct BrickMode<double> {
-  static constexpr int MODE = brick::kInputs;   // one input component at a time
-};
-
 // The single cells of a non-uniform level (those in no block): the cell
 // operator with three threads per cell, one velocity component each (a wave
 // per component, as k_vmult_uniform3), hanging nodes resolved through the
@@ -1787,10 +1774,10 @@ void launch_brick(const DevLevel& L, const T* x, T* y, T* halo, bool init, hipSt
   const int64_t n = L.n_edge;
   const int64_t nb = (n / BX) * (n / BY) * (n / BZ);
   if (init)
-    brick::k_vmult_brick<T, BX, BY, BZ, false, BrickMode<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+    brick::k_vmult_brick<T, BX, BY, BZ, false><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
         int(n), mu_of<T>(L), x, y, halo);
   else
-    brick::k_vmult_brick<T, BX, BY, BZ, true, BrickMode<T>::MODE><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
+    brick::k_vmult_brick<T, BX, BY, BZ, true><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
         int(n), mu_of<T>(L), x, y, halo);
   brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
 }
