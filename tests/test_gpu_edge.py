@@ -1,0 +1,103 @@
+"""Degenerate cases of the device path against the oracle.
+
+* The smallest mesh, 2 x 2 x 2 cells: one level, so the V-cycle is the coarse
+  solve (the dense inverse of the free block; the outer iterations then come
+  from the Schur approximation alone); operator, V-cycle and Stokes solve
+  against the oracle.
+* A zero right-hand side: every outer solver returns u = 0, p = 0 after no
+  iteration, converged, with a zero residual.
+* Contrast 1 (constant viscosity, the sinker field's degenerate case): the
+  Stokes solve against the oracle's direct solve."""
+import numpy as np
+import pytest
+
+from oracle import krylov, multigrid as mg, operators as ops
+from paper_1907_06696_amd import inputs
+from tests.parity_cases import Case, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solve_vs_direct(c, precs=("fp64", "fp32"), **kw):
+    L = c.L
+    nu, npp = c.info["n_u"][L], c.info["n_p"]
+    prob = krylov.StokesProblem(c.H, ops.harmonic_cell_viscosity(c.mu_qp_or), c.f_qp_or, gmg_kwargs={})
+    xd = prob.solve_direct()
+    pu, pp = c.dof_perm(L), c.pnode_perm()
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    c.s.assemble_rhs(c.f_qp_lib, rhs)
+    for prec in precs:
+        u = torch.empty(nu, dtype=torch.float64, device=DEV)
+        p = torch.empty(npp, dtype=torch.float64, device=DEV)
+        st = c.s.solve_stokes(rhs, u, p, vcycle_prec=prec, **kw)
+        x = np.zeros(nu + npp)
+        x[pu] = u.cpu().numpy()
+        x[nu + pp] = p.cpu().numpy()
+        x[:nu] *= c.H.leaf.free_dofs_mask()
+        x[nu:] *= c.H.leaf.pfree
+        res = prob.residual(x)
+        err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"  {prec}: its={st['iterations']} res={res:.2e} err={err:.2e}", flush=True)
+        assert st["converged"] == 1 and res <= 1.5e-8 and err <= 1e-5, (prec, res, err)
+
+
+def test_one_level_mesh():
+    c = Case(base=1, sinkers=2, dr=1e2, seed=3)
+    assert c.L == 1
+    c.s.set_viscosity(c.mu_qp_lib)
+    n = c.info["n_u"][1]
+    perm = c.dof_perm(1)
+    G = mg.GMG(c.H, c.mus)
+    x_or = inputs.uniform_vector(n, 11)
+    x_lib = x_or[perm]
+    # operator (identity rows on the constrained dofs, as the oracle's level matrix)
+    y_ref = G.A[1] @ x_or
+    xt = torch.tensor(x_lib, dtype=torch.float64, device=DEV)
+    yt = torch.empty_like(xt)
+    c.s.vmult(1, xt, yt)
+    assert rel_err(yt.cpu().numpy(), y_ref[perm]) <= 1e-12
+    # V-cycle = coarse solve
+    b_or = inputs.uniform_vector(n, 12)
+    ref = G.vcycle(b_or)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        bt = torch.tensor(b_or[perm], dtype=dt, device=DEV)
+        xt = torch.empty_like(bt)
+        c.s.vcycle(bt, xt)
+        e = rel_err(xt.double().cpu().numpy(), ref[perm])
+        print(f"  V-cycle {dt}: {e:.2e}")
+        assert e <= tol, (dt, e)
+    _solve_vs_direct(c)
+    c.close()
+
+
+def test_zero_rhs_every_solver():
+    c = Case(base=2, sinkers=3, dr=1e2, seed=4, build_oracle=False)
+    c.s.set_viscosity(c.mu_qp_lib)
+    L = c.L
+    nu, npp = c.info["n_u"][L], c.info["n_p"]
+    rhs = torch.zeros(nu, dtype=torch.float64, device=DEV)
+    for kw in (dict(), dict(krylov="gmres", schur="cheb"), dict(krylov="idr", schur="cheb"),
+               dict(block="diagonal")):
+        for prec in ("fp64", "fp32"):
+            u = torch.full((nu,), 7.0, dtype=torch.float64, device=DEV)
+            p = torch.full((npp,), 7.0, dtype=torch.float64, device=DEV)
+            st = c.s.solve_stokes(rhs, u, p, vcycle_prec=prec, **kw)
+            assert st["converged"] == 1 and st["iterations"] == 0 and st["rel_residual"] == 0.0, (kw, prec, st)
+            assert float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0, (kw, prec)
+    c.close()
+
+
+def test_constant_viscosity():
+    c = Case(base=3, corners=((2, 5, 3),), times=1, sinkers=3, dr=1.0, seed=5)
+    assert np.all(c.mu_qp_lib == c.mu_qp_lib.flat[0])
+    c.s.set_viscosity(c.mu_qp_lib)
+    _solve_vs_direct(c)
+    c.close()
