@@ -290,77 +290,102 @@ __global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, ACC>())) voi
 }
 
 // Adds the halo values of a node's lower neighbour bricks into the node, for
-// every free node on a low face of its owner brick.  One workgroup per
-// brick; its low-face nodes are enumerated as the z-face (lz = 0), then the
-// y-face without it, then the x-face without both, thread t taking
-// component t mod 3 of node t / 3 (consecutive threads, consecutive words).
-// A low x-plane node of a brick that is not the first along x holds its
-// own value in the brick's packed low plane (y is then written without being
-// read, unless accumulating), and its x neighbour's contribution in that
-// neighbour's packed high plane.
+// every free node on a low face of its owner brick.  A brick's low-face
+// nodes fall into classes by which local indices are 0: the interiors of
+// its z, y and x faces (local indices 1 .. 2B - 1 along the other two axes;
+// the closing planes of the last bricks are Dirichlet), whose nodes have one
+// lower neighbour each, and the three edges with the corner.  Items are
+// (node, component) pairs, component fastest; each wave takes 64 items of
+// one class, so a face wave issues only the loads its class needs (the
+// neighbour's value and y; on the x face the two packed planes), and only
+// the edge waves read all seven neighbours, branch free (reads that do not
+// apply go to the zero pad after the last slot).  A low x-plane node of a
+// brick that is not the first along x holds its own value in the brick's
+// packed low plane (y is written without being read, unless accumulating),
+// and its x neighbour's contribution in that neighbour's packed high plane.
+// Sums are formed in the order neighbours s = 1 .. 7 (bit x, y, z of s:
+// shifted by one brick along that axis), own plane, then y.
+template <int BX, int BY, int BZ>
+struct HaloClasses {
+  static constexpr int IX = 2 * BX - 1, IY = 2 * BY - 1, IZ = 2 * BZ - 1;
+  static constexpr int NE = IZ + IX + IY + 1;                       // edge and corner nodes
+  static constexpr int CZ = (3 * IX * IY + 63) / 64, CY = (3 * IX * IZ + 63) / 64;
+  static constexpr int CX = (3 * IY * IZ + 63) / 64, CE = (3 * NE + 63) / 64;
+  static constexpr int waves = CZ + CY + CX + CE;                    // per brick
+  static constexpr int groups = (waves + 3) / 4;                     // workgroups of 4 waves per brick
+};
+
 template <typename T, int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void k_brick_halo_add(int n, bool accumulate, const T* __restrict__ halo,
                                                         T* __restrict__ y) {
-  constexpr int NX = 2 * BX + 1, NY = 2 * BY + 1, NZ = 2 * BZ + 1, ROW = 3 * NX;
-  constexpr int MAXN = NX * NY + NX * (NZ - 1) + (NY - 1) * (NZ - 1);   // low-face nodes, at most
-  constexpr int KT = (3 * MAXN + 255) / 256;                             // items per thread
-  const int nbx = n / BX, nby = n / BY, nbz = n / BZ;
-  const int b = int(xcd_order(blockIdx.x, gridDim.x));
+  using HC = HaloClasses<BX, BY, BZ>;
+  constexpr int NY = 2 * BY + 1, ROW = 3 * (2 * BX + 1);
+  constexpr int64_t HW = halo_words<BX, BY, BZ>(), HB = halo_box_words<BX, BY, BZ>();
+  constexpr int64_t HP = halo_plane_words<BX, BY, BZ>();
+  const int nbx = n / BX, nby = n / BY;
+  const int64_t g = xcd_order(blockIdx.x, gridDim.x);
+  const int b = int(g / HC::groups);
+  const int wave = int(g % HC::groups) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
   const int m = 2 * n + 1;
   const int X0 = 2 * BX * bx, Y0 = 2 * BY * by, Z0 = 2 * BZ * bz;
-  // owned local extents: [0, e) along each axis
-  const int ex = bx == nbx - 1 ? NX : NX - 1, ey = by == nby - 1 ? NY : NY - 1, ez = bz == nbz - 1 ? NZ : NZ - 1;
-  const int y1 = bz > 0 ? 1 : 0, x1 = by > 0 ? 1 : 0;
-  const int fz = bz > 0 ? ex * ey : 0;
-  const int fy = by > 0 ? ex * (ez - y1) : 0;
-  const int fx = bx > 0 ? (ey - x1) * (ez - y1) : 0;
-  const int total = 3 * (fz + fy + fx);
-  // every load of a thread's items is issued before its first store, without
-  // branches: reads that do not apply go to the zero pad after the last slot
-  const T* zero = halo + int64_t(nbx) * nby * nbz * halo_words<BX, BY, BZ>();
-  T acc[KT], cur[KT];
-  int64_t dst[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const int t = threadIdx.x + 256 * k;
-    acc[k] = T(0), cur[k] = T(0), dst[k] = -1;
-    const int tt = t < total ? t : 0;   // items past the end are dead (read the pad, store nothing)
-    const int i = tt / 3, comp = tt - 3 * i;
-    int lx, ly, lz;
-    if (i < fz) {
-      lz = 0, ly = i / ex, lx = i - ly * ex;
-    } else if (i < fz + fy) {
-      const int j = i - fz;
-      ly = 0, lz = y1 + j / ex, lx = j % ex;
-    } else {
-      const int j = i - fz - fy, wd = ey - x1;
-      lx = 0, lz = y1 + j / wd, ly = x1 + j % wd;
-    }
-    const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
-    const bool live = t < total && !(X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1);
-    const bool lowx = live && lx == 0 && bx > 0, lowy = live && ly == 0 && by > 0, lowz = live && lz == 0 && bz > 0;
-    constexpr int64_t HB = halo_box_words<BX, BY, BZ>(), HP = halo_plane_words<BX, BY, BZ>();
+  auto dst = [&](int lx, int ly, int lz, int comp) {
+    return 3 * (int64_t(X0 + lx) + int64_t(m) * (int64_t(Y0 + ly) + int64_t(m) * (Z0 + lz))) + comp;
+  };
+  if (wave < HC::CZ) {   // z face: lower neighbour along z, its high z rows
+    const int item = wave * 64 + lane;
+    if (bz == 0 || item >= 3 * HC::IX * HC::IY) return;
+    const int k = item / 3, comp = item - 3 * k;
+    const int lx = 1 + k % HC::IX, ly = 1 + k / HC::IX;
+    const int64_t nb = b - int64_t(nbx) * nby, d = dst(lx, ly, 0, comp);
+    const T h = halo[nb * HW + (int64_t(2 * BZ) * NY + ly) * ROW + 3 * lx + comp];
+    y[d] = y[d] + h;
+  } else if (wave < HC::CZ + HC::CY) {   // y face: lower neighbour along y, its high y rows
+    const int item = (wave - HC::CZ) * 64 + lane;
+    if (by == 0 || item >= 3 * HC::IX * HC::IZ) return;
+    const int k = item / 3, comp = item - 3 * k;
+    const int lx = 1 + k % HC::IX, lz = 1 + k / HC::IX;
+    const int64_t nb = b - nbx, d = dst(lx, 0, lz, comp);
+    const T h = halo[nb * HW + (int64_t(lz) * NY + 2 * BY) * ROW + 3 * lx + comp];
+    y[d] = y[d] + h;
+  } else if (wave < HC::CZ + HC::CY + HC::CX) {   // x face: the packed planes
+    const int item = (wave - HC::CZ - HC::CY) * 64 + lane;
+    if (bx == 0 || item >= 3 * HC::IY * HC::IZ) return;
+    const int k = item / 3, comp = item - 3 * k;
+    const int ly = 1 + k % HC::IY, lz = 1 + k / HC::IY;
+    const int64_t pl = (int64_t(lz) * NY + ly) * 3 + comp, d = dst(0, ly, lz, comp);
+    const T acc = halo[(b - 1) * HW + HB + HP + pl] + halo[b * HW + HB + pl];
+    const T cur = accumulate ? y[d] : T(0);
+    y[d] = cur + acc;
+  } else {   // edges (lx = ly = 0; ly = lz = 0; lx = lz = 0) and the corner
+    const int item = (wave - HC::CZ - HC::CY - HC::CX) * 64 + lane;
+    if (item >= 3 * HC::NE) return;
+    const int k = item / 3, comp = item - 3 * k;
+    int lx = 0, ly = 0, lz = 0;
+    if (k < HC::IZ) lz = 1 + k;
+    else if (k < HC::IZ + HC::IX) lx = 1 + (k - HC::IZ);
+    else if (k < HC::IZ + HC::IX + HC::IY) ly = 1 + (k - HC::IZ - HC::IX);
+    // a local index 0 of the first brick along that axis is a Dirichlet node
+    if ((lx == 0 && bx == 0) || (ly == 0 && by == 0) || (lz == 0 && bz == 0)) return;
+    const bool lowx = lx == 0, lowy = ly == 0, lowz = lz == 0;
+    const T* zero = halo + int64_t(nbx) * nby * (n / BZ) * HW;
+    T acc = T(0);
 #pragma unroll
     for (int s = 1; s < 8; ++s) {
       const int sx = s & 1, sy = (s >> 1) & 1, sz = s >> 2;
       const bool use = !((sx && !lowx) || (sy && !lowy) || (sz && !lowz));
       const int64_t nb = (bx - sx) + int64_t(nbx) * ((by - sy) + int64_t(nby) * (bz - sz));
       const int qx = sx ? 2 * BX : lx, qy = sy ? 2 * BY : ly, qz = sz ? 2 * BZ : lz;
-      const T* src = s == 1 ? halo + nb * halo_words<BX, BY, BZ>() + HB + HP + (int64_t(lz) * NY + ly) * 3 + comp
-                            : halo + nb * halo_words<BX, BY, BZ>() + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp;
-      acc[k] += *(use ? src : zero);
+      const T* src = s == 1 ? halo + nb * HW + HB + HP + (int64_t(lz) * NY + ly) * 3 + comp
+                            : halo + nb * HW + (int64_t(qz) * NY + qy) * ROW + 3 * qx + comp;
+      acc += *(use ? src : zero);
     }
-    const bool packed = lx == 0 && bx > 0;
-    const T* own = halo + int64_t(b) * halo_words<BX, BY, BZ>() + HB + (int64_t(lz) * NY + ly) * 3 + comp;
-    acc[k] += *(live && packed ? own : zero);
-    const int64_t d = 3 * (X + int64_t(m) * (Y + int64_t(m) * Z)) + comp;
-    dst[k] = live ? d : -1;
-    cur[k] = *(live && (!packed || accumulate) ? y + d : zero);
+    acc += *(lowx ? halo + int64_t(b) * HW + HB + (int64_t(lz) * NY + ly) * 3 + comp : zero);
+    const int64_t d = dst(lx, ly, lz, comp);
+    const T cur = (!lowx || accumulate) ? y[d] : T(0);
+    y[d] = cur + acc;
   }
-#pragma unroll
-  for (int k = 0; k < KT; ++k)
-    if (dst[k] >= 0) y[dst[k]] = cur[k] + acc[k];
 }
 
 }  // namespace brick

@@ -1779,7 +1779,8 @@ void launch_brick(const DevLevel& L, const T* x, T* y, T* halo, bool init, hipSt
   else
     brick::k_vmult_brick<T, BX, BY, BZ, true><<<unsigned(nb), BX * BY * BZ, 0, s>>>(
         int(n), mu_of<T>(L), x, y, halo);
-  brick::k_brick_halo_add<T, BX, BY, BZ><<<unsigned(nb), 256, 0, s>>>(int(n), !init, halo, y);
+  brick::k_brick_halo_add<T, BX, BY, BZ>
+      <<<unsigned(nb * brick::HaloClasses<BX, BY, BZ>::groups), 256, 0, s>>>(int(n), !init, halo, y);
 }
 
 template <typename T>
