@@ -427,7 +427,6 @@ def summarize_counters(fetch_csv, write_csv, level=6):
     of the calibration copy (the largest copy dispatches, COPY_BYTES read and
     written)."""
     import csv
-    n = 1 << level
     out = {"level": level, "kernel_source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
            "note": "operator applications on rotating vector pairs (618 MB FP64, 412 MB FP32)"}
     scale = {}
@@ -445,9 +444,12 @@ def summarize_counters(fetch_csv, write_csv, level=6):
             per = {}
             for tag in tags:
                 # the probe's 20 applications: the last 20 dispatches at the leaf's
-                # grid (set-up also applies the leaf operator, to estimate lambda)
-                v = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows[name]
-                           if tag in r["Kernel_Name"] and int(r["Grid_Size"]) in (n ** 3, 2 * n ** 3))[-20:]
+                # grid, the kernel's largest (set-up also applies the leaf operator,
+                # to estimate lambda, and the lower levels' operators)
+                mine = [r for r in rows[name] if tag in r["Kernel_Name"]]
+                gmax = max((int(r["Grid_Size"]) for r in mine), default=0)
+                v = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in mine
+                           if int(r["Grid_Size"]) == gmax)[-20:]
                 per[tag.split("<")[0]] = {"dispatches": len(v), "kib_per_dispatch": sum(c for _, c in v) / max(len(v), 1)}
             b = sum(d["kib_per_dispatch"] for d in per.values()) * 1024.0 * scale[name][1]
             entry[name] = {"calibration_kib": scale[name][0], "scale_bytes_per_counted_byte": scale[name][1],
