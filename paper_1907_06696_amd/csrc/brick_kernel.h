@@ -164,7 +164,14 @@ __global__ __launch_bounds__(BX * BY * BZ, (brick_waves_per_simd<T, ACC>())) voi
     }
   });
   __syncthreads();
-  const int cx = t % BX, cy = (t / BX) % BY, cz = t / (BX * BY);
+  // Cell rows are dealt to the 8-lane groups of a z-plane two apart (8 x 8
+  // cells: lanes 0-31 take rows 0, 2, 4, 6 and lanes 32-63 rows 1, 3, 5, 7;
+  // 8 x 4: rows 0, 2, 1, 3): with the row pitch of 20 the LDS rows that one
+  // pass of a gather serves (16 lanes of 8-byte or 32 lanes of 4-byte words)
+  // then start 8 doubles or 8 floats apart, on disjoint banks, where
+  // consecutive rows (20 words apart) shared half their banks.
+  const int grp = (t / BX) % BY;
+  const int cx = t % BX, cy = 2 * (grp % (BY / 2)) + grp / (BY / 2), cz = t / (BX * BY);
   const int64_t cell = (int64_t(bx) * BX + cx) + int64_t(n) * ((int64_t(by) * BY + cy) + int64_t(n) * (int64_t(bz) * BZ + cz));
   auto zero_box = [&]() {
     constexpr int NV = (3 * CS * int(sizeof(T))) / 16;
