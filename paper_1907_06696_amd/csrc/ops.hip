@@ -821,6 +821,99 @@ __global__ void k_prolong_uniform(int nc, const T* __restrict__ xc, T* __restric
   }
 }
 
+// The same prolongation, one wave per fine lattice row (Y, Z), four rows per
+// workgroup, for coarse levels up to kRowMaxCoarse cells per edge: the wave
+// first combines the up to 3 x 3 coarse rows its (Y, Z) touches into one
+// coarse row (weights wy wz, coalesced reads along the rows) in its part of
+// LDS, then forms every fine node of the row from up to 3 of its values.  The
+// gather kernel above reads up to 27 coarse nodes per fine node with lanes two
+// nodes apart; this one reads each coarse row once per fine row it serves.
+// A wave's LDS writes and later reads are ordered by an LDS wait (its LDS
+// operations complete in order), so the rows need no workgroup barrier.
+constexpr int kRowMaxCoarse = 64;
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  asm volatile("" ::: "memory");
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_rows(int nc, const T* __restrict__ xc, T* __restrict__ xf,
+                                                      bool add) {
+  __shared__ T rcs[4][3 * (2 * kRowMaxCoarse + 1)];
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  // XCD-contiguous row ranges: neighbouring fine rows read the same coarse rows
+  const int row = 4 * int(brick::xcd_order(blockIdx.x, gridDim.x)) + w;
+  if (row >= mf * mf) return;
+  T* rc = rcs[w];
+  const int Y = row % mf, Z = row / mf;
+  T* q = xf + 3 * int64_t(mf) * row;
+  if (Y == 0 || Z == 0 || Y == mf - 1 || Z == mf - 1) {   // boundary row: receives nothing
+    if (!add)
+      for (int i = lane; i < 3 * mf; i += 64) q[i] = T(0);
+    return;
+  }
+  int iy[3], iz[3];
+  T wy[3], wz[3];
+  const int ny = prolong_axis<T>(Y, mc, iy, wy), nz = prolong_axis<T>(Z, mc, iz, wz);
+  // ny, nz (1 or 3) are the wave's: each case is unrolled, so that all loads of
+  // four row chunks are issued before the first is used
+  auto combine = [&](auto kny, auto knz) {
+    constexpr int NY = decltype(kny)::value, NZ = decltype(knz)::value;
+    const T* src[NY * NZ];
+    T ww[NY * NZ];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k)
+#pragma unroll
+      for (int j = 0; j < NY; ++j) {
+        src[j + NY * k] = xc + 3 * int64_t(mc) * (iy[j] + int64_t(mc) * iz[k]);
+        ww[j + NY * k] = wz[k] * wy[j];
+      }
+    for (int i0 = 0; i0 < 3 * mc; i0 += 256) {
+      T v[4][NY * NZ];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = min(i0 + 64 * u + lane, 3 * mc - 1);
+#pragma unroll
+        for (int e = 0; e < NY * NZ; ++e) v[u][e] = src[e][i];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u + lane;
+        T a = T(0);
+#pragma unroll
+        for (int e = 0; e < NY * NZ; ++e) a += ww[e] * v[u][e];
+        if (i < 3 * mc) rc[i] = a;
+      }
+    }
+  };
+  using one = std::integral_constant<int, 1>;
+  using three = std::integral_constant<int, 3>;
+  if (ny == 1 && nz == 1) combine(one(), one());
+  else if (ny == 1) combine(one(), three());
+  else if (nz == 1) combine(three(), one());
+  else combine(three(), three());
+  wave_lds_sync();
+  for (int i0 = 0; i0 < 3 * mf; i0 += 256) {
+    T old[4];
+    if (add) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) old[u] = q[min(i0 + 64 * u + lane, 3 * mf - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u + lane, X = i / 3, comp = i - 3 * X;
+      T a = T(0);
+      if (X > 0 && X < mf - 1) {
+        int ix[3];
+        T wx[3];
+        const int nx = prolong_axis<T>(X, mc, ix, wx);
+        for (int l = 0; l < nx; ++l) a += wx[l] * rc[3 * ix[l] + comp];
+      }
+      if (i < 3 * mf) q[i] = add ? old[u] + a : a;
+    }
+  }
+}
+
 // Restriction between uniform levels, R = P^T, as three one-axis passes
 // (each a bandwidth-bound stream with coalesced neighbours) with the 1D
 // weights of R: offsets -3, -1, 0, 1, 3 from the fine node 2C, weights
@@ -862,6 +955,55 @@ __global__ __launch_bounds__(kBlock) void k_restrict_x(int nc, const T* __restri
     }
     T* o = s1 + 3 * int64_t(v);
     o[0] = a0, o[1] = a1, o[2] = a2;
+  }
+}
+// The x pass, one wave per fine row (fy, fz), four rows per workgroup, for
+// coarse levels up to kRowMaxCoarse cells per edge: the row's residual is
+// read once, coalesced, into the wave's part of LDS, and each output
+// (cx, component) sums its five values there (the one-thread-per-output form
+// reads them from memory with lanes two nodes apart).  Same terms in the
+// same order as k_restrict_x.
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_x_rows(int nc, const T* __restrict__ b, const T* __restrict__ t,
+                                                         T* __restrict__ s1) {
+  __shared__ T rs[4][3 * (4 * kRowMaxCoarse + 1)];
+  const int mc = 2 * nc + 1, mf = 4 * nc + 1;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  const int row = 4 * int(brick::xcd_order(blockIdx.x, gridDim.x)) + w;   // fy + mf fz
+  if (row >= mf * mf) return;
+  T* r = rs[w];
+  const int fy = row % mf, fz = row / mf;
+  T* o = s1 + 3 * int64_t(mc) * row;
+  if (fy == 0 || fz == 0 || fy == mf - 1 || fz == mf - 1) {   // boundary rows count 0
+    for (int i = lane; i < 3 * mc; i += 64) o[i] = T(0);
+    return;
+  }
+  const int64_t f0 = 3 * int64_t(mf) * row;
+  // four row chunks per round, every load issued before the first is used
+  for (int i0 = 0; i0 < 3 * mf; i0 += 256) {
+    T vb[4], vt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t f = f0 + min(i0 + 64 * u + lane, 3 * mf - 1);
+      vb[u] = b[f];
+      vt[u] = t ? t[f] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u + lane, fx = i / 3;
+      if (i < 3 * mf) r[i] = (fx > 0 && fx < mf - 1) ? (t ? vb[u] - vt[u] : vb[u]) : T(0);
+    }
+  }
+  wave_lds_sync();
+  for (int i = lane; i < 3 * mc; i += 64) {
+    const int cx = i / 3, comp = i - 3 * cx;
+    T a = T(0);
+#pragma unroll
+    for (int qq = 0; qq < 5; ++qq) {
+      const int fx = 2 * cx + restrict_off(qq);
+      if (fx > 0 && fx < mf - 1) a += restrict_w<T>(cx, qq) * r[3 * fx + comp];
+    }
+    o[i] = a;
   }
 }
 template <typename T>
@@ -2286,7 +2428,11 @@ template <typename T>
 void launch_prolong_level(const DevLevel& F, const DevLevel& Cc, const int64_t* ptr, const int32_t* col,
                           const float* w, const T* xc, T* xf, bool add, hipStream_t s) {
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge) {
-    k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
+    const int64_t mf = 4 * Cc.n_edge + 1;
+    if (Cc.n_edge <= kRowMaxCoarse)
+      k_prolong_rows<T><<<unsigned((mf * mf + 3) / 4), 256, 0, s>>>(int(Cc.n_edge), xc, xf, add);
+    else
+      k_prolong_uniform<T><<<grid_for(F.nnode), kBlock, 0, s>>>(int(Cc.n_edge), xc, xf, add);
     return;
   }
   if (F.q3 && F.q3_pc0 && tr_has_scratch<T>(F)) {
@@ -2321,7 +2467,8 @@ void launch_restrict_level(const DevLevel& F, const DevLevel& Cc, const int64_t*
   }
   if (F.uniform && Cc.uniform && F.n_edge == 2 * Cc.n_edge && mc * mf * mf < (int64_t(1) << 31)) {
     const int nc = int(Cc.n_edge);
-    k_restrict_x<T><<<grid_for(mc * mf * mf), kBlock, 0, s>>>(nc, b, t, s1);
+    if (nc <= kRowMaxCoarse) k_restrict_x_rows<T><<<unsigned((mf * mf + 3) / 4), 256, 0, s>>>(nc, b, t, s1);
+    else k_restrict_x<T><<<grid_for(mc * mf * mf), kBlock, 0, s>>>(nc, b, t, s1);
     k_restrict_y<T><<<grid_for(mc * mc * mf), kBlock, 0, s>>>(nc, s1, s2);
     k_restrict_z<T><<<grid_for(mc * mc * mc), kBlock, 0, s>>>(nc, s2, xc);
     return;
