@@ -804,6 +804,12 @@ void vcycle(mfgmg_ctx* ctx, int ell, const T* b, T* x, hipStream_t s) {
   }
   LevelDev& d = ctx->lv[size_t(ell)];
   LevelDev& c = ctx->lv[size_t(ell - 1)];
+  if (ell == 2) {   // the 4^3 level and the coarse solve in one workgroup, where it applies
+    const bool sc = ctx->use_scaling && d.scaled;
+    if (launch_vcycle_tail<T>(d.v, c.v, sc ? minv_s_of<T>(d) : minv_of<T>(d), ainv_of<T>(ctx), ctx->coarse_free,
+                              ctx->ncfree, sc ? d.lambda_s : d.lambda, b, x, s))
+      return;
+  }
   const int pi = prec_index<T>();
   T* t = static_cast<T*>(d.work[pi][4]);
   T* bc = static_cast<T*>(c.work[pi][0]);

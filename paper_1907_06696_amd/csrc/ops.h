@@ -209,6 +209,15 @@ void launch_restrict_level(const DevLevel& fine, const DevLevel& coarse, const i
 // coarse solve: x[free] = Ainv b[free], x[constrained] = b
 template <typename T>
 void launch_coarse(const T* Ainv, const int32_t* free_dofs, int nfree, int n, const T* b, T* x, hipStream_t s);
+// One V-cycle on the uniform 4^3 level L with the coarse solve of the 2^3
+// level Lc below it (Ainv, free_dofs, nfree as for launch_coarse), smoother
+// M^-1 = minv on [lam / 15, lam], in a single workgroup; the same steps as
+// smoothing, residual, restriction, coarse solve, prolongation and smoothing
+// launched one by one.  Returns false (nothing launched) when L, Lc are not
+// such levels (no-normal-flux and Q3 lattice levels are not).
+template <typename T>
+bool launch_vcycle_tail(const DevLevel& L, const DevLevel& Lc, const T* minv, const T* Ainv, const int32_t* free_dofs,
+                        int nfree, double lam, const T* b, T* x, hipStream_t s);
 
 // viscosity
 void launch_harmonic_mu(int64_t ncell, const double* mu_qp, double* mu, hipStream_t s);

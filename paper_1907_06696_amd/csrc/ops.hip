@@ -1067,6 +1067,271 @@ __global__ __launch_bounds__(128) void k_coarse(const T* __restrict__ Ainv, cons
   }
 }
 
+// ------------------------------------------------------------- the 4^3 level
+// One V-cycle on the uniform 4^3 level (9^3 nodes, 64 cells) together with the
+// coarse solve of the 2^3 level below it, in one workgroup.  The level's
+// vectors (x, A x, b, the Chebyshev direction d, the inverse diagonal) live
+// in LDS, and the steps of the cycle are separated by workgroup barriers
+// instead of the ~22 kernel boundaries the level takes otherwise, each of
+// which costs more than the level's arithmetic.  Every step computes what its
+// kernel computes (some sums in another order): the Chebyshev
+// updates of k_chebx_init0 / k_chebx_step, the operator of k_vmult_uniform3
+// (three threads per cell; its sums go into LDS), the passes of
+// k_restrict_x_rows / k_restrict_y / k_restrict_z, k_coarse (a row's sum in
+// three parts) and the prolongation (here by axes, z, y, x).  Pre-smoothing
+// starts from x = 0; post-smoothing's first step has alpha = 0; steps 1-3 of
+// both take (alpha_k, beta_k).
+template <typename T>
+struct TailCoef {
+  T it0, alpha[4], beta[4];
+};
+constexpr int kTailN = 4, kTailFree = 81;   // free dofs of the 2^3 level under u = 0
+template <typename T>
+__global__ __launch_bounds__(256) void k_vcycle_tail(const T* __restrict__ mu, const T* __restrict__ minv,
+                                                     const T* __restrict__ Ainv, const int32_t* __restrict__ fd,
+                                                     TailCoef<T> cf, const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int n = kTailN, m = 2 * n + 1, NV = 3 * m * m * m, KV = (NV + 255) / 256;
+  constexpr int mc = n + 1, mf = m, NC = 3 * mc * mc * mc;
+  __shared__ T xs[NV], ts[NV], bs[NV], ds[NV], ms[NV];
+  __shared__ T wsh[3][27][64];
+  __shared__ T s1[3 * mc * mf * mf], s2[3 * mc * mc * mf], bc[NC], xc[NC], bf[kTailFree], part[3 * kTailFree];
+  const int tid = threadIdx.x;
+  // this thread's entries tid + 256 k: in range (bit k of `live`) and on a
+  // boundary node (`fixed`).  Wherever x changes, ts is set to x on the
+  // fixed entries and 0 elsewhere, the output the operator then adds to
+  // (identity rows), as the smoother's kernels prepare it.
+  unsigned live = 0, fixed = 0;
+#pragma unroll
+  for (int k = 0; k < KV; ++k) {
+    const int i = tid + 256 * k, v = i / 3, X = v % m, Y = (v / m) % m, Z = v / (m * m);
+    if (i < NV) live |= 1u << k;
+    if (i < NV && (X == 0 || Y == 0 || Z == 0 || X == m - 1 || Y == m - 1 || Z == m - 1)) fixed |= 1u << k;
+  }
+  auto each = [&](auto f) {
+#pragma unroll
+    for (int k = 0; k < KV; ++k)
+      if ((live >> k) & 1) f(tid + 256 * k, ((fixed >> k) & 1) != 0);
+  };
+  each([&](int i, bool) { bs[i] = b[i], ms[i] = minv[i]; });
+  // the operator's thread: cell `cell`, output component c (waves 0-2)
+  const bool opt = tid < 192;
+  const int c = tid >> 6, cell = tid & 63;
+  const UniformCell uc(n, cell);
+  const T mu_h = opt ? mu[cell] / T(n) : T(0);
+  __syncthreads();
+  auto apply = [&]() {   // ts += the cells' sums: ts = A xs
+    T w[27];
+    if (opt) {
+#pragma unroll
+      for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+          for (int xx = 0; xx < 3; ++xx) {
+            const int32_t sl = uc.slot(xx, yy, z);
+            const T v = xs[3 * max(sl, 0) + c];   // every read issued, the Dirichlet ones dropped
+            w[xx + 3 * yy + 9 * z] = sl >= 0 ? v : T(0);
+          }
+      cellop::interp_all(w);
+#pragma unroll
+      for (int a = 0; a < 27; ++a) wsh[c][a][cell] = w[a];
+    }
+    __syncthreads();
+    if (opt) {
+      T W[3][27];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int a = 0; a < 27; ++a) W[cc][a] = wsh[cc][a][cell];
+      if (c == 0) cellop::apply_cell_row<0>(W, w, mu_h);
+      else if (c == 1) cellop::apply_cell_row<1>(W, w, mu_h);
+      else cellop::apply_cell_row<2>(W, w, mu_h);
+      cellop::interp_all_t(w);
+      if constexpr (sizeof(T) == 8) {   // FP64: LDS atomics (the ordered form below spills here)
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+          for (int yy = 0; yy < 3; ++yy)
+#pragma unroll
+            for (int xx = 0; xx < 3; ++xx) {
+              const int32_t sl = uc.slot(xx, yy, z);
+              if (sl >= 0) atomicAdd(&ts[3 * sl + c], w[xx + 3 * yy + 9 * z]);
+            }
+      } else {
+        // FP32: the 64 cells of a wave add into ts without atomics (LDS float
+        // atomics made the whole cycle 73 instead of 56 us): local nodes in
+        // classes (0-1 | 2 per axis), within which no two (cell, local node)
+        // pairs share a node, one class after the other (a wave's LDS
+        // operations complete in order)
+#pragma unroll
+        for (int cls = 0; cls < 8; ++cls) {
+          const int a0 = (cls & 1) ? 2 : 0, a1 = (cls & 1) ? 3 : 2;
+          const int b0 = (cls & 2) ? 2 : 0, b1 = (cls & 2) ? 3 : 2;
+          const int z0 = (cls & 4) ? 2 : 0, z1 = (cls & 4) ? 3 : 2;
+          T old[8];
+#pragma unroll
+          for (int z = z0; z < z1; ++z)
+#pragma unroll
+            for (int yy = b0; yy < b1; ++yy)
+#pragma unroll
+              for (int xx = a0; xx < a1; ++xx)
+                old[(xx - a0) + 2 * (yy - b0) + 4 * (z - z0)] = ts[3 * max(uc.slot(xx, yy, z), 0) + c];
+#pragma unroll
+          for (int z = z0; z < z1; ++z)
+#pragma unroll
+            for (int yy = b0; yy < b1; ++yy)
+#pragma unroll
+              for (int xx = a0; xx < a1; ++xx) {
+                const int32_t sl = uc.slot(xx, yy, z);
+                if (sl >= 0) ts[3 * sl + c] = old[(xx - a0) + 2 * (yy - b0) + 4 * (z - z0)] + w[xx + 3 * yy + 9 * z];
+              }
+          wave_lds_sync();
+        }
+      }
+    }
+    __syncthreads();
+  };
+  auto step = [&](T alpha, T beta) {
+    each([&](int i, bool fx) {
+      const T ri = bs[i] - ts[i];
+      const T di = (alpha != T(0) ? alpha * ds[i] : T(0)) + beta * ms[i] * ri;
+      const T xi = xs[i] + di;
+      ds[i] = di;
+      xs[i] = xi;
+      ts[i] = fx ? xi : T(0);
+    });
+    __syncthreads();
+  };
+  // the coarse correction: residual restricted, coarse solve, prolongation
+  auto correct = [&]() {
+    // R (b - A x): x, y and z passes
+    for (int v = tid; v < 3 * mc * mf * mf; v += 256) {
+      const int comp = v % 3, o = v / 3, cx = o % mc, fy = (o / mc) % mf, fz = o / (mc * mf);
+      T a = T(0);
+      if (fy > 0 && fy < mf - 1 && fz > 0 && fz < mf - 1) {
+#pragma unroll
+        for (int qq = 0; qq < 5; ++qq) {
+          const int fx = 2 * cx + restrict_off(qq);
+          if (fx > 0 && fx < mf - 1) {
+            const int f = 3 * (fx + mf * (fy + mf * fz)) + comp;
+            a += restrict_w<T>(cx, qq) * (bs[f] - ts[f]);
+          }
+        }
+      }
+      s1[v] = a;
+    }
+    __syncthreads();
+    for (int v = tid; v < 3 * mc * mc * mf; v += 256) {
+      const int comp = v % 3, o = v / 3, cx = o % mc, cy = (o / mc) % mc, fz = o / (mc * mc);
+      T a = T(0);
+#pragma unroll
+      for (int qq = 0; qq < 5; ++qq) {
+        const int fy = 2 * cy + restrict_off(qq);
+        if (fy >= 0 && fy < mf) a += restrict_w<T>(cy, qq) * s1[3 * (cx + mc * (fy + mf * fz)) + comp];
+      }
+      s2[v] = a;
+    }
+    __syncthreads();
+    for (int v = tid; v < NC; v += 256) {
+      const int comp = v % 3, o = v / 3, cx = o % mc, cy = (o / mc) % mc, cz = o / (mc * mc);
+      T a = T(0);
+      if (cx > 0 && cx < mc - 1 && cy > 0 && cy < mc - 1 && cz > 0 && cz < mc - 1) {
+#pragma unroll
+        for (int qq = 0; qq < 5; ++qq) {
+          const int fz = 2 * cz + restrict_off(qq);
+          if (fz >= 0 && fz < mf) a += restrict_w<T>(cz, qq) * s2[3 * (cx + mc * (cy + mc * fz)) + comp];
+        }
+      }
+      bc[v] = a;
+    }
+    __syncthreads();
+    // coarse solve on the free dofs (the others keep b): three threads per
+    // row of Ainv, each summing a third of its columns (all loads issued
+    // first), then the row's first thread adds the three sums
+    for (int i = tid; i < kTailFree; i += 256) bf[i] = bc[fd[i]];
+    for (int i = tid; i < NC; i += 256) xc[i] = bc[i];
+    __syncthreads();
+    {
+      constexpr int JC = kTailFree / 3;
+      const int r = tid % kTailFree, q = tid / kTailFree;
+      if (tid < 3 * kTailFree) {
+        T v[JC];
+#pragma unroll
+        for (int j = 0; j < JC; ++j) v[j] = Ainv[r * kTailFree + q * JC + j];
+        T a = T(0);
+#pragma unroll
+        for (int j = 0; j < JC; ++j) a += v[j] * bf[q * JC + j];
+        part[q * kTailFree + r] = a;
+      }
+      __syncthreads();
+      if (tid < kTailFree) xc[fd[tid]] = (part[tid] + part[kTailFree + tid]) + part[2 * kTailFree + tid];
+    }
+    __syncthreads();
+    // x += P xc by axes: z (into s2 [Z][cy][cx]), y (into s1 [Z][Y][cx]), then
+    // x into the fine entries (1D weights of prolong_axis; the fine boundary
+    // receives nothing)
+    for (int v = tid; v < 3 * mc * mc * mf; v += 256) {
+      const int comp = v % 3, o = v / 3, cx = o % mc, cy = (o / mc) % mc, Z = o / (mc * mc);
+      int id[3];
+      T wt[3];
+      const int nz = prolong_axis<T>(Z, mc, id, wt);
+      T a = T(0);
+      for (int k = 0; k < nz; ++k) a += wt[k] * xc[3 * (cx + mc * (cy + mc * id[k])) + comp];
+      s2[v] = a;
+    }
+    __syncthreads();
+    for (int v = tid; v < 3 * mc * mf * mf; v += 256) {
+      const int comp = v % 3, o = v / 3, cx = o % mc, Y = (o / mc) % mf, Z = o / (mc * mf);
+      int id[3];
+      T wt[3];
+      const int ny = prolong_axis<T>(Y, mc, id, wt);
+      T a = T(0);
+      for (int j = 0; j < ny; ++j) a += wt[j] * s2[3 * (cx + mc * (id[j] + mc * Z)) + comp];
+      s1[v] = a;
+    }
+    __syncthreads();
+    each([&](int i, bool fx) {
+      if (!fx) {
+        const int comp = i % 3, v = i / 3, X = v % m, YZ = v / m;
+        int id[3];
+        T wt[3];
+        const int nx = prolong_axis<T>(X, mc, id, wt);
+        T a = T(0);
+        for (int l = 0; l < nx; ++l) a += wt[l] * s1[3 * (id[l] + mc * YZ) + comp];
+        xs[i] = xs[i] + a;
+      }
+      ts[i] = fx ? xs[i] : T(0);
+    });
+    __syncthreads();
+  };
+  // pre-smoothing from zero
+  each([&](int i, bool fx) {
+    const T di = ms[i] * bs[i] * cf.it0;
+    ds[i] = di;
+    xs[i] = di;
+    ts[i] = fx ? di : T(0);
+  });
+  __syncthreads();
+  // the cycle's eight operator applications, one copy of their code (the
+  // unrolled cycle overflows the instruction cache): p = 0-2 pre-smoothing
+  // steps 1-3, p = 3 the residual and the coarse correction, p = 4-7
+  // post-smoothing steps 0-3
+#pragma nounroll
+  for (int p = 0; p < 8; ++p) {
+    apply();
+    if (p == 3) {
+      correct();
+    } else if (p == 4) {
+      step(T(0), cf.it0);
+    } else {
+      const int k = p < 3 ? p + 1 : p - 4;
+      step(k == 1 ? cf.alpha[1] : k == 2 ? cf.alpha[2] : cf.alpha[3],
+           k == 1 ? cf.beta[1] : k == 2 ? cf.beta[2] : cf.beta[3]);
+    }
+  }
+  each([&](int i, bool) { x[i] = xs[i]; });
+}
+
 // ------------------------------------------------------------- viscosity
 __global__ void k_harmonic(int64_t ncell, const double* __restrict__ mq, double* __restrict__ mu) {
   const double w1[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
@@ -2078,6 +2343,31 @@ void launch_coarse(const T* Ainv, const int32_t* fd, int nfree, int n, const T* 
   k_coarse<T><<<1, 128, 0, s>>>(Ainv, fd, nfree, n, b, x);
 }
 template void launch_coarse<float>(const float*, const int32_t*, int, int, const float*, float*, hipStream_t);
+template <typename T>
+bool launch_vcycle_tail(const DevLevel& L, const DevLevel& Lc, const T* minv, const T* Ainv, const int32_t* fd,
+                        int nfree, double lam, const T* b, T* x, hipStream_t s) {
+  if (!(L.uniform && !L.q3 && !L.noflux && L.n_edge == kTailN && Lc.uniform && Lc.n_edge == kTailN / 2 &&
+        nfree == kTailFree))
+    return false;
+  // the smoother's coefficients (Saad, Alg. 12.1 on [lam / 15, lam]) as the separate kernels take them
+  const double lo = lam / 15.0, theta = 0.5 * (lam + lo), delta = 0.5 * (lam - lo), sigma = theta / delta;
+  TailCoef<T> cf{};
+  cf.it0 = T(1.0 / theta);
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < 4; ++k) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    cf.alpha[k] = T(rho_new * rho);
+    cf.beta[k] = T(2.0 * rho_new / delta);
+    rho = rho_new;
+  }
+  k_vcycle_tail<T><<<1, 256, 0, s>>>(mu_of<T>(L), minv, Ainv, fd, cf, b, x);
+  return true;
+}
+template bool launch_vcycle_tail<float>(const DevLevel&, const DevLevel&, const float*, const float*, const int32_t*,
+                                        int, double, const float*, float*, hipStream_t);
+template bool launch_vcycle_tail<double>(const DevLevel&, const DevLevel&, const double*, const double*,
+                                         const int32_t*, int, double, const double*, double*, hipStream_t);
+
 template void launch_coarse<double>(const double*, const int32_t*, int, int, const double*, double*, hipStream_t);
 
 void launch_harmonic_mu(int64_t ncell, const double* mq, double* mu, hipStream_t s) {
