@@ -4,6 +4,8 @@
   solve (the dense inverse of the free block; the outer iterations then come
   from the Schur approximation alone); operator, V-cycle and Stokes solve
   against the oracle.
+* Two levels, 4^3 cells over 2^3: the V-cycle is the one-workgroup kernel of
+  the 4^3 level alone; against the oracle's cycle, and a Stokes solve.
 * A zero right-hand side: every outer solver returns u = 0, p = 0 after no
   iteration, converged, with a zero residual.
 * Contrast 1 (constant viscosity, the sinker field's degenerate case): the
@@ -74,6 +76,34 @@ def test_one_level_mesh():
         e = rel_err(xt.double().cpu().numpy(), ref[perm])
         print(f"  V-cycle {dt}: {e:.2e}")
         assert e <= tol, (dt, e)
+    _solve_vs_direct(c)
+    c.close()
+
+
+def test_two_level_mesh():
+    """4^3 leaf over the 2^3 coarse level: the whole V-cycle is the
+    one-workgroup kernel of the 4^3 level (smoothing, residual, restriction,
+    coarse solve, prolongation, smoothing), compared with the oracle's cycle
+    (Sec. 2.2.1) twice in a row, and a Stokes solve with it."""
+    # contrast 1e2 as for the one-level mesh: the solve's check bounds the
+    # forward error by 1e-5, which residual 1e-8 times the conditioning of a
+    # 4^3 mesh at contrast 1e3 exceeds (1.4e-5 there, residual 8.6e-9)
+    c = Case(base=2, sinkers=3, dr=1e2, seed=5)
+    assert c.L == 2
+    c.s.set_viscosity(c.mu_qp_lib)
+    n = c.info["n_u"][2]
+    perm = c.dof_perm(2)
+    G = mg.GMG(c.H, c.mus)
+    for seed in (21, 22):
+        b_or = inputs.uniform_vector(n, seed)
+        ref = G.vcycle(b_or)
+        for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+            bt = torch.tensor(b_or[perm], dtype=dt, device=DEV)
+            xt = torch.full_like(bt, float("nan"))   # every entry must be written
+            c.s.vcycle(bt, xt)
+            e = rel_err(xt.double().cpu().numpy(), ref[perm])
+            print(f"  seed {seed} V-cycle {dt}: {e:.2e}")
+            assert e <= tol, (seed, dt, e)
     _solve_vs_direct(c)
     c.close()
 
