@@ -62,6 +62,20 @@ struct UniformCell {
   }
 };
 
+// The value of lane - 1 within the lane's row of 16 lanes (DPP row shift
+// right by one; 0 at a row's first lane)
+__device__ __forceinline__ int dpp_from_left(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float from_left_lane(float v) {
+  return __int_as_float(dpp_from_left(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(dpp_from_left(int(b))), hi = unsigned(dpp_from_left(int(b >> 32)));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // ------------------------------------------------------------- vmult
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_out_uniform(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
@@ -126,6 +140,33 @@ __global__ __launch_bounds__(192) void k_vmult_uniform3(int64_t n, const T* __re
   else if (c == 1) cellop::apply_cell_row<1>(W, w, mu_h);
   else cellop::apply_cell_row<2>(W, w, mu_h);
   cellop::interp_all_t(w);
+  // A cell's xx = 2 nodes are the next cell's xx = 0 nodes.  Within a row of
+  // 16 lanes the next cell along x is the next lane, which adds the values
+  // passed on (DPP row shift) into its own: those nodes take one atomic
+  // instead of two (device-scope atomics, served beyond the XCD's L2, are most
+  // of this kernel's time on a 16^3 level).
+  // The same along y: the next cell along y is lane + n (when still in the
+  // block), which takes the yy = 2 row of values (those not already passed on
+  // along x) into its yy = 0 row.
+  const int64_t cc0 = live ? cell : 0;
+  const int ix = int(cc0 % n), iy = int((cc0 / n) % n);
+  const bool send_x = ix < n - 1 && (lane & 15) != 15, recv_x = ix > 0 && (lane & 15) != 0;
+  const bool send_y = iy < n - 1 && lane + n < 64, recv_y = iy > 0 && lane >= n;
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int yy = 0; yy < 3; ++yy) {
+      const T r = from_left_lane(w[2 + 3 * yy + 9 * z]);
+      if (recv_x) w[3 * yy + 9 * z] += r;
+      if (send_x) w[2 + 3 * yy + 9 * z] = T(0);   // handed over
+    }
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int xx = 0; xx < 3; ++xx) {
+      const T r = __shfl_up(w[xx + 6 + 9 * z], unsigned(n));
+      if (recv_y) w[xx + 9 * z] += r;
+    }
   if (!live) return;
 #pragma unroll
   for (int z = 0; z < 3; ++z)
@@ -134,7 +175,8 @@ __global__ __launch_bounds__(192) void k_vmult_uniform3(int64_t n, const T* __re
 #pragma unroll
       for (int xx = 0; xx < 3; ++xx) {
         const int32_t sl = uc.slot(xx, yy, z);
-        if (sl >= 0) atomic_add(&y[3 * int64_t(sl) + c], w[xx + 3 * yy + 9 * z]);
+        if (sl >= 0 && !(xx == 2 && send_x) && !(yy == 2 && send_y))
+          atomic_add(&y[3 * int64_t(sl) + c], w[xx + 3 * yy + 9 * z]);
       }
 }
 
