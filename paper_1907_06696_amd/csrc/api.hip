@@ -396,6 +396,42 @@ int upload_level(mfgmg_ctx* ctx, const Level& h, LevelDev& d, bool leaf, bool to
         d.hent = ctx->upload(b.hent);
         d.hw_d = ctx->upload(b.hw);
         d.hw_f = ctx->upload(std::vector<float>(b.hw.begin(), b.hw.end()));
+        // per workgroup (64 / NC blocks): the hanging entries grouped by
+        // hanging point (consecutive already) and, reordered, by master, so
+        // that one lane sums each group (no LDS atomics)
+        {
+          const int64_t NBW = 64 / NC, nwg = (d.n + NBW - 1) / NBW;
+          std::vector<int32_t> g1off{0}, g1, g2off{0}, g2, hent2(b.hent.size()), idx;
+          std::vector<double> hw2(b.hw.size());
+          for (int64_t g = 0; g < nwg; ++g) {
+            const int32_t h0 = b.hoff[size_t(g * NBW)], h1 = b.hoff[size_t(std::min(d.n, (g + 1) * NBW))];
+            constexpr int32_t kMasterBits = 1023 << 10;   // entry = p | pm << 10 | block << 20
+            for (int32_t e = h0; e < h1; ++e)
+              if (e == h0 || (b.hent[size_t(e)] & ~kMasterBits) != (b.hent[size_t(e - 1)] & ~kMasterBits))
+                g1.push_back(e);
+            g1.push_back(h1);
+            g1off.push_back(int32_t(g1.size()));
+            idx.resize(size_t(h1 - h0));
+            for (int32_t e = h0; e < h1; ++e) idx[size_t(e - h0)] = e;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t u, int32_t v) { return (b.hent[size_t(u)] >> 10) < (b.hent[size_t(v)] >> 10); });
+            for (int32_t e = h0; e < h1; ++e) {
+              hent2[size_t(e)] = b.hent[size_t(idx[size_t(e - h0)])];
+              hw2[size_t(e)] = b.hw[size_t(idx[size_t(e - h0)])];
+            }
+            for (int32_t e = h0; e < h1; ++e)
+              if (e == h0 || (hent2[size_t(e)] >> 10) != (hent2[size_t(e - 1)] >> 10)) g2.push_back(e);
+            g2.push_back(h1);
+            g2off.push_back(int32_t(g2.size()));
+          }
+          d.g1off = ctx->upload(g1off);
+          d.g1 = ctx->upload(g1);
+          d.g2off = ctx->upload(g2off);
+          d.g2 = ctx->upload(g2);
+          d.hent2 = ctx->upload(hent2);
+          d.hw2_d = ctx->upload(hw2);
+          d.hw2_f = ctx->upload(std::vector<float>(hw2.begin(), hw2.end()));
+        }
         if (leaf) {
           d.pslots = ctx->upload(b.pslots);
           d.phoff = ctx->upload(b.phoff);

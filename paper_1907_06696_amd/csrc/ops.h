@@ -30,6 +30,17 @@ struct DevBlocks {
   const int32_t* hent = nullptr;
   const double* hw_d = nullptr;
   const float* hw_f = nullptr;
+  // the same entries grouped per workgroup for the velocity kernel, without
+  // atomics: by hanging point (consecutive in hent; group k of workgroup g is
+  // [g1[k], g1[k + 1]) for k in [g1off[g], g1off[g + 1] - 1)), and sorted by
+  // master (hent2 / hw2_*, groups g2 / g2off)
+  const int32_t* g1off = nullptr;
+  const int32_t* g1 = nullptr;
+  const int32_t* hent2 = nullptr;
+  const double* hw2_d = nullptr;
+  const float* hw2_f = nullptr;
+  const int32_t* g2off = nullptr;
+  const int32_t* g2 = nullptr;
   int64_t n = 0;
   // leaf only: the Q1 pressure lattice [(B+1)^3] of each block (node >= 0,
   // -2 hanging) and its hanging points' masters, packed as above

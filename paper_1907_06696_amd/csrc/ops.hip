@@ -315,8 +315,8 @@ __global__ __launch_bounds__(192) void k_vmult_general3(const int32_t* __restric
 // two cells of a block share a node).  Hanging points are resolved inside
 // the box: their masters are lattice points of the same block, so the
 // gather interpolates them from the staged masters and the write-back first
-// distributes their accumulated values onto the masters (LDS atomics; few
-// points).  Nodes strictly inside a block belong to its cells alone and are
+// distributes their accumulated values onto the masters (FP64: LDS atomics;
+// FP32: one lane per hanging point, then one per master).  Nodes strictly inside a block belong to its cells alone and are
 // stored; the values of its free face nodes go to the block's face slots
 // and k_face_gather adds each node's slots into y.  LDS layout per block and
 // component: every axis split into even then odd lattice points.
@@ -334,6 +334,16 @@ __device__ __forceinline__ const float* blk_hw<float>(const DevBlocks& b) {
 template <>
 __device__ __forceinline__ const double* blk_hw<double>(const DevBlocks& b) {
   return b.hw_d;
+}
+template <typename T>
+__device__ __forceinline__ const T* blk_hw2(const DevBlocks& b);
+template <>
+__device__ __forceinline__ const float* blk_hw2<float>(const DevBlocks& b) {
+  return b.hw2_f;
+}
+template <>
+__device__ __forceinline__ const double* blk_hw2<double>(const DevBlocks& b) {
+  return b.hw2_d;
 }
 
 // ACC: inner points are added to y (y += A x); otherwise stored (y was initialised to zero there)
@@ -355,7 +365,6 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     const int px = p % E, py = (p / E) % E, pz = p / (E * E);
     return bl * W + bsplit<B>(px) + E * bsplit<B>(py) + E * E * bsplit<B>(pz);
   };
-  const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
   // staging: every slot load, then every value load, issued before use;
   // points of missing blocks, Dirichlet and hanging points (and components
   // fixed by the no-normal-flux condition) store zero.  The slots stay in
@@ -386,14 +395,37 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     }
   }
   __syncthreads();
-  // hanging points: interpolate from their masters in the box
-  for (int e = h0 + lane; e < h1; e += 64) {
-    const int32_t en = blk.hent[e];
-    const int p = en & 1023, pm = (en >> 10) & 1023, bl = en >> 20;
-    const T w = hw[e];
-    const int o = lds_of(bl, p), om = lds_of(bl, pm);
+  // hanging points: interpolate from their masters in the box.  FP32: one
+  // lane per hanging point (its entries are consecutive), no LDS atomics,
+  // whose FP32 form is slow here (leaf of the adaptive 32^3 + 2 workload: 144
+  // -> 125 us per call); FP64: one lane per entry with LDS atomics (the
+  // grouped form: 198 -> 225 us)
+  if constexpr (sizeof(T) == 8) {
+    const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
+    for (int e = h0 + lane; e < h1; e += 64) {
+      const int32_t en = blk.hent[e];
+      const int p = en & 1023, pm = (en >> 10) & 1023, bl = en >> 20;
+      const T w = hw[e];
+      const int o = lds_of(bl, p), om = lds_of(bl, pm);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) atomicAdd(&buf[o + q * P], w * buf[om + q * P]);
+      for (int q = 0; q < 3; ++q) atomicAdd(&buf[o + q * P], w * buf[om + q * P]);
+    }
+  } else {
+    const int k0 = blk.g1off[blockIdx.x], k1 = blk.g1off[blockIdx.x + 1] - 1;
+    for (int k = k0 + lane; k < k1; k += 64) {
+      const int e0 = blk.g1[k], e1 = blk.g1[k + 1];
+      T a0 = T(0), a1 = T(0), a2 = T(0);
+      int o = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int32_t en = blk.hent[e];
+        const int p = en & 1023, pm = (en >> 10) & 1023, bl = en >> 20;
+        const T w = hw[e];
+        const int om = lds_of(bl, pm);
+        o = lds_of(bl, p);
+        a0 += w * buf[om], a1 += w * buf[om + P], a2 += w * buf[om + 2 * P];
+      }
+      buf[o] = a0, buf[o + P] = a1, buf[o + 2 * P] = a2;
+    }
   }
   __syncthreads();
   const int bl = lane / NC, lc = lane - bl * NC;
@@ -435,14 +467,36 @@ __global__ __launch_bounds__(64) void k_vmult_blocks(DevBlocks blk, const int8_t
     __syncthreads();
   }
   // hanging points pass their accumulated values on to their masters (the
-  // hanging entries themselves are not read again)
-  for (int e = h0 + lane; e < h1; e += 64) {
-    const int32_t en = blk.hent[e];
-    const int p = en & 1023, pm = (en >> 10) & 1023, bl2 = en >> 20;
-    const T w = hw[e];
-    const int o = lds_of(bl2, p), om = lds_of(bl2, pm);
+  // hanging entries themselves are not read again): FP64 one lane per entry
+  // with LDS atomics, FP32 one lane per master over the entries sorted by
+  // master
+  if constexpr (sizeof(T) == 8) {
+    const int h0 = blk.hoff[blk0], h1 = blk.hoff[blk0 + nb];
+    for (int e = h0 + lane; e < h1; e += 64) {
+      const int32_t en = blk.hent[e];
+      const int p = en & 1023, pm = (en >> 10) & 1023, bl2 = en >> 20;
+      const T w = hw[e];
+      const int o = lds_of(bl2, p), om = lds_of(bl2, pm);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) atomicAdd(&buf[om + q * P], w * buf[o + q * P]);
+      for (int q = 0; q < 3; ++q) atomicAdd(&buf[om + q * P], w * buf[o + q * P]);
+    }
+  } else {
+    const T* __restrict__ hw2 = blk_hw2<T>(blk);
+    const int k0 = blk.g2off[blockIdx.x], k1 = blk.g2off[blockIdx.x + 1] - 1;
+    for (int k = k0 + lane; k < k1; k += 64) {
+      const int e0 = blk.g2[k], e1 = blk.g2[k + 1];
+      T a0 = T(0), a1 = T(0), a2 = T(0);
+      int om = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int32_t en = blk.hent2[e];
+        const int p = en & 1023, pm = (en >> 10) & 1023, bl2 = en >> 20;
+        const T w = hw2[e];
+        const int o = lds_of(bl2, p);
+        om = lds_of(bl2, pm);
+        a0 += w * buf[o], a1 += w * buf[o + P], a2 += w * buf[o + 2 * P];
+      }
+      buf[om] += a0, buf[om + P] += a1, buf[om + 2 * P] += a2;
+    }
   }
   __syncthreads();
   // write-back of the free points: inside the block stored (added when
