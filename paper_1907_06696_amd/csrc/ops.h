@@ -246,7 +246,7 @@ void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* 
 // the new w: dots: result[j] = V_j . w (j < nv), result[nv] = w . w; else
 // result[0] = w . w.  partial has >= 65536 doubles.  Returns false (nothing
 // launched) unless 1 <= nv <= kMupdateDotsMax.
-constexpr int kMupdateDotsMax = 64;
+constexpr int kMupdateDotsMax = 128;
 bool launch_mupdate_dots(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, double* partial,
                          double* result, bool dots, hipStream_t s);
 // w -= sum_j h[j] V[j*ldv + i]

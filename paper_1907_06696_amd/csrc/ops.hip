@@ -2610,7 +2610,7 @@ bool launch_mupdate_dots(int64_t n, int nv, const double* V, int64_t ldv, const 
   // holds at most 65 x 512 partials (65536 from the caller)
   if (nv < 1 || nv > kMupdateDotsMax) return false;
   const unsigned rows = dots ? unsigned(nv + 1) : 1u;
-  const int nb = 512;   // rows x nb <= 65 x 512 partials
+  const int nb = nv <= 64 ? 512 : 256;   // rows x nb <= 65 x 512 or 129 x 256 partials
   // up to 32 vectors: one thread per entry holding its nv values; beyond,
   // where that form runs at one wave per SIMD, the tiles (64 vectors: 697 ->
   // 438 us per call on the 64^3 workload)
@@ -2621,10 +2621,12 @@ bool launch_mupdate_dots(int64_t n, int nv, const double* V, int64_t ldv, const 
     MFGMG_MUD(16)
   } else if (nv <= 32) {
     MFGMG_MUD(32)
-  } else if (dots) {
-    k_mupdate_tiles<16, true><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
+  } else if (nv <= 64) {
+    if (dots) k_mupdate_tiles<16, true><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
+    else k_mupdate_tiles<16, false><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
   } else {
-    k_mupdate_tiles<16, false><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
+    if (dots) k_mupdate_tiles<32, true><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
+    else k_mupdate_tiles<32, false><<<nb, 256, 0, s>>>(n, nv, V, ldv, h, w, part);
   }
 #undef MFGMG_MUD
   k_sum_partials<<<rows, kBlock, 0, s>>>(nb, part, result);
