@@ -1500,8 +1500,9 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, int nv, cons
                                                          int64_t ldv, const double* __restrict__ w,
                                                          double* __restrict__ part) {
   // grid (nb, nv or nv + 1): block (b, j) computes a partial of V_j . w, and
-  // row j = nv (when launched) one of w . w (w stays in the caches across the
-  // j; grouping several j per block measured slower)
+  // row j = nv (when launched) one of w . w; used up to 32 vectors, where
+  // its many blocks keep more loads in flight than the tiled form below
+  // (beyond, re-reading w once per vector costs more: k_mdot_tiles)
   const int j = blockIdx.y;
   double v = 0.0;
   const double* Vj = j < nv ? V + int64_t(j) * ldv : w;
