@@ -436,3 +436,39 @@ def test_nonzero_divergence_manufactured():
             print(f"  div u = g {prec}: its={st['iterations']} res={res:.2e} err={err:.2e}", flush=True)
             assert st["converged"] == 1 and res <= 2e-11 and err <= 1e-4, (prec, res, err)
         c.close()
+
+
+def test_long_restart_gram_schmidt():
+    """FGMRES with restart 100 and the block-diagonal P_D (Sec. 3.4) on a mesh
+    where it needs more than 64 iterations, so that the Arnoldi steps run the
+    Gram-Schmidt kernels at every basis size (one block per vector below 33,
+    tiles of 64 entries with 16 and then 32 vectors per wave above): the FP64
+    iteration count equals the oracle's (restart 100) up to one and the
+    solution matches the direct solve."""
+    c = Case(base=3, corners=((2, 5, 3), (0, 0, 0)), times=1, sinkers=4, dr=1e4, seed=7)
+    c.s.set_viscosity(c.mu_qp_lib)
+    L = c.L
+    nu, npp = c.info["n_u"][L], c.info["n_p"]
+    prob = krylov.StokesProblem(c.H, ops.harmonic_cell_viscosity(c.mu_qp_or), c.f_qp_or, gmg_kwargs={})
+    x_or, st_or = prob.solve(rtol=1e-8, restart=100, maxit=600, krylov="fgmres", block="diagonal")
+    assert st_or["iterations"] > 64, st_or["iterations"]
+    xd = prob.solve_direct()
+    pu, pp = c.dof_perm(L), c.pnode_perm()
+    rhs = torch.empty(nu, dtype=torch.float64, device=DEV)
+    c.s.assemble_rhs(c.f_qp_lib, rhs)
+    u = torch.empty(nu, dtype=torch.float64, device=DEV)
+    p = torch.empty(npp, dtype=torch.float64, device=DEV)
+    st = c.s.solve_stokes(rhs, u, p, vcycle_prec="fp64", max_iter=600, restart=100, krylov="fgmres",
+                          block="diagonal")
+    torch.cuda.synchronize()
+    x = np.zeros(nu + npp)
+    x[pu] = u.cpu().numpy()
+    x[nu + pp] = p.cpu().numpy()
+    x[:nu] *= c.H.leaf.free_dofs_mask()
+    x[nu:] *= c.H.leaf.pfree
+    res = prob.residual(x)
+    err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    print(f"  its={st['iterations']} (oracle {st_or['iterations']}) res={res:.2e} err={err:.2e}", flush=True)
+    assert st["converged"] == 1 and res <= 1.5e-8 and err <= 1e-5, (res, err)
+    assert abs(st["iterations"] - st_or["iterations"]) <= 1, (st["iterations"], st_or["iterations"])
+    c.close()
