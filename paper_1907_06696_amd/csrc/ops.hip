@@ -1496,22 +1496,6 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(int np, const double* _
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_mdot_partial(int64_t n, int nv, const double* __restrict__ V,
-                                                         int64_t ldv, const double* __restrict__ w,
-                                                         double* __restrict__ part) {
-  // grid (nb, nv or nv + 1): block (b, j) computes a partial of V_j . w, and
-  // row j = nv (when launched) one of w . w; used up to 32 vectors, where
-  // its many blocks keep more loads in flight than the tiled form below
-  // (beyond, re-reading w once per vector costs more: k_mdot_tiles)
-  const int j = blockIdx.y;
-  double v = 0.0;
-  const double* Vj = j < nv ? V + int64_t(j) * ldv : w;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    v += Vj[i] * w[i];
-  v = block_sum(v);
-  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = v;
-}
-
 __global__ void k_mupdate(int64_t n, int nv, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
                           double* __restrict__ w) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
@@ -2592,9 +2576,11 @@ void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* 
                  hipStream_t s, bool with_norm) {
   // part holds rows x nb partials (65536 from the caller: rows <= 256)
   const unsigned rows = unsigned(nv + (with_norm ? 1 : 0));
-  if (nv <= 32) {   // few vectors: one block per (vector, block) pair has more loads in flight
-    const int nb = 256;
-    k_mdot_partial<<<dim3(nb, rows), kBlock, 0, s>>>(n, nv, V, ldv, w, part);
+  if (nv <= 32) {   // up to 8 vectors per wave, more blocks
+    const int nb = 1024;   // rows <= 33: 33 x 1024 partials
+    if (nv <= 8) k_mdot_tiles<2><<<nb, 256, 0, s>>>(n, 0, nv, V, ldv, w, with_norm, part);
+    else if (nv <= 16) k_mdot_tiles<4><<<nb, 256, 0, s>>>(n, 0, nv, V, ldv, w, with_norm, part);
+    else k_mdot_tiles<8><<<nb, 256, 0, s>>>(n, 0, nv, V, ldv, w, with_norm, part);
     k_sum_partials<<<rows, kBlock, 0, s>>>(nb, part, result);
     return;
   }
